@@ -1,0 +1,275 @@
+"""Pins of the CPU oracle to things other than itself: the paper's worked
+examples, brute-force enumeration, closed forms and textbook special cases."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse import csgraph
+
+import oracle
+from oracle import brute
+from paper_2009_10247_amd import gen
+from tests import _golden
+
+
+def _set(v, atoms):
+    return {a for a, x in zip(atoms, v) if x}
+
+
+# ------------------------------------------------------------ worked examples
+
+def test_example1_least_model_and_products():
+    d = _golden.load("example1.txt")
+    p = _golden.program(d)
+    assert _set(oracle.least_model(p), d["atoms"]) == set(d["least_model"])
+    model, products, n_std, n_true_std = oracle.sd_fixpoint(p)
+    assert _set(model, d["atoms"]) == set(d["least_model"])
+    assert products == d["products"][0] == 3
+    assert n_std == len(d["std_atoms"]) == 7
+    assert n_true_std == len(d["std_least_model"]) == 7
+    assert brute.least_model(p) == brute.from_vector(_golden.names_to_vector(d["least_model"], d["atoms"]))
+
+
+def test_example2_stable_models():
+    d = _golden.load("example2.txt")
+    p = _golden.program(d)
+    models, res = oracle.stable_models(p)
+    assert [_set(m, d["atoms"]) for m in models] == d["stable_models"]
+    assert list(np.nonzero(res["accept"])[0]) == d["accepted_guesses"]
+    assert list(res["neg_atoms"]) == [d["atoms"].index("t")]
+    # per-guess fixpoints of Definition 8's two columns (original atoms only)
+    for j, names in d["guess_fixpoint"].items():
+        col = (res["interp"][:, 0] >> np.uint64(j)) & np.uint64(1)
+        assert _set(col, d["atoms"]) == names - {"tbar"}
+    for m in models:
+        assert oracle.gl_check(p, m)
+    assert not oracle.gl_check(p, _golden.names_to_vector({"s", "t"}, d["atoms"]))
+    want = [brute.from_vector(_golden.names_to_vector(s, d["atoms"])) for s in d["stable_models"]]
+    assert brute.stable_models(p) == want
+
+
+# ------------------------------------------------------------ brute force
+
+@pytest.mark.parametrize("block", range(8))
+def test_least_model_matches_brute_force(block):
+    for seed in range(block * 150, (block + 1) * 150):
+        p = gen.tiny_random(seed, max_atoms=16 if seed % 5 == 0 else 10, max_rules=40, max_body=4)
+        want = brute.least_model(p)
+        got = brute.from_vector(oracle.least_model(p))
+        assert got == want, seed
+        model, products, n_std, _ = oracle.sd_fixpoint(p)
+        assert brute.from_vector(model) == want, seed
+        assert 1 <= products <= n_std + 1
+
+
+@pytest.mark.parametrize("block", range(6))
+def test_stable_models_match_brute_force(block):
+    for seed in range(block * 120, (block + 1) * 120):
+        p = gen.tiny_random(10_000 + seed, max_atoms=8, max_rules=14, max_body=3, p_neg=0.35)
+        want = brute.stable_models(p)
+        models, res = oracle.stable_models(p, threads=1)
+        got = sorted(brute.from_vector(m) for m in models)
+        assert got == want, seed
+        for m in models:
+            assert oracle.gl_check(p, m), seed
+
+
+def test_per_guess_least_models_match_brute_force():
+    # L_j = LM(P+ u G_j) for every guess j, checked by model intersection over
+    # all interpretations of P+ (original atoms plus one new atom per negated atom).
+    for seed in range(60):
+        p = gen.tiny_random(20_000 + seed, max_atoms=9, max_rules=16, max_body=3, p_neg=0.3)
+        res = oracle.stable(p, want_interp=True)
+        qs = list(res["neg_atoms"])
+        K = len(qs)
+        n = p.n_atoms
+        if n + K > 16:
+            continue
+        base = []
+        for h, body in p.rules():
+            base.append((h, [lit if lit >= 0 else n + qs.index(-lit - 1) for lit in body]))
+        for j in range(1 << K):
+            rules = base + [(n + t, []) for t in range(K) if (j >> t) & 1]
+            pplus = gen.from_rules(n + K, rules)
+            lm = brute.least_model(pplus)
+            w, b = divmod(j, 64)
+            col = (res["interp"][:, w] >> np.uint64(b)) & np.uint64(1)
+            assert brute.from_vector(col) == lm & ((1 << n) - 1), (seed, j)
+            acc = all(((lm >> q) & 1) != ((lm >> (n + t)) & 1) for t, q in enumerate(qs))
+            assert bool(res["accept"][j]) == acc, (seed, j)
+
+
+def test_gl_check_rejects_every_non_stable_interpretation():
+    for seed in range(40):
+        p = gen.tiny_random(30_000 + seed, max_atoms=6, max_rules=10, max_body=3, p_neg=0.4)
+        stable = set(brute.stable_models(p))
+        for interp in range(1 << p.n_atoms):
+            assert oracle.gl_check(p, brute.to_vector(interp, p.n_atoms)) == (interp in stable)
+
+
+# ------------------------------------------------------------ closed forms / special cases
+
+def _sd_graph_distances(p):
+    """Length-1 bodies only: multi-source BFS over the standardized graph
+    body -> head (single-rule head) or body -> b_i -> head (head with k >= 2)."""
+    n = p.n_atoms
+    k = np.bincount(p.head, minlength=n)
+    nodes = n
+    edges = []
+    sources = []
+    for h, body in p.rules():
+        tgt = h
+        if k[h] >= 2:
+            tgt = nodes
+            nodes += 1
+            edges.append((tgt, h))
+        if body:
+            edges.append((body[0], tgt))
+        else:
+            sources.append(tgt)
+    S = nodes
+    edges += [(S, s) for s in sources]
+    rows = [a for a, _ in edges]
+    cols = [b for _, b in edges]
+    G = sp.csr_matrix((np.ones(len(edges)), (rows, cols)), shape=(S + 1, S + 1))
+    dist = csgraph.shortest_path(G, unweighted=True, indices=[S])[0] - 1
+    return dist, nodes
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_length_one_bodies_are_bfs(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(20, 400))
+    R = int(rng.integers(n, 3 * n))
+    rules = []
+    for r in range(R):
+        h = int(rng.integers(0, n))
+        rules.append((h, [] if rng.random() < 0.03 else [int(rng.integers(0, n))]))
+    p = gen.from_rules(n, rules)
+    dist, n_std = _sd_graph_distances(p)
+    want = np.isfinite(dist[:n]).astype(np.uint8)
+    assert np.array_equal(oracle.least_model(p), want)
+    model, products, n_std2, n_true = oracle.sd_fixpoint(p)
+    assert np.array_equal(model, want)
+    finite = dist[np.isfinite(dist)]
+    assert products == 1 + (int(finite.max()) if finite.size else 0)
+    assert n_std2 == n_std
+    assert n_true == int(np.isfinite(dist[:n_std]).sum())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_transitive_closure_is_warshall(seed):
+    V = 6 + seed
+    edges = gen.random_graph_edges(seed, V, 2 * V)
+    p = gen.transitive_closure(V, edges)
+    A = np.zeros((V, V), dtype=bool)
+    for x, y in edges:
+        A[x, y] = True
+    C = A.copy()
+    for z in range(V):
+        C |= C[:, z:z + 1] & C[z:z + 1, :]
+    lm = oracle.least_model(p)
+    assert np.array_equal(lm[V * V:].reshape(V, V).astype(bool), C)
+    assert np.array_equal(lm[:V * V].reshape(V, V).astype(bool), A)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 10, 257])
+def test_chain_products(L):
+    rules = [(0, [])] + [(i, [i - 1]) for i in range(1, L)]
+    p = gen.from_rules(L, rules)
+    model, products, _, _ = oracle.sd_fixpoint(p)
+    assert model.all() and products == L
+
+
+def test_no_facts_gives_empty_model_and_one_product():
+    p = gen.definite_uniform(3, 200, 400, fact_frac=0.0, max_body=3)
+    model, products, _, n_true = oracle.sd_fixpoint(p)
+    assert model.sum() == 0 and products == 1 and n_true == 0
+
+
+def test_facts_only():
+    p = gen.from_rules(5, [(1, []), (3, []), (3, [])])
+    model, products, n_std, n_true = oracle.sd_fixpoint(p)
+    assert list(model) == [0, 1, 0, 1, 0]
+    assert products == 2  # atom 3 has two rules: b_1, b_2 facts, then 3 <- b_1 v b_2
+    assert n_std == 7 and n_true == 4
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_even_loops_have_2_to_n_models(n):
+    p = gen.even_loops(n)
+    models, res = oracle.stable_models(p)
+    assert len(models) == 2 ** n
+    got = sorted(brute.from_vector(m) for m in models)
+    assert len(set(got)) == 2 ** n
+    for m in got:
+        for i in range(n):  # exactly one of a_i, b_i
+            assert ((m >> (2 * i)) & 1) + ((m >> (2 * i + 1)) & 1) == 1
+
+
+def test_odd_loop_has_no_model():
+    models, _ = oracle.stable_models(gen.odd_loop())
+    assert models == []
+
+
+def test_definite_program_has_one_stable_model_equal_to_lm():
+    for seed in range(20):
+        p = gen.definite_uniform(seed, 300, 600, 0.05, 4)
+        models, res = oracle.stable_models(p)
+        assert len(models) == 1 and np.array_equal(models[0], oracle.least_model(p))
+
+
+def test_stratified_program_has_its_perfect_model():
+    # Stratum 0: a definite program over atoms [0, n0). Stratum 1: rules over
+    # atoms [n0, n0+n1) whose bodies use positive atoms of both strata and
+    # negations of stratum-0 atoms only. The perfect model evaluates stratum 0,
+    # fixes its atoms, then evaluates stratum 1 with negations read off it.
+    for seed in range(10):
+        rng = np.random.default_rng(100 + seed)
+        n0, n1 = 40, 30
+        s0 = gen.definite_uniform(seed, n0, 80, 0.1, 3)
+        lm0 = oracle.least_model(s0)
+        rules = list(s0.rules())
+        negatable = rng.choice(n0, size=8, replace=False)
+        rules1 = []
+        for _ in range(60):
+            h = n0 + int(rng.integers(0, n1))
+            body = [int(x) for x in rng.choice(n0 + n1, size=int(rng.integers(0, 3)), replace=False)]
+            body += [gen.neg(int(x)) for x in rng.choice(negatable, size=int(rng.integers(0, 3)), replace=False)]
+            rules1.append((h, body))
+        p = gen.from_rules(n0 + n1, rules + rules1)
+        # reduce stratum 1 against lm0, then one definite least model
+        red = rules + [(h, [l for l in b if l >= 0]) for h, b in rules1
+                       if all(lm0[-l - 1] == 0 for l in b if l < 0)]
+        perfect = oracle.least_model(gen.from_rules(n0 + n1, red))
+        models, _ = oracle.stable_models(p)
+        assert len(models) == 1 and np.array_equal(models[0], perfect)
+
+
+def test_least_model_is_a_minimal_model():
+    # the least model satisfies every rule, and dropping any of its atoms breaks that
+    for seed in range(10):
+        p = gen.definite_uniform(seed, 500, 1000, 0.05, 4)
+        lm = oracle.least_model(p).astype(bool)
+        for h, body in p.rules():
+            if all(lm[b] for b in body):
+                assert lm[h]
+        for a in np.nonzero(lm)[0][:50]:
+            I = lm.copy()
+            I[a] = False
+            assert any(all(I[b] for b in body) and not I[h] for h, body in p.rules())
+
+
+def test_negation_rejected_by_definite_calls():
+    p = gen.from_rules(2, [(0, [gen.neg(1)])])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.least_model(p)
+    assert e.value.code == -4
+
+
+def test_malformed_input_rejected():
+    bad = gen.Program(3, np.array([5], np.int32), np.array([0, 0], np.int64), np.zeros(0, np.int32))
+    with pytest.raises(oracle.OracleError):
+        oracle.least_model(bad)
+    bad2 = gen.Program(3, np.array([0], np.int32), np.array([0, 1], np.int64), np.array([7], np.int32))
+    with pytest.raises(oracle.OracleError):
+        oracle.least_model(bad2)

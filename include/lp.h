@@ -1,0 +1,232 @@
+/*
+ * lp.h -- C ABI of the MI355X (gfx950) engine for linear-algebraic T_P
+ * fixpoints over sparse program matrices.
+ *
+ * The operations follow Nguyen, Inoue and Sakama, "Enhancing Linear Algebraic
+ * Computation of Logic Programs Using Sparse Representation" (ICLP 2020):
+ *   - the program matrix of a standardized program (Definition 2) and of the
+ *     positive form of a normal program (Definition 7), stored as CSR
+ *     (Section 3.2);
+ *   - the least-model fixpoint v <- theta(M v) from the initial vector
+ *     (Definitions 3-5, Algorithm 1);
+ *   - the stable-model fixpoint over an initial matrix with one column per
+ *     guess, followed by the column consistency test (Definition 8,
+ *     Algorithms 2 and 3).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns lp_status: LP_OK (0) or a negative error code. No C++
+ *     exception crosses this boundary. lp_last_error() returns a message for
+ *     the calling thread's last failing call.
+ *   - Pointers named in the argument lists are HOST pointers unless a name
+ *     says d_ (device). Inputs are owned by the caller and are only read
+ *     during the call; nothing is retained. Outputs go to caller-owned host
+ *     buffers and are complete when the call returns (the call synchronizes
+ *     the stream it was given).
+ *   - hip_stream is a hipStream_t passed as void*; NULL means the default
+ *     stream. All device work of a call is issued on that stream.
+ *   - An lp_matrix is immutable after lp_build_matrix and may be used by
+ *     several calls at once on distinct streams (each solve allocates its own
+ *     interpretation buffers).
+ *
+ * Program layout (the input of lp_build_matrix):
+ *   head[r]      head atom of rule r, 0 <= head[r] < n_atoms
+ *   body_ptr[r]  rule r's literals are body_lit[body_ptr[r] .. body_ptr[r+1]);
+ *                body_ptr has n_rules+1 entries, body_ptr[0] == 0, nondecreasing
+ *   body_lit[e]  a >= 0: atom a;  a < 0: the negative literal "not atom (-a-1)"
+ *   A rule with an empty body is a fact. Bodies are sets (the paper assumes
+ *   distinct body atoms), so repeated literals in one body are merged.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lp_status;
+
+enum {
+    LP_OK = 0,
+    LP_E_INVAL = -1,            /* malformed input or argument; nnz or rows >= 2^31 */
+    LP_E_NOMEM = -2,            /* host or device memory exhausted (checked before launches) */
+    LP_E_DEVICE = -3,           /* a HIP runtime call failed */
+    LP_E_NEGATION = -4,         /* lp_least_model on a program with negative literals */
+    LP_E_TOO_MANY_GUESSES = -5, /* more than LP_MAX_NEG_ATOMS negated atoms */
+    LP_E_TRUNCATED = -6,        /* more stable models than max_models (outputs still valid) */
+    LP_E_INTERNAL = -7,         /* an invariant of the fixpoint failed (should not happen) */
+    LP_E_HOST_ONLY = -8         /* solve on a matrix built with LP_BUILD_HOST_ONLY */
+};
+
+#define LP_MAX_NEG_ATOMS 24
+
+/* lp_build_matrix flags */
+enum {
+    /* Definition 8, item 3: a qbar row is fixed to 0 when q is a fact, so the
+     * guesses on such atoms are not enumerated. The stable models returned are
+     * the same; only fewer columns are computed. */
+    LP_PRUNE_FACT_GUESSES = 1u << 0,
+    /* Build the host-side CSR only (no device memory, no HIP call). Used to
+     * inspect the matrix; solve calls then return LP_E_HOST_ONLY. */
+    LP_BUILD_HOST_ONLY = 1u << 1
+};
+
+typedef struct lp_matrix lp_matrix;
+
+typedef struct lp_info {
+    int32_t n_atoms;        /* N = |B_P| as given */
+    int32_t n_rules;        /* R */
+    int32_t n_std_atoms;    /* N + new atoms of the standardization */
+    int32_t n_rows;         /* N' = n_std_atoms + n_neg: matrix dimension */
+    int64_t nnz;            /* stored nonzeros of the program matrix */
+    int32_t n_neg;          /* K: distinct atoms occurring negated */
+    int32_t n_pruned;       /* negated atoms whose guess is pruned (flag above) */
+    int32_t n_and_rows;     /* rows of a rule body (fire iff all entries true) */
+    int32_t n_or_rows;      /* OR rows of the standardization (fire iff one entry true) */
+    int32_t n_fact_rows;    /* rows of facts (self-loop, set in the initial vector) */
+    int32_t n_empty_rows;   /* atoms with no rule (never true) */
+    int32_t max_row_len;    /* longest row */
+    int32_t n_long_rows;    /* rows handled by the split long-row pass */
+    int64_t device_bytes;   /* device memory held by the matrix */
+    double sparsity;        /* equation 5: 1 - sum_r |body(r)| / N^2 */
+} lp_info;
+
+/* Device-side schedule of the fixpoint loop. Zero-initialize and set what you
+ * need: 0 in any field selects the library default. */
+enum {
+    LP_DRIVER_AUTO = 0,
+    LP_DRIVER_PLAIN = 1,      /* one launch per product, host reads the change count each time */
+    LP_DRIVER_BATCHED = 2,    /* steps_per_sync launches between host reads of the change counts */
+    LP_DRIVER_PERSISTENT = 3  /* one launch; the loop runs on the device with a grid barrier */
+};
+
+typedef struct lp_schedule {
+    int32_t driver;          /* LP_DRIVER_* */
+    int32_t steps_per_sync;  /* products issued between host checks (BATCHED) */
+    int32_t long_row;        /* reserved: the long-row threshold is fixed at build time */
+    int32_t grid;            /* workgroups of a persistent launch (0: all that fit) */
+    int32_t skip_true_rows;  /* 1: rows already true are not re-read (same result, fewer bytes) */
+    int32_t reserved[3];
+} lp_schedule;
+
+/*
+ * Build the program matrix.
+ *
+ * Definite rules are standardized first (Section 2.1, the paragraph after
+ * Definition 1; Algorithm 1 step 1): every head h with k >= 2 rules gets k new
+ * atoms b_1..b_k with rules b_i <- body(r_i) and one OR rule h <- b_1 v ... v b_k.
+ * New atoms are numbered n_atoms, n_atoms+1, ... in ascending head order and,
+ * within one head, in rule order. Negative literals "not q" are replaced by
+ * new atoms qbar (equation 4; Definition 7): the K distinct negated atoms
+ * q_0 < q_1 < ... take the last K row ids, qbar_t = n_std_atoms + t.
+ *
+ * Rows store column ids only; the 1/m weights of Definition 2 are replaced by
+ * a per-row kind: an AND row fires iff all its entries are true (the count of
+ * true entries equals the row length), an OR row iff at least one entry is
+ * true. This is the theta-threshold of Definition 5 evaluated exactly. A fact
+ * row holds its own atom (a_ii = 1) and is set in the initial vector; an atom
+ * with no rule has an empty OR row and is never true.
+ *
+ * flags: LP_PRUNE_FACT_GUESSES, LP_BUILD_HOST_ONLY.
+ * On success *out owns host metadata and (unless host-only) device buffers,
+ * uploaded on hip_stream, until lp_free_matrix.
+ * Errors: LP_E_INVAL (bad ids, body_ptr not monotone, NULL arrays with
+ * nonzero sizes, more than 2^31-1 rows or nonzeros), LP_E_NOMEM, LP_E_DEVICE.
+ */
+lp_status lp_build_matrix(int32_t n_atoms, int32_t n_rules, const int32_t *head,
+                          const int64_t *body_ptr, const int32_t *body_lit, uint32_t flags,
+                          void *hip_stream, lp_matrix **out);
+
+/* Release every host and device resource of m (NULL is accepted). */
+lp_status lp_free_matrix(lp_matrix *m);
+
+/* Sizes and statistics of m. */
+lp_status lp_matrix_info(const lp_matrix *m, lp_info *out);
+
+/* The K negated atoms q_0 < ... < q_{K-1} (out: int32[K], host). */
+lp_status lp_matrix_neg_atoms(const lp_matrix *m, int32_t *out);
+
+/*
+ * Host copy of the program matrix in CSR form (Section 3.2, Example 4):
+ * row_ptr int32[n_rows+1], col int32[nnz] (ascending within a row),
+ * kind uint8[n_rows] (1 = AND row, 0 = OR row), fact uint8[n_rows]
+ * (1 = fact row, set in the initial vector). Any output may be NULL.
+ */
+lp_status lp_matrix_csr(const lp_matrix *m, int32_t *row_ptr, int32_t *col, uint8_t *kind,
+                        uint8_t *fact);
+
+/*
+ * Least model of a definite program (Algorithm 1).
+ * model: uint8[n_atoms] host, receives 1 for atoms of the least model
+ *   (the fixpoint restricted to the original atoms).
+ * products: nullable; receives the number of theta(M v) evaluations,
+ *   including the last one that found no change (>= 1).
+ * sched: nullable (library default).
+ * Errors: LP_E_NEGATION if the program has negative literals,
+ *   LP_E_HOST_ONLY, LP_E_NOMEM, LP_E_DEVICE, LP_E_INTERNAL.
+ */
+lp_status lp_least_model(const lp_matrix *m, uint8_t *model, int32_t *products,
+                         const lp_schedule *sched, void *hip_stream);
+
+/*
+ * Stable models of a normal program (Algorithms 2 and 3).
+ * Guess j (0 <= j < 2^K) is column j of the initial matrix: bit t of j is the
+ * initial value of qbar_t (1 = q_t assumed false). Column j is accepted iff in
+ * its fixpoint exactly one of q_t, qbar_t is true for every t; its model is
+ * the column restricted to the original atoms.
+ *
+ * accepted:  uint64[ceil(2^K/64)] host; bit j%64 of word j/64 = guess j accepted.
+ * n_models:  receives the number of stable models.
+ * models:    nullable; uint8[max_models][n_atoms] host, the first max_models
+ *            models in guess order.
+ * interp:    nullable; uint64[n_atoms][ceil(2^K/64)] host, the fixpoint
+ *            interpretation matrix restricted to the original atoms (bit j of
+ *            row a = atom a true in column j). Requires no pruning.
+ * products:  nullable; number of theta(M_P M) evaluations until no column changed.
+ * K = 0 gives exactly one model, the least model.
+ * Errors: LP_E_TOO_MANY_GUESSES (K > LP_MAX_NEG_ATOMS), LP_E_TRUNCATED (more
+ *   than max_models models; every other output is still complete),
+ *   LP_E_INVAL (interp requested with pruning), LP_E_NOMEM, LP_E_DEVICE.
+ */
+lp_status lp_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_models,
+                           uint8_t *models, int64_t max_models, uint64_t *interp,
+                           int32_t *products, void *hip_stream);
+
+/*
+ * Least models of count definite programs in one persistent launch: each
+ * program's fixpoint runs on the device; programs are taken from a device work
+ * queue, largest first. models[i]: uint8[n_atoms of ms[i]] host; products:
+ * nullable int32[count]. Results equal count separate lp_least_model calls.
+ * Errors as lp_least_model, for the first failing program.
+ */
+lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_t *const *models,
+                               int32_t *products, const lp_schedule *sched, void *hip_stream);
+
+/*
+ * Average duration in milliseconds of one full-sweep T_P step (theta(M v) on
+ * the whole matrix, the change count included) over reps back-to-back
+ * launches on hip_stream, timed with HIP events. The step reads the fixpoint
+ * of m (computed first) and writes a scratch buffer, so every launch moves the
+ * same bytes. Used to measure achieved bandwidth.
+ */
+lp_status lp_bench_step(const lp_matrix *m, int32_t reps, float *avg_ms, void *hip_stream);
+
+/*
+ * Route the library's device allocations through caller-supplied functions
+ * (e.g. a framework's caching allocator). alloc(bytes, stream, ctx) returns a
+ * device pointer or NULL; release(ptr, stream, ctx) frees it. Passing NULL for
+ * both restores hipMalloc/hipFree. Not thread-safe with concurrent solves.
+ */
+lp_status lp_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
+                           void (*release)(void *ptr, void *stream, void *ctx), void *ctx);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char *lp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H */

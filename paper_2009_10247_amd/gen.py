@@ -100,6 +100,8 @@ def _draw_bodies(rng, heads, lengths, max_len, pool_size, pool_map=None):
     out = np.zeros((R, max(max_len, 0)), dtype=np.int64)
     if max_len == 0 or R == 0:
         return out
+    if int(lengths.max()) > pool_size - 1:
+        raise ValueError("body length exceeds the atoms available (distinct, never the head)")
     todo = np.arange(R)
     while todo.size:
         draw = rng.integers(0, pool_size, size=(todo.size, max_len))
@@ -129,6 +131,8 @@ def definite_uniform(seed: int, n_atoms: int = 1000, n_rules: int = 2000,
     n_facts = int(round(fact_frac * n_rules))
     lengths = rng.integers(1, max_body + 1, size=n_rules)
     lengths[:n_facts] = 0
+    # a body has distinct atoms other than its head: at most n_atoms - 1 of them
+    np.minimum(lengths, max(n_atoms - 1, 0), out=lengths)
     bodies = _draw_bodies(rng, heads, lengths, max_body, n_atoms)
     return _assemble(n_atoms, heads, lengths, bodies,
                      dict(kind="definite_uniform", seed=seed, gen_version=GEN_VERSION))

@@ -1,0 +1,252 @@
+"""Python binding of the C-ABI declared in include/lp.h (argument marshalling only).
+
+Every step of the fixpoint runs in liblp.so's HIP kernels; this module only
+converts numpy arrays to pointers and status codes to exceptions. There is no
+CPU fallback: if liblp.so is missing, loading raises.
+
+Streams may be given as None (default stream), an integer hipStream_t handle,
+or any object with a ``cuda_stream`` attribute (a torch.cuda.Stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblp.so")
+
+LP_OK = 0
+LP_E_INVAL = -1
+LP_E_NOMEM = -2
+LP_E_DEVICE = -3
+LP_E_NEGATION = -4
+LP_E_TOO_MANY_GUESSES = -5
+LP_E_TRUNCATED = -6
+LP_E_INTERNAL = -7
+LP_E_HOST_ONLY = -8
+LP_MAX_NEG_ATOMS = 24
+
+LP_PRUNE_FACT_GUESSES = 1 << 0
+LP_BUILD_HOST_ONLY = 1 << 1
+
+LP_DRIVER_AUTO = 0
+LP_DRIVER_PLAIN = 1
+LP_DRIVER_BATCHED = 2
+LP_DRIVER_PERSISTENT = 3
+
+EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg_atoms",
+           "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_least_model_batch",
+           "lp_bench_step", "lp_set_allocator", "lp_last_error")
+
+
+class LPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lp error {code}: {msg}")
+        self.code = code
+
+
+class lp_info(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_rules", ctypes.c_int32),
+                ("n_std_atoms", ctypes.c_int32), ("n_rows", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("n_neg", ctypes.c_int32), ("n_pruned", ctypes.c_int32),
+                ("n_and_rows", ctypes.c_int32), ("n_or_rows", ctypes.c_int32),
+                ("n_fact_rows", ctypes.c_int32), ("n_empty_rows", ctypes.c_int32),
+                ("max_row_len", ctypes.c_int32), ("n_long_rows", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("sparsity", ctypes.c_double)]
+
+
+class lp_schedule(ctypes.Structure):
+    _fields_ = [("driver", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
+                ("long_row", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("skip_true_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblp.so (built by paper_2009_10247_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2009_10247_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "lp_build_matrix": [i32, i32, P, P, P, u32, P, ctypes.POINTER(P)],
+        "lp_free_matrix": [P],
+        "lp_matrix_info": [P, ctypes.POINTER(lp_info)],
+        "lp_matrix_neg_atoms": [P, P],
+        "lp_matrix_csr": [P, P, P, P, P],
+        "lp_least_model": [P, P, P, P, P],
+        "lp_stable_models": [P, P, P, P, i64, P, P, P],
+        "lp_least_model_batch": [P, i32, P, P, P, P],
+        "lp_bench_step": [P, i32, ctypes.POINTER(ctypes.c_float), P],
+        "lp_set_allocator": [P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    lib.lp_last_error.argtypes = []
+    lib.lp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if hasattr(s, "cuda_stream"):
+        return ctypes.c_void_p(int(s.cuda_stream))
+    return ctypes.c_void_p(int(s))
+
+
+def _check(rc: int, allow=()):
+    if rc != LP_OK and rc not in allow:
+        raise LPError(rc, load().lp_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, grid=0, skip_true_rows=0):
+    s = lp_schedule()
+    s.driver = driver
+    s.steps_per_sync = steps_per_sync
+    s.grid = grid
+    s.skip_true_rows = skip_true_rows
+    return s
+
+
+class Matrix:
+    """Program matrix built by lp_build_matrix from a program's three arrays."""
+
+    def __init__(self, prog, flags: int = 0, stream=None):
+        lib = load()
+        self._head = np.ascontiguousarray(prog.head, dtype=np.int32)
+        self._ptr = np.ascontiguousarray(prog.body_ptr, dtype=np.int64)
+        self._lit = np.ascontiguousarray(prog.body_lit, dtype=np.int32)
+        if self._ptr.shape[0] != self._head.shape[0] + 1:
+            raise ValueError("body_ptr must have n_rules + 1 entries")
+        self.n_atoms = int(prog.n_atoms)
+        self.flags = flags
+        h = ctypes.c_void_p()
+        _check(lib.lp_build_matrix(self.n_atoms, int(self._head.shape[0]), _ptr(self._head),
+                                   self._ptr.ctypes.data, _ptr(self._lit), flags, _stream(stream),
+                                   ctypes.byref(h)))
+        self._h = h
+        # inputs are copied by the library; drop our references
+        self._head = self._ptr = self._lit = None
+        self.info = self._info()
+
+    def _info(self) -> dict:
+        inf = lp_info()
+        _check(load().lp_matrix_info(self._h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in lp_info._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().lp_free_matrix(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def neg_atoms(self) -> np.ndarray:
+        out = np.zeros(max(self.info["n_neg"], 1), dtype=np.int32)
+        _check(load().lp_matrix_neg_atoms(self._h, out.ctypes.data))
+        return out[: self.info["n_neg"]]
+
+    def csr(self):
+        """Host copy: (row_ptr int32[n+1], col int32[nnz], kind uint8[n], fact uint8[n])."""
+        n, nnz = self.info["n_rows"], self.info["nnz"]
+        rp = np.zeros(n + 1, dtype=np.int32)
+        col = np.zeros(max(nnz, 1), dtype=np.int32)
+        kind = np.zeros(max(n, 1), dtype=np.uint8)
+        fact = np.zeros(max(n, 1), dtype=np.uint8)
+        _check(load().lp_matrix_csr(self._h, rp.ctypes.data, col.ctypes.data, kind.ctypes.data,
+                                    fact.ctypes.data))
+        return rp, col[:nnz], kind[:n], fact[:n]
+
+    def least_model(self, sched=None, stream=None):
+        """(model uint8[n_atoms], products)."""
+        model = np.zeros(max(self.n_atoms, 1), dtype=np.uint8)
+        prods = ctypes.c_int32(0)
+        _check(load().lp_least_model(self._h, model.ctypes.data, ctypes.addressof(prods),
+                                     ctypes.byref(sched) if sched is not None else None,
+                                     _stream(stream)))
+        return model[: self.n_atoms], prods.value
+
+    def stable_models(self, max_models: int = 1024, want_models: bool = True,
+                      want_interp: bool = False, stream=None) -> dict:
+        """dict(accepted=uint64[W], n_models, models=uint8[m][n_atoms], interp, products, truncated)."""
+        K = self.info["n_neg"]
+        Wf = max(((1 << K) + 63) // 64, 1)
+        acc = np.zeros(Wf, dtype=np.uint64)
+        n_models = ctypes.c_int64(0)
+        prods = ctypes.c_int32(0)
+        models = np.zeros((max(max_models, 1), max(self.n_atoms, 1)), dtype=np.uint8) if want_models else None
+        interp = np.zeros((max(self.n_atoms, 1), Wf), dtype=np.uint64) if want_interp else None
+        rc = _check(load().lp_stable_models(self._h, acc.ctypes.data, ctypes.addressof(n_models),
+                                            models.ctypes.data if models is not None else None,
+                                            int(max_models),
+                                            interp.ctypes.data if interp is not None else None,
+                                            ctypes.addressof(prods), _stream(stream)),
+                    allow=(LP_E_TRUNCATED,))
+        nm = n_models.value
+        out = dict(accepted=acc, n_models=nm, products=prods.value, truncated=rc == LP_E_TRUNCATED)
+        if models is not None:
+            out["models"] = models[: min(nm, max_models), : self.n_atoms]
+        if interp is not None:
+            out["interp"] = interp[: self.n_atoms]
+        return out
+
+    def bench_step(self, reps: int = 100, stream=None) -> float:
+        """Average milliseconds of one full-sweep T_P step (HIP events)."""
+        ms = ctypes.c_float(0)
+        _check(load().lp_bench_step(self._h, int(reps), ctypes.byref(ms), _stream(stream)))
+        return ms.value
+
+
+def least_model_batch(mats, sched=None, stream=None):
+    """[(model, products)] for a list of Matrix, solved by lp_least_model_batch."""
+    n = len(mats)
+    outs = [np.zeros(max(m.n_atoms, 1), dtype=np.uint8) for m in mats]
+    hs = (ctypes.c_void_p * n)(*[m.handle.value for m in mats])
+    ptrs = (ctypes.c_void_p * n)(*[o.ctypes.data for o in outs])
+    prods = np.zeros(max(n, 1), dtype=np.int32)
+    _check(load().lp_least_model_batch(hs, n, ptrs, prods.ctypes.data,
+                                       ctypes.byref(sched) if sched is not None else None,
+                                       _stream(stream)))
+    return [(outs[i][: mats[i].n_atoms], int(prods[i])) for i in range(n)]
+
+
+def unpack_column(interp: np.ndarray, j: int) -> np.ndarray:
+    """Column j (one guess) of an interpretation matrix as uint8 per atom."""
+    w, b = divmod(int(j), 64)
+    return ((interp[:, w] >> np.uint64(b)) & np.uint64(1)).astype(np.uint8)
+
+
+def accepted_indices(accepted: np.ndarray) -> np.ndarray:
+    bits = np.unpackbits(accepted.view(np.uint8), bitorder="little")
+    return np.nonzero(bits)[0]

@@ -1,0 +1,254 @@
+"""Parity of the HIP engine (through the C-ABI) with the CPU oracle.
+
+Every comparison is exact: models, product counts, accepted-guess masks and
+per-guess fixpoints are integers and bit sets."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2009_10247_amd import gen, lp
+from tests import _golden
+
+pytestmark = pytest.mark.gpu
+
+
+def _least(prog, **kw):
+    with lp.Matrix(prog) as m:
+        return m.least_model(**kw)
+
+
+def _check_least(prog, sched=None):
+    want, want_prods, n_std, _ = oracle.sd_fixpoint(prog)
+    got, prods = _least(prog, sched=sched)
+    assert np.array_equal(got, want)
+    assert prods == want_prods
+    assert np.array_equal(want, oracle.least_model(prog))
+    return prods
+
+
+# ---------------------------------------------------------------- least models
+
+def test_example1_on_gpu():
+    d = _golden.load("example1.txt")
+    got, prods = _least(_golden.program(d))
+    assert [a for a, x in zip(d["atoms"], got) if x] == d["least_model"]
+    assert prods == d["products"][0]
+
+
+@pytest.mark.parametrize("driver", [lp.LP_DRIVER_PLAIN, lp.LP_DRIVER_BATCHED, lp.LP_DRIVER_AUTO])
+def test_tiny_programs_match_oracle(driver):
+    sched = lp.make_schedule(driver=driver, steps_per_sync=3)
+    for seed in range(150):
+        p = gen.tiny_random(seed, max_atoms=16, max_rules=40, max_body=4)
+        got, prods = _least(p, sched=sched)
+        assert brute.from_vector(got) == brute.least_model(p), seed
+        assert prods == oracle.sd_fixpoint(p)[1], seed
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_definite_1k_atoms_2k_rules(seed):
+    _check_least(gen.definite_uniform(seed, 1000, 2000, 0.05, 4))
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 255, 257, 4097])
+def test_ragged_sizes(n):
+    _check_least(gen.definite_uniform(n, n, 3 * n, 0.05, 4))
+
+
+def test_empty_and_factless_programs():
+    empty = gen.Program(0, np.zeros(0, np.int32), np.zeros(1, np.int64), np.zeros(0, np.int32))
+    got, prods = _least(empty)
+    assert got.shape == (0,) and prods == 1
+    p = gen.definite_uniform(4, 500, 1000, 0.0, 4)
+    got, prods = _least(p)
+    assert got.sum() == 0 and prods == 1
+    rule_free = gen.Program(7, np.zeros(0, np.int32), np.zeros(1, np.int64), np.zeros(0, np.int32))
+    got, prods = _least(rule_free)
+    assert got.sum() == 0 and prods == 1
+
+
+def test_long_or_and_rows_split_in_segments():
+    # one head with 10,000 rules: an OR row of 10,000 entries (3 segments);
+    # one rule with a 9,000-atom body: a split AND row (3 segments) that fires;
+    # a second split AND row that must not fire (one body atom never true).
+    rng = np.random.default_rng(7)
+    n = 20_000
+    rules = [(a, []) for a in range(0, 12_000)]
+    rules += [(19_000, [int(x)]) for x in rng.integers(12_000, 18_000, size=10_000)]
+    rules += [(19_001, list(range(0, 9_000)))]
+    rules += [(19_002, list(range(1, 9_000)) + [19_500])]
+    rules += [(int(h), [int(b)]) for h, b in zip(rng.integers(12_000, 18_000, 3000), rng.integers(0, 12_000, 3000))]
+    rules += [(19_003, [19_001, 19_000])]
+    p = gen.from_rules(n, rules)
+    with lp.Matrix(p) as m:
+        assert m.info["n_long_rows"] >= 3
+    _check_least(p)
+
+
+@pytest.mark.parametrize("L", [1, 2, 100, 1000])
+def test_chain_products(L):
+    p = gen.from_rules(L, [(0, [])] + [(i, [i - 1]) for i in range(1, L)])
+    assert _check_least(p) == L
+
+
+def test_chain_zipf_scaled():
+    p = gen.chain_zipf(1, n_atoms=100_000, n_rules=500_000, chain_len=300)
+    assert _check_least(p) == 300
+
+
+@pytest.mark.slow
+def test_chain_zipf_full_size():
+    # 1,000,000 atoms, 5,000,000 rules, 2,000-long chain: the benchmarked workload
+    p = gen.chain_zipf(0)
+    prods = _check_least(p, sched=lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=64))
+    assert prods == 2000
+
+
+def test_bench_step_runs():
+    p = gen.chain_zipf(2, n_atoms=50_000, n_rules=250_000, chain_len=50)
+    with lp.Matrix(p) as m:
+        ms = m.bench_step(reps=20)
+        assert ms > 0
+        # the step leaves the matrix usable and the answer unchanged
+        got, prods = m.least_model()
+    assert np.array_equal(got, oracle.least_model(p)) and prods == 50
+
+
+def test_concurrent_matrices_do_not_interfere():
+    progs = [gen.definite_uniform(s, 2000, 5000, 0.03, 4) for s in range(6)]
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        res = [m.least_model() for m in mats]
+        res_again = [m.least_model() for m in reversed(mats)][::-1]
+        for p, (g, pr), (g2, pr2) in zip(progs, res, res_again):
+            want, wp, _, _ = oracle.sd_fixpoint(p)
+            assert np.array_equal(g, want) and pr == wp
+            assert np.array_equal(g2, want) and pr2 == wp
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_batch_entry_point_equals_single_solves():
+    progs = gen.batch_programs(11, count=24, lo=100, hi=5000)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        out = lp.least_model_batch(mats)
+        for p, (g, pr) in zip(progs, out):
+            want, wp, _, _ = oracle.sd_fixpoint(p)
+            assert np.array_equal(g, want) and pr == wp
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_negation_rejected_by_least_model():
+    p = gen.from_rules(2, [(0, [gen.neg(1)])])
+    with lp.Matrix(p) as m:
+        with pytest.raises(lp.LPError) as e:
+            m.least_model()
+        assert e.value.code == lp.LP_E_NEGATION
+
+
+# ---------------------------------------------------------------- stable models
+
+def _check_stable(prog, flags=0, want_interp=True, threads=0):
+    res_o = oracle.stable(prog, threads=threads, want_interp=want_interp and flags == 0)
+    with lp.Matrix(prog, flags=flags) as m:
+        res = m.stable_models(max_models=4096, want_interp=want_interp and flags == 0)
+    K = res_o["neg_atoms"].shape[0]
+    acc_o = np.nonzero(res_o["accept"])[0]
+    assert np.array_equal(lp.accepted_indices(res["accepted"]), acc_o)
+    assert res["n_models"] == acc_o.shape[0]
+    if want_interp and flags == 0:
+        assert np.array_equal(res["interp"], res_o["interp"])
+        assert res["products"] == res_o["products"]
+    for i, j in enumerate(acc_o[: res["models"].shape[0]]):
+        w, b = divmod(int(j), 64)
+        col = ((res_o["interp"][:, w] >> np.uint64(b)) & np.uint64(1)).astype(np.uint8) \
+            if res_o["interp"] is not None else None
+        if col is not None:
+            assert np.array_equal(res["models"][i], col)
+        assert oracle.gl_check(prog, res["models"][i])
+    return res
+
+
+def test_example2_on_gpu():
+    d = _golden.load("example2.txt")
+    p = _golden.program(d)
+    res = _check_stable(p)
+    assert [[a for a, x in zip(d["atoms"], mdl) if x] for mdl in res["models"]] == [["t"]]
+    for flags in (0, lp.LP_PRUNE_FACT_GUESSES):
+        with lp.Matrix(p, flags=flags) as m:
+            r = m.stable_models()
+            assert list(lp.accepted_indices(r["accepted"])) == d["accepted_guesses"]
+
+
+def test_tiny_normal_programs_match_brute_force():
+    for seed in range(120):
+        p = gen.tiny_random(40_000 + seed, max_atoms=9, max_rules=16, max_body=3, p_neg=0.35)
+        res = _check_stable(p)
+        got = sorted(brute.from_vector(m) for m in res["models"])
+        assert got == brute.stable_models(p), seed
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 6, 7, 9, 12])
+def test_normal_programs_each_guess_width(k):
+    _check_stable(gen.normal_uniform(k, 600, 1200, 5, k_neg=k, p_neg=0.2))
+
+
+@pytest.mark.parametrize("n", [1, 4, 8])
+def test_even_loops(n):
+    res = _check_stable(gen.even_loops(n))
+    assert res["n_models"] == 2 ** n
+
+
+def test_even_loops_16_atoms_negated_without_oracle():
+    # 8 even loops: K = 16, 65,536 guesses, exactly 256 models, each picking
+    # exactly one atom per loop
+    p = gen.even_loops(8)
+    with lp.Matrix(p) as m:
+        res = m.stable_models(max_models=1000)
+    assert res["n_models"] == 256
+    mods = res["models"]
+    assert mods.shape == (256, 16)
+    assert np.all(mods[:, 0::2] + mods[:, 1::2] == 1)
+    assert len({bytes(r) for r in mods}) == 256
+
+
+def test_odd_loop_and_definite():
+    with lp.Matrix(gen.odd_loop()) as m:
+        assert m.stable_models()["n_models"] == 0
+    p = gen.definite_uniform(3, 400, 800)
+    with lp.Matrix(p) as m:
+        res = m.stable_models(want_interp=True)
+    assert res["n_models"] == 1 and np.array_equal(res["models"][0], oracle.least_model(p))
+
+
+def test_pruning_keeps_the_stable_models():
+    for seed in range(30):
+        base = gen.normal_uniform(seed, 200, 400, 4, k_neg=6, p_neg=0.3)
+        rng = np.random.default_rng(seed)
+        negs = oracle.negated_atoms(base)
+        facts = [(int(q), []) for q in rng.choice(negs, size=2, replace=False)]
+        p = gen.from_rules(base.n_atoms, list(base.rules()) + facts)
+        _check_stable(p, flags=lp.LP_PRUNE_FACT_GUESSES, want_interp=False)
+        with lp.Matrix(p, flags=lp.LP_PRUNE_FACT_GUESSES) as m:
+            assert m.info["n_pruned"] == 2
+            with pytest.raises(lp.LPError) as e:
+                m.stable_models(want_interp=True)
+            assert e.value.code == lp.LP_E_INVAL
+
+
+def test_truncation_reports_all_models():
+    with lp.Matrix(gen.even_loops(5)) as m:
+        res = m.stable_models(max_models=7)
+    assert res["truncated"] and res["n_models"] == 32 and res["models"].shape[0] == 7
+
+
+def test_normal_10k_atoms_16_negated_full_width():
+    # 10,000 atoms, 20,000 rules, 16 negated atoms: all 65,536 guesses, every
+    # per-guess fixpoint compared with the oracle
+    p = gen.normal_uniform(0)
+    _check_stable(p, threads=16)

@@ -78,7 +78,7 @@ def main() -> int:
     info = m.info
     log(f"[bench] matrix: N'={info['n_rows']} nnz={info['nnz']} long rows={info['n_long_rows']} "
         f"build {build_s:.2f}s")
-    sched = lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=64)
+    sched = lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT)
 
     for i in range(args.warmup):
         model, products = m.least_model(sched=sched, stream=stream)
@@ -104,14 +104,34 @@ def main() -> int:
     log(f"[bench] {args.steps} solves: {ms_per_step:.3f} ms/solve (events), wall {wall * 1e3 / args.steps:.3f} ms, "
         f"products={products}, {ms_per_step * 1e3 / products:.2f} us/product")
 
-    # dominant kernel: one full-sweep step, HIP events inside the library
-    step_ms = m.bench_step(reps=args.step_reps, stream=stream)
+    # other drivers and step kernels, for comparison
     B = step_bytes(info)
-    achieved = B / (step_ms / 1e3) / 1e9
-    log(f"[bench] tp_step_kernel: {step_ms * 1e3:.2f} us/launch, {B / 1e6:.1f} MB -> {achieved:.0f} GB/s")
+    variants = {}
+    for name, sc in (("batched_lds", lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=64,
+                                                       variant=lp.LP_STEP_LDS)),
+                     ("batched_global", lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=64,
+                                                          variant=lp.LP_STEP_GLOBAL))):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mv, pv = m.least_model(sched=sc, stream=stream)
+        torch.cuda.synchronize()
+        assert pv == products and np.array_equal(mv, model)
+        variants[name] = {"ms_per_solve": round((time.perf_counter() - t) * 1e3, 3)}
+    for name, v in (("step_lds", lp.LP_STEP_LDS), ("step_global", lp.LP_STEP_GLOBAL)):
+        ms = m.bench_step(reps=args.step_reps, sched=lp.make_schedule(variant=v), stream=stream)
+        variants[name] = {"us_per_launch": round(ms * 1e3, 3), "GB/s": round(B / (ms / 1e3) / 1e9, 1)}
+    log(f"[bench] variants: {variants}")
+
+    # dominant kernel: the persistent fixpoint kernel, one launch per solve,
+    # timed with HIP events around each launch inside the library
+    kern_ms = m.bench_step(reps=max(3, args.steps), sched=sched, stream=stream)
+    Bl = B * products
+    achieved = Bl / (kern_ms / 1e3) / 1e9
+    log(f"[bench] tp_fixpoint_persistent_kernel: {kern_ms:.3f} ms/launch, {Bl / 1e9:.2f} GB -> {achieved:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "tp_step_kernel", "bytes_per_launch": B, "us_per_launch": round(step_ms * 1e3, 3)}
+                "kernel": "tp_fixpoint_persistent_kernel", "bytes_per_launch": Bl,
+                "ms_per_launch": round(kern_ms, 4), "bytes_per_product": B}
 
     stable = None
     if not args.no_stable:
@@ -173,6 +193,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stable_models": stable,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
     m.close()

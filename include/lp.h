@@ -102,13 +102,18 @@ enum {
     LP_DRIVER_PERSISTENT = 3  /* one launch; the loop runs on the device with a grid barrier */
 };
 
+enum {
+    LP_STEP_AUTO = 0,
+    LP_STEP_GLOBAL = 1,  /* 256-thread workgroups, gathers of v from global memory */
+    LP_STEP_LDS = 2      /* one 1024-thread workgroup per CU, v staged in LDS for the gathers */
+};
+
 typedef struct lp_schedule {
     int32_t driver;          /* LP_DRIVER_* */
-    int32_t steps_per_sync;  /* products issued between host checks (BATCHED) */
-    int32_t long_row;        /* reserved: the long-row threshold is fixed at build time */
-    int32_t grid;            /* workgroups of a persistent launch (0: all that fit) */
-    int32_t skip_true_rows;  /* 1: rows already true are not re-read (same result, fewer bytes) */
-    int32_t reserved[3];
+    int32_t steps_per_sync;  /* products issued between host checks (BATCHED, AUTO) */
+    int32_t variant;         /* LP_STEP_* kernel of the least-model step */
+    int32_t grid;            /* workgroups of the LDS-staged step (0: one per CU) */
+    int32_t reserved[4];
 } lp_schedule;
 
 /*
@@ -207,11 +212,15 @@ lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_
 /*
  * Average duration in milliseconds of one full-sweep T_P step (theta(M v) on
  * the whole matrix, the change count included) over reps back-to-back
- * launches on hip_stream, timed with HIP events. The step reads the fixpoint
+ * launches on hip_stream, timed with HIP events. sched (nullable) selects the
+ * step kernel as for lp_least_model. With sched->driver == LP_DRIVER_PERSISTENT
+ * every launch instead runs the whole fixpoint (one persistent kernel from
+ * the initial vector) and the average is per launch, i.e. per fixpoint. The step reads the fixpoint
  * of m (computed first) and writes a scratch buffer, so every launch moves the
  * same bytes. Used to measure achieved bandwidth.
  */
-lp_status lp_bench_step(const lp_matrix *m, int32_t reps, float *avg_ms, void *hip_stream);
+lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t reps, float *avg_ms,
+                        void *hip_stream);
 
 /*
  * Route the library's device allocations through caller-supplied functions

@@ -125,6 +125,8 @@ struct StepParams {
     int32_t n_long_and;
     int32_t step;               // 1-based product index
     int32_t early_exit;         // 1: return at once if the previous product changed nothing
+    int32_t n_segs;             // long-row segments
+    int32_t lds_words;          // words of v staged in LDS (LDS-staged kernel)
 };
 
 __device__ inline uint64_t range_mask(int s, int t) {  // bits [s, t), 0 <= s < t <= 64
@@ -221,6 +223,195 @@ __global__ __launch_bounds__(kBlock) void tp_step_kernel(StepParams p) {
     if ((tid & 63) == 0 && my_new) atomicAdd(&s_new, my_new);
     __syncthreads();
     if (tid == 0 && s_new) atomicAdd(&p.counters[p.step & (kRing - 1)], (unsigned long long)s_new);
+}
+
+constexpr int kLdsBlock = 1024;            // 16 waves: one workgroup per CU
+constexpr int kLdsWaves = kLdsBlock / 64;
+constexpr int kUnroll = 8;                  // column chunks in flight per wave
+
+// Same step as tp_step_kernel, for a grid of one workgroup per CU. Each
+// workgroup first copies the leading lds_words words of v (the original
+// atoms, which are the only atoms rule bodies name) into LDS, so the random
+// one-bit gathers of AND rows hit LDS instead of pulling a cache line from L2
+// per entry. Waves then take 64-row blocks in a grid-stride loop, issuing
+// kUnroll coalesced column-chunk loads before consuming any of them. Long-row
+// segments follow, one wave per segment.
+// Blocks and long-row segments of one step, with the leading lds_words words
+// of v already in s_v. Returns this thread's count of new bits (nonzero only
+// on lane 0 of a wave).
+__device__ __forceinline__ uint32_t lds_step_body(const StepParams &p, const uint64_t *s_v) {
+    const int tid = threadIdx.x;
+    const int32_t lw = p.lds_words;
+    const int32_t lds_bits = lw * 64;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t n_words = ((int64_t)p.n_rows + 63) >> 6;
+    const int64_t wstride = (int64_t)gridDim.x * kLdsWaves;
+    uint32_t my_new = 0;
+    for (int64_t word = (int64_t)blockIdx.x * kLdsWaves + wave; word < n_words; word += wstride) {
+        const int64_t r0 = word * 64;
+        const int64_t r = r0 + lane;
+        const bool valid = r < p.n_rows;
+        const int64_t rlast = r0 + 64 < p.n_rows ? r0 + 64 : p.n_rows;
+        const int32_t e1 = p.row_ptr[rlast];
+        const int32_t start = valid ? p.row_ptr[r] : e1;
+        const int32_t end = valid ? p.row_ptr[r + 1] : e1;
+        const int32_t e0 = __builtin_amdgcn_readfirstlane(start);
+        const uint64_t vw = word < lw ? s_v[word] : p.v[word];
+        const bool is_and = (p.and_bits[word] >> lane) & 1ull;
+        bool acc = is_and;
+        for (int32_t base = e0 & ~63; base < e1; base += 64 * kUnroll) {
+            int32_t c[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int32_t e = base + 64 * u + lane;
+                c[u] = (e >= e0 && e < e1) ? p.col[e] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                bool b = false;
+                if (c[u] >= 0) {
+                    const uint64_t w = c[u] < lds_bits ? s_v[c[u] >> 6] : p.v[c[u] >> 6];
+                    b = (w >> (c[u] & 63)) & 1ull;
+                }
+                const uint64_t B = __ballot(b);
+                const int32_t cb = base + 64 * u;
+                const int s = start - cb > 0 ? start - cb : 0;
+                const int t = end - cb < 64 ? end - cb : 64;
+                if (s < t) {
+                    const uint64_t m = range_mask(s, t);
+                    acc = is_and ? (acc && ((B & m) == m)) : (acc || ((B & m) != 0));
+                }
+            }
+        }
+        const uint64_t res = __ballot(acc && valid);
+        if (lane == 0) {
+            if (res) atomicOr((unsigned long long *)&p.u[word], (unsigned long long)res);
+            my_new += (uint32_t)__popcll(res & ~vw);
+        }
+    }
+    for (int64_t si = (int64_t)blockIdx.x * kLdsWaves + wave; si < p.n_segs; si += wstride) {
+        const LongSeg sg = p.segs[si];
+        bool any = false, all = true;
+        for (int32_t i0 = 0; i0 < sg.len; i0 += 64 * kUnroll) {
+            int32_t c[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int32_t i = i0 + 64 * u + lane;
+                c[u] = i < sg.len ? p.long_col[sg.begin + i] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (c[u] >= 0) {
+                    const uint64_t w = c[u] < lds_bits ? s_v[c[u] >> 6] : p.v[c[u] >> 6];
+                    const bool b = (w >> (c[u] & 63)) & 1ull;
+                    any |= b;
+                    all &= b;
+                }
+            }
+        }
+        any = __ballot(any) != 0;
+        all = __ballot(!all) == 0;
+        if (lane == 0) {
+            bool fire;
+            if (!sg.is_and) {
+                fire = any;
+            } else if (sg.nseg == 1) {
+                fire = all;
+            } else {
+                uint32_t *cnt = p.and_cnt + (size_t)(p.step & 1) * p.n_long_and + sg.and_slot;
+                fire = all && atomicAdd(cnt, 1u) == (uint32_t)(sg.nseg - 1);
+                if (sg.seg == 0) p.and_cnt[(size_t)((p.step + 1) & 1) * p.n_long_and + sg.and_slot] = 0;
+            }
+            if (fire) {
+                const uint64_t bit = 1ull << (sg.row & 63);
+                const uint64_t old = atomicOr((unsigned long long *)&p.u[sg.row >> 6], (unsigned long long)bit);
+                if (!(old & bit) && !(p.v[sg.row >> 6] & bit)) my_new += 1;
+            }
+        }
+    }
+    return my_new;
+}
+
+// Adds this workgroup's count of new bits to the product's counter.
+__device__ __forceinline__ void add_new_bits(uint32_t my_new, uint32_t *s_new, unsigned long long *slot) {
+    my_new = wave_sum(my_new);
+    if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(s_new, my_new);
+    __syncthreads();
+    if (threadIdx.x == 0 && *s_new) atomicAdd(slot, (unsigned long long)*s_new);
+}
+
+__global__ __launch_bounds__(kLdsBlock) void tp_step_lds_kernel(StepParams p) {
+    extern __shared__ uint64_t s_v[];
+    __shared__ uint32_t s_new;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
+    if (p.early_exit && p.step >= 2 && p.counters[(p.step - 1) & (kRing - 1)] == 0) return;
+    if (tid == 0) s_new = 0;
+    for (int32_t i = tid; i < p.lds_words; i += kLdsBlock) s_v[i] = p.v[i];
+    __syncthreads();
+    const uint32_t my_new = lds_step_body(p, s_v);
+    add_new_bits(my_new, &s_new, &p.counters[p.step & (kRing - 1)]);
+}
+
+struct PersistParams {
+    StepParams p;
+    uint64_t *buf0;
+    uint64_t *buf1;
+    unsigned int *bar;   // [0] arrivals, [1] generation
+    int32_t max_steps;
+    int32_t *result;     // products, or -1 if max_steps was reached
+};
+
+// Grid-wide barrier for a cooperative launch (every workgroup resident).
+// Release before arriving, acquire after leaving: the next product reads the
+// buffer other XCDs just wrote.
+__device__ __forceinline__ void grid_barrier(unsigned int *bar, unsigned int n_groups) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == n_groups - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+                __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// The whole Algorithm 1 loop in one launch. Each product: stage v in LDS,
+// evaluate every row, add the new-bit count, grid barrier, read the count.
+// Every workgroup reads the same count after the barrier, so all leave the
+// loop on the same product; max_steps (n_rows + 1 bounds a monotone
+// iteration) guarantees the loop ends.
+__global__ __launch_bounds__(kLdsBlock) void tp_fixpoint_persistent_kernel(PersistParams q) {
+    extern __shared__ uint64_t s_v[];
+    __shared__ uint32_t s_new;
+    StepParams p = q.p;
+    const int tid = threadIdx.x;
+    for (int32_t step = 1;; ++step) {
+        p.step = step;
+        p.v = (step & 1) ? q.buf0 : q.buf1;
+        p.u = (step & 1) ? q.buf1 : q.buf0;
+        unsigned long long *slot = &p.counters[step & (kRing - 1)];
+        if (blockIdx.x == 0 && tid == 0) p.counters[(step + 1) & (kRing - 1)] = 0;
+        if (tid == 0) s_new = 0;
+        for (int32_t i = tid; i < p.lds_words; i += kLdsBlock) s_v[i] = p.v[i];
+        __syncthreads();
+        const uint32_t my_new = lds_step_body(p, s_v);
+        add_new_bits(my_new, &s_new, slot);
+        grid_barrier(q.bar, gridDim.x);
+        const unsigned long long changed = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (changed == 0 || step >= q.max_steps) {
+            if (blockIdx.x == 0 && tid == 0) *q.result = changed == 0 ? step : -1;
+            return;
+        }
+    }
 }
 
 struct SpmmParams {
@@ -440,6 +631,78 @@ struct DeviceGuard {
     }
 };
 
+struct DevProps {
+    int n_cu = 0;
+    int max_lds = 0;
+};
+
+static lp_status dev_props(int dev, DevProps *out) {
+    static std::mutex mu;
+    static DevProps cache[64];
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev < 0 || dev >= 64) {
+        set_error("device id out of range");
+        return LP_E_DEVICE;
+    }
+    if (cache[dev].n_cu == 0) {
+        DevProps d;
+        LP_HIP(hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        LP_HIP(hipDeviceGetAttribute(&d.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const int dyn = d.max_lds - 256;
+        if (dyn > 0) {
+            (void)hipFuncSetAttribute((const void *)tp_step_lds_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+            (void)hipFuncSetAttribute((const void *)tp_fixpoint_persistent_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        }
+        (void)hipGetLastError();
+        cache[dev] = d;
+    }
+    *out = cache[dev];
+    return LP_OK;
+}
+
+// Launch configuration of one T_P step, fixed for a whole solve.
+struct StepLaunch {
+    int variant = LP_STEP_LDS;
+    int grid = 0;
+    size_t lds_bytes = 0;
+};
+
+static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepLaunch *L) {
+    int variant = sched ? sched->variant : LP_STEP_AUTO;
+    if (variant == LP_STEP_AUTO) variant = LP_STEP_LDS;
+    L->variant = variant;
+    const int64_t n_words = n_words_of(m.n_rows);
+    if (variant == LP_STEP_GLOBAL) {
+        L->grid = p.n_blocks + p.n_segs;
+        L->lds_bytes = 0;
+        p.lds_words = 0;
+        return LP_OK;
+    }
+    if (variant != LP_STEP_LDS) {
+        set_error("unknown step variant");
+        return LP_E_INVAL;
+    }
+    DevProps d;
+    lp_status rc = dev_props(m.dev.device, &d);
+    if (rc) return rc;
+    const int64_t cap = std::max<int64_t>(0, (d.max_lds - 256) / 8);
+    p.lds_words = (int32_t)std::min<int64_t>({cap, n_words_of(m.n_atoms), n_words});
+    L->lds_bytes = (size_t)p.lds_words * 8;
+    const int64_t want = (n_words + p.n_segs + kLdsWaves - 1) / kLdsWaves;
+    int grid = sched && sched->grid > 0 ? sched->grid : d.n_cu;
+    L->grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, want));
+    return LP_OK;
+}
+
+static void launch_step(const StepLaunch &L, const StepParams &p, hipStream_t st) {
+    if (L.variant == LP_STEP_GLOBAL)
+        tp_step_kernel<<<L.grid, kBlock, 0, st>>>(p);
+    else
+        tp_step_lds_kernel<<<L.grid, kLdsBlock, L.lds_bytes, st>>>(p);
+}
+
 static StepParams step_params(const Matrix &m) {
     const DeviceMatrix &d = m.dev;
     StepParams p{};
@@ -451,8 +714,43 @@ static StepParams step_params(const Matrix &m) {
     p.n_rows = m.n_rows;
     p.n_blocks = (int32_t)((n_words_of(m.n_rows) + kWavesPerBlock - 1) / kWavesPerBlock);
     p.n_long_and = d.n_long_and;
+    p.n_segs = d.n_segs;
     p.early_exit = 1;
     return p;
+}
+
+// Launch plan of the persistent fixpoint: the LDS-staged step, at most as
+// many workgroups as can be resident at once (the grid barrier needs all of
+// them running). *grid = 0 if not even one fits.
+static lp_status plan_persistent(const Matrix &m, const lp_schedule *sched, StepParams &p, StepLaunch *L,
+                                 int *grid) {
+    lp_schedule s2 = sched ? *sched : lp_schedule{};
+    s2.variant = LP_STEP_LDS;
+    lp_status rc = plan_step(m, &s2, p, L);
+    if (rc) return rc;
+    int per_cu = 0;
+    LP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tp_fixpoint_persistent_kernel, kLdsBlock,
+                                                        L->lds_bytes));
+    DevProps d;
+    if ((rc = dev_props(m.dev.device, &d))) return rc;
+    const int64_t resident = (int64_t)per_cu * d.n_cu;
+    *grid = (int)std::min<int64_t>(L->grid, resident);
+    return LP_OK;
+}
+
+static lp_status launch_persistent(const Matrix &m, const StepParams &p, const StepLaunch &L, int grid,
+                                   uint64_t *const buf[2], unsigned int *bar, int32_t *res, hipStream_t st) {
+    PersistParams q{};
+    q.p = p;
+    q.buf0 = buf[0];
+    q.buf1 = buf[1];
+    q.bar = bar;
+    q.max_steps = (int32_t)std::min<int64_t>((int64_t)m.n_rows + 1, INT32_MAX - 1);
+    q.result = res;
+    void *args[] = {&q};
+    LP_HIP(hipLaunchCooperativeKernel((const void *)tp_fixpoint_persistent_kernel, dim3(grid), dim3(kLdsBlock),
+                                      args, (unsigned int)L.lds_bytes, st));
+    return LP_OK;
 }
 
 // Least-model fixpoint. On success *out points at the device buffer holding
@@ -477,15 +775,41 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
         return LP_OK;
     }
     int driver = sched ? sched->driver : LP_DRIVER_AUTO;
-    int batch = 1;
-    if (driver == LP_DRIVER_BATCHED || driver == LP_DRIVER_AUTO || driver == LP_DRIVER_PERSISTENT) {
-        batch = (sched && sched->steps_per_sync > 0) ? sched->steps_per_sync : 32;
-    }
-    batch = std::max(1, std::min(batch, kRing / 2 - 1));
     StepParams p = step_params(m);
     p.counters = counters;
     p.and_cnt = and_cnt;
-    const int grid = p.n_blocks + m.dev.n_segs;
+    StepLaunch L;
+    if (driver == LP_DRIVER_PERSISTENT || driver == LP_DRIVER_AUTO) {
+        int grid = 0;
+        if ((rc = plan_persistent(m, sched, p, &L, &grid))) return rc;
+        if (grid >= 1) {
+            unsigned int *bar;
+            int32_t *res;
+            if ((rc = S.get(&bar, 2)) || (rc = S.get(&res, 1))) return rc;
+            LP_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned int) * 2, st));
+            if ((rc = launch_persistent(m, p, L, grid, buf, bar, res, st))) return rc;
+            int32_t prods = 0;
+            LP_HIP(hipMemcpyAsync(&prods, res, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            LP_HIP(hipStreamSynchronize(st));
+            if (prods < 1) {
+                set_error("fixpoint not reached within n_rows+1 products");
+                return LP_E_INTERNAL;
+            }
+            *products = prods;
+            *out = buf[prods & 1];
+            return LP_OK;
+        }
+        if (driver == LP_DRIVER_PERSISTENT) {
+            set_error("the persistent step does not fit on this device");
+            return LP_E_DEVICE;
+        }
+    }
+    int batch = 1;
+    if (driver == LP_DRIVER_BATCHED || driver == LP_DRIVER_AUTO) {
+        batch = (sched && sched->steps_per_sync > 0) ? sched->steps_per_sync : 32;
+    }
+    batch = std::max(1, std::min(batch, kRing / 2 - 1));
+    if ((rc = plan_step(m, sched, p, &L))) return rc;
     unsigned long long *h = pinned_ring();
     if (!h) {
         set_error("pinned host allocation failed");
@@ -497,7 +821,7 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
             p.step = (int32_t)(t + i);
             p.v = buf[(p.step - 1) & 1];
             p.u = buf[p.step & 1];
-            tp_step_kernel<<<grid, kBlock, 0, st>>>(p);
+            launch_step(L, p, st);
         }
         LP_HIP(hipGetLastError());
         LP_HIP(hipMemcpyAsync(h, counters, sizeof(unsigned long long) * kRing, hipMemcpyDeviceToHost, st));
@@ -682,11 +1006,12 @@ static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_mod
     return LP_OK;
 }
 
-static lp_status bench_step_impl(const Matrix &m, int32_t reps, float *avg_ms, hipStream_t st) {
+static lp_status bench_step_impl(const Matrix &m, const lp_schedule *sched, int32_t reps, float *avg_ms,
+                               hipStream_t st) {
     Scratch S(st);
     uint64_t *fix = nullptr;
     int32_t prods = 0;
-    lp_status rc = least_fixpoint(m, nullptr, st, S, &fix, &prods);
+    lp_status rc = least_fixpoint(m, sched, st, S, &fix, &prods);
     if (rc) return rc;
     const int64_t W = n_words_of(m.n_rows);
     uint64_t *dst;
@@ -695,31 +1020,62 @@ static lp_status bench_step_impl(const Matrix &m, int32_t reps, float *avg_ms, h
     if ((rc = S.get(&dst, W)) || (rc = S.get(&counters, kRing)) ||
         (rc = S.get(&and_cnt, 2 * (size_t)m.dev.n_long_and)))
         return rc;
-    LP_HIP(hipMemcpyAsync(dst, fix, W * 8, hipMemcpyDeviceToDevice, st));
-    LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
-    if (m.dev.n_long_and) LP_HIP(hipMemsetAsync(and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
     StepParams p = step_params(m);
     p.counters = counters;
     p.and_cnt = and_cnt;
-    p.early_exit = 0;
-    p.v = fix;
-    p.u = dst;
-    const int grid = p.n_blocks + m.dev.n_segs;
+    StepLaunch L;
     hipEvent_t e0, e1;
     LP_HIP(hipEventCreate(&e0));
     LP_HIP(hipEventCreate(&e1));
-    LP_HIP(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i) {
-        p.step = 2 + (i & 127);
-        tp_step_kernel<<<grid, kBlock, 0, st>>>(p);
+    float total = 0.f;
+    if (sched && sched->driver == LP_DRIVER_PERSISTENT) {
+        // each launch runs the whole fixpoint from the initial vector
+        int grid = 0;
+        if ((rc = plan_persistent(m, sched, p, &L, &grid))) return rc;
+        if (grid < 1) {
+            set_error("the persistent step does not fit on this device");
+            return LP_E_DEVICE;
+        }
+        uint64_t *buf[2] = {fix, dst};
+        unsigned int *bar;
+        int32_t *res;
+        if ((rc = S.get(&bar, 2)) || (rc = S.get(&res, 1))) return rc;
+        for (int i = 0; i < reps; ++i) {
+            LP_HIP(hipMemcpyAsync(buf[0], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
+            LP_HIP(hipMemcpyAsync(buf[1], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
+            LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
+            if (m.dev.n_long_and)
+                LP_HIP(hipMemsetAsync(and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
+            LP_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned int) * 2, st));
+            LP_HIP(hipEventRecord(e0, st));
+            if ((rc = launch_persistent(m, p, L, grid, buf, bar, res, st))) return rc;
+            LP_HIP(hipEventRecord(e1, st));
+            LP_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            LP_HIP(hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        }
+    } else {
+        LP_HIP(hipMemcpyAsync(dst, fix, W * 8, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
+        if (m.dev.n_long_and) LP_HIP(hipMemsetAsync(and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
+        p.early_exit = 0;
+        p.v = fix;
+        p.u = dst;
+        if ((rc = plan_step(m, sched, p, &L))) return rc;
+        LP_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < reps; ++i) {
+            p.step = 2 + (i & 127);
+            launch_step(L, p, st);
+        }
+        LP_HIP(hipGetLastError());
+        LP_HIP(hipEventRecord(e1, st));
+        LP_HIP(hipEventSynchronize(e1));
+        LP_HIP(hipEventElapsedTime(&total, e0, e1));
     }
-    LP_HIP(hipEventRecord(e1, st));
-    LP_HIP(hipEventSynchronize(e1));
-    float ms = 0;
-    LP_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *avg_ms = reps > 0 ? ms / reps : 0.f;
+    *avg_ms = reps > 0 ? total / reps : 0.f;
     return LP_OK;
 }
 
@@ -875,7 +1231,8 @@ lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_
     LP_GUARD_END
 }
 
-lp_status lp_bench_step(const lp_matrix *m, int32_t reps, float *avg_ms, void *hip_stream) {
+lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t reps, float *avg_ms,
+                        void *hip_stream) {
     LP_GUARD_BEGIN
     lp_status rc = check_solvable(m);
     if (rc) return rc;
@@ -884,7 +1241,7 @@ lp_status lp_bench_step(const lp_matrix *m, int32_t reps, float *avg_ms, void *h
         return LP_E_INVAL;
     }
     DeviceGuard g(m->m.dev.device);
-    return bench_step_impl(m->m, reps, avg_ms, (hipStream_t)hip_stream);
+    return bench_step_impl(m->m, sched, reps, avg_ms, (hipStream_t)hip_stream);
     LP_GUARD_END
 }
 

@@ -36,6 +36,10 @@ LP_DRIVER_PLAIN = 1
 LP_DRIVER_BATCHED = 2
 LP_DRIVER_PERSISTENT = 3
 
+LP_STEP_AUTO = 0
+LP_STEP_GLOBAL = 1
+LP_STEP_LDS = 2
+
 EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg_atoms",
            "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_least_model_batch",
            "lp_bench_step", "lp_set_allocator", "lp_last_error")
@@ -59,8 +63,8 @@ class lp_info(ctypes.Structure):
 
 class lp_schedule(ctypes.Structure):
     _fields_ = [("driver", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
-                ("long_row", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("skip_true_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 _lib = None
@@ -85,7 +89,7 @@ def load():
         "lp_least_model": [P, P, P, P, P],
         "lp_stable_models": [P, P, P, P, i64, P, P, P],
         "lp_least_model_batch": [P, i32, P, P, P, P],
-        "lp_bench_step": [P, i32, ctypes.POINTER(ctypes.c_float), P],
+        "lp_bench_step": [P, P, i32, ctypes.POINTER(ctypes.c_float), P],
         "lp_set_allocator": [P, P, P],
     }
     for name, args in sig.items():
@@ -116,12 +120,12 @@ def _ptr(a):
     return a.ctypes.data if a is not None and a.size else None
 
 
-def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, grid=0, skip_true_rows=0):
+def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, variant=LP_STEP_AUTO, grid=0):
     s = lp_schedule()
     s.driver = driver
     s.steps_per_sync = steps_per_sync
+    s.variant = variant
     s.grid = grid
-    s.skip_true_rows = skip_true_rows
     return s
 
 
@@ -221,10 +225,11 @@ class Matrix:
             out["interp"] = interp[: self.n_atoms]
         return out
 
-    def bench_step(self, reps: int = 100, stream=None) -> float:
+    def bench_step(self, reps: int = 100, sched=None, stream=None) -> float:
         """Average milliseconds of one full-sweep T_P step (HIP events)."""
         ms = ctypes.c_float(0)
-        _check(load().lp_bench_step(self._h, int(reps), ctypes.byref(ms), _stream(stream)))
+        _check(load().lp_bench_step(self._h, ctypes.byref(sched) if sched is not None else None,
+                                    int(reps), ctypes.byref(ms), _stream(stream)))
         return ms.value
 
 

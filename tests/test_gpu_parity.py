@@ -36,9 +36,21 @@ def test_example1_on_gpu():
     assert prods == d["products"][0]
 
 
-@pytest.mark.parametrize("driver", [lp.LP_DRIVER_PLAIN, lp.LP_DRIVER_BATCHED, lp.LP_DRIVER_AUTO])
-def test_tiny_programs_match_oracle(driver):
-    sched = lp.make_schedule(driver=driver, steps_per_sync=3)
+SCHEDULES = {
+    "plain-global": lp.make_schedule(driver=lp.LP_DRIVER_PLAIN, variant=lp.LP_STEP_GLOBAL),
+    "plain-lds": lp.make_schedule(driver=lp.LP_DRIVER_PLAIN, variant=lp.LP_STEP_LDS),
+    "batched-global": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=3, variant=lp.LP_STEP_GLOBAL),
+    "batched-lds-grid3": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=5, variant=lp.LP_STEP_LDS,
+                                          grid=3),
+    "persistent": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT),
+    "persistent-grid2": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT, grid=2),
+    "auto": None,
+}
+
+
+@pytest.mark.parametrize("name", list(SCHEDULES))
+def test_tiny_programs_match_oracle(name):
+    sched = SCHEDULES[name]
     for seed in range(150):
         p = gen.tiny_random(seed, max_atoms=16, max_rules=40, max_body=4)
         got, prods = _least(p, sched=sched)
@@ -68,7 +80,8 @@ def test_empty_and_factless_programs():
     assert got.sum() == 0 and prods == 1
 
 
-def test_long_or_and_rows_split_in_segments():
+@pytest.mark.parametrize("name", list(SCHEDULES))
+def test_long_or_and_rows_split_in_segments(name):
     # one head with 10,000 rules: an OR row of 10,000 entries (3 segments);
     # one rule with a 9,000-atom body: a split AND row (3 segments) that fires;
     # a second split AND row that must not fire (one body atom never true).
@@ -83,7 +96,7 @@ def test_long_or_and_rows_split_in_segments():
     p = gen.from_rules(n, rules)
     with lp.Matrix(p) as m:
         assert m.info["n_long_rows"] >= 3
-    _check_least(p)
+    _check_least(p, sched=SCHEDULES[name])
 
 
 @pytest.mark.parametrize("L", [1, 2, 100, 1000])
@@ -92,24 +105,30 @@ def test_chain_products(L):
     assert _check_least(p) == L
 
 
-def test_chain_zipf_scaled():
+@pytest.mark.parametrize("name", list(SCHEDULES))
+def test_chain_zipf_scaled(name):
     p = gen.chain_zipf(1, n_atoms=100_000, n_rules=500_000, chain_len=300)
-    assert _check_least(p) == 300
+    assert _check_least(p, sched=SCHEDULES[name]) == 300
 
 
 @pytest.mark.slow
 def test_chain_zipf_full_size():
     # 1,000,000 atoms, 5,000,000 rules, 2,000-long chain: the benchmarked workload
     p = gen.chain_zipf(0)
-    prods = _check_least(p, sched=lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=64))
-    assert prods == 2000
+    want, want_prods, _, _ = oracle.sd_fixpoint(p)
+    assert want_prods == 2000
+    with lp.Matrix(p) as m:
+        for name in ("batched-global", "persistent", "auto"):
+            got, prods = m.least_model(sched=SCHEDULES[name])
+            assert np.array_equal(got, want) and prods == 2000, name
 
 
 def test_bench_step_runs():
     p = gen.chain_zipf(2, n_atoms=50_000, n_rules=250_000, chain_len=50)
     with lp.Matrix(p) as m:
-        ms = m.bench_step(reps=20)
-        assert ms > 0
+        for v in (lp.LP_STEP_GLOBAL, lp.LP_STEP_LDS):
+            ms = m.bench_step(reps=20, sched=lp.make_schedule(variant=v))
+            assert ms > 0
         # the step leaves the matrix usable and the answer unchanged
         got, prods = m.least_model()
     assert np.array_equal(got, oracle.least_model(p)) and prods == 50

@@ -52,6 +52,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stable", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    ap.add_argument("--sweep", action="store_true", help="time every step shape (diagnostic)")
+    ap.add_argument("--tune-reps", type=int, default=20)
+    ap.add_argument("--schedule", default="",
+                    help="skip the tuner: variant,wpw,unroll[,driver] e.g. lds,2,16,batched")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only time the step kernel of --schedule (for hardware-counter runs)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="with --step-only: also run one device-to-device copy of this many MiB, a "
+                         "known-size kernel that calibrates the byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -78,7 +87,32 @@ def main() -> int:
     info = m.info
     log(f"[bench] matrix: N'={info['n_rows']} nnz={info['nnz']} long rows={info['n_long_rows']} "
         f"build {build_s:.2f}s")
-    sched = lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT)
+    if args.schedule:
+        f = args.schedule.split(",")
+        sched = lp.make_schedule(variant={"lds": lp.LP_STEP_LDS, "global": lp.LP_STEP_GLOBAL}[f[0]],
+                                 wpw=int(f[1]), unroll=int(f[2]), steps_per_sync=64,
+                                 driver={"batched": lp.LP_DRIVER_BATCHED, "persistent": lp.LP_DRIVER_PERSISTENT,
+                                         "plain": lp.LP_DRIVER_PLAIN}[f[3] if len(f) > 3 else "batched"])
+        if args.step_only:
+            step_sched = lp.make_schedule(variant=sched.variant, wpw=sched.wpw, unroll=sched.unroll)
+            ms = m.bench_step(reps=args.step_reps, sched=step_sched, stream=stream)
+            log(f"[bench] step-only {args.schedule}: {ms * 1e3:.2f} us/launch, "
+                f"{step_bytes(info) / (ms / 1e3) / 1e9:.0f} GB/s")
+            if args.copy_mb:
+                n = args.copy_mb << 20
+                src = torch.ones(n // 4, dtype=torch.int32, device=dev)
+                dst = torch.empty_like(src)
+                torch.cuda.synchronize()
+                dst.copy_(src)
+                torch.cuda.synchronize()
+                log(f"[bench] copied {args.copy_mb} MiB device-to-device")
+            return 0
+    else:
+        # autotune outside the timed region (step shape and driver)
+        t = time.perf_counter()
+        sched, tune_step_ms, tune_solve_ms = m.tune(reps=args.tune_reps, stream=stream)
+        log(f"[bench] tuned in {time.perf_counter() - t:.1f}s: {lp.schedule_dict(sched)} "
+            f"step {tune_step_ms * 1e3:.1f} us, solve {tune_solve_ms:.2f} ms")
 
     for i in range(args.warmup):
         model, products = m.least_model(sched=sched, stream=stream)
@@ -104,34 +138,34 @@ def main() -> int:
     log(f"[bench] {args.steps} solves: {ms_per_step:.3f} ms/solve (events), wall {wall * 1e3 / args.steps:.3f} ms, "
         f"products={products}, {ms_per_step * 1e3 / products:.2f} us/product")
 
-    # other drivers and step kernels, for comparison
     B = step_bytes(info)
     variants = {}
-    for name, sc in (("batched_lds", lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=64,
-                                                       variant=lp.LP_STEP_LDS)),
-                     ("batched_global", lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, steps_per_sync=64,
-                                                          variant=lp.LP_STEP_GLOBAL))):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        mv, pv = m.least_model(sched=sc, stream=stream)
-        torch.cuda.synchronize()
-        assert pv == products and np.array_equal(mv, model)
-        variants[name] = {"ms_per_solve": round((time.perf_counter() - t) * 1e3, 3)}
-    for name, v in (("step_lds", lp.LP_STEP_LDS), ("step_global", lp.LP_STEP_GLOBAL)):
-        ms = m.bench_step(reps=args.step_reps, sched=lp.make_schedule(variant=v), stream=stream)
-        variants[name] = {"us_per_launch": round(ms * 1e3, 3), "GB/s": round(B / (ms / 1e3) / 1e9, 1)}
-    log(f"[bench] variants: {variants}")
+    if args.sweep:
+        for v, vname in ((lp.LP_STEP_LDS, "lds"), (lp.LP_STEP_GLOBAL, "global")):
+            for w in (1, 2, 4, 8):
+                for u in (4, 8, 16):
+                    ms = m.bench_step(reps=args.step_reps, stream=stream,
+                                      sched=lp.make_schedule(variant=v, wpw=w, unroll=u))
+                    variants[f"{vname}-w{w}-u{u}"] = round(ms * 1e3, 2)
+        log(f"[bench] step us per shape: {variants}")
 
-    # dominant kernel: the persistent fixpoint kernel, one launch per solve,
-    # timed with HIP events around each launch inside the library
-    kern_ms = m.bench_step(reps=max(3, args.steps), sched=sched, stream=stream)
-    Bl = B * products
+    # dominant kernel, timed with HIP events around its launches inside the library
+    if sched.driver == lp.LP_DRIVER_PERSISTENT:
+        kern_ms = m.bench_step(reps=max(3, args.steps), sched=sched, stream=stream)
+        Bl = B * products
+        kname = f"tp_fixpoint_persistent_kernel<{sched.wpw}, {sched.unroll}>"
+    else:
+        step_sched = lp.make_schedule(variant=sched.variant, wpw=sched.wpw, unroll=sched.unroll, grid=sched.grid)
+        kern_ms = m.bench_step(reps=args.step_reps, sched=step_sched, stream=stream)
+        Bl = B
+        kname = (f"tp_step_kernel<{'true' if sched.variant == lp.LP_STEP_LDS else 'false'}, "
+                 f"{sched.wpw}, {sched.unroll}>")
     achieved = Bl / (kern_ms / 1e3) / 1e9
-    log(f"[bench] tp_fixpoint_persistent_kernel: {kern_ms:.3f} ms/launch, {Bl / 1e9:.2f} GB -> {achieved:.0f} GB/s")
+    log(f"[bench] {kname}: {kern_ms * 1e3:.2f} us/launch, {Bl / 1e6:.1f} MB -> {achieved:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "tp_fixpoint_persistent_kernel", "bytes_per_launch": Bl,
-                "ms_per_launch": round(kern_ms, 4), "bytes_per_product": B}
+                "kernel": kname, "bytes_per_launch": Bl, "us_per_launch": round(kern_ms * 1e3, 3),
+                "bytes_per_product": B}
 
     stable = None
     if not args.no_stable:
@@ -193,7 +227,8 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stable_models": stable,
-        "variants": variants,
+        "schedule": lp.schedule_dict(sched),
+        "step_us_per_shape": variants or None,
     }
     print(json.dumps(out), flush=True)
     m.close()

@@ -105,15 +105,17 @@ enum {
 enum {
     LP_STEP_AUTO = 0,
     LP_STEP_GLOBAL = 1,  /* 256-thread workgroups, gathers of v from global memory */
-    LP_STEP_LDS = 2      /* one 1024-thread workgroup per CU, v staged in LDS for the gathers */
+    LP_STEP_LDS = 2      /* one 1024-thread workgroup per CU, the original atoms of v staged in LDS */
 };
 
 typedef struct lp_schedule {
     int32_t driver;          /* LP_DRIVER_* */
     int32_t steps_per_sync;  /* products issued between host checks (BATCHED, AUTO) */
     int32_t variant;         /* LP_STEP_* kernel of the least-model step */
-    int32_t grid;            /* workgroups of the LDS-staged step (0: one per CU) */
-    int32_t reserved[4];
+    int32_t grid;            /* workgroups of the step (0: one per CU for LDS, eight per CU otherwise) */
+    int32_t wpw;             /* 64-row words per wave: 1, 2, 4 or 8 (0: default) */
+    int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16 (0: default) */
+    int32_t reserved[2];
 } lp_schedule;
 
 /*
@@ -221,6 +223,18 @@ lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_
  */
 lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t reps, float *avg_ms,
                         void *hip_stream);
+
+/*
+ * Autotuner for least-model solves of m (a definite program). Times every
+ * supported step shape (LP_STEP_LDS / LP_STEP_GLOBAL, 1/2/4/8 words per wave,
+ * 4/8/16 chunks in flight) over reps full-sweep steps on m's own fixpoint
+ * with HIP events, then times whole solves with the batched and persistent
+ * drivers at the fastest shape, and writes the fastest schedule to *best.
+ * best_step_ms / best_solve_ms (nullable) receive the winning times. Results
+ * of lp_least_model do not depend on the schedule; only the time does.
+ */
+lp_status lp_tune_schedule(const lp_matrix *m, int32_t reps, lp_schedule *best, float *best_step_ms,
+                           float *best_solve_ms, void *hip_stream);
 
 /*
  * Route the library's device allocations through caller-supplied functions

@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblp.so")
-SOURCES = [os.path.join(CSRC, "lp_build.cpp"), os.path.join(CSRC, "lp_device.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("lp_build.cpp", "lp_step.hip", "lp_spmm.hip", "lp_runtime.hip")]
 ARCH = os.environ.get("LP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -231,7 +231,8 @@ lp_status build_host(int32_t n_atoms, int32_t n_rules, const int32_t *head, cons
         I.n_empty_rows = n_empty;
         I.max_row_len = max_len;
         int32_t n_long = 0;
-        for (int32_t i = 0; i < n_rows; ++i) n_long += len[i] > kLongRow;
+        for (int32_t i = 0; i < n_rows; ++i)
+            n_long += m->kind[i] ? (!m->fact[i] && len[i] > kLongAnd) : (len[i] > kLongOrBits);
         I.n_long_rows = n_long;
         I.sparsity = N > 0 ? 1.0 - (double)sum_body / ((double)N * (double)N) : 1.0;
     } catch (const std::bad_alloc &) {

@@ -10,42 +10,61 @@
 
 namespace lp {
 
-// Rows longer than this leave the 64-row block pass of the least-model step
-// and are evaluated by split segments (one workgroup per segment).
-constexpr int32_t kLongRow = 256;
-constexpr int32_t kSegLen = 4096;
+// Least-model device layout. Rows are grouped by 64 (one bit-packed word of
+// v). Every row is one of: empty (never true), fact (true from the initial
+// vector on, no work), AND (fires iff all of its entries are true) or OR
+// (fires iff one child is true). AND bodies name only original atoms; the k
+// children of an OR row are the consecutive new atoms of its head, so an OR
+// row is a bit range of v and stores no column indices.
+constexpr int32_t kLongAnd = 255;       // longer AND rows go to the segment pass
+constexpr int32_t kLongOrBits = 512;    // longer OR rows go to the segment pass
+constexpr int32_t kSegAnd = 4096;       // entries per AND segment
+constexpr int32_t kSegOrBits = 16384;   // bits per OR segment
 
-// Device-resident form of one matrix. All pointers are device memory owned
-// by the matrix (released by lp_free_matrix).
-struct DeviceMatrix {
-    // Least-model (SpMV) layout: 64-row block CSR with long rows emptied, plus
-    // a segment list for the long rows.
-    int32_t *row_ptr = nullptr;   // [n_rows+1]
-    int32_t *col = nullptr;       // [short nnz]
-    uint64_t *and_bits = nullptr; // [n_words]; bit = 1: AND row (long rows cleared)
-    uint64_t *fact_bits = nullptr;// [n_words]; initial vector
-    void *segs = nullptr;         // LongSeg[n_segs]
-    int32_t *long_col = nullptr;  // [long nnz]
-    int32_t n_segs = 0;
-    int32_t n_long_and = 0;
-    int64_t short_nnz = 0, long_nnz = 0;
-    // Stable-model (SpMM) layout: plain CSR.
-    int32_t *full_row_ptr = nullptr;
-    int32_t *full_col = nullptr;
-    int32_t *q_rows = nullptr;    // [K] row ids of q_t
-    int32_t *guess_pos = nullptr; // [K] bit of the compressed guess index, -1 if pruned
-    int64_t bytes = 0;
-    int device = -1;
+struct WordMeta {
+    int32_t and_base;    // offset in col of the word's first AND entry
+    int32_t or_idx;      // index in or_c0 of the word's first OR row
+    uint64_t and_bits;   // AND rows evaluated by the block pass
+    uint64_t or_bits;    // all OR rows (the block pass evaluates those not in long_bits)
+    uint64_t long_bits;  // rows evaluated by the segment pass
 };
 
 struct LongSeg {
     int32_t row;
     int32_t is_and;
-    int64_t begin;   // into long_col
-    int32_t len;
+    int64_t begin;   // AND: offset in long_col; OR: first bit of the range in v
+    int32_t len;     // AND: entries; OR: bits
     int32_t nseg;    // segments of this row
     int32_t and_slot;// index into the completion counts of split AND rows, -1 otherwise
     int32_t seg;     // index of this segment within its row
+};
+
+// Device-resident form of one matrix. All pointers are device memory owned
+// by the matrix (released by lp_free_matrix).
+struct DeviceMatrix {
+    // least models (definite programs)
+    WordMeta *words = nullptr;    // [n_words]
+    uint8_t *and_len = nullptr;   // [n_rows] AND-row length in the block pass, 0 otherwise
+    int32_t *col = nullptr;       // block AND entries in row order
+    int32_t *or_c0 = nullptr;     // [n_or + 1] first child of each OR row, ascending rows
+    int32_t *or_row = nullptr;    // [n_or] row id of each OR row, -1 if evaluated by segments
+    uint64_t *fact_bits = nullptr;// [n_words] initial vector
+    LongSeg *segs = nullptr;      // [n_segs]
+    int32_t *long_col = nullptr;  // entries of long AND rows
+    int32_t n_segs = 0;
+    int32_t n_long_and = 0;
+    int32_t n_or = 0;
+    int32_t and_max_col = -1;     // largest column of a block AND entry
+    int64_t and_nnz = 0, long_nnz = 0;
+    int64_t stream_bytes = 0;     // bytes one full step streams from memory (layout arrays)
+    // stable models (normal programs): plain CSR
+    int32_t *full_row_ptr = nullptr;
+    int32_t *full_col = nullptr;
+    uint64_t *full_and_bits = nullptr;  // [n_words] AND rows
+    int32_t *q_rows = nullptr;    // [K] row ids of q_t
+    int32_t *guess_pos = nullptr; // [K] bit of the compressed guess index, -1 if pruned
+    int64_t bytes = 0;
+    int device = -1;
 };
 
 struct Matrix {

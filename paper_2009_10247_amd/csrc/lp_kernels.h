@@ -1,0 +1,90 @@
+// lp_kernels.h -- kernel parameter blocks and launchers shared by the kernel
+// translation units (lp_step.hip, lp_spmm.hip) and the runtime (lp_runtime.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lp_internal.h"
+
+namespace lp {
+
+// Change counts live in a ring indexed by product number & (kRing - 1).
+constexpr int kRing = 256;
+
+// One least-model T_P step u = theta(M v) over the device layout of a matrix.
+struct StepParams {
+    const WordMeta *words;         // [n_words]
+    const uint8_t *and_len;        // [n_rows]
+    const int32_t *col;            // block AND entries
+    const int32_t *or_c0;          // [n_or + 1]
+    const int32_t *or_row;         // [n_or] row of each OR row, -1 for rows of the segment pass
+    const LongSeg *segs;           // [n_segs]
+    const int32_t *long_col;
+    uint32_t *and_cnt;             // [2][n_long_and] completion counts of split AND rows
+    const uint64_t *v;             // [n_words] v_t
+    uint64_t *u;                   // [n_words] holds a subset of the result; the step ORs into it
+    unsigned long long *counters;  // change-count ring
+    int32_t n_rows;
+    int32_t n_long_and;
+    int32_t n_segs;
+    int32_t n_or;
+    int32_t and_end;               // number of block AND entries
+    int32_t and_max_col;           // largest column of a block AND entry (-1 if none)
+    int32_t step;                  // 1-based product index
+    int32_t early_exit;            // 1: return at once if product step-1 changed nothing
+    int32_t lds_words;             // leading words of v staged in LDS (LDS shapes)
+};
+
+// Launch shape of the step kernel. A wave owns wpw consecutive 64-row words
+// (a super-block) and keeps unroll column chunks of 64 entries in flight.
+struct StepShape {
+    int lds = 1;        // 1: v staged in LDS, 1024-thread workgroups (one per CU)
+    int wpw = 4;        // words per wave: 1, 2, 4 or 8
+    int unroll = 8;     // 4, 8 or 16
+    int block = 1024;   // threads per workgroup
+    int grid = 0;       // workgroups (grid-stride loop over super-blocks)
+    size_t lds_bytes = 0;
+};
+
+bool step_shape_supported(const StepShape &s);
+hipError_t launch_step(const StepShape &s, const StepParams &p, hipStream_t st);
+
+// Persistent form: the whole fixpoint loop in one cooperative launch.
+struct PersistParams {
+    StepParams p;
+    uint64_t *buf0;
+    uint64_t *buf1;
+    int32_t max_steps;
+    int32_t *result;  // products, or -1 if max_steps was reached
+};
+hipError_t launch_persistent(const StepShape &s, const PersistParams &q, hipStream_t st);
+hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu);
+// Allows every LDS-staged kernel to take up to max_dynamic_lds bytes.
+void step_kernels_allow_lds(int max_dynamic_lds);
+
+// Stable models (interpretation matrix with W = 2^log2W words per row).
+struct SpmmParams {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint64_t *and_bits;  // AND rows of the full matrix
+    const uint64_t *V;
+    uint64_t *U;
+    unsigned long long *counters;
+    int64_t total;  // n_rows << log2W
+    int32_t log2W;
+    int32_t step;
+    int32_t early_exit;
+};
+hipError_t launch_spmm_step(const SpmmParams &p, hipStream_t st);
+hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std,
+                          const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff, hipStream_t st);
+hipError_t launch_stable_check(const uint64_t *V, int32_t log2W, int64_t W, const int32_t *q_rows, int32_t n_std,
+                               int32_t K, int32_t k_eff, uint64_t *accept, unsigned long long *count,
+                               hipStream_t st);
+hipError_t launch_extract(const uint64_t *V, int32_t log2W, const int64_t *cols, int64_t n_models, int32_t n_atoms,
+                          uint8_t *out, hipStream_t st);
+
+}  // namespace lp

@@ -1,0 +1,1003 @@
+// lp_runtime.hip -- device memory, matrix upload, fixpoint drivers and the C-ABI
+// entry points. The kernels are in lp_step.hip (least models) and
+// lp_spmm.hip (stable models); this file only launches them.
+//
+// Drivers of the Algorithm 1 loop:
+//   PLAIN       one step launch per product, then the host reads the count;
+//   BATCHED     steps_per_sync launches between host reads: a step whose
+//               previous product changed nothing returns at once, so steps
+//               issued past the fixpoint cost only a launch;
+//   PERSISTENT  one cooperative launch runs every product on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lp_kernels.h"
+
+namespace lp {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+// ------------------------------------------------------------------ memory
+
+static void *(*g_alloc)(size_t, void *, void *) = nullptr;
+static void (*g_release)(void *, void *, void *) = nullptr;
+static void *g_alloc_ctx = nullptr;
+
+static lp_status hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return LP_E_DEVICE;
+}
+
+#define LP_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+static lp_status dev_alloc(void **p, size_t bytes, hipStream_t st) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (g_alloc) {
+        *p = g_alloc(bytes, (void *)st, g_alloc_ctx);
+        if (!*p) {
+            set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+            return LP_E_NOMEM;
+        }
+        return LP_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of " + std::to_string(bytes) + " bytes: out of memory");
+        return LP_E_NOMEM;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    return LP_OK;
+}
+
+static void dev_free(void *p, hipStream_t st) {
+    if (!p) return;
+    if (g_release) g_release(p, (void *)st, g_alloc_ctx);
+    else (void)hipFree(p);
+}
+
+// RAII list of device buffers of one call.
+struct Scratch {
+    hipStream_t st;
+    std::vector<void *> ptrs;
+    explicit Scratch(hipStream_t s) : st(s) {}
+    template <class T>
+    lp_status get(T **p, size_t count) {
+        void *q;
+        lp_status rc = dev_alloc(&q, count * sizeof(T), st);
+        if (rc) return rc;
+        ptrs.push_back(q);
+        *p = (T *)q;
+        return LP_OK;
+    }
+    ~Scratch() {
+        if (!ptrs.empty()) (void)hipStreamSynchronize(st);
+        for (void *p : ptrs) dev_free(p, st);
+    }
+};
+
+// Small pinned host buffer per thread for change counters.
+static unsigned long long *pinned_ring() {
+    static thread_local unsigned long long *p = nullptr;
+    if (!p) {
+        if (hipHostMalloc((void **)&p, sizeof(unsigned long long) * kRing, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+        }
+    }
+    return p;
+}
+
+// ------------------------------------------------------------------ upload
+
+static int64_t n_words_of(int64_t rows) { return (rows + 63) / 64; }
+
+static std::vector<uint64_t> pack_bits(const std::vector<uint8_t> &x, int64_t words) {
+    std::vector<uint64_t> w(words ? words : 1, 0);
+    for (size_t i = 0; i < x.size(); ++i)
+        if (x[i]) w[i >> 6] |= 1ull << (i & 63);
+    return w;
+}
+
+template <class T>
+static lp_status upload(T **d, const T *h, size_t count, hipStream_t st, int64_t *bytes) {
+    lp_status rc = dev_alloc((void **)d, count * sizeof(T), st);
+    if (rc) return rc;
+    *bytes += (int64_t)(count * sizeof(T));
+    if (count) LP_HIP(hipMemcpyAsync(*d, h, count * sizeof(T), hipMemcpyHostToDevice, st));
+    return LP_OK;
+}
+
+static void free_device(Matrix &m, hipStream_t st) {
+    DeviceMatrix &d = m.dev;
+    void *ps[] = {d.words,        d.and_len,       d.col,    d.or_c0,    d.or_row, d.fact_bits, d.segs, d.long_col,
+                  d.full_row_ptr, d.full_col,      d.full_and_bits, d.q_rows, d.guess_pos};
+    for (void *p : ps) dev_free(p, st);
+    d = DeviceMatrix{};
+}
+
+// Least-model layout (see WordMeta and LongSeg): rows by kind, AND entries of
+// block rows in col, OR rows as child ranges, long rows as segments.
+static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
+    DeviceMatrix &d = m.dev;
+    const int32_t n = m.n_rows;
+    const int64_t W = n_words_of(n);
+    std::vector<WordMeta> words(W ? W : 1);
+    std::vector<uint8_t> and_len(n ? n : 1, 0);
+    std::vector<int32_t> col, lcol, or_c0, or_row;
+    std::vector<LongSeg> segs;
+    col.reserve(m.col.size());
+    int32_t n_long_and = 0, max_col = -1, n_or = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t w = i >> 6;
+        const uint64_t bit = 1ull << (i & 63);
+        if ((i & 63) == 0) {
+            words[w] = WordMeta{};
+            words[w].and_base = (int32_t)col.size();
+            words[w].or_idx = n_or;  // OR rows before this word
+        }
+        const int32_t s = m.row_ptr[i], e = m.row_ptr[i + 1], len = e - s;
+        if (m.fact[i] || len == 0) continue;  // facts: true from v0 on; empty rows: never true
+        if (m.kind[i]) {
+            if (len > kLongAnd) {
+                words[w].long_bits |= bit;
+                const int32_t nseg = (len + kSegAnd - 1) / kSegAnd;
+                const int32_t slot = nseg > 1 ? n_long_and++ : -1;
+                for (int32_t q = 0; q < nseg; ++q) {
+                    LongSeg sg{};
+                    sg.row = i;
+                    sg.is_and = 1;
+                    sg.begin = (int64_t)lcol.size() + (int64_t)q * kSegAnd;
+                    sg.len = std::min(kSegAnd, len - q * kSegAnd);
+                    sg.nseg = nseg;
+                    sg.and_slot = slot;
+                    sg.seg = q;
+                    segs.push_back(sg);
+                }
+                lcol.insert(lcol.end(), m.col.begin() + s, m.col.begin() + e);
+            } else {
+                words[w].and_bits |= bit;
+                and_len[i] = (uint8_t)len;
+                col.insert(col.end(), m.col.begin() + s, m.col.begin() + e);
+            }
+            for (int32_t j = s; j < e; ++j) max_col = std::max(max_col, m.col[j]);
+        } else {
+            // OR row: children are consecutive ids and follow the previous OR row's children
+            const int32_t c0 = m.col[s];
+            for (int32_t j = s; j < e; ++j)
+                if (m.col[j] != c0 + (j - s)) {
+                    set_error("OR row children are not consecutive");
+                    return LP_E_INTERNAL;
+                }
+            if (!or_c0.empty() && or_c0.back() != c0) {
+                set_error("OR rows' child ranges are not contiguous");
+                return LP_E_INTERNAL;
+            }
+            if (or_c0.empty()) or_c0.push_back(c0);
+            or_c0.push_back(c0 + len);  // or_c0[j] is the start of OR row j, or_c0[j+1] its end
+            or_row.push_back(len > kLongOrBits ? -1 : i);
+            ++n_or;
+            words[w].or_bits |= bit;
+            if (len > kLongOrBits) {
+                words[w].long_bits |= bit;
+                const int32_t nseg = (len + kSegOrBits - 1) / kSegOrBits;
+                for (int32_t q = 0; q < nseg; ++q) {
+                    LongSeg sg{};
+                    sg.row = i;
+                    sg.is_and = 0;
+                    sg.begin = (int64_t)c0 + (int64_t)q * kSegOrBits;
+                    sg.len = std::min(kSegOrBits, len - q * kSegOrBits);
+                    sg.nseg = nseg;
+                    sg.and_slot = -1;
+                    sg.seg = q;
+                    segs.push_back(sg);
+                }
+            }
+        }
+    }
+    d.n_or = n_or;
+    d.and_nnz = (int64_t)col.size();
+    d.long_nnz = (int64_t)lcol.size();
+    d.n_segs = (int32_t)segs.size();
+    d.n_long_and = n_long_and;
+    d.and_max_col = max_col;
+    if (or_c0.empty()) or_c0.push_back(0);
+    if (or_row.empty()) or_row.push_back(-1);
+    lp_status rc;
+    if ((rc = upload(&d.words, words.data(), words.size(), st, &d.bytes))) return rc;
+    if ((rc = upload(&d.and_len, and_len.data(), and_len.size(), st, &d.bytes))) return rc;
+    if ((rc = upload(&d.col, col.data(), col.size(), st, &d.bytes))) return rc;
+    if ((rc = upload(&d.or_c0, or_c0.data(), or_c0.size(), st, &d.bytes))) return rc;
+    if ((rc = upload(&d.or_row, or_row.data(), or_row.size(), st, &d.bytes))) return rc;
+    if ((rc = upload(&d.segs, segs.data(), segs.size(), st, &d.bytes))) return rc;
+    if ((rc = upload(&d.long_col, lcol.data(), lcol.size(), st, &d.bytes))) return rc;
+    d.stream_bytes = (int64_t)W * (int64_t)sizeof(WordMeta) + n + 4 * (d.and_nnz + d.long_nnz) +
+                     4 * (int64_t)(or_c0.size() + or_row.size()) + (int64_t)sizeof(LongSeg) * d.n_segs;
+    return LP_OK;
+}
+
+static lp_status upload_matrix(Matrix &m, hipStream_t st) {
+    DeviceMatrix &d = m.dev;
+    LP_HIP(hipGetDevice(&d.device));
+    const int64_t W = n_words_of(m.n_rows);
+    std::vector<uint64_t> fact = pack_bits(m.fact, W);
+    lp_status rc;
+    if ((rc = upload(&d.fact_bits, fact.data(), fact.size(), st, &d.bytes))) return rc;
+    if (m.K == 0) {
+        if ((rc = upload_least_layout(m, st))) return rc;
+    } else {
+        std::vector<uint64_t> andb = pack_bits(m.kind, W);
+        std::vector<int32_t> qrows(m.neg_atoms);
+        if ((rc = upload(&d.full_row_ptr, m.row_ptr.data(), m.row_ptr.size(), st, &d.bytes))) return rc;
+        if ((rc = upload(&d.full_col, m.col.data(), m.col.size(), st, &d.bytes))) return rc;
+        if ((rc = upload(&d.full_and_bits, andb.data(), andb.size(), st, &d.bytes))) return rc;
+        if ((rc = upload(&d.q_rows, qrows.data(), qrows.size(), st, &d.bytes))) return rc;
+        if ((rc = upload(&d.guess_pos, m.guess_pos.data(), m.guess_pos.size(), st, &d.bytes))) return rc;
+    }
+    LP_HIP(hipStreamSynchronize(st));
+    m.info.device_bytes = d.bytes;
+    return LP_OK;
+}
+
+// ------------------------------------------------------------------ drivers
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (dev >= 0 && hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+struct DevProps {
+    int n_cu = 0;
+    int max_lds = 0;
+};
+
+static lp_status dev_props(int dev, DevProps *out) {
+    static std::mutex mu;
+    static DevProps cache[64];
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev < 0 || dev >= 64) {
+        set_error("device id out of range");
+        return LP_E_DEVICE;
+    }
+    if (cache[dev].n_cu == 0) {
+        DevProps d;
+        LP_HIP(hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        LP_HIP(hipDeviceGetAttribute(&d.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (d.max_lds > 4096) step_kernels_allow_lds(d.max_lds - 4096);
+        cache[dev] = d;
+    }
+    *out = cache[dev];
+    return LP_OK;
+}
+
+static StepParams step_params(const Matrix &m) {
+    const DeviceMatrix &d = m.dev;
+    StepParams p{};
+    p.words = d.words;
+    p.and_len = d.and_len;
+    p.col = d.col;
+    p.or_c0 = d.or_c0;
+    p.or_row = d.or_row;
+    p.n_or = d.n_or;
+    p.segs = d.segs;
+    p.long_col = d.long_col;
+    p.n_rows = m.n_rows;
+    p.and_end = (int32_t)d.and_nnz;
+    p.and_max_col = d.and_max_col;
+    p.n_long_and = d.n_long_and;
+    p.n_segs = d.n_segs;
+    p.early_exit = 1;
+    return p;
+}
+
+// Launch shape of the step for a whole solve. LDS shapes use one 1024-thread
+// workgroup per CU (the staged v takes most of the CU's LDS); global shapes
+// use 256-thread workgroups, eight per CU.
+static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S) {
+    int variant = sched ? sched->variant : LP_STEP_AUTO;
+    if (variant == LP_STEP_AUTO) variant = LP_STEP_LDS;
+    if (variant != LP_STEP_LDS && variant != LP_STEP_GLOBAL) {
+        set_error("unknown step variant");
+        return LP_E_INVAL;
+    }
+    DevProps d;
+    lp_status rc = dev_props(m.dev.device, &d);
+    if (rc) return rc;
+    StepShape s;
+    s.lds = variant == LP_STEP_LDS;
+    s.wpw = sched && sched->wpw > 0 ? sched->wpw : (s.lds ? 4 : 2);
+    s.unroll = sched && sched->unroll > 0 ? sched->unroll : 8;
+    if (!step_shape_supported(s)) {
+        set_error("unsupported step shape (words per wave 1/2/4/8, unroll 4/8/16)");
+        return LP_E_INVAL;
+    }
+    const int64_t n_words = n_words_of(m.n_rows);
+    if (s.lds) {
+        // the kernels' static LDS (per-wave ballots, counters) takes at most 4 KiB
+        const int64_t cap = std::max<int64_t>(0, (d.max_lds - 4096) / 8);
+        p.lds_words = (int32_t)std::min<int64_t>({cap, n_words_of(m.n_atoms), n_words});
+        s.lds_bytes = (size_t)p.lds_words * 8;
+        s.block = 1024;
+    } else {
+        p.lds_words = 0;
+        s.lds_bytes = 0;
+        s.block = 256;
+    }
+    const int waves = s.block / 64;
+    const int64_t items = std::max<int64_t>({(n_words + s.wpw - 1) / s.wpw, (int64_t)p.n_segs,
+                                             ((int64_t)p.n_or + 63) / 64});
+    const int64_t want = std::max<int64_t>(1, (items + waves - 1) / waves);
+    const int64_t dflt = s.lds ? d.n_cu : (int64_t)d.n_cu * 8;
+    const int64_t grid = sched && sched->grid > 0 ? sched->grid : dflt;
+    s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, want));
+    *S = s;
+    return LP_OK;
+}
+
+// Shape of the persistent fixpoint: the LDS step with at most as many
+// workgroups as can be resident at once (the grid barrier needs all of them
+// running). S->grid = 0 if not even one fits.
+static lp_status plan_persistent(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S) {
+    lp_schedule s2 = sched ? *sched : lp_schedule{};
+    s2.variant = LP_STEP_LDS;
+    lp_status rc = plan_step(m, &s2, p, S);
+    if (rc) return rc;
+    int per_cu = 0;
+    LP_HIP(persistent_occupancy(*S, &per_cu));
+    DevProps d;
+    if ((rc = dev_props(m.dev.device, &d))) return rc;
+    const int64_t resident = (int64_t)per_cu * d.n_cu;
+    S->grid = (int)std::min<int64_t>(S->grid, resident);
+    return LP_OK;
+}
+
+static lp_status run_persistent(const Matrix &m, const StepParams &p, const StepShape &S, uint64_t *const buf[2],
+                                int32_t *res, hipStream_t st) {
+    PersistParams q{};
+    q.p = p;
+    q.buf0 = buf[0];
+    q.buf1 = buf[1];
+    q.max_steps = (int32_t)std::min<int64_t>((int64_t)m.n_rows + 1, INT32_MAX - 1);
+    q.result = res;
+    LP_HIP(launch_persistent(S, q, st));
+    return LP_OK;
+}
+
+// Least-model fixpoint. On success *out points at the device buffer holding
+// the fixpoint (one of bufs[0..1]).
+static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipStream_t st, Scratch &S,
+                                uint64_t **out, int32_t *products) {
+    const int64_t W = n_words_of(m.n_rows);
+    uint64_t *buf[2];
+    unsigned long long *counters;
+    uint32_t *and_cnt;
+    lp_status rc;
+    if ((rc = S.get(&buf[0], W)) || (rc = S.get(&buf[1], W)) || (rc = S.get(&counters, kRing)) ||
+        (rc = S.get(&and_cnt, 2 * (size_t)m.dev.n_long_and)))
+        return rc;
+    LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
+    if (m.dev.n_long_and) LP_HIP(hipMemsetAsync(and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
+    LP_HIP(hipMemcpyAsync(buf[0], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
+    LP_HIP(hipMemcpyAsync(buf[1], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
+    if (m.n_rows == 0) {
+        *out = buf[0];
+        *products = 1;
+        return LP_OK;
+    }
+    int driver = sched ? sched->driver : LP_DRIVER_AUTO;
+    StepParams p = step_params(m);
+    p.counters = counters;
+    p.and_cnt = and_cnt;
+    StepShape L;
+    if (driver == LP_DRIVER_PERSISTENT) {
+        if ((rc = plan_persistent(m, sched, p, &L))) return rc;
+        if (L.grid >= 1) {
+            int32_t *res;
+            if ((rc = S.get(&res, 1))) return rc;
+            if ((rc = run_persistent(m, p, L, buf, res, st))) return rc;
+            int32_t prods = 0;
+            LP_HIP(hipMemcpyAsync(&prods, res, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            LP_HIP(hipStreamSynchronize(st));
+            if (prods < 1) {
+                set_error("fixpoint not reached within n_rows+1 products");
+                return LP_E_INTERNAL;
+            }
+            *products = prods;
+            *out = buf[prods & 1];
+            return LP_OK;
+        }
+        set_error("the persistent step does not fit on this device");
+        return LP_E_DEVICE;
+    }
+    int batch = 1;
+    if (driver == LP_DRIVER_BATCHED || driver == LP_DRIVER_AUTO) {
+        batch = (sched && sched->steps_per_sync > 0) ? sched->steps_per_sync : 32;
+    }
+    batch = std::max(1, std::min(batch, kRing / 2 - 1));
+    if ((rc = plan_step(m, sched, p, &L))) return rc;
+    unsigned long long *h = pinned_ring();
+    if (!h) {
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
+    const int64_t limit = (int64_t)m.n_rows + 1;
+    for (int64_t t = 0;; t += batch) {
+        for (int i = 1; i <= batch; ++i) {
+            p.step = (int32_t)(t + i);
+            p.v = buf[(p.step - 1) & 1];
+            p.u = buf[p.step & 1];
+            LP_HIP(launch_step(L, p, st));
+        }
+        LP_HIP(hipMemcpyAsync(h, counters, sizeof(unsigned long long) * kRing, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        for (int i = 1; i <= batch; ++i) {
+            const int64_t s = t + i;
+            if (h[s & (kRing - 1)] == 0) {
+                *products = (int32_t)s;
+                *out = buf[s & 1];
+                return LP_OK;
+            }
+        }
+        if (t + batch > limit) {
+            set_error("fixpoint not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
+    }
+}
+
+static void unpack_model(const uint64_t *bits, int32_t n, uint8_t *model) {
+    for (int32_t a = 0; a < n; ++a) model[a] = (uint8_t)((bits[a >> 6] >> (a & 63)) & 1ull);
+}
+
+static lp_status least_model_impl(const Matrix &m, uint8_t *model, int32_t *products, const lp_schedule *sched,
+                                  hipStream_t st) {
+    Scratch S(st);
+    uint64_t *fix = nullptr;
+    int32_t prods = 0;
+    lp_status rc = least_fixpoint(m, sched, st, S, &fix, &prods);
+    if (rc) return rc;
+    const int64_t Wn = n_words_of(m.n_atoms);
+    std::vector<uint64_t> hb(Wn ? Wn : 1);
+    if (Wn) LP_HIP(hipMemcpyAsync(hb.data(), fix, Wn * 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    unpack_model(hb.data(), m.n_atoms, model);
+    if (products) *products = prods;
+    return LP_OK;
+}
+
+static int ilog2(int64_t x) {
+    int l = 0;
+    while ((1ll << l) < x) ++l;
+    return l;
+}
+
+static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
+                             int64_t max_models, uint64_t *interp, int32_t *products, hipStream_t st) {
+    const int K = m.K;
+    const int64_t H_full = 1ll << K;
+    const int64_t W_full = (H_full + 63) / 64;
+    if (K == 0) {
+        // definite program: exactly one stable model, the least model
+        std::vector<uint8_t> lm(m.n_atoms ? m.n_atoms : 1);
+        lp_status rc = least_model_impl(m, lm.data(), products, nullptr, st);
+        if (rc) return rc;
+        accepted[0] = 1;
+        *n_models = 1;
+        if (models && max_models >= 1) std::memcpy(models, lm.data(), m.n_atoms);
+        if (interp)
+            for (int32_t a = 0; a < m.n_atoms; ++a) interp[a] = lm[a];
+        if (models && max_models < 1) return LP_E_TRUNCATED;
+        return LP_OK;
+    }
+    if (interp && m.K_eff != K) {
+        set_error("interp output needs a matrix built without LP_PRUNE_FACT_GUESSES");
+        return LP_E_INVAL;
+    }
+    const int keff = m.K_eff;
+    const int64_t H = 1ll << keff;
+    const int64_t W = (H + 63) / 64;
+    const int log2W = ilog2(W);
+    const int64_t total = (int64_t)m.n_rows * W;
+    // memory check before any launch
+    size_t free_b = 0, total_b = 0;
+    LP_HIP(hipMemGetInfo(&free_b, &total_b));
+    const double need = 2.0 * (double)total * 8.0 + (double)W * 8.0 + 4096.0;
+    if (need > (double)free_b) {
+        set_error("stable models need " + std::to_string((long long)need) + " bytes of device memory, " +
+                  std::to_string((long long)free_b) + " free");
+        return LP_E_NOMEM;
+    }
+    Scratch S(st);
+    uint64_t *buf[2];
+    uint64_t *acc_d;
+    unsigned long long *counters;
+    lp_status rc;
+    if ((rc = S.get(&buf[0], total)) || (rc = S.get(&buf[1], total)) || (rc = S.get(&acc_d, W)) ||
+        (rc = S.get(&counters, kRing)))
+        return rc;
+    LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
+    LP_HIP(launch_init_m0(buf[0], buf[1], total, log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, keff, st));
+    SpmmParams p{};
+    p.row_ptr = m.dev.full_row_ptr;
+    p.col = m.dev.full_col;
+    p.and_bits = m.dev.full_and_bits;
+    p.counters = counters;
+    p.total = total;
+    p.log2W = log2W;
+    p.early_exit = 1;
+    unsigned long long *h = pinned_ring();
+    if (!h) {
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
+    const int batch = 8;
+    int32_t prods = -1;
+    uint64_t *fix = nullptr;
+    const int64_t limit = (int64_t)m.n_rows + 1;
+    for (int64_t t = 0; prods < 0; t += batch) {
+        for (int i = 1; i <= batch; ++i) {
+            p.step = (int32_t)(t + i);
+            p.V = buf[(p.step - 1) & 1];
+            p.U = buf[p.step & 1];
+            LP_HIP(launch_spmm_step(p, st));
+        }
+        LP_HIP(hipMemcpyAsync(h, counters, sizeof(unsigned long long) * kRing, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        for (int i = 1; i <= batch; ++i) {
+            const int64_t s = t + i;
+            if (h[s & (kRing - 1)] == 0) {
+                prods = (int32_t)s;
+                fix = buf[s & 1];
+                break;
+            }
+        }
+        if (prods < 0 && t + batch > limit) {
+            set_error("fixpoint not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
+    }
+    // Algorithm 3
+    unsigned long long *cnt_d = counters;  // slot 0 is free once the loop is done
+    LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
+    LP_HIP(launch_stable_check(fix, log2W, W, m.dev.q_rows, m.n_std, K, keff, acc_d, cnt_d, st));
+    std::vector<uint64_t> acc_h(W);
+    unsigned long long nm = 0;
+    LP_HIP(hipMemcpyAsync(acc_h.data(), acc_d, W * 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(&nm, cnt_d, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    // accepted guesses in the full guess space (deposit compressed bits)
+    std::memset(accepted, 0, sizeof(uint64_t) * W_full);
+    std::vector<int64_t> cols;
+    for (int64_t w = 0; w < W; ++w) {
+        uint64_t x = acc_h[w];
+        while (x) {
+            const int b = __builtin_ctzll(x);
+            x &= x - 1;
+            const int64_t jc = w * 64 + b;
+            int64_t jf = 0;
+            for (int t = 0; t < K; ++t)
+                if (m.guess_pos[t] >= 0 && ((jc >> m.guess_pos[t]) & 1)) jf |= 1ll << t;
+            accepted[jf >> 6] |= 1ull << (jf & 63);
+            if (models && (int64_t)cols.size() < max_models) cols.push_back(jc);
+        }
+    }
+    *n_models = (int64_t)nm;
+    if (interp && m.n_atoms) {
+        LP_HIP(hipMemcpyAsync(interp, fix, sizeof(uint64_t) * (size_t)m.n_atoms * W, hipMemcpyDeviceToHost, st));
+    }
+    if (models && !cols.empty() && m.n_atoms) {
+        int64_t *cols_d;
+        uint8_t *out_d;
+        const int64_t nb = (int64_t)cols.size() * m.n_atoms;
+        if ((rc = S.get(&cols_d, cols.size())) || (rc = S.get(&out_d, nb))) return rc;
+        LP_HIP(hipMemcpyAsync(cols_d, cols.data(), cols.size() * 8, hipMemcpyHostToDevice, st));
+        LP_HIP(launch_extract(fix, log2W, cols_d, (int64_t)cols.size(), m.n_atoms, out_d, st));
+        LP_HIP(hipMemcpyAsync(models, out_d, nb, hipMemcpyDeviceToHost, st));
+    }
+    LP_HIP(hipStreamSynchronize(st));
+    if (products) *products = prods;
+    if (models && (int64_t)nm > max_models) return LP_E_TRUNCATED;
+    return LP_OK;
+}
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    lp_status init() {
+        LP_HIP(hipEventCreate(&a));
+        LP_HIP(hipEventCreate(&b));
+        return LP_OK;
+    }
+    lp_status elapsed(float *ms) {
+        LP_HIP(hipEventSynchronize(b));
+        LP_HIP(hipEventElapsedTime(ms, a, b));
+        return LP_OK;
+    }
+};
+
+// Buffers for timing steps on a fixed v: the fixpoint (so every launch does
+// the same work) and a destination pre-loaded with it.
+struct StepBench {
+    uint64_t *fix = nullptr, *dst = nullptr;
+    unsigned long long *counters = nullptr;
+    uint32_t *and_cnt = nullptr;
+    int32_t products = 0;
+};
+
+static lp_status step_bench_init(const Matrix &m, const lp_schedule *sched, hipStream_t st, Scratch &S,
+                                 StepBench *B) {
+    lp_status rc = least_fixpoint(m, sched, st, S, &B->fix, &B->products);
+    if (rc) return rc;
+    const int64_t W = n_words_of(m.n_rows);
+    if ((rc = S.get(&B->dst, W)) || (rc = S.get(&B->counters, kRing)) ||
+        (rc = S.get(&B->and_cnt, 2 * (size_t)m.dev.n_long_and)))
+        return rc;
+    LP_HIP(hipMemcpyAsync(B->dst, B->fix, W * 8, hipMemcpyDeviceToDevice, st));
+    LP_HIP(hipMemsetAsync(B->counters, 0, sizeof(unsigned long long) * kRing, st));
+    if (m.dev.n_long_and) LP_HIP(hipMemsetAsync(B->and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
+    return LP_OK;
+}
+
+// Average ms of reps back-to-back full-sweep steps of shape L.
+static lp_status time_steps(const Matrix &m, const StepBench &B, const StepShape &L, StepParams p, int reps,
+                            hipStream_t st, float *avg_ms) {
+    p.counters = B.counters;
+    p.and_cnt = B.and_cnt;
+    p.early_exit = 0;
+    p.v = B.fix;
+    p.u = B.dst;
+    Events ev;
+    lp_status rc = ev.init();
+    if (rc) return rc;
+    LP_HIP(hipEventRecord(ev.a, st));
+    for (int i = 0; i < reps; ++i) {
+        p.step = 2 + (i & 127);
+        LP_HIP(launch_step(L, p, st));
+    }
+    LP_HIP(hipEventRecord(ev.b, st));
+    float total = 0.f;
+    if ((rc = ev.elapsed(&total))) return rc;
+    *avg_ms = reps > 0 ? total / reps : 0.f;
+    return LP_OK;
+}
+
+// Average ms per launch of the persistent kernel, each launch a whole fixpoint.
+static lp_status time_persistent(const Matrix &m, const StepBench &B, const StepShape &L, StepParams p, int reps,
+                                 hipStream_t st, Scratch &S, float *avg_ms) {
+    const int64_t W = n_words_of(m.n_rows);
+    uint64_t *buf[2] = {B.fix, B.dst};
+    int32_t *res;
+    lp_status rc;
+    if ((rc = S.get(&res, 1))) return rc;
+    p.counters = B.counters;
+    p.and_cnt = B.and_cnt;
+    Events ev;
+    if ((rc = ev.init())) return rc;
+    float total = 0.f;
+    for (int i = 0; i < reps; ++i) {
+        LP_HIP(hipMemcpyAsync(buf[0], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipMemcpyAsync(buf[1], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
+        LP_HIP(hipMemsetAsync(B.counters, 0, sizeof(unsigned long long) * kRing, st));
+        if (m.dev.n_long_and) LP_HIP(hipMemsetAsync(B.and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
+        LP_HIP(hipEventRecord(ev.a, st));
+        if ((rc = run_persistent(m, p, L, buf, res, st))) return rc;
+        LP_HIP(hipEventRecord(ev.b, st));
+        float ms = 0;
+        if ((rc = ev.elapsed(&ms))) return rc;
+        total += ms;
+    }
+    *avg_ms = reps > 0 ? total / reps : 0.f;
+    return LP_OK;
+}
+
+static lp_status bench_step_impl(const Matrix &m, const lp_schedule *sched, int32_t reps, float *avg_ms,
+                                 hipStream_t st) {
+    Scratch S(st);
+    StepBench B;
+    lp_status rc = step_bench_init(m, sched, st, S, &B);
+    if (rc) return rc;
+    StepParams p = step_params(m);
+    StepShape L;
+    if (sched && sched->driver == LP_DRIVER_PERSISTENT) {
+        if ((rc = plan_persistent(m, sched, p, &L))) return rc;
+        if (L.grid < 1) {
+            set_error("the persistent step does not fit on this device");
+            return LP_E_DEVICE;
+        }
+        return time_persistent(m, B, L, p, reps, st, S, avg_ms);
+    }
+    if ((rc = plan_step(m, sched, p, &L))) return rc;
+    return time_steps(m, B, L, p, reps, st, avg_ms);
+}
+
+// Autotuner: time every supported step shape (LDS-staged and global
+// gathers; 1/2/4/8 words per wave; 4/8/16 chunks in flight) on the matrix's
+// own fixpoint, then compare whole solves with the batched and persistent
+// drivers at the fastest shape.
+static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, float *best_step_ms,
+                           float *best_solve_ms, hipStream_t st) {
+    Scratch S(st);
+    StepBench B;
+    lp_status rc = step_bench_init(m, nullptr, st, S, &B);
+    if (rc) return rc;
+    lp_schedule cand{};
+    lp_schedule win{};
+    float win_ms = 0.f;
+    bool have = false;
+    const int variants[2] = {LP_STEP_LDS, LP_STEP_GLOBAL};
+    const int wpws[4] = {1, 2, 4, 8};
+    const int unrolls[3] = {4, 8, 16};
+    for (int v : variants)
+        for (int w : wpws)
+            for (int u : unrolls) {
+                cand = lp_schedule{};
+                cand.variant = v;
+                cand.wpw = w;
+                cand.unroll = u;
+                StepParams p = step_params(m);
+                StepShape L;
+                if ((rc = plan_step(m, &cand, p, &L))) return rc;
+                float ms = 0.f;
+                if ((rc = time_steps(m, B, L, p, 2, st, &ms))) return rc;  // warm-up
+                if ((rc = time_steps(m, B, L, p, reps, st, &ms))) return rc;
+                if (!have || ms < win_ms) {
+                    win = cand;
+                    win_ms = ms;
+                    have = true;
+                }
+            }
+    // drivers at the winning shape: whole solves
+    lp_schedule batched = win;
+    batched.driver = LP_DRIVER_BATCHED;
+    batched.steps_per_sync = 64;
+    lp_schedule persistent = win;
+    persistent.driver = LP_DRIVER_PERSISTENT;
+    persistent.variant = LP_STEP_LDS;
+    float t_b = 0.f, t_p = 1e30f;
+    {
+        Events ev;
+        if ((rc = ev.init())) return rc;
+        for (int i = 0; i < 2; ++i) {
+            Scratch S2(st);
+            uint64_t *fx;
+            int32_t pr;
+            LP_HIP(hipEventRecord(ev.a, st));
+            if ((rc = least_fixpoint(m, &batched, st, S2, &fx, &pr))) return rc;
+            LP_HIP(hipEventRecord(ev.b, st));
+            if ((rc = ev.elapsed(&t_b))) return rc;
+        }
+    }
+    {
+        StepParams p = step_params(m);
+        StepShape L;
+        if ((rc = plan_persistent(m, &persistent, p, &L))) return rc;
+        if (L.grid >= 1) {
+            float ms = 0.f;
+            if ((rc = time_persistent(m, B, L, p, 1, st, S, &ms))) return rc;
+            if ((rc = time_persistent(m, B, L, p, 2, st, S, &ms))) return rc;
+            t_p = ms;
+        }
+    }
+    *best = t_p < t_b ? persistent : batched;
+    if (best_step_ms) *best_step_ms = win_ms;
+    if (best_solve_ms) *best_solve_ms = t_p < t_b ? t_p : t_b;
+    return LP_OK;
+}
+
+}  // namespace lp
+
+// ------------------------------------------------------------------ C ABI
+
+using namespace lp;
+
+#define LP_GUARD_BEGIN try {
+#define LP_GUARD_END                                              \
+    }                                                             \
+    catch (const std::bad_alloc &) {                              \
+        set_error("host allocation failed");                      \
+        return LP_E_NOMEM;                                        \
+    }                                                             \
+    catch (...) {                                                 \
+        set_error("unexpected exception");                        \
+        return LP_E_INTERNAL;                                     \
+    }
+
+extern "C" {
+
+lp_status lp_build_matrix(int32_t n_atoms, int32_t n_rules, const int32_t *head, const int64_t *body_ptr,
+                          const int32_t *body_lit, uint32_t flags, void *hip_stream, lp_matrix **out) {
+    LP_GUARD_BEGIN
+    if (!out) {
+        set_error("out must be non-NULL");
+        return LP_E_INVAL;
+    }
+    *out = nullptr;
+    lp_matrix *mx = new lp_matrix();
+    lp_status rc = build_host(n_atoms, n_rules, head, body_ptr, body_lit, flags, &mx->m);
+    if (rc == LP_OK && !(flags & LP_BUILD_HOST_ONLY)) {
+        rc = upload_matrix(mx->m, (hipStream_t)hip_stream);
+        if (rc) free_device(mx->m, (hipStream_t)hip_stream);
+    }
+    if (rc) {
+        delete mx;
+        return rc;
+    }
+    *out = mx;
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_free_matrix(lp_matrix *m) {
+    LP_GUARD_BEGIN
+    if (!m) return LP_OK;
+    if (!(m->m.flags & LP_BUILD_HOST_ONLY)) {
+        DeviceGuard g(m->m.dev.device);
+        (void)hipDeviceSynchronize();
+        free_device(m->m, nullptr);
+    }
+    delete m;
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_matrix_info(const lp_matrix *m, lp_info *out) {
+    if (!m || !out) {
+        set_error("NULL argument");
+        return LP_E_INVAL;
+    }
+    *out = m->m.info;
+    return LP_OK;
+}
+
+lp_status lp_matrix_neg_atoms(const lp_matrix *m, int32_t *out) {
+    if (!m || (!out && m->m.K)) {
+        set_error("NULL argument");
+        return LP_E_INVAL;
+    }
+    if (m->m.K) std::memcpy(out, m->m.neg_atoms.data(), sizeof(int32_t) * m->m.K);
+    return LP_OK;
+}
+
+lp_status lp_matrix_csr(const lp_matrix *m, int32_t *row_ptr, int32_t *col, uint8_t *kind, uint8_t *fact) {
+    if (!m) {
+        set_error("NULL matrix");
+        return LP_E_INVAL;
+    }
+    const Matrix &M = m->m;
+    if (row_ptr) std::memcpy(row_ptr, M.row_ptr.data(), sizeof(int32_t) * M.row_ptr.size());
+    if (col && M.nnz) std::memcpy(col, M.col.data(), sizeof(int32_t) * M.nnz);
+    if (kind && M.n_rows) std::memcpy(kind, M.kind.data(), M.n_rows);
+    if (fact && M.n_rows) std::memcpy(fact, M.fact.data(), M.n_rows);
+    return LP_OK;
+}
+
+static lp_status check_solvable(const lp_matrix *m) {
+    if (!m) {
+        set_error("NULL matrix");
+        return LP_E_INVAL;
+    }
+    if (m->m.flags & LP_BUILD_HOST_ONLY) {
+        set_error("matrix was built with LP_BUILD_HOST_ONLY");
+        return LP_E_HOST_ONLY;
+    }
+    return LP_OK;
+}
+
+lp_status lp_least_model(const lp_matrix *m, uint8_t *model, int32_t *products, const lp_schedule *sched,
+                         void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K) {
+        set_error("the program has negative literals; the least model is defined for definite programs");
+        return LP_E_NEGATION;
+    }
+    if (!model && m->m.n_atoms) {
+        set_error("model must be non-NULL");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return least_model_impl(m->m, model, products, sched, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
+                           int64_t max_models, uint64_t *interp, int32_t *products, void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K > LP_MAX_NEG_ATOMS) {
+        set_error("too many negated atoms: " + std::to_string(m->m.K));
+        return LP_E_TOO_MANY_GUESSES;
+    }
+    if (!accepted || !n_models || max_models < 0) {
+        set_error("accepted and n_models must be non-NULL, max_models >= 0");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return stable_impl(m->m, accepted, n_models, models, max_models, interp, products, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_t *const *models,
+                               int32_t *products, const lp_schedule *sched, void *hip_stream) {
+    LP_GUARD_BEGIN
+    if (count < 0 || (count > 0 && (!ms || !models))) {
+        set_error("bad batch arguments");
+        return LP_E_INVAL;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        int32_t pr = 0;
+        lp_status rc = lp_least_model(ms[i], models[i], &pr, sched, hip_stream);
+        if (rc) return rc;
+        if (products) products[i] = pr;
+    }
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t reps, float *avg_ms,
+                        void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K || !avg_ms || reps < 1) {
+        set_error("lp_bench_step needs a definite program, avg_ms and reps >= 1");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return bench_step_impl(m->m, sched, reps, avg_ms, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_tune_schedule(const lp_matrix *m, int32_t reps, lp_schedule *best, float *best_step_ms,
+                           float *best_solve_ms, void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K || !best || reps < 1) {
+        set_error("lp_tune_schedule needs a definite program, best and reps >= 1");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return tune_impl(m->m, reps, best, best_step_ms, best_solve_ms, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_set_allocator(void *(*alloc)(size_t, void *, void *), void (*release)(void *, void *, void *),
+                           void *ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) {
+        set_error("alloc and release must both be set or both be NULL");
+        return LP_E_INVAL;
+    }
+    g_alloc = alloc;
+    g_release = release;
+    g_alloc_ctx = ctx;
+    return LP_OK;
+}
+
+const char *lp_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

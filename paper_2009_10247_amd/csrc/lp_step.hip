@@ -1,0 +1,441 @@
+// lp_step.hip -- the least-model T_P step u = theta(M v) on gfx950.
+//
+// Interpretations are bit-packed: bit (i & 63) of word (i >> 6) is row i.
+// theta (Definition 5) is evaluated exactly on the row kinds: an AND row fires
+// iff every entry it names is 1 in v, an OR row iff at least one child is.
+//
+// Monotonicity: from the initial vector, v_t is a subset of v_{t+1}. The step
+// ORs its result into the buffer holding v_{t-1} (a subset of the exact
+// result), so several waves may contribute bits of one word with atomicOr, no
+// clearing pass is needed, and fact rows (true in v_0) need no work at all.
+// popcount(u & ~v) counts the new atoms; the fixpoint of Algorithm 1 is the
+// first product whose count is 0.
+//
+// Layout (see WordMeta): per 64-row word the offset of its first AND entry,
+// the index of its first OR row and the row-kind bits; per row an 8-bit AND
+// length. The AND entries of a word's rows are consecutive in col, and those
+// of consecutive words follow each other, so a wave that owns WPW words (a
+// super-block) streams one contiguous stretch of col. OR rows store no
+// entries: the children of an OR row are consecutive new atoms, so the row is
+// the bit range [or_c0[i], or_c0[i+1]) of v.
+//
+// AND rows: the wave streams its stretch of col 64 entries (256 bytes,
+// coalesced) per chunk with U chunks in flight, each lane gathers the v bit of
+// its entry, and a 64-bit ballot per chunk is written to the wave's LDS slots;
+// each row-owner lane then folds the one or two chunks its row overlaps. With
+// LDS staging, the leading words of v (the original atoms, the only atoms AND
+// bodies name) are copied into LDS per workgroup, so the gathers are ds_reads.
+// OR rows are separate items, 64 per wave, one lane per row ORing the words
+// of its bit range. Rows longer than kLongAnd entries or kLongOrBits children
+// are evaluated by segments, one wave per segment.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "lp_kernels.h"
+
+namespace lp {
+
+namespace {
+
+constexpr int kMaxWaves = 16;  // waves of a 1024-thread workgroup
+
+// Pointers into LDS carry the LDS address space so every gather compiles to
+// a ds_read rather than a flat load routed through the texture path.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+
+__device__ inline uint64_t range_mask(int s, int t) {  // bits [s, t), 0 <= s < t <= 64
+    const uint64_t hi = (t >= 64) ? ~0ull : ((1ull << t) - 1ull);
+    return hi & ~((1ull << s) - 1ull);
+}
+
+__device__ inline uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Exclusive prefix sum over the 64 lanes of a wave.
+__device__ inline int32_t wave_exclusive_scan(int32_t x) {
+    const int lane = threadIdx.x & 63;
+    int32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    return incl - x;
+}
+
+// Any bit of v in [c0, c1) set (global loads), for c0 < c1.
+__device__ __forceinline__ bool any_in_range(const uint64_t *v, int64_t c0, int64_t c1) {
+    bool any = false;
+    for (int64_t wd = c0 >> 6; wd <= (c1 - 1) >> 6; ++wd) {
+        const int s = wd == (c0 >> 6) ? (int)(c0 & 63) : 0;
+        const int t = wd == ((c1 - 1) >> 6) ? (int)(((c1 - 1) & 63) + 1) : 64;
+        any |= (v[wd] & range_mask(s, t)) != 0;
+    }
+    return any;
+}
+
+template <bool LDS>
+__device__ __forceinline__ uint64_t vword(const StepParams &p, const lds_u32 *s_v, int64_t word) {
+    if (LDS && word < p.lds_words) return ((const lds_u64 *)s_v)[word];
+    return p.v[word];
+}
+
+// Row data of one super-block (WPW words of 64 rows, one row per lane and
+// word), loaded with vector loads only: scalar loads would share the lgkm
+// counter with the LDS gathers, so every LDS wait would also wait for this
+// prefetch.
+template <int WPW>
+struct SuperBlock {
+    int32_t len[WPW];     // this lane's AND length per word
+    int32_t base[WPW];    // WordMeta::and_base
+    uint64_t andb[WPW];   // block AND rows
+};
+
+template <int WPW>
+__device__ __forceinline__ void load_super_block(const StepParams &p, int64_t sb, int64_t n_words,
+                                                 SuperBlock<WPW> &m) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = sb * WPW;
+#pragma unroll
+    for (int w = 0; w < WPW; ++w) {
+        const int64_t r = (w0 + w) * 64 + lane;
+        m.len[w] = r < p.n_rows ? (int32_t)p.and_len[r] : 0;
+        if (w0 + w < n_words) {
+            const WordMeta wm = p.words[w0 + w];
+            m.base[w] = wm.and_base;
+            m.andb[w] = wm.and_bits;
+        } else {
+            m.base[w] = p.and_end;
+            m.andb[w] = 0;
+        }
+    }
+}
+
+// Block pass over this wave's super-blocks; returns this lane's count of new
+// bits. The next super-block's row data is loaded before the current one's
+// chunks, so both travel in the same memory round trip.
+template <bool LDS, int WPW, int U>
+__device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u32 *s_v, lds_u64 *s_ball) {
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int64_t n_words = ((int64_t)p.n_rows + 63) >> 6;
+    const int64_t n_sb = (n_words + WPW - 1) / WPW;
+    const int64_t stride = (int64_t)gridDim.x * waves;
+    const int32_t lds_bits = LDS ? p.lds_words * 64 : 0;
+    const bool global_gathers = !LDS || p.and_max_col >= lds_bits;
+    const uint32_t *v32 = reinterpret_cast<const uint32_t *>(p.v);
+    uint32_t my_new = 0;
+    int64_t sb = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6);
+    if (sb >= n_sb) return 0;
+    SuperBlock<WPW> cur;
+    load_super_block<WPW>(p, sb, n_words, cur);
+    for (; sb < n_sb; sb += stride) {
+        SuperBlock<WPW> nxt;
+        const bool more = sb + stride < n_sb;
+        if (more) load_super_block<WPW>(p, sb + stride, n_words, nxt);
+        const int64_t w0 = sb * WPW;
+        bool acc[WPW];
+        int32_t st[WPW], en[WPW];
+#pragma unroll
+        for (int w = 0; w < WPW; ++w) {
+            st[w] = cur.base[w] + wave_exclusive_scan(cur.len[w]);
+            en[w] = st[w] + cur.len[w];
+            acc[w] = (cur.andb[w] >> lane) & 1ull;
+        }
+        const int32_t e0 = __builtin_amdgcn_readfirstlane(cur.base[0]);
+        const int32_t e1 = __builtin_amdgcn_readlane(en[WPW - 1], 63);
+        for (int32_t base = e0 & ~63; base < e1; base += 64 * U) {
+            int32_t c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = base + 64 * u + lane;
+                c[u] = (e >= e0 && e < e1) ? p.col[e] : -1;
+            }
+            uint32_t x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = 0;
+            if (global_gathers) {
+                // bodies beyond the staged words: global gathers, all issued before any use
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (c[u] >= lds_bits) x[u] = v32[c[u] >> 5];
+            }
+            if (LDS) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (c[u] >= 0 && c[u] < lds_bits) x[u] = s_v[c[u] >> 5];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool b = c[u] >= 0 && ((x[u] >> (c[u] & 31)) & 1u);
+                const uint64_t B = __ballot(b);
+                if (lane == 0) s_ball[u] = B;
+            }
+            const int32_t lim = base + 64 * U;
+#pragma unroll
+            for (int w = 0; w < WPW; ++w) {
+                const int32_t lo = st[w] > base ? st[w] : base;
+                const int32_t hi = en[w] < lim ? en[w] : lim;
+                for (int32_t y = lo; y < hi;) {  // the chunks of this row inside the round
+                    const int32_t k = (y - base) >> 6;
+                    const int32_t cb = base + 64 * k;
+                    const int32_t t = hi - cb < 64 ? hi - cb : 64;
+                    const uint64_t m = range_mask(y - cb, t);
+                    acc[w] = acc[w] && ((s_ball[k] & m) == m);
+                    y = cb + t;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < WPW; ++w) {
+            if (w0 + w < n_words) {
+                const uint64_t res = __ballot(acc[w]);
+                if (lane == 0 && res) {
+                    atomicOr((unsigned long long *)&p.u[w0 + w], (unsigned long long)res);
+                    my_new += (uint32_t)__popcll(res & ~vword<LDS>(p, s_v, w0 + w));
+                }
+            }
+        }
+        if (more) cur = nxt;
+    }
+    return my_new;
+}
+
+// OR rows that are not long, 64 per wave: lane j takes OR row 64*tile + j,
+// reads its child range from or_c0, ORs the words of v in that range and, if
+// it fires, sets the row's bit. An OR row is evaluated by exactly one lane, so
+// it is new iff its bit is 0 in v.
+template <bool LDS>
+__device__ __forceinline__ uint32_t or_rows(const StepParams &p, const lds_u32 *s_v) {
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int64_t stride = (int64_t)gridDim.x * waves;
+    const int64_t n_tiles = ((int64_t)p.n_or + 63) >> 6;
+    uint32_t my_new = 0;
+    for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile < n_tiles; tile += stride) {
+        const int64_t j = tile * 64 + lane;
+        if (j < p.n_or) {
+            const int32_t row = p.or_row[j];
+            if (row >= 0 && any_in_range(p.v, p.or_c0[j], p.or_c0[j + 1])) {
+                const uint64_t bit = 1ull << (row & 63);
+                atomicOr((unsigned long long *)&p.u[row >> 6], (unsigned long long)bit);
+                if (!(vword<LDS>(p, s_v, row >> 6) & bit)) my_new += 1;
+            }
+        }
+    }
+    return my_new;
+}
+
+// Segments of long rows, one wave each: AND segments stream entries of
+// long_col, OR segments scan a bit range of v.
+template <bool LDS, int U>
+__device__ __forceinline__ uint32_t long_rows(const StepParams &p, const lds_u32 *s_v) {
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int64_t stride = (int64_t)gridDim.x * waves;
+    const int32_t lds_bits = LDS ? p.lds_words * 64 : 0;
+    const uint32_t *v32 = reinterpret_cast<const uint32_t *>(p.v);
+    uint32_t my_new = 0;
+    for (int64_t si = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); si < p.n_segs; si += stride) {
+        const LongSeg sg = p.segs[si];
+        bool any = false, all = true;
+        if (sg.is_and) {
+            for (int32_t i0 = 0; i0 < sg.len; i0 += 64 * U) {
+                int32_t c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t i = i0 + 64 * u + lane;
+                    c[u] = i < sg.len ? p.long_col[sg.begin + i] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (c[u] >= 0) {
+                        const uint32_t x = (LDS && c[u] < lds_bits) ? s_v[c[u] >> 5] : v32[c[u] >> 5];
+                        all &= (x >> (c[u] & 31)) & 1u;
+                    }
+                }
+            }
+        } else {
+            // bits [begin, begin + len): lane l takes words l, l + 64, ... of the range
+            const int64_t b0 = sg.begin, b1 = sg.begin + sg.len;
+            for (int64_t wd = (b0 >> 6) + lane; wd <= (b1 - 1) >> 6; wd += 64) {
+                const int s = wd == (b0 >> 6) ? (int)(b0 & 63) : 0;
+                const int t = wd == ((b1 - 1) >> 6) ? (int)(((b1 - 1) & 63) + 1) : 64;
+                any |= (p.v[wd] & range_mask(s, t)) != 0;
+            }
+        }
+        any = __ballot(any) != 0;
+        all = __ballot(!all) == 0;
+        if (lane == 0) {
+            bool fire;
+            if (!sg.is_and) {
+                fire = any;
+            } else if (sg.nseg == 1) {
+                fire = all;
+            } else {
+                // a split AND row fires when all of its segments were all-true
+                uint32_t *cnt = p.and_cnt + (size_t)(p.step & 1) * p.n_long_and + sg.and_slot;
+                fire = all && atomicAdd(cnt, 1u) == (uint32_t)(sg.nseg - 1);
+                if (sg.seg == 0)  // clear the count the next product will use
+                    p.and_cnt[(size_t)((p.step + 1) & 1) * p.n_long_and + sg.and_slot] = 0;
+            }
+            if (fire) {
+                const uint64_t bit = 1ull << (sg.row & 63);
+                const uint64_t old = atomicOr((unsigned long long *)&p.u[sg.row >> 6], (unsigned long long)bit);
+                if (!(old & bit) && !(vword<LDS>(p, s_v, sg.row >> 6) & bit)) my_new += 1;
+            }
+        }
+    }
+    return my_new;
+}
+
+// Copies the leading lds_words words of v into LDS: 16-byte loads, four in
+// flight per thread before any is stored.
+__device__ __forceinline__ void stage_v(const StepParams &p, lds_u32 *s_v) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) u32x4 lds_u4;
+    lds_u4 *d = (lds_u4 *)s_v;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v);
+    const int32_t n16 = p.lds_words >> 1;
+    const int32_t bd = blockDim.x;
+    for (int32_t i = threadIdx.x; i < n16; i += 4 * bd) {
+        u32x4 x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + k * bd < n16) x[k] = src[i + k * bd];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + k * bd < n16) d[i + k * bd] = x[k];
+    }
+    if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.lds_words - 1];
+}
+
+__device__ __forceinline__ void add_new_bits(uint32_t my_new, uint32_t *s_new, unsigned long long *slot) {
+    my_new = wave_sum(my_new);
+    if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(s_new, my_new);
+    __syncthreads();
+    if (threadIdx.x == 0 && *s_new) atomicAdd(slot, (unsigned long long)*s_new);
+}
+
+}  // namespace
+
+template <bool LDS, int WPW, int U>
+__global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
+    extern __shared__ uint64_t s_dyn[];  // 8-byte aligned
+    lds_u32 *s_v = (lds_u32 *)s_dyn;
+    __shared__ uint64_t s_ball[kMaxWaves * U];
+    __shared__ uint32_t s_new;
+    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * U;
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
+    if (p.early_exit && p.step >= 2 && p.counters[(p.step - 1) & (kRing - 1)] == 0) return;
+    if (threadIdx.x == 0) s_new = 0;
+    if (LDS) stage_v(p, s_v);
+    __syncthreads();
+    // long-row segments first: they are the longest items, so they start early
+    uint32_t my_new = long_rows<LDS, U>(p, s_v);
+    my_new += or_rows<LDS>(p, s_v);
+    my_new += block_rows<LDS, WPW, U>(p, s_v, my_ball);
+    add_new_bits(my_new, &s_new, &p.counters[p.step & (kRing - 1)]);
+}
+
+// The whole Algorithm 1 loop in one cooperative launch. Each product: stage v
+// in LDS, evaluate every row, add the new-bit count, grid-wide barrier (HIP's
+// cooperative-groups grid sync, which also orders the memory the other XCDs
+// wrote), read the count. Every workgroup reads the same count after the
+// barrier, so all leave the loop on the same product; max_steps (a monotone
+// iteration needs at most n_rows + 1 products) guarantees the loop ends.
+template <int WPW, int U>
+__global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistParams q) {
+    extern __shared__ uint64_t s_dyn[];
+    lds_u32 *s_v = (lds_u32 *)s_dyn;
+    __shared__ uint64_t s_ball[kMaxWaves * U];
+    __shared__ uint32_t s_new;
+    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * U;
+    StepParams p = q.p;
+    for (int32_t step = 1;; ++step) {
+        p.step = step;
+        p.v = (step & 1) ? q.buf0 : q.buf1;
+        p.u = (step & 1) ? q.buf1 : q.buf0;
+        unsigned long long *slot = &p.counters[step & (kRing - 1)];
+        if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(step + 1) & (kRing - 1)] = 0;
+        if (threadIdx.x == 0) s_new = 0;
+        stage_v(p, s_v);
+        __syncthreads();
+        uint32_t my_new = long_rows<true, U>(p, s_v);
+        my_new += or_rows<true>(p, s_v);
+        my_new += block_rows<true, WPW, U>(p, s_v, my_ball);
+        add_new_bits(my_new, &s_new, slot);
+        cooperative_groups::this_grid().sync();
+        const unsigned long long changed = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (changed == 0 || step >= q.max_steps) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *q.result = changed == 0 ? step : -1;
+            return;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+#define LP_STEP_SHAPES(X) \
+    X(1, 4) X(1, 8) X(1, 16) X(2, 4) X(2, 8) X(2, 16) X(4, 4) X(4, 8) X(4, 16) X(8, 4) X(8, 8) X(8, 16)
+
+bool step_shape_supported(const StepShape &s) {
+#define LP_X(W, U) \
+    if (s.wpw == W && s.unroll == U) return true;
+    LP_STEP_SHAPES(LP_X)
+#undef LP_X
+    return false;
+}
+
+hipError_t launch_step(const StepShape &s, const StepParams &p, hipStream_t st) {
+#define LP_X(W, U)                                                                                \
+    if (s.wpw == W && s.unroll == U) {                                                            \
+        if (s.lds)                                                                                \
+            hipLaunchKernelGGL((tp_step_kernel<true, W, U>), dim3(s.grid), dim3(s.block), s.lds_bytes, st, p); \
+        else                                                                                      \
+            hipLaunchKernelGGL((tp_step_kernel<false, W, U>), dim3(s.grid), dim3(s.block), 0, st, p); \
+        return hipGetLastError();                                                                 \
+    }
+    LP_STEP_SHAPES(LP_X)
+#undef LP_X
+    return hipErrorInvalidValue;
+}
+
+static const void *persistent_fn(const StepShape &s) {
+#define LP_X(W, U) \
+    if (s.wpw == W && s.unroll == U) return (const void *)tp_fixpoint_persistent_kernel<W, U>;
+    LP_STEP_SHAPES(LP_X)
+#undef LP_X
+    return nullptr;
+}
+
+hipError_t launch_persistent(const StepShape &s, const PersistParams &q, hipStream_t st) {
+    const void *fn = persistent_fn(s);
+    if (!fn) return hipErrorInvalidValue;
+    PersistParams copy = q;
+    void *args[] = {&copy};
+    return hipLaunchCooperativeKernel(fn, dim3(s.grid), dim3(s.block), args, (unsigned int)s.lds_bytes, st);
+}
+
+hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu) {
+    const void *fn = persistent_fn(s);
+    if (!fn) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, s.block, s.lds_bytes);
+}
+
+void step_kernels_allow_lds(int max_dynamic_lds) {
+#define LP_X(W, U)                                                                                      \
+    (void)hipFuncSetAttribute((const void *)tp_step_kernel<true, W, U>,                                 \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds);             \
+    (void)hipFuncSetAttribute((const void *)tp_fixpoint_persistent_kernel<W, U>,                        \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds);
+    LP_STEP_SHAPES(LP_X)
+#undef LP_X
+    (void)hipGetLastError();
+}
+
+}  // namespace lp

@@ -42,7 +42,7 @@ LP_STEP_LDS = 2
 
 EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg_atoms",
            "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_least_model_batch",
-           "lp_bench_step", "lp_set_allocator", "lp_last_error")
+           "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_last_error")
 
 
 class LPError(RuntimeError):
@@ -64,7 +64,8 @@ class lp_info(ctypes.Structure):
 class lp_schedule(ctypes.Structure):
     _fields_ = [("driver", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("wpw", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 _lib = None
@@ -90,6 +91,8 @@ def load():
         "lp_stable_models": [P, P, P, P, i64, P, P, P],
         "lp_least_model_batch": [P, i32, P, P, P, P],
         "lp_bench_step": [P, P, i32, ctypes.POINTER(ctypes.c_float), P],
+        "lp_tune_schedule": [P, i32, ctypes.POINTER(lp_schedule), ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_float), P],
         "lp_set_allocator": [P, P, P],
     }
     for name, args in sig.items():
@@ -120,12 +123,14 @@ def _ptr(a):
     return a.ctypes.data if a is not None and a.size else None
 
 
-def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, variant=LP_STEP_AUTO, grid=0):
+def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, variant=LP_STEP_AUTO, grid=0, wpw=0, unroll=0):
     s = lp_schedule()
     s.driver = driver
     s.steps_per_sync = steps_per_sync
     s.variant = variant
     s.grid = grid
+    s.wpw = wpw
+    s.unroll = unroll
     return s
 
 
@@ -231,6 +236,20 @@ class Matrix:
         _check(load().lp_bench_step(self._h, ctypes.byref(sched) if sched is not None else None,
                                     int(reps), ctypes.byref(ms), _stream(stream)))
         return ms.value
+
+    def tune(self, reps: int = 20, stream=None):
+        """(best lp_schedule, step ms, solve ms) from lp_tune_schedule."""
+        best = lp_schedule()
+        step_ms = ctypes.c_float(0)
+        solve_ms = ctypes.c_float(0)
+        _check(load().lp_tune_schedule(self._h, int(reps), ctypes.byref(best), ctypes.byref(step_ms),
+                                       ctypes.byref(solve_ms), _stream(stream)))
+        return best, step_ms.value, solve_ms.value
+
+
+def schedule_dict(s) -> dict:
+    return {name: (list(getattr(s, name)) if name == "reserved" else getattr(s, name))
+            for name, _ in lp_schedule._fields_ if name != "reserved"}
 
 
 def least_model_batch(mats, sched=None, stream=None):

@@ -44,6 +44,12 @@ SCHEDULES = {
                                           grid=3),
     "persistent": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT),
     "persistent-grid2": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT, grid=2),
+    "persistent-w8-u16": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT, wpw=8, unroll=16),
+    "lds-w1-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=1, unroll=4),
+    "lds-w8-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=8, unroll=16),
+    "global-w1-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=1, unroll=16),
+    "global-w8-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=8, unroll=4,
+                                     grid=5),
     "auto": None,
 }
 
@@ -132,6 +138,24 @@ def test_bench_step_runs():
         # the step leaves the matrix usable and the answer unchanged
         got, prods = m.least_model()
     assert np.array_equal(got, oracle.least_model(p)) and prods == 50
+
+
+def test_tuned_schedule_gives_the_same_model():
+    p = gen.chain_zipf(3, n_atoms=60_000, n_rules=300_000, chain_len=40)
+    want, want_prods, _, _ = oracle.sd_fixpoint(p)
+    with lp.Matrix(p) as m:
+        best, step_ms, solve_ms = m.tune(reps=3)
+        assert step_ms > 0 and solve_ms > 0
+        assert best.driver in (lp.LP_DRIVER_BATCHED, lp.LP_DRIVER_PERSISTENT)
+        got, prods = m.least_model(sched=best)
+    assert np.array_equal(got, want) and prods == want_prods
+
+
+def test_unsupported_shape_is_an_error():
+    with lp.Matrix(gen.definite_uniform(0, 100, 200)) as m:
+        with pytest.raises(lp.LPError) as e:
+            m.least_model(sched=lp.make_schedule(wpw=3))
+        assert e.value.code == lp.LP_E_INVAL
 
 
 def test_concurrent_matrices_do_not_interfere():

@@ -20,6 +20,7 @@ constexpr int32_t kLongAnd = 255;       // longer AND rows go to the segment pas
 constexpr int32_t kLongOrBits = 512;    // longer OR rows go to the segment pass
 constexpr int32_t kSegAnd = 4096;       // entries per AND segment
 constexpr int32_t kSegOrBits = 16384;   // bits per OR segment
+constexpr int32_t kColPad = 64 * 16;    // zero entries after col: chunk loads past the end stay in bounds
 
 struct WordMeta {
     int32_t and_base;    // offset in col of the word's first AND entry

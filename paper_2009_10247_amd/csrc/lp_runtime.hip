@@ -127,6 +127,10 @@ static void free_device(Matrix &m, hipStream_t st) {
     d = DeviceMatrix{};
 }
 
+// AND entries as the kernels read them: the byte of v holding atom c, shifted
+// left by 5, and c's bit offset in that byte in the low bits.
+static inline int32_t encode_entry(int32_t c) { return ((c >> 3) << 5) | (c & 7); }
+
 // Least-model layout (see WordMeta and LongSeg): rows by kind, AND entries of
 // block rows in col, OR rows as child ranges, long rows as segments.
 static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
@@ -165,11 +169,11 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
                     sg.seg = q;
                     segs.push_back(sg);
                 }
-                lcol.insert(lcol.end(), m.col.begin() + s, m.col.begin() + e);
+                for (int32_t j = s; j < e; ++j) lcol.push_back(encode_entry(m.col[j]));
             } else {
                 words[w].and_bits |= bit;
                 and_len[i] = (uint8_t)len;
-                col.insert(col.end(), m.col.begin() + s, m.col.begin() + e);
+                for (int32_t j = s; j < e; ++j) col.push_back(encode_entry(m.col[j]));
             }
             for (int32_t j = s; j < e; ++j) max_col = std::max(max_col, m.col[j]);
         } else {
@@ -207,6 +211,10 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
         }
     }
     d.n_or = n_or;
+    if (max_col >= (1 << 26)) {
+        set_error("least-model layout supports at most 2^26 rows");
+        return LP_E_INVAL;
+    }
     d.and_nnz = (int64_t)col.size();
     d.long_nnz = (int64_t)lcol.size();
     d.n_segs = (int32_t)segs.size();
@@ -214,6 +222,7 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
     d.and_max_col = max_col;
     if (or_c0.empty()) or_c0.push_back(0);
     if (or_row.empty()) or_row.push_back(-1);
+    col.insert(col.end(), kColPad, 0);  // chunk loads of the last rounds read up to 64*U past the end
     lp_status rc;
     if ((rc = upload(&d.words, words.data(), words.size(), st, &d.bytes))) return rc;
     if ((rc = upload(&d.and_len, and_len.data(), and_len.size(), st, &d.bytes))) return rc;

@@ -41,8 +41,14 @@ constexpr int kMaxWaves = 16;  // waves of a 1024-thread workgroup
 
 // Pointers into LDS carry the LDS address space so every gather compiles to
 // a ds_read rather than a flat load routed through the texture path.
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
+
+// AND entries are stored encoded as ((c >> 3) << 5) | (c & 7): one shift gives
+// the byte of v holding atom c, and the low five bits are its bit offset in
+// that byte, which v_bfe_u32 takes as is.
+__device__ __forceinline__ uint32_t entry_byte(int32_t e) { return (uint32_t)e >> 5; }
 
 __device__ inline uint64_t range_mask(int s, int t) {  // bits [s, t), 0 <= s < t <= 64
     const uint64_t hi = (t >= 64) ? ~0ull : ((1ull << t) - 1ull);
@@ -118,6 +124,20 @@ __device__ __forceinline__ void load_super_block(const StepParams &p, int64_t sb
 // Block pass over this wave's super-blocks; returns this lane's count of new
 // bits. The next super-block's row data is loaded before the current one's
 // chunks, so both travel in the same memory round trip.
+//
+// VALU economy (a wave64 VALU instruction takes 4 cycles on a CDNA SIMD, and
+// this loop is issue-bound, not memory-bound, when written naively):
+//  * chunk loads are unconditional, from a wave-uniform base plus the lane
+//    offset (col carries kColPad zero entries after its end), so no per-entry
+//    predicate or address arithmetic;
+//  * a gather is one shift (the byte of v), one byte read and one v_bfe_u32
+//    (see entry_byte);
+//  * entries outside the super-block are gathered like the others (they name
+//    valid atoms) and simply fall outside every row's range;
+//  * the U chunk ballots of a round go to this wave's LDS slots;
+//  * each row reads the 64-bit window of ballot bits starting at its first
+//    entry (a funnel shift of two consecutive ballots) and compares it with a
+//    mask of its length: one step for rows of up to 64 entries in a round.
 template <bool LDS, int WPW, int U>
 __device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u32 *s_v, lds_u64 *s_ball) {
     const int lane = threadIdx.x & 63;
@@ -125,9 +145,10 @@ __device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u3
     const int64_t n_words = ((int64_t)p.n_rows + 63) >> 6;
     const int64_t n_sb = (n_words + WPW - 1) / WPW;
     const int64_t stride = (int64_t)gridDim.x * waves;
-    const int32_t lds_bits = LDS ? p.lds_words * 64 : 0;
-    const bool global_gathers = !LDS || p.and_max_col >= lds_bits;
-    const uint32_t *v32 = reinterpret_cast<const uint32_t *>(p.v);
+    const uint32_t lds_bytes = LDS ? (uint32_t)p.lds_words * 8u : 0u;
+    const bool lds_only = LDS && (int64_t)p.and_max_col < (int64_t)lds_bytes * 8;
+    const lds_u8 *s_v8 = (const lds_u8 *)s_v;
+    const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
     uint32_t my_new = 0;
     int64_t sb = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6);
     if (sb >= n_sb) return 0;
@@ -149,44 +170,42 @@ __device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u3
         const int32_t e0 = __builtin_amdgcn_readfirstlane(cur.base[0]);
         const int32_t e1 = __builtin_amdgcn_readlane(en[WPW - 1], 63);
         for (int32_t base = e0 & ~63; base < e1; base += 64 * U) {
+            const int32_t *cb = p.col + base;
             int32_t c[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t e = base + 64 * u + lane;
-                c[u] = (e >= e0 && e < e1) ? p.col[e] : -1;
-            }
+            for (int u = 0; u < U; ++u) c[u] = cb[64 * u + lane];
             uint32_t x[U];
+            if (lds_only) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) x[u] = 0;
-            if (global_gathers) {
-                // bodies beyond the staged words: global gathers, all issued before any use
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (c[u] >= lds_bits) x[u] = v32[c[u] >> 5];
-            }
-            if (LDS) {
+                for (int u = 0; u < U; ++u) x[u] = s_v8[entry_byte(c[u])];
+            } else {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (c[u] >= 0 && c[u] < lds_bits) x[u] = s_v[c[u] >> 5];
+                    if (!LDS || entry_byte(c[u]) >= lds_bytes) x[u] = v8[entry_byte(c[u])];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (LDS && entry_byte(c[u]) < lds_bytes) x[u] = s_v8[entry_byte(c[u])];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const bool b = c[u] >= 0 && ((x[u] >> (c[u] & 31)) & 1u);
-                const uint64_t B = __ballot(b);
+                const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[u], (uint32_t)c[u], 1u));
                 if (lane == 0) s_ball[u] = B;
             }
             const int32_t lim = base + 64 * U;
 #pragma unroll
             for (int w = 0; w < WPW; ++w) {
-                const int32_t lo = st[w] > base ? st[w] : base;
+                int32_t lo = st[w] > base ? st[w] : base;
                 const int32_t hi = en[w] < lim ? en[w] : lim;
-                for (int32_t y = lo; y < hi;) {  // the chunks of this row inside the round
-                    const int32_t k = (y - base) >> 6;
-                    const int32_t cb = base + 64 * k;
-                    const int32_t t = hi - cb < 64 ? hi - cb : 64;
-                    const uint64_t m = range_mask(y - cb, t);
-                    acc[w] = acc[w] && ((s_ball[k] & m) == m);
-                    y = cb + t;
+                while (lo < hi) {
+                    const int32_t rel = lo - base;
+                    const int32_t k = rel >> 6, off = rel & 63;
+                    const int32_t n = hi - lo < 64 ? hi - lo : 64;
+                    const uint64_t b0 = s_ball[k];
+                    const uint64_t b1 = s_ball[k + 1];  // slot U is always 0
+                    const uint64_t win = off ? ((b0 >> off) | (b1 << (64 - off))) : b0;
+                    const uint64_t m = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+                    acc[w] = acc[w] && ((win & m) == m);
+                    lo += n;
                 }
             }
         }
@@ -237,8 +256,9 @@ __device__ __forceinline__ uint32_t long_rows(const StepParams &p, const lds_u32
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int64_t stride = (int64_t)gridDim.x * waves;
-    const int32_t lds_bits = LDS ? p.lds_words * 64 : 0;
-    const uint32_t *v32 = reinterpret_cast<const uint32_t *>(p.v);
+    const uint32_t lds_bytes = LDS ? (uint32_t)p.lds_words * 8u : 0u;
+    const lds_u8 *s_v8 = (const lds_u8 *)s_v;
+    const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
     uint32_t my_new = 0;
     for (int64_t si = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); si < p.n_segs; si += stride) {
         const LongSeg sg = p.segs[si];
@@ -254,8 +274,9 @@ __device__ __forceinline__ uint32_t long_rows(const StepParams &p, const lds_u32
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (c[u] >= 0) {
-                        const uint32_t x = (LDS && c[u] < lds_bits) ? s_v[c[u] >> 5] : v32[c[u] >> 5];
-                        all &= (x >> (c[u] & 31)) & 1u;
+                        const uint32_t bi = entry_byte(c[u]);
+                        const uint32_t x = (LDS && bi < lds_bytes) ? s_v8[bi] : v8[bi];
+                        all &= __builtin_amdgcn_ubfe(x, (uint32_t)c[u], 1u) != 0;
                     }
                 }
             }
@@ -327,9 +348,10 @@ template <bool LDS, int WPW, int U>
 __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
     extern __shared__ uint64_t s_dyn[];  // 8-byte aligned
     lds_u32 *s_v = (lds_u32 *)s_dyn;
-    __shared__ uint64_t s_ball[kMaxWaves * U];
+    __shared__ uint64_t s_ball[kMaxWaves * (U + 1)];
     __shared__ uint32_t s_new;
-    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * U;
+    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * (U + 1);
+    if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
     if (p.early_exit && p.step >= 2 && p.counters[(p.step - 1) & (kRing - 1)] == 0) return;
     if (threadIdx.x == 0) s_new = 0;
@@ -352,9 +374,10 @@ template <int WPW, int U>
 __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistParams q) {
     extern __shared__ uint64_t s_dyn[];
     lds_u32 *s_v = (lds_u32 *)s_dyn;
-    __shared__ uint64_t s_ball[kMaxWaves * U];
+    __shared__ uint64_t s_ball[kMaxWaves * (U + 1)];
     __shared__ uint32_t s_new;
-    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * U;
+    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * (U + 1);
+    if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
     StepParams p = q.p;
     for (int32_t step = 1;; ++step) {
         p.step = step;

@@ -61,16 +61,18 @@ __device__ inline uint32_t wave_sum(uint32_t x) {
     return x;
 }
 
-// Exclusive prefix sum over the 64 lanes of a wave.
+// Exclusive prefix sum over the 64 lanes of a wave, with DPP: shifts by 1, 2,
+// 4 and 8 inside each row of 16 lanes, then row_bcast:15 and row_bcast:31 carry
+// the row totals into the rows above.
 __device__ inline int32_t wave_exclusive_scan(int32_t x) {
-    const int lane = threadIdx.x & 63;
-    int32_t incl = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
-    return incl - x;
+    int32_t t = x;
+    t += __builtin_amdgcn_update_dpp(0, t, 0x111, 0xf, 0xf, false);  // row_shr:1
+    t += __builtin_amdgcn_update_dpp(0, t, 0x112, 0xf, 0xf, false);  // row_shr:2
+    t += __builtin_amdgcn_update_dpp(0, t, 0x114, 0xf, 0xf, false);  // row_shr:4
+    t += __builtin_amdgcn_update_dpp(0, t, 0x118, 0xf, 0xf, false);  // row_shr:8
+    t += __builtin_amdgcn_update_dpp(0, t, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    t += __builtin_amdgcn_update_dpp(0, t, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return t - x;
 }
 
 // Any bit of v in [c0, c1) set (global loads), for c0 < c1.
@@ -135,9 +137,10 @@ __device__ __forceinline__ void load_super_block(const StepParams &p, int64_t sb
 //  * entries outside the super-block are gathered like the others (they name
 //    valid atoms) and simply fall outside every row's range;
 //  * the U chunk ballots of a round go to this wave's LDS slots;
-//  * each row reads the 64-bit window of ballot bits starting at its first
-//    entry (a funnel shift of two consecutive ballots) and compares it with a
-//    mask of its length: one step for rows of up to 64 entries in a round.
+//  * each row reads the 32-bit window of ballot bits starting at its first
+//    entry (v_alignbit of two consecutive ballot dwords) and compares it with
+//    a mask of its length: one step for rows of up to 32 entries in a round;
+//  * the row-start scan uses DPP, not cross-lane LDS shuffles.
 template <bool LDS, int WPW, int U>
 __device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u32 *s_v, lds_u64 *s_ball) {
     const int lane = threadIdx.x & 63;
@@ -192,18 +195,16 @@ __device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u3
                 if (lane == 0) s_ball[u] = B;
             }
             const int32_t lim = base + 64 * U;
+            const lds_u32 *b32 = (const lds_u32 *)s_ball;  // the round's ballot bits, 32 per word
 #pragma unroll
             for (int w = 0; w < WPW; ++w) {
                 int32_t lo = st[w] > base ? st[w] : base;
                 const int32_t hi = en[w] < lim ? en[w] : lim;
-                while (lo < hi) {
+                while (lo < hi) {  // 32 entries per pass: one pass for rows of up to 32 entries
                     const int32_t rel = lo - base;
-                    const int32_t k = rel >> 6, off = rel & 63;
-                    const int32_t n = hi - lo < 64 ? hi - lo : 64;
-                    const uint64_t b0 = s_ball[k];
-                    const uint64_t b1 = s_ball[k + 1];  // slot U is always 0
-                    const uint64_t win = off ? ((b0 >> off) | (b1 << (64 - off))) : b0;
-                    const uint64_t m = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+                    const int32_t n = hi - lo < 32 ? hi - lo : 32;
+                    const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
+                    const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
                     acc[w] = acc[w] && ((win & m) == m);
                     lo += n;
                 }

@@ -35,9 +35,37 @@ def log(*a):
 
 
 def step_bytes(info: dict) -> int:
-    """Algorithmic bytes of one full-sweep step on the bit-packed layout:
-    row pointers, column indices, the row-kind bits, one read of v and one
-    write of u (bit-packed)."""
+    """Algorithmic bytes of one full-sweep step on the device layout the
+    kernel reads (lp_info.step_bytes): the per-word metadata, the 8-bit AND
+    lengths, the AND column entries, the OR child-range table, the long-row
+    segments, one read of v and one write of u (bit-packed)."""
+    return int(info["step_bytes"])
+
+
+def recorded_traffic(kernel: str, step_bytes_now: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (2 x FETCH_SIZE + WRITE_SIZE, calibrated against a known-size copy), or
+    None when no record matches the current kernel source and layout."""
+    import glob
+    import hashlib
+    import re
+
+    src = os.path.join(ROOT, "paper_2009_10247_amd", "csrc", "lp_step.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            if not line.startswith("traffic-record:"):
+                continue
+            m = re.match(r'traffic-record: kernel="([^"]+)" source_sha1=(\w+) step_bytes=(\d+) .*'
+                         r'bytes_per_launch=(\d+)', line.strip())
+            if m and m.group(1) == kernel and m.group(2) == sha and int(m.group(3)) == step_bytes_now:
+                return int(m.group(4))
+    return None
+
+
+def csr_step_bytes(info: dict) -> int:
+    """The same step on a plain int32 CSR (row pointers, column indices,
+    row-kind bits, v and u bit-packed): what a CSR kernel would move."""
     n, nnz = info["n_rows"], info["nnz"]
     return 4 * (n + 1) + 4 * nnz + 3 * ((n + 7) // 8)
 
@@ -162,10 +190,14 @@ def main() -> int:
                  f"{sched.wpw}, {sched.unroll}>")
     achieved = Bl / (kern_ms / 1e3) / 1e9
     log(f"[bench] {kname}: {kern_ms * 1e3:.2f} us/launch, {Bl / 1e6:.1f} MB -> {achieved:.0f} GB/s")
+    Bc = csr_step_bytes(info) * (products if sched.driver == lp.LP_DRIVER_PERSISTENT else 1)
+    traffic = recorded_traffic(kname, B) if sched.driver != lp.LP_DRIVER_PERSISTENT else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "bytes_per_launch": Bl, "us_per_launch": round(kern_ms * 1e3, 3),
-                "bytes_per_product": B}
+                "bytes_per_product": B,
+                "csr_equivalent": {"bytes_per_launch": Bc,
+                                   "GB/s": round(Bc / (kern_ms / 1e3) / 1e9, 1)}}
 
     stable = None
     if not args.no_stable:

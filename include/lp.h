@@ -90,6 +90,9 @@ typedef struct lp_info {
     int32_t max_row_len;    /* longest row */
     int32_t n_long_rows;    /* rows handled by the split long-row pass */
     int64_t device_bytes;   /* device memory held by the matrix */
+    int64_t step_bytes;     /* bytes one full-sweep step must move on this device layout
+                               (least models: the layout arrays, one read of v, one write
+                               of u; stable models: CSR, one read of V, one write of U) */
     double sparsity;        /* equation 5: 1 - sum_r |body(r)| / N^2 */
 } lp_info;
 
@@ -228,8 +231,9 @@ lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t re
  * Autotuner for least-model solves of m (a definite program). Times every
  * supported step shape (LP_STEP_LDS / LP_STEP_GLOBAL, 1/2/4/8 words per wave,
  * 4/8/16 chunks in flight) over reps full-sweep steps on m's own fixpoint
- * with HIP events, then times whole solves with the batched and persistent
- * drivers at the fastest shape, and writes the fastest schedule to *best.
+ * with HIP events, then times whole solves with the batched driver and, when
+ * the fastest step is shorter than 20 us (where launch overhead matters), the
+ * persistent driver, at the fastest shape; writes the fastest schedule to *best.
  * best_step_ms / best_solve_ms (nullable) receive the winning times. Results
  * of lp_least_model do not depend on the schedule; only the time does.
  */

@@ -256,6 +256,14 @@ static lp_status upload_matrix(Matrix &m, hipStream_t st) {
     }
     LP_HIP(hipStreamSynchronize(st));
     m.info.device_bytes = d.bytes;
+    const int64_t vbytes = (m.n_rows + 7) / 8;
+    if (m.K == 0) {
+        m.info.step_bytes = d.stream_bytes + 2 * vbytes;
+    } else {
+        const int keff = m.K_eff;
+        const int64_t wbytes = ((((int64_t)1 << keff) + 63) / 64) * 8;
+        m.info.step_bytes = 4 * ((int64_t)m.n_rows + 1) + 4 * m.nnz + vbytes + 2 * (int64_t)m.n_rows * wbytes;
+    }
     return LP_OK;
 }
 
@@ -798,7 +806,10 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
             if ((rc = ev.elapsed(&t_b))) return rc;
         }
     }
-    {
+    // The persistent form only pays when a product is short enough for launch
+    // overhead to matter; above ~20 us a back-to-back launch is cheaper than
+    // the grid-wide barrier, so larger matrices skip the trial.
+    if (win_ms < 0.020f) {
         StepParams p = step_params(m);
         StepShape L;
         if ((rc = plan_persistent(m, &persistent, p, &L))) return rc;

@@ -58,7 +58,8 @@ class lp_info(ctypes.Structure):
                 ("n_and_rows", ctypes.c_int32), ("n_or_rows", ctypes.c_int32),
                 ("n_fact_rows", ctypes.c_int32), ("n_empty_rows", ctypes.c_int32),
                 ("max_row_len", ctypes.c_int32), ("n_long_rows", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("sparsity", ctypes.c_double)]
+                ("device_bytes", ctypes.c_int64), ("step_bytes", ctypes.c_int64),
+                ("sparsity", ctypes.c_double)]
 
 
 class lp_schedule(ctypes.Structure):

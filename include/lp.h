@@ -118,7 +118,8 @@ typedef struct lp_schedule {
     int32_t grid;            /* workgroups of the step (0: one per CU for LDS, eight per CU otherwise) */
     int32_t wpw;             /* 64-row words per wave: 1, 2, 4 or 8 (0: default) */
     int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16 (0: default) */
-    int32_t reserved[2];
+    int32_t block;           /* batch kernel: threads per workgroup, 256, 512 or 1024 (0: 512) */
+    int32_t reserved;
 } lp_schedule;
 
 /*
@@ -205,14 +206,84 @@ lp_status lp_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_mo
                            int32_t *products, void *hip_stream);
 
 /*
- * Least models of count definite programs in one persistent launch: each
- * program's fixpoint runs on the device; programs are taken from a device work
- * queue, largest first. models[i]: uint8[n_atoms of ms[i]] host; products:
- * nullable int32[count]. Results equal count separate lp_least_model calls.
- * Errors as lp_least_model, for the first failing program.
+ * Least models of count definite programs (Algorithm 1 for each) in one
+ * persistent launch: lp_batch_create, lp_batch_run, lp_batch_results and
+ * lp_batch_free in one call. models[i]: uint8[n_atoms of ms[i]] host,
+ * non-NULL; products: nullable int32[count]. Results equal count separate
+ * lp_least_model calls. Errors as lp_least_model, for the first failing
+ * program; LP_E_INVAL if the matrices live on different devices.
  */
 lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_t *const *models,
                                int32_t *products, const lp_schedule *sched, void *hip_stream);
+
+/*
+ * Batch plans: the device side of many least-model solves, kept for repeated
+ * runs. Each workgroup of the batch kernel takes programs from a device work
+ * queue (largest first by stored entries) and runs a program's whole
+ * fixpoint by itself, with v_t and v_{t-1} in its LDS; a run is one launch of
+ * a hipGraph captured at creation, with no host round trip and no allocation.
+ * Programs whose two bit-packed buffers exceed the workgroup's LDS (about
+ * 600,000 matrix rows on gfx950) are solved by lp_least_model's drivers, with
+ * sched, inside lp_batch_results.
+ *
+ * The plan holds pointers into the matrices' device layouts: the matrices
+ * must outlive it. Calls on one plan must not overlap (the queue and the
+ * outputs are the plan's own); distinct plans may run concurrently.
+ */
+typedef struct lp_batch lp_batch;
+
+typedef struct lp_batch_info {
+    int32_t count;          /* programs of the plan */
+    int32_t n_resident;     /* programs solved by the batch kernel */
+    int32_t wpw;            /* batch kernel shape: words per wave */
+    int32_t unroll;         /* chunks in flight per wave */
+    int32_t block;          /* threads per workgroup */
+    int32_t grid;           /* workgroups (0: no resident program) */
+    int64_t lds_bytes;      /* dynamic LDS per workgroup: the two buffers of the largest program */
+    int64_t nnz;            /* sum of the programs' stored nonzeros */
+    int64_t step_bytes;     /* sum of the programs' lp_info.step_bytes */
+    float tuned_ms;         /* time per run found by lp_batch_tune, 0 before */
+    int32_t reserved;
+} lp_batch_info;
+
+/*
+ * Plan for ms[0..count) (definite programs on one device). sched (nullable):
+ * wpw, unroll, block and grid select the batch kernel's shape (0: defaults,
+ * grid: as many workgroups as are resident at once, at most count); the whole
+ * schedule is used for the programs solved by the single-program drivers.
+ * Uploads the descriptors on hip_stream and synchronizes it.
+ * Errors: LP_E_NEGATION, LP_E_HOST_ONLY, LP_E_INVAL (NULL matrix, mixed
+ * devices, unsupported shape), LP_E_NOMEM, LP_E_DEVICE.
+ */
+lp_status lp_batch_create(const lp_matrix *const *ms, int32_t count, const lp_schedule *sched, void *hip_stream,
+                          lp_batch **out);
+
+/* Enqueue one run of the batch kernel on hip_stream (asynchronous; one graph
+ * launch, nothing allocated). The results of the last run are read by
+ * lp_batch_results on the same stream. */
+lp_status lp_batch_run(lp_batch *b, void *hip_stream);
+
+/*
+ * Results of the last run (stream-ordered after it): models[i] (nullable
+ * array, nullable entries) uint8[n_atoms of program i] host; products
+ * (nullable) int32[count]. Solves the programs that are not resident first.
+ * Synchronizes hip_stream. LP_E_INTERNAL if a fixpoint was not reached.
+ */
+lp_status lp_batch_results(const lp_batch *b, uint8_t *const *models, int32_t *products, void *hip_stream);
+
+/*
+ * Autotuner of the batch kernel: times every supported shape (words per wave
+ * / chunks in flight 1/8, 2/8, 4/4, 1/16, 2/16; 256, 512 and 1024 threads
+ * per workgroup) over reps runs of the whole batch with HIP events, keeps the
+ * fastest and captures the graph again. best_ms (nullable) receives its time
+ * per run. Results do not depend on the shape.
+ */
+lp_status lp_batch_tune(lp_batch *b, int32_t reps, float *best_ms, void *hip_stream);
+
+lp_status lp_batch_get_info(const lp_batch *b, lp_batch_info *out);
+
+/* Release the plan (NULL is accepted). Waits for the device. */
+lp_status lp_batch_free(lp_batch *b);
 
 /*
  * Average duration in milliseconds of one full-sweep T_P step (theta(M v) on

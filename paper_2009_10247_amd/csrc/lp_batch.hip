@@ -1,0 +1,328 @@
+// lp_batch.hip -- least models of many definite programs in one persistent
+// launch (Algorithm 1 per program).
+//
+// Each workgroup takes programs from a device work queue (an atomic counter
+// over programs sorted by decreasing size, so the longest start first) and
+// runs a program's whole fixpoint by itself: both interpretation buffers of
+// the program live in LDS, every product is evaluated by the workgroup's
+// waves, products are separated by workgroup barriers, and no host round trip
+// or grid-wide barrier is needed. The matrix layout is each program's own
+// least-model layout (see WordMeta); programs whose two bit-packed buffers do
+// not fit in LDS are solved by the single-program drivers instead.
+//
+// The evaluation of one product is the step of lp_step.hip with v and u in
+// LDS: AND rows by super-blocks (coalesced column chunks, byte gathers from
+// LDS, ballots, one window fold per row), OR rows as child bit ranges, long
+// rows by segments. Results are ORed into the buffer holding v_{t-1}
+// (monotone), and the new-bit count decides the loop.
+#include <hip/hip_runtime.h>
+
+#include "lp_dev.h"
+#include "lp_kernels.h"
+
+namespace lp {
+
+namespace {
+
+// Descriptor pointers are loaded from memory, where the compiler cannot tell
+// global from LDS addresses; the copies below carry the global address space
+// so every access compiles to a global load (flat loads would also count
+// against the LDS wait counter and serialize the LDS gathers).
+template <class T>
+using gp = const __attribute__((address_space(1))) T *;
+
+template <class T>
+__device__ __forceinline__ gp<T> as_global(const T *p) {
+    return (gp<T>)p;
+}
+
+struct GProg {
+    gp<WordMeta> words;
+    gp<uint8_t> and_len;
+    gp<int32_t> col;
+    gp<int32_t> or_c0;
+    gp<int32_t> or_row;
+    gp<LongSeg> segs;
+    gp<int32_t> long_col;
+    int32_t n_rows, n_or, n_segs, and_end;
+};
+
+__device__ __forceinline__ bool lds_any_in_range(const lds_u64 *v, int64_t c0, int64_t c1) {
+    bool any = false;
+    for (int64_t wd = c0 >> 6; wd <= (c1 - 1) >> 6; ++wd) {
+        const int s = wd == (c0 >> 6) ? (int)(c0 & 63) : 0;
+        const int t = wd == ((c1 - 1) >> 6) ? (int)(((c1 - 1) & 63) + 1) : 64;
+        any |= (v[wd] & range_mask(s, t)) != 0;
+    }
+    return any;
+}
+
+// Sets bit `row` of u; returns 1 if the row is new (in neither u before nor v).
+__device__ __forceinline__ uint32_t lds_set_bit(lds_u64 *u, const lds_u64 *v, int32_t row) {
+    const uint64_t bit = 1ull << (row & 63);
+    const uint64_t old = __hip_atomic_fetch_or(&u[row >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return (!(old & bit) && !(v[row >> 6] & bit)) ? 1u : 0u;
+}
+
+template <int WPW>
+struct WgSuperBlock {
+    int32_t len[WPW];
+    int32_t base[WPW];
+    uint64_t andb[WPW];
+};
+
+template <int WPW>
+__device__ __forceinline__ void wg_load_super_block(const GProg &d, int64_t sb, int64_t n_words,
+                                                    WgSuperBlock<WPW> &m) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = sb * WPW;
+#pragma unroll
+    for (int w = 0; w < WPW; ++w) {
+        const int64_t r = (w0 + w) * 64 + lane;
+        m.len[w] = r < d.n_rows ? (int32_t)d.and_len[r] : 0;
+        if (w0 + w < n_words) {
+            m.base[w] = d.words[w0 + w].and_base;
+            m.andb[w] = d.words[w0 + w].and_bits;
+        } else {
+            m.base[w] = d.and_end;
+            m.andb[w] = 0;
+        }
+    }
+}
+
+// AND rows of the block pass (see block_rows in lp_step.hip).
+template <int WPW, int U>
+__device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 *v, lds_u64 *u,
+                                                  lds_u64 *s_ball) {
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int64_t n_words = ((int64_t)d.n_rows + 63) >> 6;
+    const int64_t n_sb = (n_words + WPW - 1) / WPW;
+    const lds_u8 *v8 = (const lds_u8 *)v;
+    const lds_u32 *b32 = (const lds_u32 *)s_ball;
+    uint32_t my_new = 0;
+    int64_t sb = threadIdx.x >> 6;
+    if (sb >= n_sb) return 0;
+    WgSuperBlock<WPW> cur;
+    wg_load_super_block<WPW>(d, sb, n_words, cur);
+    for (; sb < n_sb; sb += waves) {
+        WgSuperBlock<WPW> nxt;
+        const bool more = sb + waves < n_sb;
+        if (more) wg_load_super_block<WPW>(d, sb + waves, n_words, nxt);
+        const int64_t w0 = sb * WPW;
+        bool acc[WPW];
+        int32_t st[WPW], en[WPW];
+#pragma unroll
+        for (int w = 0; w < WPW; ++w) {
+            st[w] = cur.base[w] + wave_exclusive_scan(cur.len[w]);
+            en[w] = st[w] + cur.len[w];
+            acc[w] = (cur.andb[w] >> lane) & 1ull;
+        }
+        const int32_t e0 = __builtin_amdgcn_readfirstlane(cur.base[0]);
+        const int32_t e1 = __builtin_amdgcn_readlane(en[WPW - 1], 63);
+        for (int32_t base = e0 & ~63; base < e1; base += 64 * U) {
+            const gp<int32_t> cb = d.col + base;
+            int32_t c[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) c[k] = cb[64 * k + lane];
+            uint32_t x[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) x[k] = v8[entry_byte(c[k])];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[k], (uint32_t)c[k], 1u));
+                if (lane == 0) s_ball[k] = B;
+            }
+            const int32_t lim = base + 64 * U;
+#pragma unroll
+            for (int w = 0; w < WPW; ++w) {
+                int32_t lo = st[w] > base ? st[w] : base;
+                const int32_t hi = en[w] < lim ? en[w] : lim;
+                while (lo < hi) {
+                    const int32_t rel = lo - base;
+                    const int32_t n = hi - lo < 32 ? hi - lo : 32;
+                    const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
+                    const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
+                    acc[w] = acc[w] && ((win & m) == m);
+                    lo += n;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < WPW; ++w) {
+            if (w0 + w < n_words) {
+                const uint64_t res = __ballot(acc[w]);
+                if (lane == 0 && res) {
+                    __hip_atomic_fetch_or(&u[w0 + w], res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    my_new += (uint32_t)__popcll(res & ~v[w0 + w]);
+                }
+            }
+        }
+        if (more) cur = nxt;
+    }
+    return my_new;
+}
+
+// OR rows (one lane each) and long rows (one wave per OR segment, one wave per
+// whole long AND row, looping over its segments).
+__device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const lds_u64 *v, lds_u64 *u) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const lds_u8 *v8 = (const lds_u8 *)v;
+    uint32_t my_new = 0;
+    for (int64_t j = threadIdx.x; j < d.n_or; j += blockDim.x) {
+        const int32_t row = d.or_row[j];
+        if (row >= 0 && lds_any_in_range(v, d.or_c0[j], d.or_c0[j + 1])) my_new += lds_set_bit(u, v, row);
+    }
+    for (int64_t si = wave; si < d.n_segs; si += waves) {
+        const gp<LongSeg> sg = d.segs + si;
+        bool fire = false;
+        if (!sg->is_and) {
+            bool any = false;
+            const int64_t b0 = sg->begin, b1 = sg->begin + sg->len;
+            for (int64_t wd = (b0 >> 6) + lane; wd <= (b1 - 1) >> 6; wd += 64) {
+                const int s = wd == (b0 >> 6) ? (int)(b0 & 63) : 0;
+                const int t = wd == ((b1 - 1) >> 6) ? (int)(((b1 - 1) & 63) + 1) : 64;
+                any |= (v[wd] & range_mask(s, t)) != 0;
+            }
+            fire = __ballot(any) != 0;
+        } else if (sg->seg == 0) {
+            // the whole row: its nseg segments are consecutive in segs and in long_col
+            bool all = true;
+            int64_t total = 0;
+            const int32_t nseg = sg->nseg;
+            const int64_t begin = sg->begin;
+            for (int q = 0; q < nseg; ++q) total += sg[q].len;
+            for (int64_t i = lane; i < total; i += 64) {
+                const int32_t e = d.long_col[begin + i];
+                all &= __builtin_amdgcn_ubfe((uint32_t)v8[entry_byte(e)], (uint32_t)e, 1u) != 0;
+            }
+            fire = __ballot(!all) == 0;
+        }
+        if (fire && lane == 0) my_new += lds_set_bit(u, v, sg->row);
+    }
+    return my_new;
+}
+
+}  // namespace
+
+template <int WPW, int U>
+__global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
+    extern __shared__ uint64_t s_dyn[];
+    __shared__ uint64_t s_ball[kMaxWaves * (U + 1)];
+    // New-bit counts by product index mod 3: the slot of product t+1 is
+    // cleared during product t, after every wave has read it for product t-2,
+    // so one barrier per product suffices.
+    __shared__ uint32_t s_new[3];
+    __shared__ int32_t s_item;
+    lds_u64 *buf0 = (lds_u64 *)s_dyn;
+    lds_u64 *buf1 = buf0 + b.lds_words;
+    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * (U + 1);
+    if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&b.queue[0], 1u);
+        if (threadIdx.x < 3) s_new[threadIdx.x] = 0;
+        __syncthreads();
+        const int32_t item = s_item;
+        if (item >= b.n_progs) break;
+        const ProgDesc pd = b.progs[b.order[item]];
+        GProg d;
+        d.words = as_global(pd.words);
+        d.and_len = as_global(pd.and_len);
+        d.col = as_global(pd.col);
+        d.or_c0 = as_global(pd.or_c0);
+        d.or_row = as_global(pd.or_row);
+        d.segs = as_global(pd.segs);
+        d.long_col = as_global(pd.long_col);
+        d.n_rows = pd.n_rows;
+        d.n_or = pd.n_or;
+        d.n_segs = pd.n_segs;
+        d.and_end = pd.and_end;
+        const gp<uint64_t> fact_bits = as_global(pd.fact_bits);
+        const int32_t n_words = (d.n_rows + 63) >> 6;
+        for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
+            const uint64_t f = fact_bits[i];
+            buf0[i] = f;
+            buf1[i] = f;
+        }
+        __syncthreads();
+        lds_u64 *cur = buf0, *nxt = buf1;  // cur holds v_t, nxt holds v_{t-1}
+        int32_t step = 1, slot = 1;        // slot = step mod 3
+        uint32_t changed = 0;
+        for (;;) {
+            if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
+            uint32_t my_new = wg_or_and_long_rows(d, cur, nxt);
+            my_new += wg_block_rows<WPW, U>(d, cur, nxt, my_ball);
+            my_new = wave_sum(my_new);
+            if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
+            __syncthreads();
+            changed = s_new[slot];
+            if (changed == 0 || step > d.n_rows) break;
+            lds_u64 *t = cur;
+            cur = nxt;
+            nxt = t;
+            ++step;
+            slot = slot == 2 ? 0 : slot + 1;
+        }
+        // nxt holds the last product, equal to cur at the fixpoint
+        typedef __attribute__((address_space(1))) uint64_t g_u64;
+        typedef __attribute__((address_space(1))) int32_t g_i32;
+        g_u64 *out = (g_u64 *)pd.out_bits;
+        const int32_t out_words = (pd.n_atoms + 63) >> 6;
+        for (int32_t i = threadIdx.x; i < out_words; i += blockDim.x) out[i] = nxt[i];
+        if (threadIdx.x == 0) *(g_i32 *)pd.out_products = changed == 0 ? step : -1;
+        __syncthreads();  // the buffers, s_item and s_new are reused by the next program
+    }
+    // The last workgroup to finish rewinds the queue for the next launch.
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&b.queue[1], 1u) == gridDim.x - 1) {
+            atomicExch(&b.queue[0], 0u);
+            atomicExch(&b.queue[1], 0u);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+#define LP_BATCH_SHAPES(X) X(1, 8) X(2, 8) X(4, 4) X(1, 16) X(2, 16)
+
+static const void *batch_fn(int wpw, int unroll) {
+#define LP_X(W, U) \
+    if (wpw == W && unroll == U) return (const void *)tp_batch_kernel<W, U>;
+    LP_BATCH_SHAPES(LP_X)
+#undef LP_X
+    return nullptr;
+}
+
+bool batch_shape_supported(int wpw, int unroll) { return batch_fn(wpw, unroll) != nullptr; }
+
+hipError_t launch_batch(int wpw, int unroll, int grid, int block, size_t lds_bytes, const BatchParams &b,
+                        hipStream_t st) {
+#define LP_X(W, U)                                                                                           \
+    if (wpw == W && unroll == U) {                                                                           \
+        hipLaunchKernelGGL((tp_batch_kernel<W, U>), dim3(grid), dim3(block), lds_bytes, st, b);              \
+        return hipGetLastError();                                                                            \
+    }
+    LP_BATCH_SHAPES(LP_X)
+#undef LP_X
+    return hipErrorInvalidValue;
+}
+
+hipError_t batch_occupancy(int wpw, int unroll, int block, size_t lds_bytes, int *blocks_per_cu) {
+    const void *fn = batch_fn(wpw, unroll);
+    if (!fn) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, lds_bytes);
+}
+
+void batch_kernels_allow_lds(int max_dynamic_lds) {
+#define LP_X(W, U)                                                                                      \
+    (void)hipFuncSetAttribute((const void *)tp_batch_kernel<W, U>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              max_dynamic_lds);
+    LP_BATCH_SHAPES(LP_X)
+#undef LP_X
+    (void)hipGetLastError();
+}
+
+}  // namespace lp

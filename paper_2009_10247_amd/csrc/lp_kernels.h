@@ -1,5 +1,5 @@
 // lp_kernels.h -- kernel parameter blocks and launchers shared by the kernel
-// translation units (lp_step.hip, lp_spmm.hip) and the runtime (lp_runtime.hip).
+// translation units (lp_step.hip, lp_batch.hip, lp_spmm.hip) and the runtime (lp_runtime.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,6 +64,39 @@ hipError_t launch_persistent(const StepShape &s, const PersistParams &q, hipStre
 hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu);
 // Allows every LDS-staged kernel to take up to max_dynamic_lds bytes.
 void step_kernels_allow_lds(int max_dynamic_lds);
+
+// Many least models in one launch: each workgroup runs whole fixpoints of the
+// programs it takes from a device work queue, with both buffers in LDS.
+struct ProgDesc {
+    const WordMeta *words;
+    const uint8_t *and_len;
+    const int32_t *col;
+    const int32_t *or_c0;
+    const int32_t *or_row;
+    const LongSeg *segs;
+    const int32_t *long_col;
+    const uint64_t *fact_bits;
+    uint64_t *out_bits;      // [ceil(n_atoms / 64)] fixpoint restricted to the first words
+    int32_t *out_products;   // products, or -1 if the product bound was exceeded
+    int32_t n_rows;
+    int32_t n_atoms;
+    int32_t n_or;
+    int32_t n_segs;
+    int32_t and_end;
+    int32_t pad;
+};
+struct BatchParams {
+    const ProgDesc *progs;
+    const int32_t *order;    // queue position -> program, largest first
+    unsigned int *queue;     // [0] next position, [1] finished workgroups; zero between launches
+    int32_t n_progs;
+    int32_t lds_words;       // words of each of the two LDS buffers
+};
+bool batch_shape_supported(int wpw, int unroll);
+hipError_t launch_batch(int wpw, int unroll, int grid, int block, size_t lds_bytes, const BatchParams &b,
+                        hipStream_t st);
+hipError_t batch_occupancy(int wpw, int unroll, int block, size_t lds_bytes, int *blocks_per_cu);
+void batch_kernels_allow_lds(int max_dynamic_lds);
 
 // Stable models (interpretation matrix with W = 2^log2W words per row).
 struct SpmmParams {

@@ -299,7 +299,10 @@ static lp_status dev_props(int dev, DevProps *out) {
         DevProps d;
         LP_HIP(hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         LP_HIP(hipDeviceGetAttribute(&d.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        if (d.max_lds > 4096) step_kernels_allow_lds(d.max_lds - 4096);
+        if (d.max_lds > 4096) {
+            step_kernels_allow_lds(d.max_lds - 4096);
+            batch_kernels_allow_lds(d.max_lds - 4096);
+        }
         cache[dev] = d;
     }
     *out = cache[dev];
@@ -826,9 +829,301 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
     return LP_OK;
 }
 
+// ------------------------------------------------------------------ batches
+//
+// A batch plan holds, for many definite programs, one descriptor per program
+// (pointers into the programs' own device layouts), the queue order (largest
+// first), the output words of every program and one hipGraph with the batch
+// kernel. A run is one graph launch; results are read afterwards. Programs
+// whose two LDS buffers exceed the workgroup's LDS are solved by the
+// single-program drivers when the results are read.
+
+struct BatchShape {
+    int wpw = 2;
+    int unroll = 8;
+    int block = 512;
+    int grid = 0;
+    size_t lds_bytes = 0;
+};
+
+struct BatchPlan {
+    int device = -1;
+    std::vector<const Matrix *> ms;
+    std::vector<int32_t> order;      // queue position -> program (resident programs only)
+    std::vector<int32_t> large;      // programs solved by the single-program drivers
+    std::vector<int64_t> out_off;    // first output word of each resident program, -1 otherwise
+    int64_t out_words = 0;
+    int32_t lds_words = 0;
+    ProgDesc *d_progs = nullptr;
+    int32_t *d_order = nullptr;
+    unsigned int *d_queue = nullptr;
+    uint64_t *d_out = nullptr;
+    int32_t *d_prod = nullptr;
+    BatchShape shape;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    lp_schedule sched{};             // schedule of the single-program solves
+    float tuned_ms = 0.f;
+};
+
+static void batch_release(BatchPlan &b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    void *ps[] = {b.d_progs, b.d_order, b.d_queue, b.d_out, b.d_prod};
+    for (void *p : ps) dev_free(p, nullptr);
+    b.d_progs = nullptr;
+    b.d_order = nullptr;
+    b.d_queue = nullptr;
+    b.d_out = nullptr;
+    b.d_prod = nullptr;
+}
+
+static BatchParams batch_params(const BatchPlan &b) {
+    BatchParams q{};
+    q.progs = b.d_progs;
+    q.order = b.d_order;
+    q.queue = b.d_queue;
+    q.n_progs = (int32_t)b.order.size();
+    q.lds_words = b.lds_words;
+    return q;
+}
+
+// Fills in lds_bytes and grid: as many workgroups as fit on the device at
+// once, but no more than there are programs.
+static lp_status batch_fit_shape(const BatchPlan &b, BatchShape *s) {
+    if (!batch_shape_supported(s->wpw, s->unroll) || (s->block != 256 && s->block != 512 && s->block != 1024)) {
+        set_error("unsupported batch shape (wpw/unroll 1/8, 2/8, 4/4, 1/16, 2/16; block 256, 512 or 1024)");
+        return LP_E_INVAL;
+    }
+    DevProps d;
+    lp_status rc = dev_props(b.device, &d);
+    if (rc) return rc;
+    s->lds_bytes = (size_t)b.lds_words * 16;
+    int per_cu = 0;
+    LP_HIP(batch_occupancy(s->wpw, s->unroll, s->block, s->lds_bytes, &per_cu));
+    if (per_cu < 1) {
+        set_error("the batch kernel does not fit on this device");
+        return LP_E_DEVICE;
+    }
+    const int64_t resident = (int64_t)per_cu * d.n_cu;
+    const int64_t want = s->grid > 0 ? s->grid : resident;
+    s->grid = (int)std::max<int64_t>(1, std::min<int64_t>({want, resident, (int64_t)b.order.size()}));
+    return LP_OK;
+}
+
+// Captures the batch kernel into b.exec (on a stream of its own: the legacy
+// default stream cannot be captured).
+static lp_status batch_capture(BatchPlan &b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    if (b.order.empty()) return LP_OK;
+    hipStream_t cs;
+    LP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const BatchShape &s = b.shape;
+        hipError_t el = launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b), cs);
+        e = hipStreamEndCapture(cs, &b.graph);
+        if (e == hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+    return LP_OK;
+}
+
+static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const lp_schedule *sched, hipStream_t st,
+                              BatchPlan &b) {
+    b.ms.resize(count);
+    for (int32_t i = 0; i < count; ++i) {
+        if (!ms[i]) {
+            set_error("NULL matrix at batch position " + std::to_string(i));
+            return LP_E_INVAL;
+        }
+        const Matrix &m = ms[i]->m;
+        if (m.flags & LP_BUILD_HOST_ONLY) {
+            set_error("matrix " + std::to_string(i) + " was built with LP_BUILD_HOST_ONLY");
+            return LP_E_HOST_ONLY;
+        }
+        if (m.K) {
+            set_error("program " + std::to_string(i) + " has negative literals");
+            return LP_E_NEGATION;
+        }
+        if (i == 0) b.device = m.dev.device;
+        else if (m.dev.device != b.device) {
+            set_error("the matrices of a batch must live on one device");
+            return LP_E_INVAL;
+        }
+        b.ms[i] = &m;
+    }
+    if (count == 0) {
+        LP_HIP(hipGetDevice(&b.device));
+    }
+    DevProps d;
+    lp_status rc = dev_props(b.device, &d);
+    if (rc) return rc;
+    // programs whose two buffers fit in the dynamic LDS (the kernel's static
+    // LDS takes at most 4 KiB); largest first by stored entries
+    const int64_t cap_words = std::max<int64_t>(0, (d.max_lds - 4096) / 16);
+    std::vector<int32_t> idx;
+    for (int32_t i = 0; i < count; ++i) {
+        if (n_words_of(b.ms[i]->n_rows) <= cap_words) idx.push_back(i);
+        else b.large.push_back(i);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+        const Matrix &a = *b.ms[x], &c = *b.ms[y];
+        const int64_t wa = a.dev.and_nnz + a.dev.long_nnz + a.n_rows, wc = c.dev.and_nnz + c.dev.long_nnz + c.n_rows;
+        return wa > wc;
+    });
+    b.order = idx;
+    b.out_off.assign(count, -1);
+    std::vector<ProgDesc> desc(count ? count : 1);
+    int64_t off = 0;
+    int32_t maxw = 0;
+    for (int32_t i : idx) {
+        b.out_off[i] = off;
+        off += n_words_of(b.ms[i]->n_atoms);
+        maxw = std::max<int32_t>(maxw, (int32_t)n_words_of(b.ms[i]->n_rows));
+    }
+    b.out_words = off;
+    b.lds_words = maxw;
+    if ((rc = dev_alloc((void **)&b.d_out, (size_t)std::max<int64_t>(1, off) * 8, st))) return rc;
+    if ((rc = dev_alloc((void **)&b.d_prod, sizeof(int32_t) * std::max(1, count), st))) return rc;
+    for (int32_t i : idx) {
+        const Matrix &m = *b.ms[i];
+        const DeviceMatrix &dm = m.dev;
+        ProgDesc &g = desc[i];
+        g.words = dm.words;
+        g.and_len = dm.and_len;
+        g.col = dm.col;
+        g.or_c0 = dm.or_c0;
+        g.or_row = dm.or_row;
+        g.segs = dm.segs;
+        g.long_col = dm.long_col;
+        g.fact_bits = dm.fact_bits;
+        g.out_bits = b.d_out + b.out_off[i];
+        g.out_products = b.d_prod + i;
+        g.n_rows = m.n_rows;
+        g.n_atoms = m.n_atoms;
+        g.n_or = dm.n_or;
+        g.n_segs = dm.n_segs;
+        g.and_end = (int32_t)dm.and_nnz;
+    }
+    int64_t dummy = 0;
+    if ((rc = upload(&b.d_progs, desc.data(), desc.size(), st, &dummy))) return rc;
+    std::vector<int32_t> ord(b.order);
+    if (ord.empty()) ord.push_back(0);
+    if ((rc = upload(&b.d_order, ord.data(), ord.size(), st, &dummy))) return rc;
+    if ((rc = dev_alloc((void **)&b.d_queue, sizeof(unsigned int) * 2, st))) return rc;
+    LP_HIP(hipMemsetAsync(b.d_queue, 0, sizeof(unsigned int) * 2, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if (sched) b.sched = *sched;
+    BatchShape s;
+    if (sched && sched->wpw > 0) s.wpw = sched->wpw;
+    if (sched && sched->unroll > 0) s.unroll = sched->unroll;
+    if (sched && sched->block > 0) s.block = sched->block;
+    if (sched && sched->grid > 0) s.grid = sched->grid;
+    if (!b.order.empty()) {
+        if ((rc = batch_fit_shape(b, &s))) return rc;
+    }
+    b.shape = s;
+    return batch_capture(b);
+}
+
+static lp_status batch_run(const BatchPlan &b, hipStream_t st) {
+    if (b.exec) LP_HIP(hipGraphLaunch(b.exec, st));
+    return LP_OK;
+}
+
+static lp_status batch_results(const BatchPlan &b, uint8_t *const *models, int32_t *products, hipStream_t st) {
+    const int32_t count = (int32_t)b.ms.size();
+    std::vector<uint64_t> hb(std::max<int64_t>(1, b.out_words));
+    std::vector<int32_t> hp(std::max(1, count));
+    if (b.out_words) LP_HIP(hipMemcpyAsync(hb.data(), b.d_out, b.out_words * 8, hipMemcpyDeviceToHost, st));
+    if (count) LP_HIP(hipMemcpyAsync(hp.data(), b.d_prod, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    for (int32_t i : b.order) {
+        if (hp[i] < 1) {
+            set_error("fixpoint of batch program " + std::to_string(i) + " not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
+        if (models && models[i]) unpack_model(hb.data() + b.out_off[i], b.ms[i]->n_atoms, models[i]);
+        if (products) products[i] = hp[i];
+    }
+    for (int32_t i : b.large) {
+        int32_t pr = 0;
+        std::vector<uint8_t> tmp;
+        uint8_t *dst = models ? models[i] : nullptr;
+        if (!dst) {
+            tmp.resize(std::max(1, b.ms[i]->n_atoms));
+            dst = tmp.data();
+        }
+        lp_status rc = least_model_impl(*b.ms[i], dst, &pr, &b.sched, st);
+        if (rc) return rc;
+        if (products) products[i] = pr;
+    }
+    return LP_OK;
+}
+
+// Autotuner of the batch kernel: times every supported shape (words per
+// wave and chunks in flight, 256/512/1024-thread workgroups) over reps
+// launches of the whole batch and keeps the fastest.
+static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStream_t st) {
+    if (b.order.empty()) {
+        if (best_ms) *best_ms = 0.f;
+        return LP_OK;
+    }
+    static const int shapes[][2] = {{1, 8}, {2, 8}, {4, 4}, {1, 16}, {2, 16}};
+    static const int blocks[] = {256, 512, 1024};
+    Events ev;
+    lp_status rc = ev.init();
+    if (rc) return rc;
+    BatchShape win;
+    float win_ms = 0.f;
+    bool have = false;
+    const BatchParams q = batch_params(b);
+    for (const auto &sh : shapes)
+        for (int blk : blocks) {
+            BatchShape s;
+            s.wpw = sh[0];
+            s.unroll = sh[1];
+            s.block = blk;
+            s.grid = 0;
+            if (batch_fit_shape(b, &s)) continue;  // shapes that do not fit are skipped
+            LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, q, st));  // warm-up
+            LP_HIP(hipEventRecord(ev.a, st));
+            for (int r = 0; r < reps; ++r) LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, q, st));
+            LP_HIP(hipEventRecord(ev.b, st));
+            float ms = 0.f;
+            if ((rc = ev.elapsed(&ms))) return rc;
+            ms /= (float)reps;
+            if (!have || ms < win_ms) {
+                win = s;
+                win_ms = ms;
+                have = true;
+            }
+        }
+    if (!have) {
+        set_error("no batch shape fits on this device");
+        return LP_E_DEVICE;
+    }
+    b.shape = win;
+    b.tuned_ms = win_ms;
+    if (best_ms) *best_ms = win_ms;
+    return batch_capture(b);
+}
+
 }  // namespace lp
 
 // ------------------------------------------------------------------ C ABI
+
+struct lp_batch {
+    lp::BatchPlan b;
+};
 
 using namespace lp;
 
@@ -968,12 +1263,118 @@ lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_
         set_error("bad batch arguments");
         return LP_E_INVAL;
     }
-    for (int32_t i = 0; i < count; ++i) {
-        int32_t pr = 0;
-        lp_status rc = lp_least_model(ms[i], models[i], &pr, sched, hip_stream);
-        if (rc) return rc;
-        if (products) products[i] = pr;
+    for (int32_t i = 0; i < count; ++i)
+        if (!models[i]) {
+            set_error("models[" + std::to_string(i) + "] is NULL");
+            return LP_E_INVAL;
+        }
+    if (count == 0) return LP_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    BatchPlan b;
+    lp_status rc = LP_OK;
+    {
+        DeviceGuard g(ms[0] ? ms[0]->m.dev.device : -1);
+        rc = batch_create(ms, count, sched, st, b);
+        if (!rc) rc = batch_run(b, st);
+        if (!rc) rc = batch_results(b, models, products, st);
+        (void)hipStreamSynchronize(st);
+        batch_release(b);
     }
+    return rc;
+    LP_GUARD_END
+}
+
+lp_status lp_batch_create(const lp_matrix *const *ms, int32_t count, const lp_schedule *sched, void *hip_stream,
+                          lp_batch **out) {
+    LP_GUARD_BEGIN
+    if (!out || count < 0 || (count > 0 && !ms)) {
+        set_error("bad batch arguments");
+        return LP_E_INVAL;
+    }
+    *out = nullptr;
+    lp_batch *b = new lp_batch();
+    lp_status rc;
+    {
+        DeviceGuard g(count > 0 && ms[0] ? ms[0]->m.dev.device : -1);
+        rc = batch_create(ms, count, sched, (hipStream_t)hip_stream, b->b);
+        if (rc) batch_release(b->b);
+    }
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_batch_run(lp_batch *b, void *hip_stream) {
+    LP_GUARD_BEGIN
+    if (!b) {
+        set_error("NULL batch");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(b->b.device);
+    return batch_run(b->b, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_batch_results(const lp_batch *b, uint8_t *const *models, int32_t *products, void *hip_stream) {
+    LP_GUARD_BEGIN
+    if (!b) {
+        set_error("NULL batch");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(b->b.device);
+    return batch_results(b->b, models, products, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_batch_tune(lp_batch *b, int32_t reps, float *best_ms, void *hip_stream) {
+    LP_GUARD_BEGIN
+    if (!b || reps < 1) {
+        set_error("lp_batch_tune needs a batch and reps >= 1");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(b->b.device);
+    return batch_tune(b->b, reps, best_ms, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_batch_get_info(const lp_batch *b, lp_batch_info *out) {
+    LP_GUARD_BEGIN
+    if (!b || !out) {
+        set_error("NULL argument");
+        return LP_E_INVAL;
+    }
+    const BatchPlan &p = b->b;
+    lp_batch_info I{};
+    I.count = (int32_t)p.ms.size();
+    I.n_resident = (int32_t)p.order.size();
+    I.wpw = p.shape.wpw;
+    I.unroll = p.shape.unroll;
+    I.block = p.shape.block;
+    I.grid = p.order.empty() ? 0 : p.shape.grid;
+    I.lds_bytes = (int64_t)p.shape.lds_bytes;
+    for (const Matrix *m : p.ms) {
+        I.nnz += m->nnz;
+        I.step_bytes += m->info.step_bytes;
+    }
+    I.tuned_ms = p.tuned_ms;
+    *out = I;
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_batch_free(lp_batch *b) {
+    LP_GUARD_BEGIN
+    if (!b) return LP_OK;
+    {
+        DeviceGuard g(b->b.device);
+        (void)hipDeviceSynchronize();
+        batch_release(b->b);
+    }
+    delete b;
     return LP_OK;
     LP_GUARD_END
 }

@@ -42,6 +42,8 @@ LP_STEP_LDS = 2
 
 EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg_atoms",
            "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_least_model_batch",
+           "lp_batch_create", "lp_batch_run", "lp_batch_results", "lp_batch_tune",
+           "lp_batch_get_info", "lp_batch_free",
            "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_last_error")
 
 
@@ -66,7 +68,16 @@ class lp_schedule(ctypes.Structure):
     _fields_ = [("driver", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("wpw", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lp_batch_info(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n_resident", ctypes.c_int32),
+                ("wpw", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("step_bytes", ctypes.c_int64), ("tuned_ms", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -91,6 +102,12 @@ def load():
         "lp_least_model": [P, P, P, P, P],
         "lp_stable_models": [P, P, P, P, i64, P, P, P],
         "lp_least_model_batch": [P, i32, P, P, P, P],
+        "lp_batch_create": [P, i32, P, P, ctypes.POINTER(P)],
+        "lp_batch_run": [P, P],
+        "lp_batch_results": [P, P, P, P],
+        "lp_batch_tune": [P, i32, ctypes.POINTER(ctypes.c_float), P],
+        "lp_batch_get_info": [P, ctypes.POINTER(lp_batch_info)],
+        "lp_batch_free": [P],
         "lp_bench_step": [P, P, i32, ctypes.POINTER(ctypes.c_float), P],
         "lp_tune_schedule": [P, i32, ctypes.POINTER(lp_schedule), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float), P],
@@ -124,8 +141,10 @@ def _ptr(a):
     return a.ctypes.data if a is not None and a.size else None
 
 
-def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, variant=LP_STEP_AUTO, grid=0, wpw=0, unroll=0):
+def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, variant=LP_STEP_AUTO, grid=0, wpw=0, unroll=0,
+                  block=0):
     s = lp_schedule()
+    s.block = block
     s.driver = driver
     s.steps_per_sync = steps_per_sync
     s.variant = variant
@@ -249,8 +268,7 @@ class Matrix:
 
 
 def schedule_dict(s) -> dict:
-    return {name: (list(getattr(s, name)) if name == "reserved" else getattr(s, name))
-            for name, _ in lp_schedule._fields_ if name != "reserved"}
+    return {name: getattr(s, name) for name, _ in lp_schedule._fields_ if name != "reserved"}
 
 
 def least_model_batch(mats, sched=None, stream=None):
@@ -264,6 +282,59 @@ def least_model_batch(mats, sched=None, stream=None):
                                        ctypes.byref(sched) if sched is not None else None,
                                        _stream(stream)))
     return [(outs[i][: mats[i].n_atoms], int(prods[i])) for i in range(n)]
+
+
+class Batch:
+    """Batch plan (lp_batch_create) over a list of Matrix; the matrices must
+    outlive it. run() enqueues one graph launch; results() reads the last run."""
+
+    def __init__(self, mats, sched=None, stream=None):
+        self.mats = list(mats)
+        n = len(self.mats)
+        hs = (ctypes.c_void_p * max(n, 1))(*[m.handle.value for m in self.mats])
+        h = ctypes.c_void_p()
+        _check(load().lp_batch_create(hs, n, ctypes.byref(sched) if sched is not None else None,
+                                      _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            load().lp_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, stream=None):
+        _check(load().lp_batch_run(self._h, _stream(stream)))
+
+    def results(self, stream=None):
+        """[(model uint8[n_atoms], products)] of the last run."""
+        n = len(self.mats)
+        outs = [np.zeros(max(m.n_atoms, 1), dtype=np.uint8) for m in self.mats]
+        ptrs = (ctypes.c_void_p * max(n, 1))(*[o.ctypes.data for o in outs])
+        prods = np.zeros(max(n, 1), dtype=np.int32)
+        _check(load().lp_batch_results(self._h, ptrs, prods.ctypes.data, _stream(stream)))
+        return [(outs[i][: self.mats[i].n_atoms], int(prods[i])) for i in range(n)]
+
+    def tune(self, reps: int = 3, stream=None) -> float:
+        ms = ctypes.c_float(0)
+        _check(load().lp_batch_tune(self._h, int(reps), ctypes.byref(ms), _stream(stream)))
+        return ms.value
+
+    def info(self) -> dict:
+        inf = lp_batch_info()
+        _check(load().lp_batch_get_info(self._h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in lp_batch_info._fields_ if name != "reserved"}
 
 
 def unpack_column(interp: np.ndarray, j: int) -> np.ndarray:

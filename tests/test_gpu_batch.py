@@ -1,0 +1,179 @@
+"""Parity of the batched least-model kernel (many programs in one launch,
+each workgroup running whole fixpoints from a device work queue) with the CPU
+oracle, through the C-ABI. Models and product counts must match exactly, for
+every shape, on graph replays and whatever the batch composition."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_10247_amd import gen, lp
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 8), (2, 8), (4, 4), (1, 16), (2, 16)]
+
+
+def _want(progs):
+    return [oracle.sd_fixpoint(p)[:2] for p in progs]
+
+
+def _assert_equal(got, want, tag=""):
+    assert len(got) == len(want)
+    for i, ((g, pr), (w, wp)) in enumerate(zip(got, want)):
+        assert np.array_equal(g, w), (tag, i)
+        assert pr == wp, (tag, i, pr, wp)
+
+
+def _edge_programs():
+    rng = np.random.default_rng(3)
+    out = [
+        gen.from_rules(0, []),                                   # no atoms
+        gen.from_rules(1, []),                                   # one atom, no rule
+        gen.from_rules(1, [(0, [])]),                            # one fact
+        gen.from_rules(5, [(a, []) for a in range(5)]),          # facts only
+        gen.from_rules(64, [(0, [])] + [(i, [i - 1]) for i in range(1, 64)]),   # chain over one word
+        gen.from_rules(65, [(0, [])] + [(i, [i - 1]) for i in range(1, 65)]),   # ragged last word
+        gen.from_rules(300, [(i, [i - 1]) for i in range(1, 300)]),             # no facts: empty model
+    ]
+    # long OR and AND rows (segment pass): one head with 10,000 rules, a
+    # 9,000-atom body that fires and one that does not
+    n = 20_000
+    rules = [(a, []) for a in range(0, 12_000)]
+    rules += [(19_000, [int(x)]) for x in rng.integers(12_000, 18_000, size=10_000)]
+    rules += [(19_001, list(range(0, 9_000)))]
+    rules += [(19_002, list(range(1, 9_000)) + [19_500])]
+    rules += [(int(h), [int(b)]) for h, b in zip(rng.integers(12_000, 18_000, 3000), rng.integers(0, 12_000, 3000))]
+    rules += [(19_003, [19_001, 19_000])]
+    out.append(gen.from_rules(n, rules))
+    return out
+
+
+def test_batch_config_512_programs_vs_oracle():
+    # 512 programs, atoms log-uniform in 1e3..1e5, 2x rules, bodies 1..6, 2% facts
+    progs = gen.batch_programs(0, 512)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        with lp.Batch(mats) as b:
+            info = b.info()
+            assert info["count"] == 512 and info["n_resident"] == 512
+            b.run()
+            _assert_equal(b.results(), want, "default")
+            b.tune(reps=1)
+            b.run()
+            _assert_equal(b.results(), want, "tuned")
+        _assert_equal(lp.least_model_batch(mats), want, "one call")
+    finally:
+        for m in mats:
+            m.close()
+
+
+@pytest.mark.parametrize("wpw,unroll", SHAPES)
+@pytest.mark.parametrize("block", [256, 1024])
+def test_batch_shapes(wpw, unroll, block):
+    progs = gen.batch_programs(5, count=40, lo=50, hi=20_000) + _edge_programs()
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        sched = lp.make_schedule(wpw=wpw, unroll=unroll, block=block)
+        _assert_equal(lp.least_model_batch(mats, sched=sched), want, (wpw, unroll, block))
+    finally:
+        for m in mats:
+            m.close()
+
+
+@pytest.mark.parametrize("grid", [1, 3])
+def test_batch_few_workgroups_take_many_programs(grid):
+    progs = gen.batch_programs(9, count=30, lo=20, hi=3000) + _edge_programs()
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        sched = lp.make_schedule(grid=grid)
+        with lp.Batch(mats, sched=sched) as b:
+            assert b.info()["grid"] == grid
+            b.run()
+            _assert_equal(b.results(), want, grid)
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_batch_graph_replays_with_work_between():
+    progs = gen.batch_programs(21, count=64, lo=100, hi=30_000)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    other = gen.definite_uniform(99, 5000, 12_000, 0.02, 5)
+    try:
+        with lp.Batch(mats) as b, lp.Matrix(other) as mo:
+            w_other = oracle.sd_fixpoint(other)[:2]
+            for rep in range(3):
+                b.run()
+                _assert_equal(b.results(), want, rep)
+                g, pr = mo.least_model()  # eager work between replays
+                assert np.array_equal(g, w_other[0]) and pr == w_other[1]
+            for rep in range(3):  # back-to-back replays, one read
+                b.run()
+            _assert_equal(b.results(), want, "back-to-back")
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_batch_results_independent_of_composition():
+    progs = gen.batch_programs(33, count=48, lo=100, hi=50_000)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        alone = [lp.least_model_batch([m])[0] for m in mats]
+        _assert_equal(alone, want, "alone")
+        mixed = lp.least_model_batch(mats)
+        _assert_equal(mixed, want, "mixed")
+        perm = np.random.default_rng(1).permutation(len(mats))
+        shuffled = lp.least_model_batch([mats[i] for i in perm])
+        _assert_equal(shuffled, [want[i] for i in perm], "shuffled")
+        single = [m.least_model() for m in mats]
+        _assert_equal(single, want, "single-program driver")
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_batch_program_larger_than_lds_uses_single_driver():
+    # ~820k matrix rows: two bit-packed buffers exceed a workgroup's LDS
+    big = gen.definite_uniform(4, 300_000, 600_000, 0.02, 4)
+    progs = [gen.definite_uniform(5, 2000, 4000, 0.02, 4), big, gen.definite_uniform(6, 3000, 6000, 0.02, 4)]
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        with lp.Batch(mats) as b:
+            assert b.info()["n_resident"] == 2
+            b.run()
+            _assert_equal(b.results(), want)
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_batch_rejects_negation_and_accepts_empty():
+    pos = gen.definite_uniform(1, 100, 200, 0.05, 3)
+    negp = gen.from_rules(2, [(0, [gen.neg(1)])])
+    with lp.Matrix(pos) as a, lp.Matrix(negp) as b:
+        with pytest.raises(lp.LPError) as e:
+            lp.least_model_batch([a, b])
+        assert e.value.code == lp.LP_E_NEGATION
+    assert lp.least_model_batch([]) == []
+    with lp.Batch([]) as b:
+        b.run()
+        assert b.results() == []
+        assert b.info()["n_resident"] == 0
+
+
+def test_batch_unsupported_shape_rejected():
+    p = gen.definite_uniform(1, 100, 200, 0.05, 3)
+    with lp.Matrix(p) as m:
+        with pytest.raises(lp.LPError) as e:
+            lp.least_model_batch([m], sched=lp.make_schedule(wpw=8, unroll=16))
+        assert e.value.code == lp.LP_E_INVAL
+        with pytest.raises(lp.LPError) as e:
+            lp.least_model_batch([m], sched=lp.make_schedule(block=128))
+        assert e.value.code == lp.LP_E_INVAL

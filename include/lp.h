@@ -57,7 +57,8 @@ enum {
     LP_E_TOO_MANY_GUESSES = -5, /* more than LP_MAX_NEG_ATOMS negated atoms */
     LP_E_TRUNCATED = -6,        /* more stable models than max_models (outputs still valid) */
     LP_E_INTERNAL = -7,         /* an invariant of the fixpoint failed (should not happen) */
-    LP_E_HOST_ONLY = -8         /* solve on a matrix built with LP_BUILD_HOST_ONLY */
+    LP_E_HOST_ONLY = -8,        /* solve on a matrix built with LP_BUILD_HOST_ONLY */
+    LP_E_TIMEOUT = -9           /* lp_server_wait_any: nothing completed in time */
 };
 
 #define LP_MAX_NEG_ATOMS 24
@@ -152,6 +153,18 @@ lp_status lp_build_matrix(int32_t n_atoms, int32_t n_rules, const int32_t *head,
 
 /* Release every host and device resource of m (NULL is accepted). */
 lp_status lp_free_matrix(lp_matrix *m);
+
+/*
+ * Resident-matrix management. lp_matrix_evict releases m's device copy and
+ * keeps the host CSR: m then behaves as if built with LP_BUILD_HOST_ONLY
+ * (solves return LP_E_HOST_ONLY, lp_info.device_bytes = 0). The caller
+ * guarantees that no solve or batch plan on m is in flight. lp_matrix_upload
+ * builds the device copy again from the host CSR on hip_stream (synchronized
+ * before it returns); on a matrix that is already on the device it does
+ * nothing. Results after a round trip are those of a fresh build.
+ */
+lp_status lp_matrix_evict(lp_matrix *m);
+lp_status lp_matrix_upload(lp_matrix *m, void *hip_stream);
 
 /* Sizes and statistics of m. */
 lp_status lp_matrix_info(const lp_matrix *m, lp_info *out);
@@ -315,10 +328,108 @@ lp_status lp_tune_schedule(const lp_matrix *m, int32_t reps, lp_schedule *best, 
  * Route the library's device allocations through caller-supplied functions
  * (e.g. a framework's caching allocator). alloc(bytes, stream, ctx) returns a
  * device pointer or NULL; release(ptr, stream, ctx) frees it. Passing NULL for
- * both restores hipMalloc/hipFree. Not thread-safe with concurrent solves.
+ * both restores the library's own pool. Not thread-safe with concurrent
+ * solves; LP_E_INVAL while blocks of the library's pool are in use.
  */
 lp_status lp_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
                            void (*release)(void *ptr, void *stream, void *ctx), void *ctx);
+
+/*
+ * Serving: a request loop over registered programs. Requests are least-model
+ * queries (programs without negation) or stable-model queries (programs with
+ * K > 0 negated atoms; the accepted mask over all 2^K guesses, the number of
+ * models and the first model in guess order). n_slots worker threads, each
+ * with a HIP stream of its own, take work as soon as they are free:
+ *   - admission by device memory: a request starts only when its matrix (if
+ *     not resident) and its solve buffers fit in hbm_budget; idle resident
+ *     matrices are evicted least recently used first to make room, and a
+ *     request that does not fit waits while later ones that fit go ahead;
+ *   - matrices stay resident between requests;
+ *   - continuous batching: a free slot takes every waiting least-model
+ *     request of a matrix with at most batch_rows rows (and within the batch
+ *     kernel's LDS), up to batch_max, and solves them in one batch launch;
+ *     other requests run alone. Work of different slots overlaps on the device.
+ * Results equal those of lp_least_model / lp_stable_models on the program.
+ */
+typedef struct lp_server lp_server;
+
+typedef struct lp_server_config {
+    int32_t n_slots;      /* worker threads / streams (0: 8; at most 64) */
+    int32_t batch_max;    /* least-model requests per batch launch (0: 64; 1: no batching) */
+    int32_t batch_rows;   /* largest matrix (rows) taken into batches (0: 65536) */
+    int32_t device;       /* HIP device (-1 or 0..: -1 means the current device) */
+    int64_t hbm_budget;   /* device bytes for resident matrices and running solves
+                             (0: 90% of the free memory at creation) */
+    int64_t reserved;
+} lp_server_config;
+
+typedef struct lp_request_info {
+    int64_t request_id;
+    int32_t program_id;
+    int32_t kind;         /* 0: least model, 1: stable models */
+    lp_status status;     /* the solve's status (LP_OK on success) */
+    int32_t products;     /* fixpoint products */
+    int64_t n_models;     /* 1 for a least model; the number of stable models */
+    int32_t batch_size;   /* requests solved by the same launch (1: alone) */
+    int32_t built;        /* 1 if the matrix was uploaded for this request */
+    int64_t nnz;          /* stored nonzeros of the program matrix */
+    double t_submit;      /* seconds on the server's steady clock: submitted, */
+    double t_start;       /*   taken by a slot, */
+    double t_done;        /*   result in host memory */
+} lp_request_info;
+
+typedef struct lp_server_stats {
+    int32_t n_programs;
+    int32_t n_resident;
+    int64_t pending;
+    int64_t completed;
+    int64_t batches;            /* batch launches */
+    int64_t batched_requests;   /* requests solved in them */
+    int64_t alone_requests;
+    int64_t uploads;            /* matrix uploads (first use and after eviction) */
+    int64_t evictions;
+    int64_t used_bytes;         /* accounted device bytes now */
+    int64_t peak_used_bytes;
+    int64_t hbm_budget;
+} lp_server_stats;
+
+/* cfg nullable (defaults). Errors: LP_E_INVAL, LP_E_DEVICE. */
+lp_status lp_server_create(const lp_server_config *cfg, lp_server **out);
+
+/* Register a program (arrays as for lp_build_matrix, copied; the host matrix
+ * is built now, the device copy on first use). Errors: as lp_build_matrix,
+ * LP_E_TOO_MANY_GUESSES, LP_E_NOMEM if it can never fit in the budget. */
+lp_status lp_server_add_program(lp_server *s, int32_t n_atoms, int32_t n_rules, const int32_t *head,
+                                const int64_t *body_ptr, const int32_t *body_lit, int32_t *program_id);
+
+/* Queue a request on a registered program (thread-safe, returns at once). */
+lp_status lp_server_submit(lp_server *s, int32_t program_id, int64_t *request_id);
+
+/* Wait up to timeout_ms for a completed request not yet reported and
+ * describe it; LP_E_TIMEOUT if none completed in time. Each completed
+ * request is reported once, in completion order. */
+lp_status lp_server_wait_any(lp_server *s, int32_t timeout_ms, lp_request_info *out);
+
+/* Copy a completed request's result and forget it. model (nullable):
+ * uint8[n_atoms], the least model or the first stable model (zeros if none);
+ * accepted (nullable, stable only): uint64[ceil(2^K/64)]. */
+lp_status lp_server_take_result(lp_server *s, int64_t request_id, uint8_t *model, uint64_t *accepted);
+
+lp_status lp_server_get_stats(lp_server *s, lp_server_stats *out);
+
+/* Stop the workers after their current work (queued requests are dropped),
+ * release every resident matrix and the streams. */
+lp_status lp_server_free(lp_server *s);
+
+/*
+ * The library's own device allocations go through a caching pool: hipFree
+ * waits for the whole device, so blocks released by a finished call are kept
+ * for reuse instead (sizes rounded up by at most 12.5%). in_use / cached
+ * (nullable) receive the bytes held by live objects and by the cache, over all
+ * devices. lp_release_cached_memory returns the cached blocks to the driver.
+ */
+lp_status lp_memory_stats(int64_t *in_use, int64_t *cached);
+lp_status lp_release_cached_memory(void);
 
 /* Message of the calling thread's last failing call ("" if none). */
 const char *lp_last_error(void);

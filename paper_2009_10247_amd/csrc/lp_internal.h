@@ -86,6 +86,10 @@ lp_status build_host(int32_t n_atoms, int32_t n_rules, const int32_t *head, cons
 
 void set_error(const std::string &msg);
 
+// Largest matrix (rows) whose two bit-packed buffers fit in the batch
+// kernel's LDS on `device` (0 if the device cannot be queried).
+int64_t batch_max_rows(int device);
+
 }  // namespace lp
 
 struct lp_matrix {

@@ -13,8 +13,10 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "lp_kernels.h"
@@ -41,6 +43,60 @@ static lp_status hip_fail(hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
+// Caching pool behind the default allocation path. hipFree waits for the
+// whole device, which would serialize solves running concurrently on other
+// streams, so released blocks are kept for reuse. A block is handed back only
+// once its last use has completed (Scratch synchronizes its stream first; a
+// matrix or batch plan is released after its work is done), so a cached block
+// may go to any stream. Sizes are rounded up to one of eight classes per
+// power of two (at most 12.5% slack).
+struct DevicePool {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void *>> free_blocks;  // (device, class) -> blocks
+    std::unordered_map<void *, std::pair<int, size_t>> live;            // block -> (device, class)
+    int64_t in_use = 0;
+    int64_t cached = 0;
+};
+
+static DevicePool &pool() {
+    static DevicePool *p = new DevicePool();  // never destroyed: blocks may be released at exit
+    return *p;
+}
+
+static size_t size_class(size_t b) {
+    if (b <= 4096) return (b + 255) & ~(size_t)255;
+    int k = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t step = (size_t)1 << (k - 3);
+    return (b + step - 1) & ~(step - 1);
+}
+
+// Frees every cached block of `device` (-1: all devices).
+static void pool_trim(int device) {
+    DevicePool &P = pool();
+    std::vector<std::pair<int, void *>> victims;
+    {
+        std::lock_guard<std::mutex> lock(P.mu);
+        for (auto it = P.free_blocks.begin(); it != P.free_blocks.end();) {
+            if (device < 0 || it->first.first == device) {
+                for (void *q : it->second) {
+                    victims.emplace_back(it->first.first, q);
+                    P.cached -= (int64_t)it->first.second;
+                }
+                it = P.free_blocks.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    for (auto &v : victims) {
+        (void)hipSetDevice(v.first);
+        (void)hipFree(v.second);
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
+
 static lp_status dev_alloc(void **p, size_t bytes, hipStream_t st) {
     *p = nullptr;
     if (bytes == 0) bytes = 8;
@@ -52,20 +108,55 @@ static lp_status dev_alloc(void **p, size_t bytes, hipStream_t st) {
         }
         return LP_OK;
     }
-    hipError_t e = hipMalloc(p, bytes);
+    int dev = 0;
+    LP_HIP(hipGetDevice(&dev));
+    const size_t cls = size_class(bytes);
+    DevicePool &P = pool();
+    {
+        std::lock_guard<std::mutex> lock(P.mu);
+        auto it = P.free_blocks.find({dev, cls});
+        if (it != P.free_blocks.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            P.cached -= (int64_t)cls;
+            P.in_use += (int64_t)cls;
+            P.live[*p] = {dev, cls};
+            return LP_OK;
+        }
+    }
+    hipError_t e = hipMalloc(p, cls);
     if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
+        pool_trim(dev);
+        e = hipMalloc(p, cls);
+    }
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        *p = nullptr;
         set_error("hipMalloc of " + std::to_string(bytes) + " bytes: out of memory");
         return LP_E_NOMEM;
     }
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    std::lock_guard<std::mutex> lock(P.mu);
+    P.in_use += (int64_t)cls;
+    P.live[*p] = {dev, cls};
     return LP_OK;
 }
 
 static void dev_free(void *p, hipStream_t st) {
     if (!p) return;
-    if (g_release) g_release(p, (void *)st, g_alloc_ctx);
-    else (void)hipFree(p);
+    if (g_release) {
+        g_release(p, (void *)st, g_alloc_ctx);
+        return;
+    }
+    DevicePool &P = pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    auto it = P.live.find(p);
+    if (it == P.live.end()) return;  // not a pool block: nothing to do
+    P.free_blocks[it->second].push_back(p);
+    P.in_use -= (int64_t)it->second.second;
+    P.cached += (int64_t)it->second.second;
+    P.live.erase(it);
 }
 
 // RAII list of device buffers of one call.
@@ -540,10 +631,16 @@ static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_mod
     // memory check before any launch
     size_t free_b = 0, total_b = 0;
     LP_HIP(hipMemGetInfo(&free_b, &total_b));
+    double avail = (double)free_b;
+    {
+        DevicePool &P = pool();
+        std::lock_guard<std::mutex> lock(P.mu);
+        avail += (double)P.cached;  // cached blocks are reused or trimmed before an allocation fails
+    }
     const double need = 2.0 * (double)total * 8.0 + (double)W * 8.0 + 4096.0;
-    if (need > (double)free_b) {
+    if (need > avail) {
         set_error("stable models need " + std::to_string((long long)need) + " bytes of device memory, " +
-                  std::to_string((long long)free_b) + " free");
+                  std::to_string((long long)avail) + " available");
         return LP_E_NOMEM;
     }
     Scratch S(st);
@@ -864,6 +961,7 @@ struct BatchPlan {
     hipGraphExec_t exec = nullptr;
     lp_schedule sched{};             // schedule of the single-program solves
     float tuned_ms = 0.f;
+    bool use_graph = true;           // runs replay a captured graph (else a direct launch)
 };
 
 static void batch_release(BatchPlan &b) {
@@ -937,7 +1035,8 @@ static lp_status batch_capture(BatchPlan &b) {
 }
 
 static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const lp_schedule *sched, hipStream_t st,
-                              BatchPlan &b) {
+                              bool use_graph, BatchPlan &b) {
+    b.use_graph = use_graph;
     b.ms.resize(count);
     for (int32_t i = 0; i < count; ++i) {
         if (!ms[i]) {
@@ -1031,12 +1130,24 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
         if ((rc = batch_fit_shape(b, &s))) return rc;
     }
     b.shape = s;
-    return batch_capture(b);
+    return b.use_graph ? batch_capture(b) : LP_OK;
 }
 
 static lp_status batch_run(const BatchPlan &b, hipStream_t st) {
-    if (b.exec) LP_HIP(hipGraphLaunch(b.exec, st));
+    if (b.order.empty()) return LP_OK;
+    if (b.exec) {
+        LP_HIP(hipGraphLaunch(b.exec, st));
+    } else {
+        const BatchShape &s = b.shape;
+        LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b), st));
+    }
     return LP_OK;
+}
+
+int64_t batch_max_rows(int device) {
+    DevProps d;
+    if (dev_props(device, &d)) return 0;
+    return std::max<int64_t>(0, (d.max_lds - 4096) / 16) * 64;
 }
 
 static lp_status batch_results(const BatchPlan &b, uint8_t *const *models, int32_t *products, hipStream_t st) {
@@ -1114,7 +1225,7 @@ static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStrea
     b.shape = win;
     b.tuned_ms = win_ms;
     if (best_ms) *best_ms = win_ms;
-    return batch_capture(b);
+    return b.use_graph ? batch_capture(b) : LP_OK;
 }
 
 }  // namespace lp
@@ -1173,6 +1284,57 @@ lp_status lp_free_matrix(lp_matrix *m) {
         free_device(m->m, nullptr);
     }
     delete m;
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_matrix_upload(lp_matrix *m, void *hip_stream) {
+    LP_GUARD_BEGIN
+    if (!m) {
+        set_error("NULL matrix");
+        return LP_E_INVAL;
+    }
+    if (!(m->m.flags & LP_BUILD_HOST_ONLY)) return LP_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    lp_status rc = upload_matrix(m->m, st);
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        free_device(m->m, st);
+        return rc;
+    }
+    m->m.flags &= ~(uint32_t)LP_BUILD_HOST_ONLY;
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_matrix_evict(lp_matrix *m) {
+    LP_GUARD_BEGIN
+    if (!m) {
+        set_error("NULL matrix");
+        return LP_E_INVAL;
+    }
+    if (m->m.flags & LP_BUILD_HOST_ONLY) return LP_OK;
+    {
+        DeviceGuard g(m->m.dev.device);
+        free_device(m->m, nullptr);
+    }
+    m->m.flags |= LP_BUILD_HOST_ONLY;
+    m->m.info.device_bytes = 0;
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_memory_stats(int64_t *in_use, int64_t *cached) {
+    DevicePool &P = pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    if (in_use) *in_use = P.in_use;
+    if (cached) *cached = P.cached;
+    return LP_OK;
+}
+
+lp_status lp_release_cached_memory(void) {
+    LP_GUARD_BEGIN
+    pool_trim(-1);
     return LP_OK;
     LP_GUARD_END
 }
@@ -1274,7 +1436,7 @@ lp_status lp_least_model_batch(const lp_matrix *const *ms, int32_t count, uint8_
     lp_status rc = LP_OK;
     {
         DeviceGuard g(ms[0] ? ms[0]->m.dev.device : -1);
-        rc = batch_create(ms, count, sched, st, b);
+        rc = batch_create(ms, count, sched, st, false, b);
         if (!rc) rc = batch_run(b, st);
         if (!rc) rc = batch_results(b, models, products, st);
         (void)hipStreamSynchronize(st);
@@ -1296,8 +1458,11 @@ lp_status lp_batch_create(const lp_matrix *const *ms, int32_t count, const lp_sc
     lp_status rc;
     {
         DeviceGuard g(count > 0 && ms[0] ? ms[0]->m.dev.device : -1);
-        rc = batch_create(ms, count, sched, (hipStream_t)hip_stream, b->b);
-        if (rc) batch_release(b->b);
+        rc = batch_create(ms, count, sched, (hipStream_t)hip_stream, true, b->b);
+        if (rc) {
+            (void)hipStreamSynchronize((hipStream_t)hip_stream);
+            batch_release(b->b);
+        }
     }
     if (rc) {
         delete b;
@@ -1412,6 +1577,14 @@ lp_status lp_set_allocator(void *(*alloc)(size_t, void *, void *), void (*releas
     if ((alloc == nullptr) != (release == nullptr)) {
         set_error("alloc and release must both be set or both be NULL");
         return LP_E_INVAL;
+    }
+    {
+        DevicePool &P = pool();
+        std::lock_guard<std::mutex> lock(P.mu);
+        if (P.in_use > 0 && alloc) {
+            set_error("blocks of the library's own pool are live (free every matrix and plan first)");
+            return LP_E_INVAL;
+        }
     }
     g_alloc = alloc;
     g_release = release;

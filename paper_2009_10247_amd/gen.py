@@ -234,9 +234,58 @@ def _negate_some(rng, prog: Program, neg_atoms, p_neg: float, max_neg: int) -> P
     return Program(prog.n_atoms, prog.head, prog.body_ptr, lit.astype(np.int32), dict(prog.meta))
 
 
+def _negate_some_vec(rng, prog: Program, neg_atoms, p_neg: float, max_neg: int,
+                     tries: int = 32) -> Program:
+    """Array form of _negate_some for large programs (same constraints, other
+    draws): each rule with a non-empty body, with probability p_neg, gets
+    c ~ U{1..max_neg} (at most its body length) negations 'not q', q taken
+    from neg_atoms as c consecutive entries from a random start, placed in c
+    consecutive body slots (cyclically) from a random start; q != head and q
+    not positive in the original body, redrawing the start up to `tries`
+    times, else the rule keeps its positive body."""
+    Q = np.asarray(neg_atoms, dtype=np.int64)
+    K = Q.shape[0]
+    lit = prog.body_lit.astype(np.int64).copy()
+    if K == 0:
+        return Program(prog.n_atoms, prog.head, prog.body_ptr, lit.astype(np.int32), dict(prog.meta))
+    bp = prog.body_ptr.astype(np.int64)
+    L = np.diff(bp)
+    R = prog.n_rules
+    pick = np.nonzero((rng.random(R) < p_neg) & (L > 0))[0]
+    c = np.minimum(np.minimum(rng.integers(1, max_neg + 1, size=pick.shape[0]), L[pick]), K)
+    Lm = int(L.max()) if R else 0
+    body = np.full((pick.shape[0], max(Lm, 1)), -1, dtype=np.int64)
+    for j in range(Lm):
+        has = L[pick] > j
+        body[has, j] = lit[bp[pick[has]] + j]
+    head = prog.head.astype(np.int64)[pick]
+    t0 = rng.integers(0, K, size=pick.shape[0])
+    ok = np.zeros(pick.shape[0], dtype=bool)
+    todo = np.arange(pick.shape[0])
+    for _ in range(tries):
+        if todo.shape[0] == 0:
+            break
+        good = np.ones(todo.shape[0], dtype=bool)
+        for j in range(max_neg):
+            act = c[todo] > j
+            q = Q[(t0[todo] + j) % K]
+            bad = (q == head[todo]) | (body[todo] == q[:, None]).any(axis=1)
+            good &= ~(act & bad)
+        ok[todo[good]] = True
+        todo = todo[~good]
+        t0[todo] = rng.integers(0, K, size=todo.shape[0])
+    s0 = (rng.random(pick.shape[0]) * L[pick]).astype(np.int64)
+    for j in range(max_neg):
+        act = ok & (c > j)
+        r = pick[act]
+        slot = (s0[act] + j) % L[r]
+        lit[bp[r] + slot] = -Q[(t0[act] + j) % K] - 1
+    return Program(prog.n_atoms, prog.head, prog.body_ptr, lit.astype(np.int32), dict(prog.meta))
+
+
 def normal_uniform(seed: int, n_atoms: int = 10_000, n_rules: int = 20_000, max_body: int = 5,
                    k_neg: int = 16, p_neg: float = 0.1, max_neg: int = 2,
-                   fact_frac: float = 0.0) -> Program:
+                   fact_frac: float = 0.0, vectorized: bool = False) -> Program:
     """Normal program with k_neg atoms appearing negated.
 
     Uniform heads, bodies of length 1..max_body (fact_frac of the rules are
@@ -245,13 +294,14 @@ def normal_uniform(seed: int, n_atoms: int = 10_000, n_rules: int = 20_000, max_
     negated, so exactly k_neg atoms are negated and there are 2^k_neg guesses.
 
     At the defaults: 10,000 atoms, 20,000 rules, 16 negated atoms (65,536 guesses).
+    vectorized=True places the negations with _negate_some_vec (for large programs).
     """
     attempt = 0
     while True:
         rng = _rng(seed * 1000 + attempt)
         base = definite_uniform(int(rng.integers(0, 2**62)), n_atoms, n_rules, fact_frac, max_body)
         Q = rng.choice(n_atoms, size=k_neg, replace=False) if k_neg > 0 else np.zeros(0, np.int64)
-        prog = _negate_some(rng, base, Q, p_neg, max_neg)
+        prog = (_negate_some_vec if vectorized else _negate_some)(rng, base, Q, p_neg, max_neg)
         negs = np.unique(-prog.body_lit[prog.body_lit < 0].astype(np.int64) - 1)
         if negs.shape[0] == k_neg:
             prog.meta = dict(kind="normal_uniform", seed=seed, k_neg=k_neg, attempt=attempt,
@@ -349,5 +399,5 @@ def serving_pool(seed: int = 0, count: int = 256, lo: float = 1e3, hi: float = 1
             out.append(definite_uniform(sub, n, rule_factor * n, fact_frac, max_body))
         else:
             out.append(normal_uniform(sub, n, rule_factor * n, max_body, k, p_neg, max_neg,
-                                      fact_frac))
+                                      fact_frac, vectorized=True))
     return out

@@ -26,6 +26,7 @@ LP_E_TOO_MANY_GUESSES = -5
 LP_E_TRUNCATED = -6
 LP_E_INTERNAL = -7
 LP_E_HOST_ONLY = -8
+LP_E_TIMEOUT = -9
 LP_MAX_NEG_ATOMS = 24
 
 LP_PRUNE_FACT_GUESSES = 1 << 0
@@ -43,7 +44,10 @@ LP_STEP_LDS = 2
 EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg_atoms",
            "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_least_model_batch",
            "lp_batch_create", "lp_batch_run", "lp_batch_results", "lp_batch_tune",
-           "lp_batch_get_info", "lp_batch_free",
+           "lp_batch_get_info", "lp_batch_free", "lp_matrix_evict", "lp_matrix_upload",
+           "lp_server_create", "lp_server_add_program", "lp_server_submit", "lp_server_wait_any",
+           "lp_server_take_result", "lp_server_get_stats", "lp_server_free",
+           "lp_memory_stats", "lp_release_cached_memory",
            "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_last_error")
 
 
@@ -80,6 +84,28 @@ class lp_batch_info(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class lp_server_config(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("batch_max", ctypes.c_int32),
+                ("batch_rows", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+
+
+class lp_request_info(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_int64), ("program_id", ctypes.c_int32),
+                ("kind", ctypes.c_int32), ("status", ctypes.c_int32), ("products", ctypes.c_int32),
+                ("n_models", ctypes.c_int64), ("batch_size", ctypes.c_int32), ("built", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class lp_server_stats(ctypes.Structure):
+    _fields_ = [("n_programs", ctypes.c_int32), ("n_resident", ctypes.c_int32),
+                ("pending", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("batched_requests", ctypes.c_int64), ("alone_requests", ctypes.c_int64),
+                ("uploads", ctypes.c_int64), ("evictions", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
+                ("peak_used_bytes", ctypes.c_int64), ("hbm_budget", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -112,6 +138,17 @@ def load():
         "lp_tune_schedule": [P, i32, ctypes.POINTER(lp_schedule), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float), P],
         "lp_set_allocator": [P, P, P],
+        "lp_matrix_evict": [P],
+        "lp_matrix_upload": [P, P],
+        "lp_server_create": [ctypes.POINTER(lp_server_config), ctypes.POINTER(P)],
+        "lp_server_add_program": [P, i32, i32, P, P, P, ctypes.POINTER(i32)],
+        "lp_server_submit": [P, i32, ctypes.POINTER(i64)],
+        "lp_server_wait_any": [P, i32, ctypes.POINTER(lp_request_info)],
+        "lp_server_take_result": [P, i64, P, P],
+        "lp_server_get_stats": [P, ctypes.POINTER(lp_server_stats)],
+        "lp_server_free": [P],
+        "lp_memory_stats": [ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "lp_release_cached_memory": [],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -200,6 +237,16 @@ class Matrix:
 
     def __exit__(self, *exc):
         self.close()
+
+    def evict(self):
+        """Release the device copy (lp_matrix_evict); solves then raise LP_E_HOST_ONLY."""
+        _check(load().lp_matrix_evict(self._h))
+        self.info = self._info()
+
+    def upload(self, stream=None):
+        """Rebuild the device copy from the host CSR (lp_matrix_upload)."""
+        _check(load().lp_matrix_upload(self._h, _stream(stream)))
+        self.info = self._info()
 
     def neg_atoms(self) -> np.ndarray:
         out = np.zeros(max(self.info["n_neg"], 1), dtype=np.int32)
@@ -335,6 +382,88 @@ class Batch:
         inf = lp_batch_info()
         _check(load().lp_batch_get_info(self._h, ctypes.byref(inf)))
         return {name: getattr(inf, name) for name, _ in lp_batch_info._fields_ if name != "reserved"}
+
+
+def memory_stats() -> dict:
+    """Bytes of the library's device pool: held by live objects and cached."""
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load().lp_memory_stats(ctypes.byref(a), ctypes.byref(b)))
+    return {"in_use": a.value, "cached": b.value}
+
+
+def release_cached_memory():
+    _check(load().lp_release_cached_memory())
+
+
+class Server:
+    """Request loop of lp_server_create: register programs, submit requests,
+    collect completions (argument marshalling only; the loop is native)."""
+
+    def __init__(self, n_slots=0, batch_max=0, batch_rows=0, hbm_budget=0, device=-1):
+        cfg = lp_server_config(n_slots=n_slots, batch_max=batch_max, batch_rows=batch_rows, device=device,
+                               hbm_budget=int(hbm_budget))
+        h = ctypes.c_void_p()
+        _check(load().lp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.n_atoms = {}
+        self.n_neg = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lp_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add_program(self, prog) -> int:
+        head = np.ascontiguousarray(prog.head, dtype=np.int32)
+        ptr = np.ascontiguousarray(prog.body_ptr, dtype=np.int64)
+        lit = np.ascontiguousarray(prog.body_lit, dtype=np.int32)
+        pid = ctypes.c_int32(0)
+        _check(load().lp_server_add_program(self._h, int(prog.n_atoms), int(head.shape[0]), _ptr(head),
+                                            ptr.ctypes.data, _ptr(lit), ctypes.byref(pid)))
+        self.n_atoms[pid.value] = int(prog.n_atoms)
+        neg = lit[lit < 0]
+        self.n_neg[pid.value] = int(np.unique(neg).shape[0])
+        return pid.value
+
+    def submit(self, program_id: int) -> int:
+        rid = ctypes.c_int64(0)
+        _check(load().lp_server_submit(self._h, int(program_id), ctypes.byref(rid)))
+        return rid.value
+
+    def wait_any(self, timeout_ms: int = 1000):
+        """Info dict of the next completed request, or None on timeout."""
+        inf = lp_request_info()
+        rc = _check(load().lp_server_wait_any(self._h, int(timeout_ms), ctypes.byref(inf)), allow=(LP_E_TIMEOUT,))
+        if rc == LP_E_TIMEOUT:
+            return None
+        return {name: getattr(inf, name) for name, _ in lp_request_info._fields_}
+
+    def take_result(self, request_id: int, program_id: int):
+        """(model uint8[n_atoms], accepted uint64[ceil(2^K/64)] or None)."""
+        n = self.n_atoms[program_id]
+        k = self.n_neg[program_id]
+        model = np.zeros(max(n, 1), dtype=np.uint8)
+        acc = np.zeros(max(((1 << k) + 63) // 64, 1), dtype=np.uint64) if k else None
+        _check(load().lp_server_take_result(self._h, int(request_id), model.ctypes.data,
+                                            acc.ctypes.data if acc is not None else None))
+        return model[:n], acc
+
+    def stats(self) -> dict:
+        st = lp_server_stats()
+        _check(load().lp_server_get_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in lp_server_stats._fields_}
 
 
 def unpack_column(interp: np.ndarray, j: int) -> np.ndarray:

@@ -385,10 +385,11 @@ def tiny_random(seed: int, max_atoms: int = 16, max_rules: int = 40, max_body: i
 
 def serving_pool(seed: int = 0, count: int = 256, lo: float = 1e3, hi: float = 1e6,
                  rule_factor: int = 3, max_body: int = 6, fact_frac: float = 0.02,
-                 max_k: int = 12, p_neg: float = 0.1, max_neg: int = 2):
+                 max_k: int = 12, p_neg: float = 0.1, max_neg: int = 2, progress=None):
     """Pool of request programs: n log-uniform in [lo, hi], rule_factor*n rules,
     bodies 1..max_body, fact_frac facts, k ~ U{0..max_k} negated atoms
-    (k = 0 gives a least-model query, k > 0 a stable-model query)."""
+    (k = 0 gives a least-model query, k > 0 a stable-model query).
+    progress (nullable) is called with the number of programs drawn so far."""
     rng = _rng(seed ^ 0xC5C5)
     out = []
     for i in range(count):
@@ -400,4 +401,6 @@ def serving_pool(seed: int = 0, count: int = 256, lo: float = 1e3, hi: float = 1
         else:
             out.append(normal_uniform(sub, n, rule_factor * n, max_body, k, p_neg, max_neg,
                                       fact_frac, vectorized=True))
+        if progress is not None:
+            progress(i + 1)
     return out

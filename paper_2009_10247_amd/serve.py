@@ -29,10 +29,14 @@ def zipf_weights(n: int, s: float = 1.0) -> np.ndarray:
     return w / w.sum()
 
 
-def _collect(server, n, out, deadline):
+def _collect(server, n, out, deadline, progress=None):
     got = 0
+    t_log = time.perf_counter()
     while got < n and time.perf_counter() < deadline:
         info = server.wait_any(500)
+        if progress is not None and time.perf_counter() - t_log > 30.0:
+            t_log = time.perf_counter()
+            progress(f"{got}/{n} requests completed")
         if info is None:
             continue
         model, acc = server.take_result(info["request_id"], info["program_id"])
@@ -59,15 +63,16 @@ def solve_alone(server, pids, timeout_s: float = 600.0) -> dict:
 
 
 def run_stream(server, pids, weights, rate: float, n_requests: int, seed: int, ref: dict | None = None,
-               timeout_s: float = 900.0) -> dict:
+               timeout_s: float = 900.0, progress=None) -> dict:
     """Submit n_requests at Poisson(rate) arrival times; return latency and
-    throughput statistics. With ref, every result is compared with it."""
+    throughput statistics. With ref, every result is compared with it.
+    progress (nullable) receives a status line about every 30 s."""
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
     choice = rng.choice(len(pids), size=n_requests, p=weights)
     results = {}
     collector = threading.Thread(target=_collect,
-                                 args=(server, n_requests, results, time.perf_counter() + timeout_s))
+                                 args=(server, n_requests, results, time.perf_counter() + timeout_s, progress))
     collector.start()
     t0 = time.perf_counter()
     late = 0.0
@@ -134,12 +139,23 @@ def main(argv=None) -> int:
         print(*a, file=sys.stderr, flush=True)
 
     t = time.perf_counter()
-    pool = gen.serving_pool(args.seed, args.pool, args.lo, args.hi, max_k=args.max_k)
+    t_log = [t]
+
+    def every_30s(msg):
+        if time.perf_counter() - t_log[0] > 30.0:
+            t_log[0] = time.perf_counter()
+            log(f"[serve] {msg}")
+
+    pool = gen.serving_pool(args.seed, args.pool, args.lo, args.hi, max_k=args.max_k,
+                            progress=lambda i: every_30s(f"{i}/{args.pool} programs drawn"))
     log(f"[serve] pool of {len(pool)} programs generated in {time.perf_counter() - t:.1f}s")
     with lp.Server(n_slots=args.slots, batch_max=args.batch_max,
                    hbm_budget=int(args.budget_gb * 2**30)) as srv:
         t = time.perf_counter()
-        pids = [srv.add_program(p) for p in pool]
+        pids = []
+        for p in pool:
+            pids.append(srv.add_program(p))
+            every_30s(f"{len(pids)}/{len(pool)} programs registered")
         log(f"[serve] registered in {time.perf_counter() - t:.1f}s")
         t = time.perf_counter()
         ref = solve_alone(srv, pids)
@@ -147,7 +163,8 @@ def main(argv=None) -> int:
         weights = zipf_weights(len(pids))
         rows = []
         for k, rate in enumerate(float(x) for x in args.rates.split(",")):
-            row = run_stream(srv, pids, weights, rate, args.requests, args.seed + 1 + k, ref)
+            row = run_stream(srv, pids, weights, rate, args.requests, args.seed + 1 + k, ref,
+                             progress=lambda msg, r=rate: log(f"[serve] rate {r:g}: {msg}"))
             log(f"[serve] {json.dumps(row)}")
             rows.append(row)
         st = srv.stats()

@@ -11,8 +11,10 @@ and resident in HBM before the timed region.
 value = rule-body entries processed per second = nnz * products / seconds.
 
 Also reported: the dominant kernel (one full-sweep T_P step) against the HBM
-roofline, the CPU oracle timed on this host, and stable-model guesses/s on a
-normal program with 10,000 atoms, 20,000 rules and 16 negated atoms.
+roofline, the CPU oracle timed on this host, stable-model guesses/s on a
+normal program with 10,000 atoms, 20,000 rules and 16 negated atoms, and 512
+programs of 1e3-1e5 atoms solved by one batch launch against 512 sequential
+single-program solves.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
@@ -63,11 +65,91 @@ def recorded_traffic(kernel: str, step_bytes_now: int):
     return None
 
 
+def step_mode(info: dict, sched) -> int:
+    """Form of the step kernel the library launches: 0 gathers from global
+    memory, 1 all of v staged in LDS (the original atoms fit in the 160 KB of a
+    workgroup beside the ballot slots), 2 mixed."""
+    from paper_2009_10247_amd import lp
+    if sched.variant == lp.LP_STEP_GLOBAL:
+        return 0
+    cap_words = 163840 // 8 - 16 * (sched.unroll + 1) - 2
+    return 1 if (info["n_atoms"] + 63) // 64 <= cap_words else 2
+
+
 def csr_step_bytes(info: dict) -> int:
     """The same step on a plain int32 CSR (row pointers, column indices,
     row-kind bits, v and u bit-packed): what a CSR kernel would move."""
     n, nnz = info["n_rows"], info["nnz"]
     return 4 * (n + 1) + 4 * nnz + 3 * ((n + 7) // 8)
+
+
+def bench_batch(args, torch, gen, lp, stream) -> dict:
+    """Many programs at once: 512 definite programs (atoms log-uniform in
+    1e3..1e5, 2x rules, bodies 1..6, 2% facts) solved by one launch of the
+    batch kernel (a replay of the plan's hipGraph, shape autotuned first),
+    against the same 512 solved one after another by the plain driver (one
+    launch and one host read of the change count per product) and by the
+    library's default driver."""
+    t = time.perf_counter()
+    progs = gen.batch_programs(args.seed, 512)
+    mats = [lp.Matrix(p, stream=stream) for p in progs]
+    log(f"[bench] batch: 512 programs generated and built in {time.perf_counter() - t:.1f}s")
+    try:
+        plan = lp.Batch(mats, stream=stream)
+        tuned_ms = plan.tune(reps=3, stream=stream)
+        binfo = plan.info()
+        plan.run(stream=stream)
+        res = plan.results(stream=stream)
+        torch.cuda.synchronize()
+        reps = max(5, args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.run(stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dev_ms = e0.elapsed_time(e1) / reps
+        t = time.perf_counter()
+        for _ in range(reps):
+            plan.run(stream=stream)
+            res2 = plan.results(stream=stream)
+        e2e_ms = (time.perf_counter() - t) * 1e3 / reps
+        plain = lp.make_schedule(driver=lp.LP_DRIVER_PLAIN)
+        seq = {}
+        for name, sched in (("plain", plain), ("default", None)):
+            for mm in mats[:8]:  # warm the step kernels
+                mm.least_model(sched=sched, stream=stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = [mm.least_model(sched=sched, stream=stream) for mm in mats]
+            seq[name] = (time.perf_counter() - t) * 1e3
+            for (g, pr), (g2, pr2) in zip(res, out):
+                assert pr == pr2 and (g == g2).all(), "batch result differs from the single-program solve"
+        for (g, pr), (g2, pr2) in zip(res, res2):
+            assert pr == pr2 and (g == g2).all()
+        prods = [pr for _, pr in res]
+        entries = sum(mm.info["nnz"] * pr for mm, pr in zip(mats, prods))
+        layout = sum((mm.info["step_bytes"] - 2 * ((mm.info["n_rows"] + 7) // 8)) * pr
+                     for mm, pr in zip(mats, prods))
+        out = {"workload": "512 definite programs, atoms log-uniform 1e3-1e5, rules 2x atoms, bodies 1-6, "
+                           "2% facts; one launch of the batch kernel (graph replay)",
+               "programs": 512, "atoms": sum(p.n_atoms for p in progs), "nnz": binfo["nnz"],
+               "products_total": int(sum(prods)), "products_max": int(max(prods)),
+               "ms_per_batch": round(dev_ms, 3), "ms_per_batch_with_results": round(e2e_ms, 3),
+               "entries_per_s": round(entries / (dev_ms / 1e3), 1),
+               "layout_GB/s": round(layout / (dev_ms / 1e3) / 1e9, 1),
+               "sequential_plain_ms": round(seq["plain"], 3), "sequential_default_ms": round(seq["default"], 3),
+               "speedup_vs_sequential_plain": round(seq["plain"] / e2e_ms, 2),
+               "speedup_vs_sequential_default": round(seq["default"] / e2e_ms, 2),
+               "shape": {k: binfo[k] for k in ("wpw", "unroll", "block", "grid", "lds_bytes")},
+               "tuned_ms": round(tuned_ms, 3)}
+        log(f"[bench] batch: {out}")
+        plan.close()
+        return out
+    finally:
+        for mm in mats:
+            mm.close()
 
 
 def main() -> int:
@@ -79,6 +161,7 @@ def main() -> int:
     ap.add_argument("--step-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stable", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true", help="time every step shape (diagnostic)")
     ap.add_argument("--tune-reps", type=int, default=20)
@@ -170,8 +253,8 @@ def main() -> int:
     variants = {}
     if args.sweep:
         for v, vname in ((lp.LP_STEP_LDS, "lds"), (lp.LP_STEP_GLOBAL, "global")):
-            for w in (1, 2, 4, 8):
-                for u in (4, 8, 16):
+            for w in (4, 8, 16):
+                for u in (4, 8, 16) if w < 16 else (8, 16):
                     ms = m.bench_step(reps=args.step_reps, stream=stream,
                                       sched=lp.make_schedule(variant=v, wpw=w, unroll=u))
                     variants[f"{vname}-w{w}-u{u}"] = round(ms * 1e3, 2)
@@ -186,8 +269,7 @@ def main() -> int:
         step_sched = lp.make_schedule(variant=sched.variant, wpw=sched.wpw, unroll=sched.unroll, grid=sched.grid)
         kern_ms = m.bench_step(reps=args.step_reps, sched=step_sched, stream=stream)
         Bl = B
-        kname = (f"tp_step_kernel<{'true' if sched.variant == lp.LP_STEP_LDS else 'false'}, "
-                 f"{sched.wpw}, {sched.unroll}>")
+        kname = f"tp_step_kernel<{step_mode(info, sched)}, {sched.wpw}, {sched.unroll}>"
     achieved = Bl / (kern_ms / 1e3) / 1e9
     log(f"[bench] {kname}: {kern_ms * 1e3:.2f} us/launch, {Bl / 1e6:.1f} MB -> {achieved:.0f} GB/s")
     Bc = csr_step_bytes(info) * (products if sched.driver == lp.LP_DRIVER_PERSISTENT else 1)
@@ -219,6 +301,8 @@ def main() -> int:
                       "guesses": H, "ms_per_solve": round(sms, 3), "guesses_per_s": round(H / (sms / 1e3), 1),
                       "n_models": r["n_models"], "products": r["products"]}
         log(f"[bench] stable: {stable}")
+
+    batch = None if args.no_batch else bench_batch(args, torch, gen, lp, stream)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -259,6 +343,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stable_models": stable,
+        "batch": batch,
         "schedule": lp.schedule_dict(sched),
         "step_us_per_shape": variants or None,
     }

@@ -92,8 +92,10 @@ typedef struct lp_info {
     int32_t n_long_rows;    /* rows handled by the split long-row pass */
     int64_t device_bytes;   /* device memory held by the matrix */
     int64_t step_bytes;     /* bytes one full-sweep step must move on this device layout
-                               (least models: the layout arrays, one read of v, one write
-                               of u; stable models: CSR, one read of V, one write of U) */
+                               (least models: the AND lengths, one entry offset per four
+                               words, the AND entries, the OR range table, the long-row
+                               segments, one read of v and one write of u; stable models:
+                               CSR, one read of V, one write of U) */
     double sparsity;        /* equation 5: 1 - sum_r |body(r)| / N^2 */
 } lp_info;
 
@@ -117,8 +119,10 @@ typedef struct lp_schedule {
     int32_t steps_per_sync;  /* products issued between host checks (BATCHED, AUTO) */
     int32_t variant;         /* LP_STEP_* kernel of the least-model step */
     int32_t grid;            /* workgroups of the step (0: one per CU for LDS, eight per CU otherwise) */
-    int32_t wpw;             /* 64-row words per wave: 1, 2, 4 or 8 (0: default) */
-    int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16 (0: default) */
+    int32_t wpw;             /* step: 64-row words per super-block, 4, 8 or 16; batch kernel: words per
+                                wave, 1, 2 or 4 (0: default) */
+    int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16; 16 words per
+                                super-block take 8 or 16 (0: default) */
     int32_t block;           /* batch kernel: threads per workgroup, 256, 512 or 1024 (0: 512) */
     int32_t reserved;
 } lp_schedule;
@@ -312,8 +316,20 @@ lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t re
                         void *hip_stream);
 
 /*
+ * Average duration in milliseconds of one stable-model step U = theta(M_P V)
+ * (Algorithm 2's product over all guess columns, change count included) over
+ * reps launches on hip_stream, timed with HIP events, on the fixpoint
+ * interpretation matrix of m (computed first, from Definition 8's initial
+ * matrix); every launch reads the same V and writes the same U. products
+ * (nullable) receives the fixpoint's product count. Used to measure achieved
+ * bandwidth. Errors: LP_E_INVAL for a definite program or bad arguments; as
+ * lp_stable_models otherwise.
+ */
+lp_status lp_bench_spmm(const lp_matrix *m, int32_t reps, float *avg_ms, int32_t *products, void *hip_stream);
+
+/*
  * Autotuner for least-model solves of m (a definite program). Times every
- * supported step shape (LP_STEP_LDS / LP_STEP_GLOBAL, 1/2/4/8 words per wave,
+ * supported step shape (LP_STEP_LDS / LP_STEP_GLOBAL, 4/8/16 words per super-block,
  * 4/8/16 chunks in flight) over reps full-sweep steps on m's own fixpoint
  * with HIP events, then times whole solves with the batched driver and, when
  * the fastest step is shorter than 20 us (where launch overhead matters), the

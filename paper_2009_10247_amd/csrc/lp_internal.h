@@ -21,6 +21,7 @@ constexpr int32_t kLongOrBits = 512;    // longer OR rows go to the segment pass
 constexpr int32_t kSegAnd = 4096;       // entries per AND segment
 constexpr int32_t kSegOrBits = 16384;   // bits per OR segment
 constexpr int32_t kColPad = 64 * 16;    // zero entries after col: chunk loads past the end stay in bounds
+constexpr int32_t kWordPad = 16;        // empty words after the last: super-block loads past the end stay in bounds
 
 struct WordMeta {
     int32_t and_base;    // offset in col of the word's first AND entry
@@ -44,8 +45,10 @@ struct LongSeg {
 // by the matrix (released by lp_free_matrix).
 struct DeviceMatrix {
     // least models (definite programs)
-    WordMeta *words = nullptr;    // [n_words]
-    uint8_t *and_len = nullptr;   // [n_rows] AND-row length in the block pass, 0 otherwise
+    WordMeta *words = nullptr;    // [n_words + kWordPad]
+    uint8_t *and_len = nullptr;   // [(n_words + kWordPad) * 64] AND-row length in the block pass, 0 otherwise
+    uint32_t *lens4 = nullptr;    // the same lengths by lane: entry 64 q + l holds rows 64 (4q + k) + l, k < 4,
+                                  // one byte each (byte k), for the n_words + kWordPad words
     int32_t *col = nullptr;       // block AND entries in row order
     int32_t *or_c0 = nullptr;     // [n_or + 1] first child of each OR row, ascending rows
     int32_t *or_row = nullptr;    // [n_or] row id of each OR row, -1 if evaluated by segments

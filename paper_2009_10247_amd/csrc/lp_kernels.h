@@ -18,6 +18,7 @@ constexpr int kRing = 256;
 struct StepParams {
     const WordMeta *words;         // [n_words]
     const uint8_t *and_len;        // [n_rows]
+    const uint32_t *lens4;         // AND lengths of four consecutive words per lane
     const int32_t *col;            // block AND entries
     const int32_t *or_c0;          // [n_or + 1]
     const int32_t *or_row;         // [n_or] row of each OR row, -1 for rows of the segment pass
@@ -38,15 +39,25 @@ struct StepParams {
     int32_t lds_words;             // leading words of v staged in LDS (LDS shapes)
 };
 
+// Forms of the step kernel: gathers of v from global memory; from v staged
+// in LDS (every AND entry names a staged atom); or mixed (atoms past the
+// staged words are read from global memory).
+enum StepMode : int { kStepGlobal = 0, kStepLds = 1, kStepMixed = 2 };
+
+// LDS of the staged forms (static, so v sits at LDS address 0): the staged
+// words of v, then one ballot slot area per wave (16 waves x (unroll + 1)
+// words), then the new-bit count. gfx950 gives a workgroup 160 KB.
+constexpr int kStepLdsBytes = 163840;
+inline int32_t step_lds_v_words(int unroll) { return kStepLdsBytes / 8 - 16 * (unroll + 1) - 2; }
+
 // Launch shape of the step kernel. A wave owns wpw consecutive 64-row words
 // (a super-block) and keeps unroll column chunks of 64 entries in flight.
 struct StepShape {
-    int lds = 1;        // 1: v staged in LDS, 1024-thread workgroups (one per CU)
-    int wpw = 4;        // words per wave: 1, 2, 4 or 8
-    int unroll = 8;     // 4, 8 or 16
-    int block = 1024;   // threads per workgroup
-    int grid = 0;       // workgroups (grid-stride loop over super-blocks)
-    size_t lds_bytes = 0;
+    int mode = kStepLds;  // StepMode; staged forms use 1024-thread workgroups, one per CU
+    int wpw = 8;          // words per super-block: 4, 8 or 16
+    int unroll = 8;       // 4, 8 or 16
+    int block = 1024;     // threads per workgroup
+    int grid = 0;         // workgroups (grid-stride loop over super-blocks)
 };
 
 bool step_shape_supported(const StepShape &s);
@@ -62,8 +73,6 @@ struct PersistParams {
 };
 hipError_t launch_persistent(const StepShape &s, const PersistParams &q, hipStream_t st);
 hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu);
-// Allows every LDS-staged kernel to take up to max_dynamic_lds bytes.
-void step_kernels_allow_lds(int max_dynamic_lds);
 
 // Many least models in one launch: each workgroup runs whole fixpoints of the
 // programs it takes from a device work queue, with both buffers in LDS.
@@ -105,15 +114,17 @@ struct SpmmParams {
     const uint64_t *and_bits;  // AND rows of the full matrix
     const uint64_t *V;
     uint64_t *U;
-    unsigned long long *counters;
+    unsigned long long *counters;  // ring: bit count of the product's result, slot 0 the initial matrix's
     int64_t total;  // n_rows << log2W
     int32_t log2W;
     int32_t step;
     int32_t early_exit;
 };
-hipError_t launch_spmm_step(const SpmmParams &p, hipStream_t st);
+// max_grid: workgroups of 256 threads (grid-stride loop over the items).
+hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st);
 hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std,
-                          const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff, hipStream_t st);
+                          const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff,
+                          unsigned long long *count, unsigned long long bits, hipStream_t st);
 hipError_t launch_stable_check(const uint64_t *V, int32_t log2W, int64_t W, const int32_t *q_rows, int32_t n_std,
                                int32_t K, int32_t k_eff, uint64_t *accept, unsigned long long *count,
                                hipStream_t st);

@@ -212,7 +212,7 @@ static lp_status upload(T **d, const T *h, size_t count, hipStream_t st, int64_t
 
 static void free_device(Matrix &m, hipStream_t st) {
     DeviceMatrix &d = m.dev;
-    void *ps[] = {d.words,        d.and_len,       d.col,    d.or_c0,    d.or_row, d.fact_bits, d.segs, d.long_col,
+    void *ps[] = {d.words,        d.and_len,       d.lens4,  d.col,      d.or_c0,  d.or_row,    d.fact_bits, d.segs, d.long_col,
                   d.full_row_ptr, d.full_col,      d.full_and_bits, d.q_rows, d.guess_pos};
     for (void *p : ps) dev_free(p, st);
     d = DeviceMatrix{};
@@ -228,8 +228,10 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
     DeviceMatrix &d = m.dev;
     const int32_t n = m.n_rows;
     const int64_t W = n_words_of(n);
-    std::vector<WordMeta> words(W ? W : 1);
-    std::vector<uint8_t> and_len(n ? n : 1, 0);
+    // kWordPad words (and their rows) past the end: the step kernels load the
+    // row data of a super-block without bounds checks
+    std::vector<WordMeta> words(W + kWordPad);
+    std::vector<uint8_t> and_len((size_t)(W + kWordPad) * 64, 0);
     std::vector<int32_t> col, lcol, or_c0, or_row;
     std::vector<LongSeg> segs;
     col.reserve(m.col.size());
@@ -302,6 +304,11 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
         }
     }
     d.n_or = n_or;
+    for (int64_t w = W; w < W + kWordPad; ++w) {
+        words[w] = WordMeta{};
+        words[w].and_base = (int32_t)col.size();
+        words[w].or_idx = n_or;
+    }
     if (max_col >= (1 << 26)) {
         set_error("least-model layout supports at most 2^26 rows");
         return LP_E_INVAL;
@@ -317,12 +324,26 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
     lp_status rc;
     if ((rc = upload(&d.words, words.data(), words.size(), st, &d.bytes))) return rc;
     if ((rc = upload(&d.and_len, and_len.data(), and_len.size(), st, &d.bytes))) return rc;
+    {
+        const int64_t n_quads = (W + kWordPad + 3) / 4;
+        std::vector<uint32_t> lens4((size_t)n_quads * 64, 0);
+        for (int64_t q = 0; q < n_quads; ++q)
+            for (int k = 0; k < 4; ++k) {
+                const int64_t w = 4 * q + k;
+                if (w >= W + kWordPad) break;
+                for (int l = 0; l < 64; ++l) lens4[q * 64 + l] |= (uint32_t)and_len[w * 64 + l] << (8 * k);
+            }
+        if ((rc = upload(&d.lens4, lens4.data(), lens4.size(), st, &d.bytes))) return rc;
+    }
     if ((rc = upload(&d.col, col.data(), col.size(), st, &d.bytes))) return rc;
     if ((rc = upload(&d.or_c0, or_c0.data(), or_c0.size(), st, &d.bytes))) return rc;
     if ((rc = upload(&d.or_row, or_row.data(), or_row.size(), st, &d.bytes))) return rc;
     if ((rc = upload(&d.segs, segs.data(), segs.size(), st, &d.bytes))) return rc;
     if ((rc = upload(&d.long_col, lcol.data(), lcol.size(), st, &d.bytes))) return rc;
-    d.stream_bytes = (int64_t)W * (int64_t)sizeof(WordMeta) + n + 4 * (d.and_nnz + d.long_nnz) +
+    // what one step reads of the layout: the 8-bit AND lengths, the first AND
+    // entry of every super-block (at most one per four words), the AND entries,
+    // the OR range table and the long-row segments
+    d.stream_bytes = n + 4 * ((W + 3) / 4) + 4 * (d.and_nnz + d.long_nnz) +
                      4 * (int64_t)(or_c0.size() + or_row.size()) + (int64_t)sizeof(LongSeg) * d.n_segs;
     return LP_OK;
 }
@@ -390,10 +411,7 @@ static lp_status dev_props(int dev, DevProps *out) {
         DevProps d;
         LP_HIP(hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         LP_HIP(hipDeviceGetAttribute(&d.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        if (d.max_lds > 4096) {
-            step_kernels_allow_lds(d.max_lds - 4096);
-            batch_kernels_allow_lds(d.max_lds - 4096);
-        }
+        if (d.max_lds > 4096) batch_kernels_allow_lds(d.max_lds - 4096);
         cache[dev] = d;
     }
     *out = cache[dev];
@@ -405,6 +423,7 @@ static StepParams step_params(const Matrix &m) {
     StepParams p{};
     p.words = d.words;
     p.and_len = d.and_len;
+    p.lens4 = d.lens4;
     p.col = d.col;
     p.or_c0 = d.or_c0;
     p.or_row = d.or_row;
@@ -434,30 +453,32 @@ static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams
     lp_status rc = dev_props(m.dev.device, &d);
     if (rc) return rc;
     StepShape s;
-    s.lds = variant == LP_STEP_LDS;
-    s.wpw = sched && sched->wpw > 0 ? sched->wpw : (s.lds ? 4 : 2);
-    s.unroll = sched && sched->unroll > 0 ? sched->unroll : 8;
+    const bool staged = variant == LP_STEP_LDS;
+    s.wpw = sched && sched->wpw > 0 ? sched->wpw : 8;
+    s.unroll = sched && sched->unroll > 0 ? sched->unroll : (staged ? 16 : 8);
     if (!step_shape_supported(s)) {
-        set_error("unsupported step shape (words per wave 1/2/4/8, unroll 4/8/16)");
+        set_error("unsupported step shape (words per super-block 4/8/16 with 4/8/16 chunks; 16 words with 8 or 16)");
         return LP_E_INVAL;
     }
     const int64_t n_words = n_words_of(m.n_rows);
-    if (s.lds) {
-        // the kernels' static LDS (per-wave ballots, counters) takes at most 4 KiB
-        const int64_t cap = std::max<int64_t>(0, (d.max_lds - 4096) / 8);
-        p.lds_words = (int32_t)std::min<int64_t>({cap, n_words_of(m.n_atoms), n_words});
-        s.lds_bytes = (size_t)p.lds_words * 8;
+    if (staged) {
+        if (d.max_lds < kStepLdsBytes) {
+            set_error("the LDS-staged step needs 160 KB of LDS per workgroup");
+            return LP_E_DEVICE;
+        }
+        p.lds_words = (int32_t)std::min<int64_t>({(int64_t)step_lds_v_words(s.unroll), n_words_of(m.n_atoms), n_words});
+        s.mode = (int64_t)m.dev.and_max_col < (int64_t)p.lds_words * 64 ? kStepLds : kStepMixed;
         s.block = 1024;
     } else {
         p.lds_words = 0;
-        s.lds_bytes = 0;
+        s.mode = kStepGlobal;
         s.block = 256;
     }
     const int waves = s.block / 64;
     const int64_t items = std::max<int64_t>({(n_words + s.wpw - 1) / s.wpw, (int64_t)p.n_segs,
                                              ((int64_t)p.n_or + 63) / 64});
     const int64_t want = std::max<int64_t>(1, (items + waves - 1) / waves);
-    const int64_t dflt = s.lds ? d.n_cu : (int64_t)d.n_cu * 8;
+    const int64_t dflt = staged ? d.n_cu : (int64_t)d.n_cu * 8;
     const int64_t grid = sched && sched->grid > 0 ? sched->grid : dflt;
     s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, want));
     *S = s;
@@ -601,6 +622,70 @@ static int ilog2(int64_t x) {
     return l;
 }
 
+// Workgroups of the stable-model step: eight per CU.
+static int spmm_grid(const Matrix &m) {
+    DevProps d;
+    if (dev_props(m.dev.device, &d) || d.n_cu <= 0) return 2048;
+    return 8 * d.n_cu;
+}
+
+static SpmmParams spmm_params(const Matrix &m, unsigned long long *counters) {
+    const int64_t W = ((1ll << m.K_eff) + 63) / 64;
+    SpmmParams p{};
+    p.row_ptr = m.dev.full_row_ptr;
+    p.col = m.dev.full_col;
+    p.and_bits = m.dev.full_and_bits;
+    p.counters = counters;
+    p.log2W = ilog2(W);
+    p.total = (int64_t)m.n_rows * W;
+    p.early_exit = 1;
+    return p;
+}
+
+// Algorithm 2's loop from the initial matrix (Definition 8) until no column
+// changes; *fix is the buffer holding the fixpoint. The counters hold the bit
+// count of each product's result (slot 0: the initial matrix); product s
+// changed nothing iff its count equals that of product s - 1.
+static lp_status stable_fixpoint(const Matrix &m, hipStream_t st, uint64_t *const buf[2],
+                                 unsigned long long *counters, int32_t *products, uint64_t **fix) {
+    SpmmParams p = spmm_params(m, counters);
+    LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
+    // |M0|: every fact row holds all 2^K_eff guesses, every guessed qbar row half of them
+    const unsigned long long H = 1ull << m.K_eff;
+    const unsigned long long m0_bits = (unsigned long long)m.info.n_fact_rows * H + (unsigned long long)m.K_eff * (H / 2);
+    LP_HIP(launch_init_m0(buf[0], buf[1], p.total, p.log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, m.K_eff,
+                          &counters[0], m0_bits, st));
+    unsigned long long *h = pinned_ring();
+    if (!h) {
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
+    const int batch = 8;
+    const int64_t limit = (int64_t)m.n_rows + 1;
+    for (int64_t t = 0;; t += batch) {
+        for (int i = 1; i <= batch; ++i) {
+            p.step = (int32_t)(t + i);
+            p.V = buf[(p.step - 1) & 1];
+            p.U = buf[p.step & 1];
+            LP_HIP(launch_spmm_step(p, spmm_grid(m), st));
+        }
+        LP_HIP(hipMemcpyAsync(h, counters, sizeof(unsigned long long) * kRing, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        for (int i = 1; i <= batch; ++i) {
+            const int64_t s = t + i;
+            if (h[s & (kRing - 1)] == h[(s - 1) & (kRing - 1)]) {
+                *products = (int32_t)s;
+                *fix = buf[s & 1];
+                return LP_OK;
+            }
+        }
+        if (t + batch > limit) {
+            set_error("fixpoint not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
+    }
+}
+
 static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
                              int64_t max_models, uint64_t *interp, int32_t *products, hipStream_t st) {
     const int K = m.K;
@@ -651,47 +736,9 @@ static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_mod
     if ((rc = S.get(&buf[0], total)) || (rc = S.get(&buf[1], total)) || (rc = S.get(&acc_d, W)) ||
         (rc = S.get(&counters, kRing)))
         return rc;
-    LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
-    LP_HIP(launch_init_m0(buf[0], buf[1], total, log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, keff, st));
-    SpmmParams p{};
-    p.row_ptr = m.dev.full_row_ptr;
-    p.col = m.dev.full_col;
-    p.and_bits = m.dev.full_and_bits;
-    p.counters = counters;
-    p.total = total;
-    p.log2W = log2W;
-    p.early_exit = 1;
-    unsigned long long *h = pinned_ring();
-    if (!h) {
-        set_error("pinned host allocation failed");
-        return LP_E_NOMEM;
-    }
-    const int batch = 8;
     int32_t prods = -1;
     uint64_t *fix = nullptr;
-    const int64_t limit = (int64_t)m.n_rows + 1;
-    for (int64_t t = 0; prods < 0; t += batch) {
-        for (int i = 1; i <= batch; ++i) {
-            p.step = (int32_t)(t + i);
-            p.V = buf[(p.step - 1) & 1];
-            p.U = buf[p.step & 1];
-            LP_HIP(launch_spmm_step(p, st));
-        }
-        LP_HIP(hipMemcpyAsync(h, counters, sizeof(unsigned long long) * kRing, hipMemcpyDeviceToHost, st));
-        LP_HIP(hipStreamSynchronize(st));
-        for (int i = 1; i <= batch; ++i) {
-            const int64_t s = t + i;
-            if (h[s & (kRing - 1)] == 0) {
-                prods = (int32_t)s;
-                fix = buf[s & 1];
-                break;
-            }
-        }
-        if (prods < 0 && t + batch > limit) {
-            set_error("fixpoint not reached within n_rows+1 products");
-            return LP_E_INTERNAL;
-        }
-    }
+    if ((rc = stable_fixpoint(m, st, buf, counters, &prods, &fix))) return rc;
     // Algorithm 3
     unsigned long long *cnt_d = counters;  // slot 0 is free once the loop is done
     LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
@@ -829,6 +876,37 @@ static lp_status time_persistent(const Matrix &m, const StepBench &B, const Step
     return LP_OK;
 }
 
+// Average ms of the stable-model step on m's fixpoint interpretation matrix
+// (every launch reads the same V and writes the same U), over reps launches.
+static lp_status bench_spmm_impl(const Matrix &m, int32_t reps, float *avg_ms, int32_t *products, hipStream_t st) {
+    const int64_t W = ((1ll << m.K_eff) + 63) / 64;
+    const int64_t total = (int64_t)m.n_rows * W;
+    Scratch S(st);
+    uint64_t *buf[2];
+    unsigned long long *counters;
+    lp_status rc;
+    if ((rc = S.get(&buf[0], total)) || (rc = S.get(&buf[1], total)) || (rc = S.get(&counters, kRing))) return rc;
+    int32_t prods = 0;
+    uint64_t *fix = nullptr;
+    if ((rc = stable_fixpoint(m, st, buf, counters, &prods, &fix))) return rc;
+    SpmmParams p = spmm_params(m, counters);
+    p.early_exit = 0;
+    p.V = fix;
+    p.U = fix == buf[0] ? buf[1] : buf[0];
+    p.step = 1;
+    LP_HIP(launch_spmm_step(p, spmm_grid(m), st));  // warm-up
+    Events ev;
+    if ((rc = ev.init())) return rc;
+    LP_HIP(hipEventRecord(ev.a, st));
+    for (int i = 0; i < reps; ++i) LP_HIP(launch_spmm_step(p, spmm_grid(m), st));
+    LP_HIP(hipEventRecord(ev.b, st));
+    float ms = 0.f;
+    if ((rc = ev.elapsed(&ms))) return rc;
+    *avg_ms = ms / (float)reps;
+    if (products) *products = prods;
+    return LP_OK;
+}
+
 static lp_status bench_step_impl(const Matrix &m, const lp_schedule *sched, int32_t reps, float *avg_ms,
                                  hipStream_t st) {
     Scratch S(st);
@@ -864,7 +942,7 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
     float win_ms = 0.f;
     bool have = false;
     const int variants[2] = {LP_STEP_LDS, LP_STEP_GLOBAL};
-    const int wpws[4] = {1, 2, 4, 8};
+    const int wpws[3] = {4, 8, 16};
     const int unrolls[3] = {4, 8, 16};
     for (int v : variants)
         for (int w : wpws)
@@ -873,6 +951,10 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
                 cand.variant = v;
                 cand.wpw = w;
                 cand.unroll = u;
+                StepShape probe;
+                probe.wpw = w;
+                probe.unroll = u;
+                if (!step_shape_supported(probe)) continue;
                 StepParams p = step_params(m);
                 StepShape L;
                 if ((rc = plan_step(m, &cand, p, &L))) return rc;
@@ -1555,6 +1637,19 @@ lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t re
     }
     DeviceGuard g(m->m.dev.device);
     return bench_step_impl(m->m, sched, reps, avg_ms, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_bench_spmm(const lp_matrix *m, int32_t reps, float *avg_ms, int32_t *products, void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K == 0 || m->m.K > LP_MAX_NEG_ATOMS || !avg_ms || reps < 1) {
+        set_error("lp_bench_spmm needs a normal program (1 <= K <= 24), avg_ms and reps >= 1");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return bench_spmm_impl(m->m, reps, avg_ms, products, (hipStream_t)hip_stream);
     LP_GUARD_END
 }
 

@@ -55,135 +55,235 @@ __device__ __forceinline__ uint64_t vword(const StepParams &p, const lds_u32 *s_
     return p.v[word];
 }
 
-// Row data of one super-block (WPW words of 64 rows, one row per lane and
-// word), loaded with vector loads only: scalar loads would share the lgkm
-// counter with the LDS gathers, so every LDS wait would also wait for this
-// prefetch.
+// Row data of one super-block (WPW words of 64 rows), loaded with vector
+// loads only (scalar loads would share the lgkm counter with the LDS gathers,
+// so every LDS wait would also wait for this prefetch): this lane's AND length
+// in each word, four words per dword (lens4 stores them so), and the
+// super-block's first AND entry (the same in every lane).
 template <int WPW>
-struct SuperBlock {
-    int32_t len[WPW];     // this lane's AND length per word
-    int32_t base[WPW];    // WordMeta::and_base
-    uint64_t andb[WPW];   // block AND rows
+struct SbMeta {
+    uint32_t lens[WPW / 4];
+    int32_t b0;
+    uint64_t vw;  // lane w < WPW: word w of the super-block in v (for the new-bit count)
 };
 
 template <int WPW>
-__device__ __forceinline__ void load_super_block(const StepParams &p, int64_t sb, int64_t n_words,
-                                                 SuperBlock<WPW> &m) {
+__device__ __forceinline__ void load_sb_meta(const StepParams &p, int64_t sb, int64_t n_words, SbMeta<WPW> &m) {
+    // lens4 and words carry kWordPad empty words after the end, so every
+    // super-block index below n_sb loads in bounds without checks
     const int lane = threadIdx.x & 63;
-    const int64_t w0 = sb * WPW;
+    const int64_t q0 = sb * (WPW / 4);
+#pragma unroll
+    for (int k = 0; k < WPW / 4; ++k) m.lens[k] = p.lens4[(q0 + k) * 64 + lane];
+    m.b0 = p.words[sb * WPW].and_base;
+    const int64_t wv = sb * WPW + (lane < WPW ? lane : WPW - 1);
+    m.vw = p.v[wv < n_words ? wv : n_words - 1];
+}
+
+template <int WPW>
+__device__ __forceinline__ int32_t lane_len(const uint32_t (&lens)[WPW / 4], int w) {
+    return (int32_t)((lens[w >> 2] >> ((w & 3) * 8)) & 0xffu);
+}
+
+// Loads the U chunks of 64 entries starting at entry base (a multiple of 64):
+// col[base + 64 u + lane]. In bounds: base is at most the number of entries
+// and col carries kColPad zero entries after its end.
+template <int U>
+__device__ __forceinline__ void load_chunks(const StepParams &p, int32_t base, int32_t (&c)[U]) {
+    const int32_t *cb = p.col + base;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = cb[64 * u + lane];
+}
+
+// State of the super-block being evaluated: each lane's first entry per
+// word, the words' entry ranges (wave-uniform: word w covers [ws[w],
+// ws[w + 1])) and this lane's AND results, one bit per word.
+template <int WPW>
+struct SbState {
+    int32_t st[WPW];
+    int32_t ws[WPW + 1];
+    uint32_t lens[WPW / 4];
+    uint32_t accm;
+    uint64_t vw;
+};
+
+// Row starts from the 8-bit lengths: a DPP wave scan per word.
+template <int WPW>
+__device__ __forceinline__ void sb_setup(const SbMeta<WPW> &m, SbState<WPW> &S) {
+    const uint32_t (&lens)[WPW / 4] = m.lens;
+    int32_t run = __builtin_amdgcn_readfirstlane(m.b0);
+    S.accm = 0;
+    S.vw = m.vw;
+#pragma unroll
+    for (int k = 0; k < WPW / 4; ++k) S.lens[k] = lens[k];
 #pragma unroll
     for (int w = 0; w < WPW; ++w) {
-        const int64_t r = (w0 + w) * 64 + lane;
-        m.len[w] = r < p.n_rows ? (int32_t)p.and_len[r] : 0;
-        if (w0 + w < n_words) {
-            const WordMeta wm = p.words[w0 + w];
-            m.base[w] = wm.and_base;
-            m.andb[w] = wm.and_bits;
-        } else {
-            m.base[w] = p.and_end;
-            m.andb[w] = 0;
+        const int32_t len = lane_len<WPW>(lens, w);
+        const int32_t ex = wave_exclusive_scan(len);
+        S.st[w] = run + ex;
+        S.ws[w] = run;
+        if (len) S.accm |= 1u << w;  // block AND rows are exactly the rows with a length
+        run += __builtin_amdgcn_readlane(ex + len, 63);
+    }
+    S.ws[WPW] = run;
+}
+
+// One round: the v bits of the U chunks starting at entry base, one ballot
+// per chunk into the wave's LDS slots, and each row-owner lane's fold of the
+// ballot bits of its entries in this round into its word bit of accm.
+template <int MODE, int WPW, int U>
+__device__ __forceinline__ void eval_round(const lds_u8 *s_v8, const uint8_t *v8, uint32_t lds_bytes,
+                                           const int32_t (&c)[U], int32_t base, SbState<WPW> &S,
+                                           lds_u64 *s_ball) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x[U];
+    if (MODE == kStepLds) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = s_v8[entry_byte(c[u])];
+    } else if (MODE == kStepGlobal) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = v8[entry_byte(c[u])];
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (entry_byte(c[u]) >= lds_bytes) x[u] = v8[entry_byte(c[u])];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (entry_byte(c[u]) < lds_bytes) x[u] = s_v8[entry_byte(c[u])];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[u], (uint32_t)c[u], 1u));
+        if (lane == 0) s_ball[u] = B;
+    }
+    const int32_t lim = base + 64 * U;
+    const lds_u32 *b32 = (const lds_u32 *)s_ball;  // the round's ballot bits, 32 per word
+#pragma unroll
+    for (int w = 0; w < WPW; ++w) {
+        if (S.ws[w + 1] <= base || S.ws[w] >= lim) continue;  // word outside the round (wave-uniform)
+        int32_t lo = S.st[w] > base ? S.st[w] : base;
+        const int32_t en = S.st[w] + lane_len<WPW>(S.lens, w);
+        const int32_t hi = en < lim ? en : lim;
+        while (lo < hi) {  // 32 entries per pass: one pass for rows of up to 32 entries
+            const int32_t rel = lo - base;
+            const int32_t n = hi - lo < 32 ? hi - lo : 32;
+            const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
+            const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
+            if ((win & m) != m) S.accm &= ~(1u << w);
+            lo += n;
         }
     }
 }
 
-// Block pass over this wave's super-blocks; returns this lane's count of new
-// bits. The next super-block's row data is loaded before the current one's
-// chunks, so both travel in the same memory round trip.
+// Results of a finished super-block: one atomic OR per word with AND rows
+// that fire, and the wave's count of new bits (counted in lane 0). The words
+// of v came with the row data, so nothing here waits for memory.
+template <int WPW>
+__device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int64_t sb, int64_t n_words,
+                                              const SbState<WPW> &S) {
+    const int lane = threadIdx.x & 63;
+    uint32_t n_new = 0;
+    const uint32_t vlo = (uint32_t)S.vw, vhi = (uint32_t)(S.vw >> 32);
+#pragma unroll
+    for (int w = 0; w < WPW; ++w) {
+        const int64_t wd = sb * WPW + w;
+        const uint64_t res = __ballot((S.accm >> w) & 1u);
+        if (wd < n_words && res) {
+            // readlane returns int: go through uint32_t so the low half is not sign-extended
+            const uint64_t v = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(vhi, w) << 32) |
+                               (uint64_t)(uint32_t)__builtin_amdgcn_readlane(vlo, w);
+            n_new += (uint32_t)__popcll(res & ~v);
+            if (lane == 0) atomicOr((unsigned long long *)&p.u[wd], (unsigned long long)res);
+        }
+    }
+    return lane == 0 ? n_new : 0;
+}
+
+// Block pass: AND rows of up to kLongAnd entries, as a stream.
 //
-// VALU economy (a wave64 VALU instruction takes 4 cycles on a CDNA SIMD, and
-// this loop is issue-bound, not memory-bound, when written naively):
+// A wave takes super-blocks of WPW words in a grid-stride loop and streams
+// the entries of each one in rounds of U chunks of 64 entries (256 bytes per
+// chunk, coalesced), from the super-block's first entry rounded down to 64 to
+// its last; since a wave's rounds follow each other, the next round's chunks
+// (or the next super-block's first round) are always in flight while the
+// current one is evaluated, and the next super-block's row data is loaded a
+// whole super-block ahead. The round body is written twice with the chunk
+// buffers swapped, so no chunk register is copied (a copy would wait for its
+// load).
+//
+// VALU economy (a wave64 VALU instruction takes 4 cycles on a CDNA SIMD):
 //  * chunk loads are unconditional, from a wave-uniform base plus the lane
-//    offset (col carries kColPad zero entries after its end), so no per-entry
-//    predicate or address arithmetic;
+//    offset, so no per-entry predicate or address arithmetic;
 //  * a gather is one shift (the byte of v), one byte read and one v_bfe_u32
-//    (see entry_byte);
+//    (see entry_byte); v sits at LDS address 0, so the shifted entry is the
+//    address;
 //  * entries outside the super-block are gathered like the others (they name
 //    valid atoms) and simply fall outside every row's range;
-//  * the U chunk ballots of a round go to this wave's LDS slots;
 //  * each row reads the 32-bit window of ballot bits starting at its first
 //    entry (v_alignbit of two consecutive ballot dwords) and compares it with
 //    a mask of its length: one step for rows of up to 32 entries in a round;
-//  * the row-start scan uses DPP, not cross-lane LDS shuffles.
-template <bool LDS, int WPW, int U>
+//  * row starts come from a DPP scan of 8-bit lengths; the AND row bits are
+//    the rows with a nonzero length; per word a lane keeps one start and one
+//    result bit.
+template <int MODE, int WPW, int U>
 __device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u32 *s_v, lds_u64 *s_ball) {
-    const int lane = threadIdx.x & 63;
+    constexpr bool LDS = MODE != kStepGlobal;
     const int waves = blockDim.x >> 6;
     const int64_t n_words = ((int64_t)p.n_rows + 63) >> 6;
     const int64_t n_sb = (n_words + WPW - 1) / WPW;
     const int64_t stride = (int64_t)gridDim.x * waves;
     const uint32_t lds_bytes = LDS ? (uint32_t)p.lds_words * 8u : 0u;
-    const bool lds_only = LDS && (int64_t)p.and_max_col < (int64_t)lds_bytes * 8;
     const lds_u8 *s_v8 = (const lds_u8 *)s_v;
     const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
-    uint32_t my_new = 0;
     int64_t sb = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6);
     if (sb >= n_sb) return 0;
-    SuperBlock<WPW> cur;
-    load_super_block<WPW>(p, sb, n_words, cur);
-    for (; sb < n_sb; sb += stride) {
-        SuperBlock<WPW> nxt;
-        const bool more = sb + stride < n_sb;
-        if (more) load_super_block<WPW>(p, sb + stride, n_words, nxt);
-        const int64_t w0 = sb * WPW;
-        bool acc[WPW];
-        int32_t st[WPW], en[WPW];
-#pragma unroll
-        for (int w = 0; w < WPW; ++w) {
-            st[w] = cur.base[w] + wave_exclusive_scan(cur.len[w]);
-            en[w] = st[w] + cur.len[w];
-            acc[w] = (cur.andb[w] >> lane) & 1ull;
+    // Prefetches past the wave's last super-block reload a valid one (the
+    // last), so every load is unconditional.
+    const int64_t last = n_sb - 1;
+    uint32_t my_new = 0;
+    SbMeta<WPW> nxt;
+    SbState<WPW> S;
+    {
+        SbMeta<WPW> cur;
+        load_sb_meta<WPW>(p, sb, n_words, cur);
+        load_sb_meta<WPW>(p, sb + stride < n_sb ? sb + stride : last, n_words, nxt);
+        sb_setup<WPW>(cur, S);
+    }
+    int32_t base = __builtin_amdgcn_readfirstlane(S.ws[0]) & ~63;
+    int32_t ca[U], cb[U];
+    load_chunks<U>(p, base, ca);
+    // Let the prologue's loads land before the loop: otherwise the compiler's
+    // wait counting merges them into the loop header's state and waits for
+    // every load in flight at the top of each round.
+    __builtin_amdgcn_s_waitcnt(0);
+    // One round: prefetch the next round into cn, evaluate c; at the end of a
+    // super-block, finish it and set up the next. Returns false when the
+    // wave has no super-block left. Every load is issued unconditionally
+    // (the next super-block's row data is simply reloaded while the current
+    // one lasts), and the row data is issued before the chunks, so waiting for
+    // this round's chunks never waits on a load issued later.
+    auto round = [&](const int32_t (&c)[U], int32_t (&cn)[U]) -> bool {
+        const int32_t nb_same = base + 64 * U;
+        const bool same = __builtin_amdgcn_readfirstlane(nb_same < S.ws[WPW] ? 1 : 0) != 0;
+        const SbMeta<WPW> cur = nxt;  // the next super-block's row data (loaded before this round's chunks)
+        const int32_t nb = same ? nb_same : (__builtin_amdgcn_readfirstlane(cur.b0) & ~63);
+        const int64_t meta_sb = same ? sb + stride : sb + 2 * stride;
+        load_sb_meta<WPW>(p, meta_sb < n_sb ? meta_sb : last, n_words, nxt);
+        load_chunks<U>(p, nb, cn);
+        eval_round<MODE, WPW, U>(s_v8, v8, lds_bytes, c, base, S, s_ball);
+        if (!same) {
+            my_new += sb_finish<WPW>(p, sb, n_words, S);
+            sb += stride;
+            if (sb >= n_sb) return false;
+            sb_setup<WPW>(cur, S);
         }
-        const int32_t e0 = __builtin_amdgcn_readfirstlane(cur.base[0]);
-        const int32_t e1 = __builtin_amdgcn_readlane(en[WPW - 1], 63);
-        for (int32_t base = e0 & ~63; base < e1; base += 64 * U) {
-            const int32_t *cb = p.col + base;
-            int32_t c[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) c[u] = cb[64 * u + lane];
-            uint32_t x[U];
-            if (lds_only) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) x[u] = s_v8[entry_byte(c[u])];
-            } else {
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (!LDS || entry_byte(c[u]) >= lds_bytes) x[u] = v8[entry_byte(c[u])];
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (LDS && entry_byte(c[u]) < lds_bytes) x[u] = s_v8[entry_byte(c[u])];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[u], (uint32_t)c[u], 1u));
-                if (lane == 0) s_ball[u] = B;
-            }
-            const int32_t lim = base + 64 * U;
-            const lds_u32 *b32 = (const lds_u32 *)s_ball;  // the round's ballot bits, 32 per word
-#pragma unroll
-            for (int w = 0; w < WPW; ++w) {
-                int32_t lo = st[w] > base ? st[w] : base;
-                const int32_t hi = en[w] < lim ? en[w] : lim;
-                while (lo < hi) {  // 32 entries per pass: one pass for rows of up to 32 entries
-                    const int32_t rel = lo - base;
-                    const int32_t n = hi - lo < 32 ? hi - lo : 32;
-                    const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
-                    const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
-                    acc[w] = acc[w] && ((win & m) == m);
-                    lo += n;
-                }
-            }
-        }
-#pragma unroll
-        for (int w = 0; w < WPW; ++w) {
-            if (w0 + w < n_words) {
-                const uint64_t res = __ballot(acc[w]);
-                if (lane == 0 && res) {
-                    atomicOr((unsigned long long *)&p.u[w0 + w], (unsigned long long)res);
-                    my_new += (uint32_t)__popcll(res & ~vword<LDS>(p, s_v, w0 + w));
-                }
-            }
-        }
-        if (more) cur = nxt;
+        base = nb;
+        return true;
+    };
+    for (;;) {
+        if (!round(ca, cb)) break;
+        if (!round(cb, ca)) break;
     }
     return my_new;
 }
@@ -278,54 +378,72 @@ __device__ __forceinline__ uint32_t long_rows(const StepParams &p, const lds_u32
     return my_new;
 }
 
-// Copies the leading lds_words words of v into LDS: 16-byte loads, four in
-// flight per thread before any is stored.
+// Copies the leading lds_words words of v into LDS: 16-byte loads, up to
+// eight in flight per thread before any is stored (one memory round trip for
+// 128 KB with 1,024 threads).
 __device__ __forceinline__ void stage_v(const StepParams &p, lds_u32 *s_v) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(3))) u32x4 lds_u4;
+    constexpr int kInFlight = 8;
     lds_u4 *d = (lds_u4 *)s_v;
     const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v);
     const int32_t n16 = p.lds_words >> 1;
     const int32_t bd = blockDim.x;
-    for (int32_t i = threadIdx.x; i < n16; i += 4 * bd) {
-        u32x4 x[4];
+    for (int32_t i = threadIdx.x; i < n16; i += kInFlight * bd) {
+        u32x4 x[kInFlight];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < kInFlight; ++k)
             if (i + k * bd < n16) x[k] = src[i + k * bd];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < kInFlight; ++k)
             if (i + k * bd < n16) d[i + k * bd] = x[k];
     }
     if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.lds_words - 1];
 }
 
-__device__ __forceinline__ void add_new_bits(uint32_t my_new, uint32_t *s_new, unsigned long long *slot) {
+__device__ __forceinline__ void add_new_bits(uint32_t my_new, lds_u32 *s_new, unsigned long long *slot) {
     my_new = wave_sum(my_new);
-    if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(s_new, my_new);
+    if ((threadIdx.x & 63) == 0 && my_new)
+        __hip_atomic_fetch_add(s_new, my_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
     if (threadIdx.x == 0 && *s_new) atomicAdd(slot, (unsigned long long)*s_new);
 }
 
 }  // namespace
 
-template <bool LDS, int WPW, int U>
+// LDS of the staged forms, one static array so that v sits at LDS address 0
+// and a gather's address is the shifted entry itself: [v: step_lds_v_words]
+// [ballot slots: kMaxWaves x (U + 1) words][new-bit count]. The global form
+// keeps only the ballot slots and the count.
+template <int MODE, int U>
+struct StepLds {
+    static constexpr int kV = MODE == kStepGlobal ? 0 : kStepLdsBytes / 8 - kMaxWaves * (U + 1) - 2;
+    static constexpr int kWords = kV + kMaxWaves * (U + 1) + 2;
+    lds_u32 *v;
+    lds_u64 *my_ball;
+    lds_u32 *n_new;
+    __device__ __forceinline__ explicit StepLds(lds_u64 *base) {
+        v = (lds_u32 *)base;
+        my_ball = base + kV + (threadIdx.x >> 6) * (U + 1);
+        n_new = (lds_u32 *)(base + kV + kMaxWaves * (U + 1));
+    }
+};
+
+template <int MODE, int WPW, int U>
 __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
-    extern __shared__ uint64_t s_dyn[];  // 8-byte aligned
-    lds_u32 *s_v = (lds_u32 *)s_dyn;
-    __shared__ uint64_t s_ball[kMaxWaves * (U + 1)];
-    __shared__ uint32_t s_new;
-    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * (U + 1);
-    if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
+    __shared__ uint64_t s_lds[StepLds<MODE, U>::kWords];
+    const StepLds<MODE, U> L((lds_u64 *)s_lds);
+    if ((threadIdx.x & 63) == 0) L.my_ball[U] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
     if (p.early_exit && p.step >= 2 && p.counters[(p.step - 1) & (kRing - 1)] == 0) return;
-    if (threadIdx.x == 0) s_new = 0;
-    if (LDS) stage_v(p, s_v);
+    if (threadIdx.x == 0) *L.n_new = 0;
+    if (MODE != kStepGlobal) stage_v(p, L.v);
     __syncthreads();
     // long-row segments first: they are the longest items, so they start early
-    uint32_t my_new = long_rows<LDS, U>(p, s_v);
-    my_new += or_rows<LDS>(p, s_v);
-    my_new += block_rows<LDS, WPW, U>(p, s_v, my_ball);
-    add_new_bits(my_new, &s_new, &p.counters[p.step & (kRing - 1)]);
+    uint32_t my_new = long_rows<MODE != kStepGlobal, U>(p, L.v);
+    my_new += or_rows<MODE != kStepGlobal>(p, L.v);
+    my_new += block_rows<MODE, WPW, U>(p, L.v, L.my_ball);
+    add_new_bits(my_new, L.n_new, &p.counters[p.step & (kRing - 1)]);
 }
 
 // The whole Algorithm 1 loop in one cooperative launch. Each product: stage v
@@ -334,13 +452,13 @@ __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
 // wrote), read the count. Every workgroup reads the same count after the
 // barrier, so all leave the loop on the same product; max_steps (a monotone
 // iteration needs at most n_rows + 1 products) guarantees the loop ends.
-template <int WPW, int U>
+template <int MODE, int WPW, int U>
 __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistParams q) {
-    extern __shared__ uint64_t s_dyn[];
-    lds_u32 *s_v = (lds_u32 *)s_dyn;
-    __shared__ uint64_t s_ball[kMaxWaves * (U + 1)];
-    __shared__ uint32_t s_new;
-    lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * (U + 1);
+    __shared__ uint64_t s_lds[StepLds<MODE, U>::kWords];
+    const StepLds<MODE, U> L((lds_u64 *)s_lds);
+    lds_u32 *s_v = L.v;
+    lds_u64 *my_ball = L.my_ball;
+    lds_u32 *s_new_p = L.n_new;
     if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
     StepParams p = q.p;
     for (int32_t step = 1;; ++step) {
@@ -349,13 +467,13 @@ __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistPar
         p.u = (step & 1) ? q.buf1 : q.buf0;
         unsigned long long *slot = &p.counters[step & (kRing - 1)];
         if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(step + 1) & (kRing - 1)] = 0;
-        if (threadIdx.x == 0) s_new = 0;
+        if (threadIdx.x == 0) *s_new_p = 0;
         stage_v(p, s_v);
         __syncthreads();
         uint32_t my_new = long_rows<true, U>(p, s_v);
         my_new += or_rows<true>(p, s_v);
-        my_new += block_rows<true, WPW, U>(p, s_v, my_ball);
-        add_new_bits(my_new, &s_new, slot);
+        my_new += block_rows<MODE, WPW, U>(p, s_v, my_ball);
+        add_new_bits(my_new, s_new_p, slot);
         cooperative_groups::this_grid().sync();
         const unsigned long long changed = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (changed == 0 || step >= q.max_steps) {
@@ -367,8 +485,7 @@ __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistPar
 
 // ------------------------------------------------------------------ launchers
 
-#define LP_STEP_SHAPES(X) \
-    X(1, 4) X(1, 8) X(1, 16) X(2, 4) X(2, 8) X(2, 16) X(4, 4) X(4, 8) X(4, 16) X(8, 4) X(8, 8) X(8, 16)
+#define LP_STEP_SHAPES(X) X(4, 4) X(4, 8) X(4, 16) X(8, 4) X(8, 8) X(8, 16) X(16, 8) X(16, 16)
 
 bool step_shape_supported(const StepShape &s) {
 #define LP_X(W, U) \
@@ -379,13 +496,15 @@ bool step_shape_supported(const StepShape &s) {
 }
 
 hipError_t launch_step(const StepShape &s, const StepParams &p, hipStream_t st) {
-#define LP_X(W, U)                                                                                \
-    if (s.wpw == W && s.unroll == U) {                                                            \
-        if (s.lds)                                                                                \
-            hipLaunchKernelGGL((tp_step_kernel<true, W, U>), dim3(s.grid), dim3(s.block), s.lds_bytes, st, p); \
-        else                                                                                      \
-            hipLaunchKernelGGL((tp_step_kernel<false, W, U>), dim3(s.grid), dim3(s.block), 0, st, p); \
-        return hipGetLastError();                                                                 \
+#define LP_X(W, U)                                                                                       \
+    if (s.wpw == W && s.unroll == U) {                                                                   \
+        if (s.mode == kStepLds)                                                                          \
+            hipLaunchKernelGGL((tp_step_kernel<kStepLds, W, U>), dim3(s.grid), dim3(s.block), 0, st, p);   \
+        else if (s.mode == kStepMixed)                                                                   \
+            hipLaunchKernelGGL((tp_step_kernel<kStepMixed, W, U>), dim3(s.grid), dim3(s.block), 0, st, p); \
+        else                                                                                             \
+            hipLaunchKernelGGL((tp_step_kernel<kStepGlobal, W, U>), dim3(s.grid), dim3(s.block), 0, st, p); \
+        return hipGetLastError();                                                                        \
     }
     LP_STEP_SHAPES(LP_X)
 #undef LP_X
@@ -393,8 +512,12 @@ hipError_t launch_step(const StepShape &s, const StepParams &p, hipStream_t st) 
 }
 
 static const void *persistent_fn(const StepShape &s) {
-#define LP_X(W, U) \
-    if (s.wpw == W && s.unroll == U) return (const void *)tp_fixpoint_persistent_kernel<W, U>;
+#define LP_X(W, U)                                                                                       \
+    if (s.wpw == W && s.unroll == U) {                                                                   \
+        if (s.mode == kStepLds) return (const void *)tp_fixpoint_persistent_kernel<kStepLds, W, U>;     \
+        if (s.mode == kStepMixed) return (const void *)tp_fixpoint_persistent_kernel<kStepMixed, W, U>; \
+        return nullptr;                                                                                  \
+    }
     LP_STEP_SHAPES(LP_X)
 #undef LP_X
     return nullptr;
@@ -405,24 +528,13 @@ hipError_t launch_persistent(const StepShape &s, const PersistParams &q, hipStre
     if (!fn) return hipErrorInvalidValue;
     PersistParams copy = q;
     void *args[] = {&copy};
-    return hipLaunchCooperativeKernel(fn, dim3(s.grid), dim3(s.block), args, (unsigned int)s.lds_bytes, st);
+    return hipLaunchCooperativeKernel(fn, dim3(s.grid), dim3(s.block), args, 0, st);
 }
 
 hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu) {
     const void *fn = persistent_fn(s);
     if (!fn) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, s.block, s.lds_bytes);
-}
-
-void step_kernels_allow_lds(int max_dynamic_lds) {
-#define LP_X(W, U)                                                                                      \
-    (void)hipFuncSetAttribute((const void *)tp_step_kernel<true, W, U>,                                 \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds);             \
-    (void)hipFuncSetAttribute((const void *)tp_fixpoint_persistent_kernel<W, U>,                        \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds);
-    LP_STEP_SHAPES(LP_X)
-#undef LP_X
-    (void)hipGetLastError();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, s.block, 0);
 }
 
 }  // namespace lp

@@ -47,7 +47,7 @@ EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg
            "lp_batch_get_info", "lp_batch_free", "lp_matrix_evict", "lp_matrix_upload",
            "lp_server_create", "lp_server_add_program", "lp_server_submit", "lp_server_wait_any",
            "lp_server_take_result", "lp_server_get_stats", "lp_server_free",
-           "lp_memory_stats", "lp_release_cached_memory",
+           "lp_memory_stats", "lp_release_cached_memory", "lp_bench_spmm",
            "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_last_error")
 
 
@@ -149,6 +149,7 @@ def load():
         "lp_server_free": [P],
         "lp_memory_stats": [ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "lp_release_cached_memory": [],
+        "lp_bench_spmm": [P, i32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32), P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -303,6 +304,13 @@ class Matrix:
         _check(load().lp_bench_step(self._h, ctypes.byref(sched) if sched is not None else None,
                                     int(reps), ctypes.byref(ms), _stream(stream)))
         return ms.value
+
+    def bench_spmm(self, reps: int = 20, stream=None):
+        """(average ms of one stable-model step on the fixpoint, fixpoint products)."""
+        ms = ctypes.c_float(0)
+        pr = ctypes.c_int32(0)
+        _check(load().lp_bench_spmm(self._h, int(reps), ctypes.byref(ms), ctypes.byref(pr), _stream(stream)))
+        return ms.value, pr.value
 
     def tune(self, reps: int = 20, stream=None):
         """(best lp_schedule, step ms, solve ms) from lp_tune_schedule."""

@@ -45,9 +45,10 @@ SCHEDULES = {
     "persistent": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT),
     "persistent-grid2": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT, grid=2),
     "persistent-w8-u16": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT, wpw=8, unroll=16),
-    "lds-w1-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=1, unroll=4),
+    "lds-w4-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=4, unroll=4),
+    "lds-w16-u8": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=16, unroll=8),
     "lds-w8-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=8, unroll=16),
-    "global-w1-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=1, unroll=16),
+    "global-w16-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=16, unroll=16),
     "global-w8-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=8, unroll=4,
                                      grid=5),
     "auto": None,
@@ -127,6 +128,20 @@ def test_chain_zipf_full_size():
         for name in ("batched-global", "persistent", "auto"):
             got, prods = m.least_model(sched=SCHEDULES[name])
             assert np.array_equal(got, want) and prods == 2000, name
+
+
+@pytest.mark.parametrize("variant", ["lds", "global"])
+def test_more_atoms_than_lds_holds(variant):
+    # 1,400,000 atoms: more original atoms than one workgroup's LDS can stage
+    # (about 1.29 million), so the staged step gathers the rest from global
+    # memory (the mixed form)
+    p = gen.definite_uniform(11, 1_400_000, 2_000_000, 0.01, 4)
+    want, want_prods, _, _ = oracle.sd_fixpoint(p)
+    v = lp.LP_STEP_LDS if variant == "lds" else lp.LP_STEP_GLOBAL
+    for shape in ((8, 16), (4, 8)):
+        got, prods = _least(p, sched=lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=v, wpw=shape[0],
+                                                      unroll=shape[1]))
+        assert np.array_equal(got, want) and prods == want_prods, shape
 
 
 def test_bench_step_runs():

@@ -127,7 +127,7 @@ __device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 
             for (int k = 0; k < U; ++k) c[k] = cb[64 * k + lane];
             uint32_t x[U];
 #pragma unroll
-            for (int k = 0; k < U; ++k) x[k] = v8[entry_byte(c[k])];
+            for (int k = 0; k < U; ++k) x[k] = entry_word(v8, c[k]);
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[k], (uint32_t)c[k], 1u));
@@ -196,7 +196,7 @@ __device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const ld
             for (int q = 0; q < nseg; ++q) total += sg[q].len;
             for (int64_t i = lane; i < total; i += 64) {
                 const int32_t e = d.long_col[begin + i];
-                all &= __builtin_amdgcn_ubfe((uint32_t)v8[entry_byte(e)], (uint32_t)e, 1u) != 0;
+                all &= __builtin_amdgcn_ubfe(entry_word(v8, e), (uint32_t)e, 1u) != 0;
             }
             fire = __ballot(!all) == 0;
         }

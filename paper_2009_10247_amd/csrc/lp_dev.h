@@ -17,10 +17,27 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 
-// AND entries are stored encoded as ((c >> 3) << 5) | (c & 7): one shift gives
-// the byte of v holding atom c, and the low five bits are its bit offset in
-// that byte, which v_bfe_u32 takes as is.
+// AND entries are stored encoded as ((c >> 5) << 7) | (c & 31): one shift
+// gives the byte address of the 32-bit word of v holding atom c (a multiple
+// of 4), and the low five bits are its bit offset in that word, which
+// v_bfe_u32 takes as is. Gathers read whole aligned words, so no masking of a
+// narrower load is needed.
 __device__ __forceinline__ uint32_t entry_byte(int32_t e) { return (uint32_t)e >> 5; }
+
+__device__ __forceinline__ uint32_t entry_word(const lds_u8 *v, int32_t e) {
+    return *(const lds_u32 *)(v + entry_byte(e));
+}
+
+__device__ __forceinline__ uint32_t entry_word(const uint8_t *v, int32_t e) {
+    return *reinterpret_cast<const uint32_t *>(v + entry_byte(e));
+}
+
+// Index of this wave in the grid (blockIdx.x * waves + wave in block), made
+// visibly wave-uniform so that loop counters derived from it stay scalar.
+__device__ __forceinline__ int64_t grid_wave() {
+    const int32_t w = (int32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    return (int64_t)__builtin_amdgcn_readfirstlane(w);
+}
 
 __device__ inline uint64_t range_mask(int s, int t) {  // bits [s, t), 0 <= s < t <= 64
     const uint64_t hi = (t >= 64) ? ~0ull : ((1ull << t) - 1ull);

@@ -218,9 +218,10 @@ static void free_device(Matrix &m, hipStream_t st) {
     d = DeviceMatrix{};
 }
 
-// AND entries as the kernels read them: the byte of v holding atom c, shifted
-// left by 5, and c's bit offset in that byte in the low bits.
-static inline int32_t encode_entry(int32_t c) { return ((c >> 3) << 5) | (c & 7); }
+// AND entries as the kernels read them: the byte address of the 32-bit word
+// of v holding atom c, shifted left by 5, and c's bit offset in that word in
+// the low five bits.
+static inline int32_t encode_entry(int32_t c) { return ((c >> 5) << 7) | (c & 31); }
 
 // Least-model layout (see WordMeta and LongSeg): rows by kind, AND entries of
 // block rows in col, OR rows as child ranges, long rows as segments.

@@ -108,23 +108,36 @@ struct SbState {
     uint64_t vw;
 };
 
-// Row starts from the 8-bit lengths: a DPP wave scan per word.
+// Row starts from the 8-bit lengths. The lengths of words 4k and 4k + 2 (and
+// of 4k + 1 and 4k + 3) are scanned together as the two 16-bit halves of one
+// 32-bit DPP wave scan: a half's sum is at most 64 x 255 < 2^16, so no carry
+// crosses between them. Two scans per four words.
 template <int WPW>
 __device__ __forceinline__ void sb_setup(const SbMeta<WPW> &m, SbState<WPW> &S) {
-    const uint32_t (&lens)[WPW / 4] = m.lens;
     int32_t run = __builtin_amdgcn_readfirstlane(m.b0);
     S.accm = 0;
     S.vw = m.vw;
 #pragma unroll
-    for (int k = 0; k < WPW / 4; ++k) S.lens[k] = lens[k];
+    for (int k = 0; k < WPW / 4; ++k) {
+        const uint32_t L = m.lens[k];
+        S.lens[k] = L;
+        const int32_t pa = (int32_t)(L & 0x00ff00ffu);         // words 4k and 4k + 2
+        const int32_t pb = (int32_t)((L >> 8) & 0x00ff00ffu);  // words 4k + 1 and 4k + 3
+        const int32_t ea = wave_exclusive_scan(pa);
+        const int32_t eb = wave_exclusive_scan(pb);
+        const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane(ea + pa, 63);
+        const uint32_t tb = (uint32_t)__builtin_amdgcn_readlane(eb + pb, 63);
+        const int32_t ex[4] = {ea & 0xffff, eb & 0xffff, (int32_t)((uint32_t)ea >> 16), (int32_t)((uint32_t)eb >> 16)};
+        const int32_t tot[4] = {(int32_t)(ta & 0xffffu), (int32_t)(tb & 0xffffu), (int32_t)(ta >> 16),
+                                (int32_t)(tb >> 16)};
 #pragma unroll
-    for (int w = 0; w < WPW; ++w) {
-        const int32_t len = lane_len<WPW>(lens, w);
-        const int32_t ex = wave_exclusive_scan(len);
-        S.st[w] = run + ex;
-        S.ws[w] = run;
-        if (len) S.accm |= 1u << w;  // block AND rows are exactly the rows with a length
-        run += __builtin_amdgcn_readlane(ex + len, 63);
+        for (int j = 0; j < 4; ++j) {
+            const int w = 4 * k + j;
+            S.st[w] = run + ex[j];
+            S.ws[w] = run;
+            if ((L >> (8 * j)) & 0xffu) S.accm |= 1u << w;  // block AND rows are exactly the rows with a length
+            run += tot[j];
+        }
     }
     S.ws[WPW] = run;
 }
@@ -140,17 +153,17 @@ __device__ __forceinline__ void eval_round(const lds_u8 *s_v8, const uint8_t *v8
     uint32_t x[U];
     if (MODE == kStepLds) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = s_v8[entry_byte(c[u])];
+        for (int u = 0; u < U; ++u) x[u] = entry_word(s_v8, c[u]);
     } else if (MODE == kStepGlobal) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = v8[entry_byte(c[u])];
+        for (int u = 0; u < U; ++u) x[u] = entry_word(v8, c[u]);
     } else {
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (entry_byte(c[u]) >= lds_bytes) x[u] = v8[entry_byte(c[u])];
+            if (entry_byte(c[u]) >= lds_bytes) x[u] = entry_word(v8, c[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (entry_byte(c[u]) < lds_bytes) x[u] = s_v8[entry_byte(c[u])];
+            if (entry_byte(c[u]) < lds_bytes) x[u] = entry_word(s_v8, c[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -165,14 +178,15 @@ __device__ __forceinline__ void eval_round(const lds_u8 *s_v8, const uint8_t *v8
         int32_t lo = S.st[w] > base ? S.st[w] : base;
         const int32_t en = S.st[w] + lane_len<WPW>(S.lens, w);
         const int32_t hi = en < lim ? en : lim;
+        uint32_t bad = 0;  // entries of the row that are 0
         while (lo < hi) {  // 32 entries per pass: one pass for rows of up to 32 entries
             const int32_t rel = lo - base;
             const int32_t n = hi - lo < 32 ? hi - lo : 32;
-            const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
-            const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
-            if ((win & m) != m) S.accm &= ~(1u << w);
+            const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], (uint32_t)rel);
+            bad |= ~win & (0xffffffffu >> (32 - n));  // the window's first n bits
             lo += n;
         }
+        if (bad) S.accm &= ~(1u << w);
     }
 }
 
@@ -215,9 +229,9 @@ __device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int64_t sb, i
 // VALU economy (a wave64 VALU instruction takes 4 cycles on a CDNA SIMD):
 //  * chunk loads are unconditional, from a wave-uniform base plus the lane
 //    offset, so no per-entry predicate or address arithmetic;
-//  * a gather is one shift (the byte of v), one byte read and one v_bfe_u32
-//    (see entry_byte); v sits at LDS address 0, so the shifted entry is the
-//    address;
+//  * a gather is one shift (the 32-bit word of v), one word read and one
+//    v_bfe_u32 (see entry_byte); v sits at LDS address 0, so the shifted entry
+//    is the address;
 //  * entries outside the super-block are gathered like the others (they name
 //    valid atoms) and simply fall outside every row's range;
 //  * each row reads the 32-bit window of ballot bits starting at its first
@@ -236,7 +250,7 @@ __device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u3
     const uint32_t lds_bytes = LDS ? (uint32_t)p.lds_words * 8u : 0u;
     const lds_u8 *s_v8 = (const lds_u8 *)s_v;
     const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
-    int64_t sb = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6);
+    int64_t sb = grid_wave();
     if (sb >= n_sb) return 0;
     // Prefetches past the wave's last super-block reload a valid one (the
     // last), so every load is unconditional.
@@ -299,7 +313,7 @@ __device__ __forceinline__ uint32_t or_rows(const StepParams &p, const lds_u32 *
     const int64_t stride = (int64_t)gridDim.x * waves;
     const int64_t n_tiles = ((int64_t)p.n_or + 63) >> 6;
     uint32_t my_new = 0;
-    for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile < n_tiles; tile += stride) {
+    for (int64_t tile = grid_wave(); tile < n_tiles; tile += stride) {
         const int64_t j = tile * 64 + lane;
         if (j < p.n_or) {
             const int32_t row = p.or_row[j];
@@ -324,7 +338,7 @@ __device__ __forceinline__ uint32_t long_rows(const StepParams &p, const lds_u32
     const lds_u8 *s_v8 = (const lds_u8 *)s_v;
     const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
     uint32_t my_new = 0;
-    for (int64_t si = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); si < p.n_segs; si += stride) {
+    for (int64_t si = grid_wave(); si < p.n_segs; si += stride) {
         const LongSeg sg = p.segs[si];
         bool any = false, all = true;
         if (sg.is_and) {
@@ -338,8 +352,8 @@ __device__ __forceinline__ uint32_t long_rows(const StepParams &p, const lds_u32
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (c[u] >= 0) {
-                        const uint32_t bi = entry_byte(c[u]);
-                        const uint32_t x = (LDS && bi < lds_bytes) ? s_v8[bi] : v8[bi];
+                        const uint32_t x = (LDS && entry_byte(c[u]) < lds_bytes) ? entry_word(s_v8, c[u])
+                                                                                : entry_word(v8, c[u]);
                         all &= __builtin_amdgcn_ubfe(x, (uint32_t)c[u], 1u) != 0;
                     }
                 }

@@ -253,8 +253,8 @@ def main() -> int:
     variants = {}
     if args.sweep:
         for v, vname in ((lp.LP_STEP_LDS, "lds"), (lp.LP_STEP_GLOBAL, "global")):
-            for w in (4, 8, 16):
-                for u in (4, 8, 16) if w < 16 else (8, 16):
+            for w in (4, 8):
+                for u in (4, 8, 16):
                     ms = m.bench_step(reps=args.step_reps, stream=stream,
                                       sched=lp.make_schedule(variant=v, wpw=w, unroll=u))
                     variants[f"{vname}-w{w}-u{u}"] = round(ms * 1e3, 2)

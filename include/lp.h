@@ -119,10 +119,9 @@ typedef struct lp_schedule {
     int32_t steps_per_sync;  /* products issued between host checks (BATCHED, AUTO) */
     int32_t variant;         /* LP_STEP_* kernel of the least-model step */
     int32_t grid;            /* workgroups of the step (0: one per CU for LDS, eight per CU otherwise) */
-    int32_t wpw;             /* step: 64-row words per super-block, 4, 8 or 16; batch kernel: words per
+    int32_t wpw;             /* step: 64-row words per super-block, 4 or 8; batch kernel: words per
                                 wave, 1, 2 or 4 (0: default) */
-    int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16; 16 words per
-                                super-block take 8 or 16 (0: default) */
+    int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16 (0: default) */
     int32_t block;           /* batch kernel: threads per workgroup, 256, 512 or 1024 (0: 512) */
     int32_t reserved;
 } lp_schedule;
@@ -329,7 +328,7 @@ lp_status lp_bench_spmm(const lp_matrix *m, int32_t reps, float *avg_ms, int32_t
 
 /*
  * Autotuner for least-model solves of m (a definite program). Times every
- * supported step shape (LP_STEP_LDS / LP_STEP_GLOBAL, 4/8/16 words per super-block,
+ * supported step shape (LP_STEP_LDS / LP_STEP_GLOBAL, 4 or 8 words per super-block,
  * 4/8/16 chunks in flight) over reps full-sweep steps on m's own fixpoint
  * with HIP events, then times whole solves with the batched driver and, when
  * the fastest step is shorter than 20 us (where launch overhead matters), the

@@ -90,7 +90,7 @@ __device__ __forceinline__ void wg_load_super_block(const GProg &d, int64_t sb, 
     }
 }
 
-// AND rows of the block pass (see block_rows in lp_step.hip).
+// AND rows of the block pass (see BlockPass in lp_step.hip).
 template <int WPW, int U>
 __device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 *v, lds_u64 *u,
                                                   lds_u64 *s_ball) {

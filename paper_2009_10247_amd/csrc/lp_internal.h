@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "lp.h"
@@ -61,6 +62,10 @@ struct DeviceMatrix {
     int32_t and_max_col = -1;     // largest column of a block AND entry
     int64_t and_nnz = 0, long_nnz = 0;
     int64_t stream_bytes = 0;     // bytes one full step streams from memory (layout arrays)
+    std::vector<int32_t> word_base;  // host: first AND entry of each word, then the entry count [n_words + 1]
+    // device splits of the block pass between waves, one per wave count
+    // (created on first use by the step planner, under its lock)
+    mutable std::vector<std::pair<int32_t, int32_t *>> wave_parts;
     // stable models (normal programs): plain CSR
     int32_t *full_row_ptr = nullptr;
     int32_t *full_col = nullptr;

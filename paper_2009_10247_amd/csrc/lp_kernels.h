@@ -28,6 +28,7 @@ struct StepParams {
     const uint64_t *v;             // [n_words] v_t
     uint64_t *u;                   // [n_words] holds a subset of the result; the step ORs into it
     unsigned long long *counters;  // change-count ring
+    const int32_t *wave_part;      // [2 (waves + 1)]: wave k's first word and that word's first AND entry
     int32_t n_rows;
     int32_t n_long_and;
     int32_t n_segs;
@@ -54,7 +55,7 @@ inline int32_t step_lds_v_words(int unroll) { return kStepLdsBytes / 8 - 16 * (u
 // (a super-block) and keeps unroll column chunks of 64 entries in flight.
 struct StepShape {
     int mode = kStepLds;  // StepMode; staged forms use 1024-thread workgroups, one per CU
-    int wpw = 8;          // words per super-block: 4, 8 or 16
+    int wpw = 8;          // words per super-block: 4 or 8
     int unroll = 8;       // 4, 8 or 16
     int block = 1024;     // threads per workgroup
     int grid = 0;         // workgroups (grid-stride loop over super-blocks)

@@ -215,6 +215,7 @@ static void free_device(Matrix &m, hipStream_t st) {
     void *ps[] = {d.words,        d.and_len,       d.lens4,  d.col,      d.or_c0,  d.or_row,    d.fact_bits, d.segs, d.long_col,
                   d.full_row_ptr, d.full_col,      d.full_and_bits, d.q_rows, d.guess_pos};
     for (void *p : ps) dev_free(p, st);
+    for (auto &wp : d.wave_parts) dev_free(wp.second, st);
     d = DeviceMatrix{};
 }
 
@@ -315,6 +316,9 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
         return LP_E_INVAL;
     }
     d.and_nnz = (int64_t)col.size();
+    d.word_base.resize((size_t)W + 1);
+    for (int64_t w = 0; w < W; ++w) d.word_base[w] = words[w].and_base;
+    d.word_base[W] = (int32_t)d.and_nnz;
     d.long_nnz = (int64_t)lcol.size();
     d.n_segs = (int32_t)segs.size();
     d.n_long_and = n_long_and;
@@ -440,10 +444,59 @@ static StepParams step_params(const Matrix &m) {
     return p;
 }
 
+// Per-word cost of the block pass split, in AND entries. A word's row data
+// (lengths, scans, the result) is cheap in dense stretches, but where words
+// have few entries a round ends several super-blocks and each further one
+// waits for its row data; measured on MI355X, the split balances best with a
+// word counted as about 600 entries (the benchmark program has ~245 AND
+// entries per word on average, with a stretch of sparse words).
+constexpr int64_t kWordCost = 600;
+
+// Split of the block pass between `waves` waves: wave k takes the words
+// [t[2k], t[2k + 2]) and t[2k + 1] is the first AND entry of word t[2k]. Each
+// wave gets about the same cost (AND entries + kWordCost per word), so the
+// waves' streams end together. Created once per wave count and kept with the
+// matrix's device arrays.
+static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, const int32_t **out) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    const DeviceMatrix &d = m.dev;
+    for (const auto &wp : d.wave_parts)
+        if (wp.first == waves) {
+            *out = wp.second;
+            return LP_OK;
+        }
+    const std::vector<int32_t> &b = d.word_base;
+    if (b.empty() || waves < 1) {
+        set_error("no least-model layout to split");
+        return LP_E_INTERNAL;
+    }
+    const int64_t W = (int64_t)b.size() - 1;
+    const int64_t total = (int64_t)b[W] + kWordCost * W;
+    std::vector<int32_t> t(2 * ((size_t)waves + 1));
+    int64_t w = 0;
+    for (int32_t k = 0; k < waves; ++k) {
+        const int64_t target = total * k / waves;
+        while (w < W && (int64_t)b[w] + kWordCost * w < target) ++w;
+        t[2 * (size_t)k] = (int32_t)w;
+        t[2 * (size_t)k + 1] = b[w];
+    }
+    t[2 * (size_t)waves] = (int32_t)W;
+    t[2 * (size_t)waves + 1] = b[W];
+    int32_t *dp = nullptr;
+    int64_t bytes = 0;
+    lp_status rc = upload(&dp, t.data(), t.size(), st, &bytes);
+    if (rc) return rc;
+    LP_HIP(hipStreamSynchronize(st));  // t is a local
+    d.wave_parts.emplace_back(waves, dp);
+    *out = dp;
+    return LP_OK;
+}
+
 // Launch shape of the step for a whole solve. LDS shapes use one 1024-thread
 // workgroup per CU (the staged v takes most of the CU's LDS); global shapes
 // use 256-thread workgroups, eight per CU.
-static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S) {
+static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S, hipStream_t st) {
     int variant = sched ? sched->variant : LP_STEP_AUTO;
     if (variant == LP_STEP_AUTO) variant = LP_STEP_LDS;
     if (variant != LP_STEP_LDS && variant != LP_STEP_GLOBAL) {
@@ -458,7 +511,7 @@ static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams
     s.wpw = sched && sched->wpw > 0 ? sched->wpw : 8;
     s.unroll = sched && sched->unroll > 0 ? sched->unroll : (staged ? 16 : 8);
     if (!step_shape_supported(s)) {
-        set_error("unsupported step shape (words per super-block 4/8/16 with 4/8/16 chunks; 16 words with 8 or 16)");
+        set_error("unsupported step shape (words per super-block 4 or 8, chunks in flight 4, 8 or 16)");
         return LP_E_INVAL;
     }
     const int64_t n_words = n_words_of(m.n_rows);
@@ -483,16 +536,17 @@ static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams
     const int64_t grid = sched && sched->grid > 0 ? sched->grid : dflt;
     s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, want));
     *S = s;
-    return LP_OK;
+    return wave_partition(m, s.grid * waves, st, &p.wave_part);
 }
 
 // Shape of the persistent fixpoint: the LDS step with at most as many
 // workgroups as can be resident at once (the grid barrier needs all of them
 // running). S->grid = 0 if not even one fits.
-static lp_status plan_persistent(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S) {
+static lp_status plan_persistent(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S,
+                                 hipStream_t st) {
     lp_schedule s2 = sched ? *sched : lp_schedule{};
     s2.variant = LP_STEP_LDS;
-    lp_status rc = plan_step(m, &s2, p, S);
+    lp_status rc = plan_step(m, &s2, p, S, st);
     if (rc) return rc;
     int per_cu = 0;
     LP_HIP(persistent_occupancy(*S, &per_cu));
@@ -500,7 +554,8 @@ static lp_status plan_persistent(const Matrix &m, const lp_schedule *sched, Step
     if ((rc = dev_props(m.dev.device, &d))) return rc;
     const int64_t resident = (int64_t)per_cu * d.n_cu;
     S->grid = (int)std::min<int64_t>(S->grid, resident);
-    return LP_OK;
+    if (S->grid < 1) return LP_OK;
+    return wave_partition(m, S->grid * (S->block / 64), st, &p.wave_part);
 }
 
 static lp_status run_persistent(const Matrix &m, const StepParams &p, const StepShape &S, uint64_t *const buf[2],
@@ -542,7 +597,7 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
     p.and_cnt = and_cnt;
     StepShape L;
     if (driver == LP_DRIVER_PERSISTENT) {
-        if ((rc = plan_persistent(m, sched, p, &L))) return rc;
+        if ((rc = plan_persistent(m, sched, p, &L, st))) return rc;
         if (L.grid >= 1) {
             int32_t *res;
             if ((rc = S.get(&res, 1))) return rc;
@@ -566,7 +621,7 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
         batch = (sched && sched->steps_per_sync > 0) ? sched->steps_per_sync : 32;
     }
     batch = std::max(1, std::min(batch, kRing / 2 - 1));
-    if ((rc = plan_step(m, sched, p, &L))) return rc;
+    if ((rc = plan_step(m, sched, p, &L, st))) return rc;
     unsigned long long *h = pinned_ring();
     if (!h) {
         set_error("pinned host allocation failed");
@@ -917,19 +972,19 @@ static lp_status bench_step_impl(const Matrix &m, const lp_schedule *sched, int3
     StepParams p = step_params(m);
     StepShape L;
     if (sched && sched->driver == LP_DRIVER_PERSISTENT) {
-        if ((rc = plan_persistent(m, sched, p, &L))) return rc;
+        if ((rc = plan_persistent(m, sched, p, &L, st))) return rc;
         if (L.grid < 1) {
             set_error("the persistent step does not fit on this device");
             return LP_E_DEVICE;
         }
         return time_persistent(m, B, L, p, reps, st, S, avg_ms);
     }
-    if ((rc = plan_step(m, sched, p, &L))) return rc;
+    if ((rc = plan_step(m, sched, p, &L, st))) return rc;
     return time_steps(m, B, L, p, reps, st, avg_ms);
 }
 
 // Autotuner: time every supported step shape (LDS-staged and global
-// gathers; 1/2/4/8 words per wave; 4/8/16 chunks in flight) on the matrix's
+// gathers; 4 or 8 words per super-block; 4/8/16 chunks in flight) on the matrix's
 // own fixpoint, then compare whole solves with the batched and persistent
 // drivers at the fastest shape.
 static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, float *best_step_ms,
@@ -943,7 +998,7 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
     float win_ms = 0.f;
     bool have = false;
     const int variants[2] = {LP_STEP_LDS, LP_STEP_GLOBAL};
-    const int wpws[3] = {4, 8, 16};
+    const int wpws[2] = {4, 8};
     const int unrolls[3] = {4, 8, 16};
     for (int v : variants)
         for (int w : wpws)
@@ -958,7 +1013,7 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
                 if (!step_shape_supported(probe)) continue;
                 StepParams p = step_params(m);
                 StepShape L;
-                if ((rc = plan_step(m, &cand, p, &L))) return rc;
+                if ((rc = plan_step(m, &cand, p, &L, st))) return rc;
                 float ms = 0.f;
                 if ((rc = time_steps(m, B, L, p, 2, st, &ms))) return rc;  // warm-up
                 if ((rc = time_steps(m, B, L, p, reps, st, &ms))) return rc;
@@ -995,7 +1050,7 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
     if (win_ms < 0.020f) {
         StepParams p = step_params(m);
         StepShape L;
-        if ((rc = plan_persistent(m, &persistent, p, &L))) return rc;
+        if ((rc = plan_persistent(m, &persistent, p, &L, st))) return rc;
         if (L.grid >= 1) {
             float ms = 0.f;
             if ((rc = time_persistent(m, B, L, p, 1, st, S, &ms))) return rc;

@@ -55,11 +55,12 @@ __device__ __forceinline__ uint64_t vword(const StepParams &p, const lds_u32 *s_
     return p.v[word];
 }
 
-// Row data of one super-block (WPW words of 64 rows), loaded with vector
-// loads only (scalar loads would share the lgkm counter with the LDS gathers,
-// so every LDS wait would also wait for this prefetch): this lane's AND length
-// in each word, four words per dword (lens4 stores them so), and the
-// super-block's first AND entry (the same in every lane).
+// Row data of one super-block (WPW words of 64 rows from word sbw, a
+// multiple of 4), loaded with vector loads only (scalar loads would share the
+// lgkm counter with the LDS gathers, so every LDS wait would also wait for
+// this prefetch): this lane's AND length in each word, four words per dword
+// (lens4 stores them so), the first AND entry of the super-block's first word
+// in the wave's range (the same in every lane) and the v words.
 template <int WPW>
 struct SbMeta {
     uint32_t lens[WPW / 4];
@@ -68,15 +69,16 @@ struct SbMeta {
 };
 
 template <int WPW>
-__device__ __forceinline__ void load_sb_meta(const StepParams &p, int64_t sb, int64_t n_words, SbMeta<WPW> &m) {
+__device__ __forceinline__ void load_sb_meta(const StepParams &p, int32_t sbw, int32_t w_begin, int32_t n_words,
+                                             SbMeta<WPW> &m) {
     // lens4 and words carry kWordPad empty words after the end, so every
-    // super-block index below n_sb loads in bounds without checks
+    // super-block that starts before the last word loads in bounds
     const int lane = threadIdx.x & 63;
-    const int64_t q0 = sb * (WPW / 4);
+    const int64_t q0 = sbw >> 2;
 #pragma unroll
     for (int k = 0; k < WPW / 4; ++k) m.lens[k] = p.lens4[(q0 + k) * 64 + lane];
-    m.b0 = p.words[sb * WPW].and_base;
-    const int64_t wv = sb * WPW + (lane < WPW ? lane : WPW - 1);
+    m.b0 = p.words[sbw > w_begin ? sbw : w_begin].and_base;
+    const int32_t wv = sbw + (lane < WPW ? lane : WPW - 1);
     m.vw = p.v[wv < n_words ? wv : n_words - 1];
 }
 
@@ -87,7 +89,7 @@ __device__ __forceinline__ int32_t lane_len(const uint32_t (&lens)[WPW / 4], int
 
 // Loads the U chunks of 64 entries starting at entry base (a multiple of 64):
 // col[base + 64 u + lane]. In bounds: base is at most the number of entries
-// and col carries kColPad zero entries after its end.
+// rounded down to 64, and col carries kColPad zero entries after its end.
 template <int U>
 __device__ __forceinline__ void load_chunks(const StepParams &p, int32_t base, int32_t (&c)[U]) {
     const int32_t *cb = p.col + base;
@@ -108,18 +110,24 @@ struct SbState {
     uint64_t vw;
 };
 
-// Row starts from the 8-bit lengths. The lengths of words 4k and 4k + 2 (and
-// of 4k + 1 and 4k + 3) are scanned together as the two 16-bit halves of one
-// 32-bit DPP wave scan: a half's sum is at most 64 x 255 < 2^16, so no carry
-// crosses between them. Two scans per four words.
+// Row starts from the 8-bit lengths of the words in [w_begin, w_end) (the
+// others are masked to length 0: they belong to another wave). The lengths
+// of words 4k and 4k + 2 (and of 4k + 1 and 4k + 3) are scanned together as
+// the two 16-bit halves of one 32-bit DPP wave scan: a half's sum is at most
+// 64 x 255 < 2^16, so no carry crosses between them. Two scans per four words.
 template <int WPW>
-__device__ __forceinline__ void sb_setup(const SbMeta<WPW> &m, SbState<WPW> &S) {
+__device__ __forceinline__ void sb_setup(const SbMeta<WPW> &m, int32_t sbw, int32_t w_begin, int32_t w_end,
+                                         SbState<WPW> &S) {
     int32_t run = __builtin_amdgcn_readfirstlane(m.b0);
     S.accm = 0;
     S.vw = m.vw;
 #pragma unroll
     for (int k = 0; k < WPW / 4; ++k) {
-        const uint32_t L = m.lens[k];
+        // bytes of the words in [w_begin, w_end) (wave-uniform)
+        const int32_t lo = min(max(w_begin - sbw - 4 * k, 0), 4);
+        const int32_t hi = min(max(w_end - sbw - 4 * k, 0), 4);
+        const uint32_t keep = (hi == 4 ? ~0u : (1u << (8 * hi)) - 1u) & (lo == 4 ? 0u : ~((1u << (8 * lo)) - 1u));
+        const uint32_t L = m.lens[k] & keep;
         S.lens[k] = L;
         const int32_t pa = (int32_t)(L & 0x00ff00ffu);         // words 4k and 4k + 2
         const int32_t pb = (int32_t)((L >> 8) & 0x00ff00ffu);  // words 4k + 1 and 4k + 3
@@ -142,13 +150,11 @@ __device__ __forceinline__ void sb_setup(const SbMeta<WPW> &m, SbState<WPW> &S) 
     S.ws[WPW] = run;
 }
 
-// One round: the v bits of the U chunks starting at entry base, one ballot
-// per chunk into the wave's LDS slots, and each row-owner lane's fold of the
-// ballot bits of its entries in this round into its word bit of accm.
-template <int MODE, int WPW, int U>
-__device__ __forceinline__ void eval_round(const lds_u8 *s_v8, const uint8_t *v8, uint32_t lds_bytes,
-                                           const int32_t (&c)[U], int32_t base, SbState<WPW> &S,
-                                           lds_u64 *s_ball) {
+// The v bits of the U chunks of one round, one ballot per chunk into the
+// wave's LDS slots.
+template <int MODE, int U>
+__device__ __forceinline__ void round_ballots(const lds_u8 *s_v8, const uint8_t *v8, uint32_t lds_bytes,
+                                              const int32_t (&c)[U], lds_u64 *s_ball) {
     const int lane = threadIdx.x & 63;
     uint32_t x[U];
     if (MODE == kStepLds) {
@@ -170,6 +176,12 @@ __device__ __forceinline__ void eval_round(const lds_u8 *s_v8, const uint8_t *v8
         const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[u], (uint32_t)c[u], 1u));
         if (lane == 0) s_ball[u] = B;
     }
+}
+
+// Each row-owner lane's fold of the ballot bits of its entries in the round
+// [base, base + 64 U) into its word bit of accm.
+template <int WPW, int U>
+__device__ __forceinline__ void fold_round(const lds_u64 *s_ball, int32_t base, SbState<WPW> &S) {
     const int32_t lim = base + 64 * U;
     const lds_u32 *b32 = (const lds_u32 *)s_ball;  // the round's ballot bits, 32 per word
 #pragma unroll
@@ -194,14 +206,14 @@ __device__ __forceinline__ void eval_round(const lds_u8 *s_v8, const uint8_t *v8
 // that fire, and the wave's count of new bits (counted in lane 0). The words
 // of v came with the row data, so nothing here waits for memory.
 template <int WPW>
-__device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int64_t sb, int64_t n_words,
+__device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int32_t sbw, int32_t n_words,
                                               const SbState<WPW> &S) {
     const int lane = threadIdx.x & 63;
     uint32_t n_new = 0;
     const uint32_t vlo = (uint32_t)S.vw, vhi = (uint32_t)(S.vw >> 32);
 #pragma unroll
     for (int w = 0; w < WPW; ++w) {
-        const int64_t wd = sb * WPW + w;
+        const int32_t wd = sbw + w;
         const uint64_t res = __ballot((S.accm >> w) & 1u);
         if (wd < n_words && res) {
             // readlane returns int: go through uint32_t so the low half is not sign-extended
@@ -214,15 +226,17 @@ __device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int64_t sb, i
     return lane == 0 ? n_new : 0;
 }
 
-// Block pass: AND rows of up to kLongAnd entries, as a stream.
+// Block pass: AND rows of up to kLongAnd entries, as one stream per wave.
 //
-// A wave takes super-blocks of WPW words in a grid-stride loop and streams
-// the entries of each one in rounds of U chunks of 64 entries (256 bytes per
-// chunk, coalesced), from the super-block's first entry rounded down to 64 to
-// its last; since a wave's rounds follow each other, the next round's chunks
-// (or the next super-block's first round) are always in flight while the
-// current one is evaluated, and the next super-block's row data is loaded a
-// whole super-block ahead. The round body is written twice with the chunk
+// Wave k owns the words [wave_part[2k], wave_part[2k + 2]) (a host-computed
+// split with about the same number of AND entries per wave) and streams their
+// AND entries, one contiguous stretch of col, in rounds of U chunks of 64
+// entries (256 bytes per chunk, coalesced). The rows are taken in
+// super-blocks of WPW words aligned to 4 words; words of a super-block outside
+// the wave's range count as empty. The next round's chunks are always in
+// flight while the current round is evaluated, and the next super-block's row
+// data is loaded a super-block ahead. A round may end one super-block and
+// continue into the next. The round body is written twice with the chunk
 // buffers swapped, so no chunk register is copied (a copy would wait for its
 // load).
 //
@@ -232,7 +246,7 @@ __device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int64_t sb, i
 //  * a gather is one shift (the 32-bit word of v), one word read and one
 //    v_bfe_u32 (see entry_byte); v sits at LDS address 0, so the shifted entry
 //    is the address;
-//  * entries outside the super-block are gathered like the others (they name
+//  * entries outside the wave's range are gathered like the others (they name
 //    valid atoms) and simply fall outside every row's range;
 //  * each row reads the 32-bit window of ballot bits starting at its first
 //    entry (v_alignbit of two consecutive ballot dwords) and compares it with
@@ -241,86 +255,149 @@ __device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int64_t sb, i
 //    the rows with a nonzero length; per word a lane keeps one start and one
 //    result bit.
 template <int MODE, int WPW, int U>
-__device__ __forceinline__ uint32_t block_rows(const StepParams &p, const lds_u32 *s_v, lds_u64 *s_ball) {
-    constexpr bool LDS = MODE != kStepGlobal;
-    const int waves = blockDim.x >> 6;
-    const int64_t n_words = ((int64_t)p.n_rows + 63) >> 6;
-    const int64_t n_sb = (n_words + WPW - 1) / WPW;
-    const int64_t stride = (int64_t)gridDim.x * waves;
-    const uint32_t lds_bytes = LDS ? (uint32_t)p.lds_words * 8u : 0u;
-    const lds_u8 *s_v8 = (const lds_u8 *)s_v;
-    const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
-    int64_t sb = grid_wave();
-    if (sb >= n_sb) return 0;
-    // Prefetches past the wave's last super-block reload a valid one (the
-    // last), so every load is unconditional.
-    const int64_t last = n_sb - 1;
-    uint32_t my_new = 0;
-    SbMeta<WPW> nxt;
+struct BlockPass {
+    int32_t w_begin, w_end;  // the wave's words
+    int32_t sbw;             // first word of the current super-block
+    int32_t sb_last;         // first word of the wave's last super-block
+    int32_t n_words;
+    int32_t base;            // first entry of the current round (a multiple of 64)
+    SbMeta<WPW> cur, nxt, alt;  // cur: the first super-block's row data, until start()
     SbState<WPW> S;
-    {
-        SbMeta<WPW> cur;
-        load_sb_meta<WPW>(p, sb, n_words, cur);
-        load_sb_meta<WPW>(p, sb + stride < n_sb ? sb + stride : last, n_words, nxt);
-        sb_setup<WPW>(cur, S);
-    }
-    int32_t base = __builtin_amdgcn_readfirstlane(S.ws[0]) & ~63;
     int32_t ca[U], cb[U];
-    load_chunks<U>(p, base, ca);
-    // Let the prologue's loads land before the loop: otherwise the compiler's
-    // wait counting merges them into the loop header's state and waits for
-    // every load in flight at the top of each round.
-    __builtin_amdgcn_s_waitcnt(0);
-    // One round: prefetch the next round into cn, evaluate c; at the end of a
-    // super-block, finish it and set up the next. Returns false when the
-    // wave has no super-block left. Every load is issued unconditionally
-    // (the next super-block's row data is simply reloaded while the current
-    // one lasts), and the row data is issued before the chunks, so waiting for
-    // this round's chunks never waits on a load issued later.
-    auto round = [&](const int32_t (&c)[U], int32_t (&cn)[U]) -> bool {
-        const int32_t nb_same = base + 64 * U;
-        const bool same = __builtin_amdgcn_readfirstlane(nb_same < S.ws[WPW] ? 1 : 0) != 0;
-        const SbMeta<WPW> cur = nxt;  // the next super-block's row data (loaded before this round's chunks)
-        const int32_t nb = same ? nb_same : (__builtin_amdgcn_readfirstlane(cur.b0) & ~63);
-        const int64_t meta_sb = same ? sb + stride : sb + 2 * stride;
-        load_sb_meta<WPW>(p, meta_sb < n_sb ? meta_sb : last, n_words, nxt);
-        load_chunks<U>(p, nb, cn);
-        eval_round<MODE, WPW, U>(s_v8, v8, lds_bytes, c, base, S, s_ball);
-        if (!same) {
-            my_new += sb_finish<WPW>(p, sb, n_words, S);
-            sb += stride;
-            if (sb >= n_sb) return false;
-            sb_setup<WPW>(cur, S);
-        }
-        base = nb;
+
+    // Issues the row data of the wave's first two super-blocks and its first
+    // round of chunks. Called before v is staged, so these loads overlap the
+    // staging and everything else the wave does before the stream. False if
+    // the wave has no words.
+    __device__ __forceinline__ bool prefetch(const StepParams &p) {
+        n_words = (p.n_rows + 63) >> 6;
+        const int64_t k = grid_wave();
+        w_begin = p.wave_part[2 * k];
+        w_end = p.wave_part[2 * k + 2];
+        if (w_begin >= w_end) return false;
+        sbw = w_begin & ~3;
+        sb_last = sbw + ((w_end - 1 - sbw) / WPW) * WPW;
+        base = p.wave_part[2 * k + 1] & ~63;
+        load_sb_meta<WPW>(p, sbw, w_begin, n_words, cur);
+        load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
+        load_chunks<U>(p, base, ca);
         return true;
-    };
-    for (;;) {
-        if (!round(ca, cb)) break;
-        if (!round(cb, ca)) break;
     }
-    return my_new;
-}
+
+    // Sets up the first super-block (its row data has landed by now).
+    __device__ __forceinline__ void start() { sb_setup<WPW>(cur, sbw, w_begin, w_end, S); }
+
+    __device__ __forceinline__ uint32_t run(const StepParams &p, const lds_u32 *s_v, lds_u64 *s_ball) {
+        const uint32_t lds_bytes = MODE != kStepGlobal ? (uint32_t)p.lds_words * 8u : 0u;
+        const lds_u8 *s_v8 = (const lds_u8 *)s_v;
+        const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
+        const int32_t e_cap = p.and_end & ~63;  // chunk loads start at most here (col is padded past it)
+        uint32_t my_new = 0;
+        // Let the loads issued so far land before the loop: otherwise the
+        // compiler's wait counting merges them into the loop header's state
+        // and waits for every load in flight at the top of each round.
+        __builtin_amdgcn_s_waitcnt(0);
+        // One round: prefetch the next round into cn and row data into mb,
+        // evaluate c. ma holds the row data of the super-block after the
+        // current one (loaded at least a round ago); mb receives the one after
+        // the next if the current super-block ends in this round, else the
+        // next one again, so that every round issues the same loads and mb
+        // ends the round holding the super-block after the (new) current one.
+        // The row data alternates between two register sets like the chunks,
+        // so nothing waits for a load to copy it. Returns false when the
+        // wave's last super-block is done.
+        auto round = [&](const int32_t (&c)[U], int32_t (&cn)[U], const SbMeta<WPW> &ma,
+                         SbMeta<WPW> &mb) -> bool {
+            const int32_t lim = base + 64 * U;
+            const bool ends = __builtin_amdgcn_readfirstlane(S.ws[WPW]) <= lim;
+            const int32_t mw = ends ? sbw + 2 * WPW : sbw + WPW;
+            load_sb_meta<WPW>(p, mw <= sb_last ? mw : sb_last, w_begin, n_words, mb);
+            load_chunks<U>(p, lim < e_cap ? lim : e_cap, cn);
+            // keep the scheduler from hoisting this round's gathers (which
+            // wait for its chunks) above the next round's loads
+            __builtin_amdgcn_sched_barrier(0);
+            round_ballots<MODE, U>(s_v8, v8, lds_bytes, c, s_ball);
+            fold_round<WPW, U>(s_ball, base, S);
+            if (ends) {
+                my_new += sb_finish<WPW>(p, sbw, n_words, S);
+                if (sbw >= sb_last) return false;
+                sbw += WPW;
+                sb_setup<WPW>(ma, sbw, w_begin, w_end, S);
+                // super-blocks with fewer entries than a round: mb already
+                // holds the next one (loaded above), the one after it is
+                // loaded here and waited for at once, so that the common
+                // path's wait counts at the top of a round stay exact
+                while (S.ws[WPW] <= lim) {
+                    fold_round<WPW, U>(s_ball, base, S);
+                    my_new += sb_finish<WPW>(p, sbw, n_words, S);
+                    if (sbw >= sb_last) return false;
+                    sbw += WPW;
+                    sb_setup<WPW>(mb, sbw, w_begin, w_end, S);
+                    load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, mb);
+                    __builtin_amdgcn_s_waitcnt(0);
+                }
+                fold_round<WPW, U>(s_ball, base, S);
+            }
+            base = lim;
+            return true;
+        };
+        for (;;) {
+            if (!round(ca, cb, nxt, alt)) break;
+            if (!round(cb, ca, alt, nxt)) break;
+        }
+        return my_new;
+    }
+};
 
 // OR rows that are not long, 64 per wave: lane j takes OR row 64*tile + j,
 // reads its child range from or_c0, ORs the words of v in that range and, if
 // it fires, sets the row's bit. An OR row is evaluated by exactly one lane, so
-// it is new iff its bit is 0 in v.
+// it is new iff its bit is 0 in v. A wave takes four of its tiles at a time
+// and issues all their loads together: the range table, then the first and
+// last word of every range (the words between them, rare for OR rows of at
+// most kLongOrBits children, are read after).
 template <bool LDS>
 __device__ __forceinline__ uint32_t or_rows(const StepParams &p, const lds_u32 *s_v) {
+    constexpr int G = 4;
     const int lane = threadIdx.x & 63;
-    const int waves = blockDim.x >> 6;
-    const int64_t stride = (int64_t)gridDim.x * waves;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t n_tiles = ((int64_t)p.n_or + 63) >> 6;
     uint32_t my_new = 0;
-    for (int64_t tile = grid_wave(); tile < n_tiles; tile += stride) {
-        const int64_t j = tile * 64 + lane;
-        if (j < p.n_or) {
-            const int32_t row = p.or_row[j];
-            if (row >= 0 && any_in_range(p.v, p.or_c0[j], p.or_c0[j + 1])) {
-                const uint64_t bit = 1ull << (row & 63);
-                atomicOr((unsigned long long *)&p.u[row >> 6], (unsigned long long)bit);
-                if (!(vword<LDS>(p, s_v, row >> 6) & bit)) my_new += 1;
+    for (int64_t t0 = grid_wave(); t0 < n_tiles; t0 += G * stride) {
+        int32_t row[G], c0[G], c1[G];
+        uint64_t a[G], z[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {  // j clamped to the last OR row: in bounds, marked invalid
+            const int64_t j = (t0 + g * stride) * 64 + lane;
+            const int64_t jc = j < p.n_or ? j : p.n_or - 1;
+            row[g] = p.or_row[jc];
+            c0[g] = p.or_c0[jc];
+            c1[g] = p.or_c0[jc + 1];
+            if (j >= p.n_or || c1[g] <= c0[g]) row[g] = -1;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int32_t w0 = row[g] >= 0 ? c0[g] >> 6 : 0;
+            const int32_t w1 = row[g] >= 0 ? (c1[g] - 1) >> 6 : 0;
+            a[g] = p.v[w0];
+            z[g] = p.v[w1];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (row[g] < 0) continue;
+            const int32_t w0 = c0[g] >> 6, w1 = (c1[g] - 1) >> 6;
+            const int s = c0[g] & 63, t = ((c1[g] - 1) & 63) + 1;
+            bool any;
+            if (w0 == w1) {
+                any = (a[g] & range_mask(s, t)) != 0;
+            } else {
+                any = (a[g] & range_mask(s, 64)) != 0 || (z[g] & range_mask(0, t)) != 0;
+                for (int32_t wd = w0 + 1; wd < w1 && !any; ++wd) any = p.v[wd] != 0;
+            }
+            if (any) {
+                const uint64_t bit = 1ull << (row[g] & 63);
+                atomicOr((unsigned long long *)&p.u[row[g] >> 6], (unsigned long long)bit);
+                if (!(vword<LDS>(p, s_v, row[g] >> 6) & bit)) my_new += 1;
             }
         }
     }
@@ -451,12 +528,17 @@ __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
     if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
     if (p.early_exit && p.step >= 2 && p.counters[(p.step - 1) & (kRing - 1)] == 0) return;
     if (threadIdx.x == 0) *L.n_new = 0;
+    // The block pass's first loads go out first, so the stream is in flight
+    // while v is staged and while the OR rows and segments are evaluated.
+    BlockPass<MODE, WPW, U> bp;
+    const bool blocks = bp.prefetch(p);
     if (MODE != kStepGlobal) stage_v(p, L.v);
+    if (blocks) bp.start();
     __syncthreads();
     // long-row segments first: they are the longest items, so they start early
     uint32_t my_new = long_rows<MODE != kStepGlobal, U>(p, L.v);
     my_new += or_rows<MODE != kStepGlobal>(p, L.v);
-    my_new += block_rows<MODE, WPW, U>(p, L.v, L.my_ball);
+    if (blocks) my_new += bp.run(p, L.v, L.my_ball);
     add_new_bits(my_new, L.n_new, &p.counters[p.step & (kRing - 1)]);
 }
 
@@ -482,11 +564,14 @@ __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistPar
         unsigned long long *slot = &p.counters[step & (kRing - 1)];
         if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(step + 1) & (kRing - 1)] = 0;
         if (threadIdx.x == 0) *s_new_p = 0;
+        BlockPass<MODE, WPW, U> bp;
+        const bool blocks = bp.prefetch(p);
         stage_v(p, s_v);
+        if (blocks) bp.start();
         __syncthreads();
         uint32_t my_new = long_rows<true, U>(p, s_v);
         my_new += or_rows<true>(p, s_v);
-        my_new += block_rows<MODE, WPW, U>(p, s_v, my_ball);
+        if (blocks) my_new += bp.run(p, s_v, my_ball);
         add_new_bits(my_new, s_new_p, slot);
         cooperative_groups::this_grid().sync();
         const unsigned long long changed = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -499,7 +584,7 @@ __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistPar
 
 // ------------------------------------------------------------------ launchers
 
-#define LP_STEP_SHAPES(X) X(4, 4) X(4, 8) X(4, 16) X(8, 4) X(8, 8) X(8, 16) X(16, 8) X(16, 16)
+#define LP_STEP_SHAPES(X) X(4, 4) X(4, 8) X(4, 16) X(8, 4) X(8, 8) X(8, 16)
 
 bool step_shape_supported(const StepShape &s) {
 #define LP_X(W, U) \

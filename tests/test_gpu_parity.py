@@ -46,9 +46,9 @@ SCHEDULES = {
     "persistent-grid2": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT, grid=2),
     "persistent-w8-u16": lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT, wpw=8, unroll=16),
     "lds-w4-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=4, unroll=4),
-    "lds-w16-u8": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=16, unroll=8),
+    "lds-w4-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=4, unroll=16),
     "lds-w8-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_LDS, wpw=8, unroll=16),
-    "global-w16-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=16, unroll=16),
+    "global-w4-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=4, unroll=16),
     "global-w8-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=8, unroll=4,
                                      grid=5),
     "auto": None,
@@ -170,6 +170,9 @@ def test_unsupported_shape_is_an_error():
     with lp.Matrix(gen.definite_uniform(0, 100, 200)) as m:
         with pytest.raises(lp.LPError) as e:
             m.least_model(sched=lp.make_schedule(wpw=3))
+        assert e.value.code == lp.LP_E_INVAL
+        with pytest.raises(lp.LPError) as e:
+            m.least_model(sched=lp.make_schedule(wpw=16))
         assert e.value.code == lp.LP_E_INVAL
 
 

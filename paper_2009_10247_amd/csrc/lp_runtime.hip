@@ -451,12 +451,16 @@ static StepParams step_params(const Matrix &m) {
 // word counted as about 600 entries (the benchmark program has ~245 AND
 // entries per word on average, with a stretch of sparse words).
 constexpr int64_t kWordCost = 600;
+// Cost of an OR tile and of a long-row segment in the same units: a wave that
+// evaluates them gets that much less of the block pass.
+constexpr int64_t kOrTileCost = 3200;
+constexpr int64_t kSegCost = 3200;
 
 // Split of the block pass between `waves` waves: wave k takes the words
 // [t[2k], t[2k + 2]) and t[2k + 1] is the first AND entry of word t[2k]. Each
-// wave gets about the same cost (AND entries + kWordCost per word), so the
-// waves' streams end together. Created once per wave count and kept with the
-// matrix's device arrays.
+// wave gets about the same cost (AND entries + kWordCost per word of its
+// block pass, plus its OR tiles and segments), so the waves end together.
+// Created once per wave count and kept with the matrix's device arrays.
 static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, const int32_t **out) {
     static std::mutex mu;
     std::lock_guard<std::mutex> lock(mu);
@@ -472,14 +476,22 @@ static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, 
         return LP_E_INTERNAL;
     }
     const int64_t W = (int64_t)b.size() - 1;
-    const int64_t total = (int64_t)b[W] + kWordCost * W;
+    // wave k also evaluates OR tiles k, k + waves, ... and segments k, k + waves, ...
+    const int64_t n_tiles = ((int64_t)d.n_or + 63) / 64;
+    auto extra = [&](int64_t k) -> int64_t {
+        const int64_t tiles = k < n_tiles ? (n_tiles - 1 - k) / waves + 1 : 0;
+        const int64_t segs = k < d.n_segs ? ((int64_t)d.n_segs - 1 - k) / waves + 1 : 0;
+        return kOrTileCost * tiles + kSegCost * segs;
+    };
+    int64_t total = (int64_t)b[W] + kWordCost * W;
+    for (int64_t k = 0; k < waves; ++k) total += extra(k);
     std::vector<int32_t> t(2 * ((size_t)waves + 1));
-    int64_t w = 0;
+    int64_t w = 0, cut = 0;  // cut: block-pass cost before wave k's first word
     for (int32_t k = 0; k < waves; ++k) {
-        const int64_t target = total * k / waves;
-        while (w < W && (int64_t)b[w] + kWordCost * w < target) ++w;
+        while (w < W && (int64_t)b[w] + kWordCost * w < cut) ++w;
         t[2 * (size_t)k] = (int32_t)w;
         t[2 * (size_t)k + 1] = b[w];
+        cut += std::max<int64_t>(0, total / waves - extra(k));
     }
     t[2 * (size_t)waves] = (int32_t)W;
     t[2 * (size_t)waves + 1] = b[W];

@@ -88,8 +88,9 @@ __device__ __forceinline__ int32_t lane_len(const uint32_t (&lens)[WPW / 4], int
 }
 
 // Loads the U chunks of 64 entries starting at entry base (a multiple of 64):
-// col[base + 64 u + lane]. In bounds: base is at most the number of entries
-// rounded down to 64, and col carries kColPad zero entries after its end.
+// col[base + 64 u + lane]. In bounds: base + 64 U is at most the number of
+// entries rounded up to 64, or a small wave's first chunk + 64 U, and col
+// carries kColPad zero entries after its end.
 template <int U>
 __device__ __forceinline__ void load_chunks(const StepParams &p, int32_t base, int32_t (&c)[U]) {
     const int32_t *cb = p.col + base;
@@ -261,7 +262,8 @@ struct BlockPass {
     int32_t sb_last;         // first word of the wave's last super-block
     int32_t n_words;
     int32_t base;            // first entry of the current round (a multiple of 64)
-    SbMeta<WPW> cur, nxt, alt;  // cur: the first super-block's row data, until start()
+    int32_t last_base;       // start of the round that ends at the wave's last entry (rounded up to 64)
+    SbMeta<WPW> cur, nxt;    // cur: the first super-block's row data, until start()
     SbState<WPW> S;
     int32_t ca[U], cb[U];
 
@@ -278,6 +280,7 @@ struct BlockPass {
         sbw = w_begin & ~3;
         sb_last = sbw + ((w_end - 1 - sbw) / WPW) * WPW;
         base = p.wave_part[2 * k + 1] & ~63;
+        last_base = max(0, ((p.wave_part[2 * k + 3] + 63) & ~63) - 64 * U);
         load_sb_meta<WPW>(p, sbw, w_begin, n_words, cur);
         load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
         load_chunks<U>(p, base, ca);
@@ -291,59 +294,47 @@ struct BlockPass {
         const uint32_t lds_bytes = MODE != kStepGlobal ? (uint32_t)p.lds_words * 8u : 0u;
         const lds_u8 *s_v8 = (const lds_u8 *)s_v;
         const uint8_t *v8 = reinterpret_cast<const uint8_t *>(p.v);
-        const int32_t e_cap = p.and_end & ~63;  // chunk loads start at most here (col is padded past it)
         uint32_t my_new = 0;
         // Let the loads issued so far land before the loop: otherwise the
         // compiler's wait counting merges them into the loop header's state
         // and waits for every load in flight at the top of each round.
         __builtin_amdgcn_s_waitcnt(0);
-        // One round: prefetch the next round into cn and row data into mb,
-        // evaluate c. ma holds the row data of the super-block after the
-        // current one (loaded at least a round ago); mb receives the one after
-        // the next if the current super-block ends in this round, else the
-        // next one again, so that every round issues the same loads and mb
-        // ends the round holding the super-block after the (new) current one.
-        // The row data alternates between two register sets like the chunks,
-        // so nothing waits for a load to copy it. Returns false when the
+        // One round: prefetch the next round into cn, evaluate c, and finish
+        // every super-block that ends in this round. At each such end the
+        // next super-block is set up from nxt and the one after it is loaded
+        // into nxt, to be used at the next end (normally a round or more
+        // later; a round that ends several super-blocks waits for it). Row
+        // data is thus read once per super-block. Returns false when the
         // wave's last super-block is done.
-        auto round = [&](const int32_t (&c)[U], int32_t (&cn)[U], const SbMeta<WPW> &ma,
-                         SbMeta<WPW> &mb) -> bool {
+        auto round = [&](const int32_t (&c)[U], int32_t (&cn)[U]) -> bool {
             const int32_t lim = base + 64 * U;
-            const bool ends = __builtin_amdgcn_readfirstlane(S.ws[WPW]) <= lim;
-            const int32_t mw = ends ? sbw + 2 * WPW : sbw + WPW;
-            load_sb_meta<WPW>(p, mw <= sb_last ? mw : sb_last, w_begin, n_words, mb);
-            load_chunks<U>(p, lim < e_cap ? lim : e_cap, cn);
+            // The next round starts at lim, except that no round reads past
+            // the wave's last entry (rounded up to 64): those entries belong to
+            // the next wave, which read them long ago, so reading them again
+            // would come from memory. The last round therefore starts earlier
+            // and evaluates some entries twice (harmless: a row's fold only
+            // clears bits), and the round after the last one reloads it.
+            const int32_t nb = max(base, min(lim, last_base));
+            load_chunks<U>(p, nb, cn);
             // keep the scheduler from hoisting this round's gathers (which
             // wait for its chunks) above the next round's loads
             __builtin_amdgcn_sched_barrier(0);
             round_ballots<MODE, U>(s_v8, v8, lds_bytes, c, s_ball);
             fold_round<WPW, U>(s_ball, base, S);
-            if (ends) {
+            while (__builtin_amdgcn_readfirstlane(S.ws[WPW]) <= lim) {
                 my_new += sb_finish<WPW>(p, sbw, n_words, S);
                 if (sbw >= sb_last) return false;
                 sbw += WPW;
-                sb_setup<WPW>(ma, sbw, w_begin, w_end, S);
-                // super-blocks with fewer entries than a round: mb already
-                // holds the next one (loaded above), the one after it is
-                // loaded here and waited for at once, so that the common
-                // path's wait counts at the top of a round stay exact
-                while (S.ws[WPW] <= lim) {
-                    fold_round<WPW, U>(s_ball, base, S);
-                    my_new += sb_finish<WPW>(p, sbw, n_words, S);
-                    if (sbw >= sb_last) return false;
-                    sbw += WPW;
-                    sb_setup<WPW>(mb, sbw, w_begin, w_end, S);
-                    load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, mb);
-                    __builtin_amdgcn_s_waitcnt(0);
-                }
+                sb_setup<WPW>(nxt, sbw, w_begin, w_end, S);
+                load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
                 fold_round<WPW, U>(s_ball, base, S);
             }
-            base = lim;
+            base = nb;
             return true;
         };
         for (;;) {
-            if (!round(ca, cb, nxt, alt)) break;
-            if (!round(cb, ca, alt, nxt)) break;
+            if (!round(ca, cb)) break;
+            if (!round(cb, ca)) break;
         }
         return my_new;
     }

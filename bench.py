@@ -152,6 +152,27 @@ def bench_batch(args, torch, gen, lp, stream) -> dict:
             mm.close()
 
 
+def copy_probe(torch, dev, stream, mib: int = 1024) -> float:
+    """Device-to-device copy bandwidth (bytes read + written per second, in
+    GB/s) of a mib-MiB buffer: the bandwidth a plain streaming kernel reaches
+    on this GPU, beside the published peak."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * (mib << 20) / (ms / 1e3) / 1e9
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +190,12 @@ def main() -> int:
                     help="skip the tuner: variant,wpw,unroll[,driver] e.g. lds,2,16,batched")
     ap.add_argument("--step-only", action="store_true",
                     help="only time the step kernel of --schedule (for hardware-counter runs)")
+    ap.add_argument("--scale-rules", type=int, default=1,
+                    help="multiply the program's rules (4: a layout larger than the 256 MB Infinity "
+                         "Cache, so the stream comes from DRAM)")
+    ap.add_argument("--scale-atoms", type=int, default=1,
+                    help="multiply the program's atoms (past about 1.29 million original atoms the "
+                         "staged step gathers the rest from global memory)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="with --step-only: also run one device-to-device copy of this many MiB, a "
                          "known-size kernel that calibrates the byte counters")
@@ -189,8 +216,9 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
 
     t = time.perf_counter()
-    prog = gen.chain_zipf(args.seed)
-    log(f"[bench] generated chain_zipf seed={args.seed}: {prog.n_rules} rules, "
+    n_atoms, n_rules = 1_000_000 * args.scale_atoms, 5_000_000 * args.scale_rules
+    prog = gen.chain_zipf(args.seed, n_atoms=n_atoms, n_rules=n_rules)
+    log(f"[bench] generated chain_zipf seed={args.seed}: {n_atoms} atoms, {prog.n_rules} rules, "
         f"{prog.n_literals} literals in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     m = lp.Matrix(prog, stream=stream)
@@ -271,13 +299,16 @@ def main() -> int:
         Bl = B
         kname = f"tp_step_kernel<{step_mode(info, sched)}, {sched.wpw}, {sched.unroll}>"
     achieved = Bl / (kern_ms / 1e3) / 1e9
-    log(f"[bench] {kname}: {kern_ms * 1e3:.2f} us/launch, {Bl / 1e6:.1f} MB -> {achieved:.0f} GB/s")
+    copy_gbs = copy_probe(torch, dev, stream)
+    log(f"[bench] {kname}: {kern_ms * 1e3:.2f} us/launch, {Bl / 1e6:.1f} MB -> {achieved:.0f} GB/s "
+        f"(device copy probe: {copy_gbs:.0f} GB/s)")
     Bc = csr_step_bytes(info) * (products if sched.driver == lp.LP_DRIVER_PERSISTENT else 1)
     traffic = recorded_traffic(kname, B) if sched.driver != lp.LP_DRIVER_PERSISTENT else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "bytes_per_launch": Bl, "us_per_launch": round(kern_ms * 1e3, 3),
                 "bytes_per_product": B,
+                "copy_probe_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "csr_equivalent": {"bytes_per_launch": Bc,
                                    "GB/s": round(Bc / (kern_ms / 1e3) / 1e9, 1)}}
 
@@ -336,7 +367,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "chain_zipf: definite program, 1,000,000 atoms, 5,000,000 rules, bodies 1-8, "
+        "config": {"workload": f"chain_zipf: definite program, {n_atoms:,} atoms, "
+                               f"{n_rules:,} rules, bodies 1-8, "
                                "1% facts, Zipf(1.1) heads, 2,000-long chain; least model, full-sweep products",
                    "seed": args.seed, "n_rows": info["n_rows"], "nnz": info["nnz"], "products": products,
                    "build_s": round(build_s, 3), "us_per_product": round(ms_per_step * 1e3 / products, 3)},

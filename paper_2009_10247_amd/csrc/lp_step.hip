@@ -274,13 +274,17 @@ struct BlockPass {
     __device__ __forceinline__ bool prefetch(const StepParams &p) {
         n_words = (p.n_rows + 63) >> 6;
         const int64_t k = grid_wave();
+        // the wave's four split entries (the test names all four, so they are
+        // read together rather than two of them after it)
         w_begin = p.wave_part[2 * k];
+        const int32_t e_begin = p.wave_part[2 * k + 1];
         w_end = p.wave_part[2 * k + 2];
-        if (w_begin >= w_end) return false;
+        const int32_t e_end = p.wave_part[2 * k + 3];
+        if (w_begin >= w_end || e_begin > e_end) return false;  // (e_begin <= e_end always)
         sbw = w_begin & ~3;
         sb_last = sbw + ((w_end - 1 - sbw) / WPW) * WPW;
-        base = p.wave_part[2 * k + 1] & ~63;
-        last_base = max(0, ((p.wave_part[2 * k + 3] + 63) & ~63) - 64 * U);
+        base = e_begin & ~63;
+        last_base = max(0, ((e_end + 63) & ~63) - 64 * U);
         load_sb_meta<WPW>(p, sbw, w_begin, n_words, cur);
         load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
         load_chunks<U>(p, base, ca);
@@ -517,12 +521,15 @@ __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
     const StepLds<MODE, U> L((lds_u64 *)s_lds);
     if ((threadIdx.x & 63) == 0) L.my_ball[U] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
-    if (p.early_exit && p.step >= 2 && p.counters[(p.step - 1) & (kRing - 1)] == 0) return;
+    // early exit past the fixpoint: the previous product's count is read while
+    // the block pass's first loads are already in flight
+    const unsigned long long prev = p.counters[(p.step - 1) & (kRing - 1)];
     if (threadIdx.x == 0) *L.n_new = 0;
     // The block pass's first loads go out first, so the stream is in flight
     // while v is staged and while the OR rows and segments are evaluated.
     BlockPass<MODE, WPW, U> bp;
     const bool blocks = bp.prefetch(p);
+    if (p.early_exit && p.step >= 2 && prev == 0) return;
     if (MODE != kStepGlobal) stage_v(p, L.v);
     if (blocks) bp.start();
     __syncthreads();

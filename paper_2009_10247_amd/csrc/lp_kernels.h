@@ -70,7 +70,9 @@ struct PersistParams {
     uint64_t *buf0;
     uint64_t *buf1;
     int32_t max_steps;
-    int32_t *result;  // products, or -1 if max_steps was reached
+    int32_t *result;  // products, -1 if max_steps was reached, -2 if a grid barrier was abandoned
+    uint32_t *bar;    // grid barrier arrivals (0 at launch)
+    int32_t *abort;   // set when a workgroup gives up waiting at a barrier (0 at launch)
 };
 hipError_t launch_persistent(const StepShape &s, const PersistParams &q, hipStream_t st);
 hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu);

@@ -570,6 +570,7 @@ static lp_status plan_persistent(const Matrix &m, const lp_schedule *sched, Step
     return wave_partition(m, S->grid * (S->block / 64), st, &p.wave_part);
 }
 
+// res: int32[4] device scratch (result, barrier count, abort flag).
 static lp_status run_persistent(const Matrix &m, const StepParams &p, const StepShape &S, uint64_t *const buf[2],
                                 int32_t *res, hipStream_t st) {
     PersistParams q{};
@@ -578,6 +579,9 @@ static lp_status run_persistent(const Matrix &m, const StepParams &p, const Step
     q.buf1 = buf[1];
     q.max_steps = (int32_t)std::min<int64_t>((int64_t)m.n_rows + 1, INT32_MAX - 1);
     q.result = res;
+    q.bar = reinterpret_cast<uint32_t *>(res + 1);
+    q.abort = res + 2;
+    LP_HIP(hipMemsetAsync(res, 0, 4 * sizeof(int32_t), st));
     LP_HIP(launch_persistent(S, q, st));
     return LP_OK;
 }
@@ -612,11 +616,15 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
         if ((rc = plan_persistent(m, sched, p, &L, st))) return rc;
         if (L.grid >= 1) {
             int32_t *res;
-            if ((rc = S.get(&res, 1))) return rc;
+            if ((rc = S.get(&res, 4))) return rc;
             if ((rc = run_persistent(m, p, L, buf, res, st))) return rc;
             int32_t prods = 0;
             LP_HIP(hipMemcpyAsync(&prods, res, sizeof(int32_t), hipMemcpyDeviceToHost, st));
             LP_HIP(hipStreamSynchronize(st));
+            if (prods == -2) {
+                set_error("persistent step: a workgroup gave up waiting at the grid barrier");
+                return LP_E_INTERNAL;
+            }
             if (prods < 1) {
                 set_error("fixpoint not reached within n_rows+1 products");
                 return LP_E_INTERNAL;
@@ -922,7 +930,7 @@ static lp_status time_persistent(const Matrix &m, const StepBench &B, const Step
     uint64_t *buf[2] = {B.fix, B.dst};
     int32_t *res;
     lp_status rc;
-    if ((rc = S.get(&res, 1))) return rc;
+    if ((rc = S.get(&res, 4))) return rc;
     p.counters = B.counters;
     p.and_cnt = B.and_cnt;
     Events ev;
@@ -939,6 +947,13 @@ static lp_status time_persistent(const Matrix &m, const StepBench &B, const Step
         float ms = 0;
         if ((rc = ev.elapsed(&ms))) return rc;
         total += ms;
+        int32_t prods = 0;
+        LP_HIP(hipMemcpy(&prods, res, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (prods < 1) {
+            set_error(prods == -2 ? "persistent step: a workgroup gave up waiting at the grid barrier"
+                                  : "fixpoint not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
     }
     *avg_ms = reps > 0 ? total / reps : 0.f;
     return LP_OK;

@@ -540,12 +540,47 @@ __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
     add_new_bits(my_new, L.n_new, &p.counters[p.step & (kRing - 1)]);
 }
 
+// Grid-wide barrier of a cooperative launch (every workgroup is resident):
+// each workgroup adds 1 to *count with an agent-scope release (its writes,
+// made visible to the workgroup by __syncthreads, are written back past the
+// XCD's L2 first), then its first thread polls *count with relaxed
+// agent-scope loads until it reaches target and ends with one agent-scope
+// acquire fence. The poll is bounded: after
+// kBarrierPolls reads, or when another workgroup has given up, it sets
+// *abort. Returns false (in every thread of the workgroup) if the barrier was
+// abandoned.
+constexpr uint32_t kBarrierPolls = 1u << 22;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t *count, uint32_t target, int32_t *abort, lds_u32 *s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (uint32_t polls = 0;; ++polls) {
+            // relaxed polls (an acquire on each would invalidate the L2 every time)
+            if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (polls >= kBarrierPolls ||
+                ((polls & 63) == 63 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_flag = ok;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
 // The whole Algorithm 1 loop in one cooperative launch. Each product: stage v
-// in LDS, evaluate every row, add the new-bit count, grid-wide barrier (HIP's
-// cooperative-groups grid sync, which also orders the memory the other XCDs
-// wrote), read the count. Every workgroup reads the same count after the
-// barrier, so all leave the loop on the same product; max_steps (a monotone
-// iteration needs at most n_rows + 1 products) guarantees the loop ends.
+// in LDS, evaluate every row, add the new-bit count, grid-wide barrier
+// (grid_barrier, which also orders the memory the other XCDs wrote), read the
+// count. Every workgroup reads the same count after the barrier, so all leave
+// the loop on the same product; max_steps (a monotone iteration needs at most
+// n_rows + 1 products) guarantees the loop ends, and an abandoned barrier ends
+// it with result -2.
 template <int MODE, int WPW, int U>
 __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistParams q) {
     __shared__ uint64_t s_lds[StepLds<MODE, U>::kWords];
@@ -571,7 +606,10 @@ __global__ __launch_bounds__(1024) void tp_fixpoint_persistent_kernel(PersistPar
         my_new += or_rows<true>(p, s_v);
         if (blocks) my_new += bp.run(p, s_v, my_ball);
         add_new_bits(my_new, s_new_p, slot);
-        cooperative_groups::this_grid().sync();
+        if (!grid_barrier(q.bar, gridDim.x * (uint32_t)step, q.abort, s_new_p + 1)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *q.result = -2;
+            return;
+        }
         const unsigned long long changed = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (changed == 0 || step >= q.max_steps) {
             if (blockIdx.x == 0 && threadIdx.x == 0) *q.result = changed == 0 ? step : -1;

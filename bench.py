@@ -183,6 +183,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stable", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-frontier", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true", help="time every step shape (diagnostic)")
     ap.add_argument("--tune-reps", type=int, default=20)
@@ -312,6 +313,29 @@ def main() -> int:
                 "csr_equivalent": {"bytes_per_launch": Bc,
                                    "GB/s": round(Bc / (kern_ms / 1e3) / 1e9, 1)}}
 
+    # the frontier driver on the same matrix: end-to-end solve time (it visits each entry once per
+    # solve, so its bytes are not those of the full-sweep product and no GB/s is claimed for it)
+    frontier = None
+    if not args.no_frontier:
+        fs = lp.make_schedule(driver=lp.LP_DRIVER_FRONTIER)
+        t = time.perf_counter()
+        fmodel, fprods = m.least_model(sched=fs, stream=stream)
+        first_ms = (time.perf_counter() - t) * 1e3
+        assert fprods == products and np.array_equal(fmodel, model), "frontier result differs from the full sweep"
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(args.steps):
+            m.least_model(sched=fs, stream=stream)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        fms = f0.elapsed_time(f1) / max(args.steps, 1)
+        frontier = {"driver": "frontier (semi-naive push through the transposed matrix)",
+                    "ms_per_solve": round(fms, 4), "products": fprods,
+                    "speedup_vs_full_sweep": round(ms_per_step / fms, 2),
+                    "first_call_ms_with_transpose_build": round(first_ms, 1)}
+        log(f"[bench] frontier: {frontier}")
+
     stable = None
     if not args.no_stable:
         q = gen.normal_uniform(args.seed)
@@ -376,6 +400,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "stable_models": stable,
         "batch": batch,
+        "frontier": frontier,
         "schedule": lp.schedule_dict(sched),
         "step_us_per_shape": variants or None,
     }

@@ -105,7 +105,11 @@ enum {
     LP_DRIVER_AUTO = 0,
     LP_DRIVER_PLAIN = 1,      /* one launch per product, host reads the change count each time */
     LP_DRIVER_BATCHED = 2,    /* steps_per_sync launches between host reads of the change counts */
-    LP_DRIVER_PERSISTENT = 3  /* one launch; the loop runs on the device with a grid barrier */
+    LP_DRIVER_PERSISTENT = 3, /* one launch; the loop runs on the device with a grid barrier */
+    LP_DRIVER_FRONTIER = 4    /* least models only: newly true rows pushed through the transposed
+                                 matrix, one launch per product; each entry is visited once per
+                                 solve (same model and product count; builds the transpose on
+                                 first use, about 4 (n_rows + nnz) more device bytes) */
 };
 
 enum {

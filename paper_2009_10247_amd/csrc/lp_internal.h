@@ -66,6 +66,12 @@ struct DeviceMatrix {
     // device splits of the block pass between waves, one per wave count
     // (created on first use by the step planner, under its lock)
     mutable std::vector<std::pair<int32_t, int32_t *>> wave_parts;
+    // transposed matrix of the frontier driver (built on first use, under its lock)
+    mutable int32_t *fr_ptr = nullptr;    // [n_rows + 1]
+    mutable int32_t *fr_occ = nullptr;    // rows naming each row, ascending
+    mutable int32_t *fr_cnt0 = nullptr;   // [n_rows] entries still false at the start: AND length, OR 1
+    mutable int32_t *fr_facts = nullptr;  // fact rows (F_0)
+    mutable int32_t fr_n_facts = 0;
     // stable models (normal programs): plain CSR
     int32_t *full_row_ptr = nullptr;
     int32_t *full_col = nullptr;

@@ -125,6 +125,24 @@ struct SpmmParams {
 };
 // max_grid: workgroups of 256 threads (grid-stride loop over the items).
 hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st);
+// Frontier (semi-naive) least models: one launch per level. occ_ptr/occ is
+// the transposed matrix (for each row, the rows whose entries name it); cnt
+// holds each row's count of entries still false (an OR row starts at 1).
+constexpr int kFrontierRing = 4;     // frontier sizes, indexed by level % kFrontierRing
+constexpr int kFrontierHist = 128;   // |F_t| history, indexed by level % kFrontierHist
+struct FrontierParams {
+    const int32_t *occ_ptr;  // [n_rows + 1]
+    const int32_t *occ;      // rows naming each row
+    int32_t *cnt;            // [n_rows]
+    uint64_t *v;             // [n_words] the interpretation (ORed into)
+    const int32_t *in;       // F_level
+    int32_t *out;            // F_level+1 (capacity n_rows)
+    uint32_t *sizes;         // [kFrontierRing]
+    int32_t *hist;           // [kFrontierHist]
+    int32_t level;
+};
+hipError_t launch_frontier_level(const FrontierParams &f, int grid, hipStream_t st);
+
 hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std,
                           const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff,
                           unsigned long long *count, unsigned long long bits, hipStream_t st);

@@ -216,6 +216,7 @@ static void free_device(Matrix &m, hipStream_t st) {
                   d.full_row_ptr, d.full_col,      d.full_and_bits, d.q_rows, d.guess_pos};
     for (void *p : ps) dev_free(p, st);
     for (auto &wp : d.wave_parts) dev_free(wp.second, st);
+    for (void *p : {(void *)d.fr_ptr, (void *)d.fr_occ, (void *)d.fr_cnt0, (void *)d.fr_facts}) dev_free(p, st);
     d = DeviceMatrix{};
 }
 
@@ -588,8 +589,15 @@ static lp_status run_persistent(const Matrix &m, const StepParams &p, const Step
 
 // Least-model fixpoint. On success *out points at the device buffer holding
 // the fixpoint (one of bufs[0..1]).
+static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products);
+
 static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipStream_t st, Scratch &S,
                                 uint64_t **out, int32_t *products) {
+    if (sched && (sched->driver < LP_DRIVER_AUTO || sched->driver > LP_DRIVER_FRONTIER)) {
+        set_error("unknown driver " + std::to_string(sched->driver));
+        return LP_E_INVAL;
+    }
+    if (sched && sched->driver == LP_DRIVER_FRONTIER) return frontier_fixpoint(m, st, S, out, products);
     const int64_t W = n_words_of(m.n_rows);
     uint64_t *buf[2];
     unsigned long long *counters;
@@ -666,6 +674,118 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
             }
         }
         if (t + batch > limit) {
+            set_error("fixpoint not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
+    }
+}
+
+// Transposed matrix of the frontier driver, built on first use from the host
+// CSR and kept with the matrix: for each row c, the rows whose entries name c
+// (fact rows and empty rows have no entries and are never counted down);
+// each row's count of entries still false at the start (AND rows: their
+// length; OR rows: 1, so the first true child fires them); the fact rows.
+static lp_status ensure_frontier(const Matrix &m, hipStream_t st) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    const DeviceMatrix &d = m.dev;
+    if (d.fr_ptr) return LP_OK;
+    const int32_t n = m.n_rows;
+    std::vector<int32_t> ptr((size_t)n + 1, 0), cnt0((size_t)std::max(n, 1), 0), facts;
+    for (int32_t r = 0; r < n; ++r) {
+        if (m.fact[r]) {
+            facts.push_back(r);
+            continue;
+        }
+        for (int32_t j = m.row_ptr[r]; j < m.row_ptr[r + 1]; ++j) ++ptr[(size_t)m.col[j] + 1];
+        const int32_t len = m.row_ptr[r + 1] - m.row_ptr[r];
+        cnt0[r] = len == 0 ? 0 : (m.kind[r] ? len : 1);
+    }
+    for (int32_t c = 0; c < n; ++c) ptr[(size_t)c + 1] += ptr[c];
+    std::vector<int32_t> occ((size_t)std::max<int32_t>(ptr[n], 1)), fill(ptr.begin(), ptr.end() - 1);
+    for (int32_t r = 0; r < n; ++r) {
+        if (m.fact[r]) continue;
+        for (int32_t j = m.row_ptr[r]; j < m.row_ptr[r + 1]; ++j) occ[(size_t)fill[m.col[j]]++] = r;
+    }
+    if (facts.empty()) facts.push_back(0);  // not read: the fact count is 0
+    int64_t bytes = 0;
+    int32_t *dp = nullptr, *dq = nullptr, *dc = nullptr, *df = nullptr;
+    lp_status rc;
+    if ((rc = upload(&dp, ptr.data(), ptr.size(), st, &bytes)) || (rc = upload(&dq, occ.data(), occ.size(), st, &bytes)) ||
+        (rc = upload(&dc, cnt0.data(), cnt0.size(), st, &bytes)) ||
+        (rc = upload(&df, facts.data(), facts.size(), st, &bytes))) {
+        for (void *x : {(void *)dp, (void *)dq, (void *)dc, (void *)df}) dev_free(x, st);
+        return rc;
+    }
+    LP_HIP(hipStreamSynchronize(st));  // the host vectors are locals
+    d.fr_ptr = dp;
+    d.fr_occ = dq;
+    d.fr_cnt0 = dc;
+    d.fr_facts = df;
+    d.fr_n_facts = (int32_t)std::count(m.fact.begin(), m.fact.end(), (uint8_t)1);
+    return LP_OK;
+}
+
+// Least-model fixpoint by levels (lp_frontier.hip): level t pushes F_t and
+// collects F_{t+1}; levels are issued kFrontierHist / 2 at a time and the
+// host reads their |F_t| history; the first empty F_t (t >= 1) ends the solve
+// with t products, like the full sweep.
+static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products) {
+    lp_status rc;
+    if ((rc = ensure_frontier(m, st))) return rc;
+    const DeviceMatrix &d = m.dev;
+    const int32_t n = m.n_rows;
+    const int64_t W = n_words_of(n);
+    uint64_t *v;
+    int32_t *cnt, *q[2], *hist;
+    uint32_t *sizes;
+    if ((rc = S.get(&v, W)) || (rc = S.get(&cnt, std::max(n, 1))) || (rc = S.get(&q[0], std::max(n, 1))) ||
+        (rc = S.get(&q[1], std::max(n, 1))) || (rc = S.get(&sizes, kFrontierRing)) || (rc = S.get(&hist, kFrontierHist)))
+        return rc;
+    LP_HIP(hipMemcpyAsync(v, d.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
+    *out = v;
+    if (n == 0) {
+        *products = 1;
+        return LP_OK;
+    }
+    LP_HIP(hipMemcpyAsync(cnt, d.fr_cnt0, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    DevProps dp;
+    if ((rc = dev_props(d.device, &dp))) return rc;
+    const int grid = 4 * std::max(dp.n_cu, 1);
+    unsigned long long *h = pinned_ring();
+    if (!h) {
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
+    int32_t *hh = reinterpret_cast<int32_t *>(h);  // kRing x 8 bytes >= kFrontierHist x 4 bytes
+    // sizes = {|F_0|, 0, ...}, copied from the pinned buffer (written again only by a later copy on st)
+    for (int i = 0; i < kFrontierRing; ++i) hh[i] = i == 0 ? d.fr_n_facts : 0;
+    LP_HIP(hipMemcpyAsync(sizes, hh, sizeof(uint32_t) * kFrontierRing, hipMemcpyHostToDevice, st));
+    constexpr int kBatch = kFrontierHist / 2;
+    const int64_t limit = (int64_t)n + 1;
+    FrontierParams f{};
+    f.occ_ptr = d.fr_ptr;
+    f.occ = d.fr_occ;
+    f.cnt = cnt;
+    f.v = v;
+    f.sizes = sizes;
+    f.hist = hist;
+    for (int64_t t0 = 0;; t0 += kBatch) {
+        for (int64_t t = t0; t < t0 + kBatch; ++t) {
+            f.level = (int32_t)t;
+            f.in = t == 0 ? d.fr_facts : q[t & 1];
+            f.out = q[(t + 1) & 1];
+            LP_HIP(launch_frontier_level(f, grid, st));
+        }
+        LP_HIP(hipMemcpyAsync(hh, hist, sizeof(int32_t) * kFrontierHist, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        for (int64_t t = t0; t < t0 + kBatch; ++t) {
+            if (hh[t % kFrontierHist] == 0) {
+                *products = (int32_t)std::max<int64_t>(t, 1);
+                return LP_OK;
+            }
+        }
+        if (t0 + kBatch > limit) {
             set_error("fixpoint not reached within n_rows+1 products");
             return LP_E_INTERNAL;
         }

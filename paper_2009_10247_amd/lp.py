@@ -36,6 +36,7 @@ LP_DRIVER_AUTO = 0
 LP_DRIVER_PLAIN = 1
 LP_DRIVER_BATCHED = 2
 LP_DRIVER_PERSISTENT = 3
+LP_DRIVER_FRONTIER = 4
 
 LP_STEP_AUTO = 0
 LP_STEP_GLOBAL = 1

@@ -51,6 +51,7 @@ SCHEDULES = {
     "global-w4-u16": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=4, unroll=16),
     "global-w8-u4": lp.make_schedule(driver=lp.LP_DRIVER_BATCHED, variant=lp.LP_STEP_GLOBAL, wpw=8, unroll=4,
                                      grid=5),
+    "frontier": lp.make_schedule(driver=lp.LP_DRIVER_FRONTIER),
     "auto": None,
 }
 

@@ -454,8 +454,8 @@ static StepParams step_params(const Matrix &m) {
 constexpr int64_t kWordCost = 600;
 // Cost of an OR tile and of a long-row segment in the same units: a wave that
 // evaluates them gets that much less of the block pass.
-constexpr int64_t kOrTileCost = 3200;
-constexpr int64_t kSegCost = 3200;
+constexpr int64_t kOrTileCost = 1600;
+constexpr int64_t kSegCost = 1600;
 
 // Split of the block pass between `waves` waves: wave k takes the words
 // [t[2k], t[2k + 2]) and t[2k + 1] is the first AND entry of word t[2k]. Each

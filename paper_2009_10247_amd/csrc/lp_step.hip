@@ -268,9 +268,9 @@ struct BlockPass {
     int32_t ca[U], cb[U];
 
     // Issues the row data of the wave's first two super-blocks and its first
-    // round of chunks. Called before v is staged, so these loads overlap the
-    // staging and everything else the wave does before the stream. False if
-    // the wave has no words.
+    // round of chunks. Called while v is being staged, so these loads overlap
+    // the staging and everything else the wave does before the stream. False
+    // if the wave has no words.
     __device__ __forceinline__ bool prefetch(const StepParams &p) {
         n_words = (p.n_rows + 63) >> 6;
         const int64_t k = grid_wave();
@@ -280,15 +280,18 @@ struct BlockPass {
         const int32_t e_begin = p.wave_part[2 * k + 1];
         w_end = p.wave_part[2 * k + 2];
         const int32_t e_end = p.wave_part[2 * k + 3];
-        if (w_begin >= w_end || e_begin > e_end) return false;  // (e_begin <= e_end always)
+        // Every wave issues the same loads, also one with no words (its
+        // range is empty and lies within the padded arrays), so the wait
+        // counts of the loads issued after these are the same on every path.
+        const bool has = w_begin < w_end && e_begin <= e_end;  // (e_begin <= e_end always)
         sbw = w_begin & ~3;
-        sb_last = sbw + ((w_end - 1 - sbw) / WPW) * WPW;
+        sb_last = has ? sbw + ((w_end - 1 - sbw) / WPW) * WPW : sbw;
         base = e_begin & ~63;
         last_base = max(0, ((e_end + 63) & ~63) - 64 * U);
         load_sb_meta<WPW>(p, sbw, w_begin, n_words, cur);
         load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
         load_chunks<U>(p, base, ca);
-        return true;
+        return has;
     }
 
     // Sets up the first super-block (its row data has landed by now).
@@ -348,35 +351,48 @@ struct BlockPass {
 // reads its child range from or_c0, ORs the words of v in that range and, if
 // it fires, sets the row's bit. An OR row is evaluated by exactly one lane, so
 // it is new iff its bit is 0 in v. A wave takes four of its tiles at a time
-// and issues all their loads together: the range table, then the first and
-// last word of every range (the words between them, rare for OR rows of at
-// most kLongOrBits children, are read after).
+// (tiles t0 + g * stride) in three steps whose loads can be issued early:
+// the range table, then the first and last word of every range (the words
+// between them, rare for OR rows of at most kLongOrBits children, are read at
+// the end), then the evaluation.
 template <bool LDS>
-__device__ __forceinline__ uint32_t or_rows(const StepParams &p, const lds_u32 *s_v) {
-    constexpr int G = 4;
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int64_t n_tiles = ((int64_t)p.n_or + 63) >> 6;
-    uint32_t my_new = 0;
-    for (int64_t t0 = grid_wave(); t0 < n_tiles; t0 += G * stride) {
-        int32_t row[G], c0[G], c1[G];
-        uint64_t a[G], z[G];
+struct OrTiles {
+    static constexpr int G = 4;
+    int32_t row[G], c0[G], c1[G];
+    uint64_t a[G], z[G];
+    bool any_tile;
+
+    // The loads are issued in every wave, also one with no tile (clamped to
+    // the table's first entries, which always exist), so the wait counts of
+    // later loads are the same on every path.
+    __device__ __forceinline__ void load_ranges(const StepParams &p, int64_t t0, int64_t stride) {
+        const int lane = threadIdx.x & 63;
+        any_tile = t0 < (((int64_t)p.n_or + 63) >> 6);  // wave-uniform
 #pragma unroll
-        for (int g = 0; g < G; ++g) {  // j clamped to the last OR row: in bounds, marked invalid
+        for (int g = 0; g < G; ++g) {  // j clamped to the last OR row: in bounds, marked invalid below
             const int64_t j = (t0 + g * stride) * 64 + lane;
-            const int64_t jc = j < p.n_or ? j : p.n_or - 1;
-            row[g] = p.or_row[jc];
+            const int64_t jc = j < p.n_or ? j : (p.n_or > 0 ? p.n_or - 1 : 0);
+            const int32_t rr = p.or_row[jc];
+            row[g] = j < p.n_or ? rr : -1;
             c0[g] = p.or_c0[jc];
-            c1[g] = p.or_c0[jc + 1];
-            if (j >= p.n_or || c1[g] <= c0[g]) row[g] = -1;
+            c1[g] = p.or_c0[jc + 1 <= p.n_or ? jc + 1 : p.n_or];
         }
+    }
+
+    __device__ __forceinline__ void load_words(const StepParams &p) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
+            if (c1[g] <= c0[g]) row[g] = -1;
             const int32_t w0 = row[g] >= 0 ? c0[g] >> 6 : 0;
             const int32_t w1 = row[g] >= 0 ? (c1[g] - 1) >> 6 : 0;
             a[g] = p.v[w0];
             z[g] = p.v[w1];
         }
+    }
+
+    __device__ __forceinline__ uint32_t finish(const StepParams &p, const lds_u32 *s_v) {
+        uint32_t my_new = 0;
+        if (!any_tile) return 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (row[g] < 0) continue;
@@ -395,6 +411,39 @@ __device__ __forceinline__ uint32_t or_rows(const StepParams &p, const lds_u32 *
                 if (!(vword<LDS>(p, s_v, row[g] >> 6) & bit)) my_new += 1;
             }
         }
+        return my_new;
+    }
+};
+
+// All of the wave's OR tiles, four at a time, each batch's loads issued
+// together (the persistent kernel, whose loop state leaves no registers for
+// issuing them earlier).
+template <bool LDS>
+__device__ __forceinline__ uint32_t or_rows(const StepParams &p, const lds_u32 *s_v) {
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t n_tiles = ((int64_t)p.n_or + 63) >> 6;
+    uint32_t my_new = 0;
+    for (int64_t t0 = grid_wave(); t0 < n_tiles; t0 += OrTiles<LDS>::G * stride) {
+        OrTiles<LDS> ot;
+        ot.load_ranges(p, t0, stride);
+        ot.load_words(p);
+        my_new += ot.finish(p, s_v);
+    }
+    return my_new;
+}
+
+// The wave's OR tiles after its first four (which the step kernel takes
+// through OrTiles with its loads issued before staging v).
+template <bool LDS>
+__device__ __forceinline__ uint32_t or_rows_rest(const StepParams &p, const lds_u32 *s_v) {
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t n_tiles = ((int64_t)p.n_or + 63) >> 6;
+    uint32_t my_new = 0;
+    for (int64_t t0 = grid_wave() + OrTiles<LDS>::G * stride; t0 < n_tiles; t0 += OrTiles<LDS>::G * stride) {
+        OrTiles<LDS> ot;
+        ot.load_ranges(p, t0, stride);
+        ot.load_words(p);
+        my_new += ot.finish(p, s_v);
     }
     return my_new;
 }
@@ -487,6 +536,52 @@ __device__ __forceinline__ void stage_v(const StepParams &p, lds_u32 *s_v) {
     if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.lds_words - 1];
 }
 
+// stage_v split in two: the first loads (up to eight 16-byte loads per
+// thread, 128 KB per 1,024 threads) are issued before the wave's other
+// prologue loads and written to LDS after them. Every thread issues all eight
+// (indices past the end reload the last 16 bytes), so the wait counts of the
+// loads issued in between are the same on every path.
+struct StageV {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) u32x4 lds_u4;
+    static constexpr int kInFlight = 8;
+    u32x4 x[kInFlight];
+
+    __device__ __forceinline__ void issue(const StepParams &p) {
+        const int32_t n16 = p.lds_words >> 1;
+        if (n16 == 0) return;  // the same in every thread of the launch
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v);
+        const int32_t bd = blockDim.x;
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) {
+            const int32_t i = threadIdx.x + k * bd;
+            x[k] = src[i < n16 ? i : n16 - 1];
+        }
+    }
+
+    __device__ __forceinline__ void commit(const StepParams &p, lds_u32 *s_v) {
+        lds_u4 *d = (lds_u4 *)s_v;
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v);
+        const int32_t n16 = p.lds_words >> 1;
+        const int32_t bd = blockDim.x;
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) {
+            const int32_t i = threadIdx.x + k * bd;
+            if (i < n16) d[i] = x[k];
+        }
+        for (int32_t i = threadIdx.x + kInFlight * bd; i < n16; i += kInFlight * bd) {  // past 128 KB
+            u32x4 y[kInFlight];
+#pragma unroll
+            for (int k = 0; k < kInFlight; ++k)
+                if (i + k * bd < n16) y[k] = src[i + k * bd];
+#pragma unroll
+            for (int k = 0; k < kInFlight; ++k)
+                if (i + k * bd < n16) d[i + k * bd] = y[k];
+        }
+        if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.lds_words - 1];
+    }
+};
+
 __device__ __forceinline__ void add_new_bits(uint32_t my_new, lds_u32 *s_new, unsigned long long *slot) {
     my_new = wave_sum(my_new);
     if ((threadIdx.x & 63) == 0 && my_new)
@@ -521,21 +616,29 @@ __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
     const StepLds<MODE, U> L((lds_u64 *)s_lds);
     if ((threadIdx.x & 63) == 0) L.my_ball[U] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
-    // early exit past the fixpoint: the previous product's count is read while
-    // the block pass's first loads are already in flight
+    // Prologue loads, in this order: the previous product's count (early
+    // exit past the fixpoint), the staging of v, the block pass's row data
+    // and first chunks, the first OR tiles' ranges; then v goes to LDS, the
+    // OR tiles' words are loaded, and they are evaluated after the barrier.
+    // So the stream is in flight while v is staged and while the OR rows and
+    // segments are evaluated, and no round trip of the prologue waits alone.
     const unsigned long long prev = p.counters[(p.step - 1) & (kRing - 1)];
+    StageV sv;
+    if (MODE != kStepGlobal) sv.issue(p);
     if (threadIdx.x == 0) *L.n_new = 0;
-    // The block pass's first loads go out first, so the stream is in flight
-    // while v is staged and while the OR rows and segments are evaluated.
     BlockPass<MODE, WPW, U> bp;
     const bool blocks = bp.prefetch(p);
+    OrTiles<MODE != kStepGlobal> ot;
+    ot.load_ranges(p, grid_wave(), (int64_t)gridDim.x * (blockDim.x >> 6));
+    if (MODE != kStepGlobal) sv.commit(p, L.v);
     if (p.early_exit && p.step >= 2 && prev == 0) return;
-    if (MODE != kStepGlobal) stage_v(p, L.v);
+    ot.load_words(p);
     if (blocks) bp.start();
     __syncthreads();
     // long-row segments first: they are the longest items, so they start early
     uint32_t my_new = long_rows<MODE != kStepGlobal, U>(p, L.v);
-    my_new += or_rows<MODE != kStepGlobal>(p, L.v);
+    my_new += ot.finish(p, L.v);
+    my_new += or_rows_rest<MODE != kStepGlobal>(p, L.v);
     if (blocks) my_new += bp.run(p, L.v, L.my_ball);
     add_new_bits(my_new, L.n_new, &p.counters[p.step & (kRing - 1)]);
 }

@@ -30,9 +30,10 @@ __device__ inline uint64_t valid_mask(int32_t k_eff) {
 
 // Thread g owns word (g & (W-1)) of row (g >> log2W): it ANDs (AND row) or ORs
 // (OR row) that word of every row its row names; a grid-stride loop gives each
-// thread several such items. With W >= 64 a wave covers 64 consecutive words
-// of one row, so each gather is one coalesced 512-byte read and the row's CSR
-// entries are wave-uniform loads.
+// thread several such items. (Launched for W < 64; wider matrices take
+// spmm_step_wide_kernel below, where a wave covers 64 consecutive words of one
+// row per chunk, so each gather is one coalesced 512-byte read and the row's
+// CSR entries are wave-uniform loads.)
 //
 // Columns are independent, so the monotone argument of the least-model step
 // holds per column: U contains V, and U = V iff both hold the same number of
@@ -43,7 +44,6 @@ __device__ inline uint64_t valid_mask(int32_t k_eff) {
 // per CU (atomics on one address serialize). Product t changed nothing iff
 // counters[t] == counters[t-1]; a launch after such a product returns at once
 // and copies the count forward.
-template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void spmm_step_kernel(SpmmParams p) {
     __shared__ uint32_t s_bits;
     const int tid = threadIdx.x;
@@ -60,8 +60,7 @@ __global__ __launch_bounds__(kBlock) void spmm_step_kernel(SpmmParams p) {
     uint32_t my_bits = 0;
     const int64_t mask_w = (1ll << p.log2W) - 1;
     for (int64_t g = (int64_t)blockIdx.x * kBlock + tid; g < p.total; g += (int64_t)gridDim.x * kBlock) {
-        int32_t row = (int32_t)(g >> p.log2W);
-        if (WIDE) row = __builtin_amdgcn_readfirstlane(row);
+        const int32_t row = (int32_t)(g >> p.log2W);
         const int64_t w = g & mask_w;
         const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
         const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
@@ -74,6 +73,65 @@ __global__ __launch_bounds__(kBlock) void spmm_step_kernel(SpmmParams p) {
         if (s == e) acc = 0;
         my_bits += (uint32_t)__popcll(acc);
         p.U[g] = acc;
+    }
+    my_bits = wave_sum(my_bits);
+    if ((tid & 63) == 0 && my_bits) atomicAdd(&s_bits, my_bits);
+    __syncthreads();
+    if (tid == 0 && s_bits) atomicAdd(&p.counters[p.step & (kRing - 1)], (unsigned long long)s_bits);
+}
+
+// The same step for W >= 64 with more loads in flight: a wave takes one row
+// and GC chunks of 64 consecutive words of it (GC x 512 bytes per named row),
+// and E entries of the row per pass, so each pass issues E GC coalesced loads
+// before it combines any (a row names about three others on average; one load
+// in flight per wave left the step waiting on memory latency).
+template <int GC, int E>
+__global__ __launch_bounds__(kBlock) void spmm_step_wide_kernel(SpmmParams p) {
+    __shared__ uint32_t s_bits;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    if (blockIdx.x == 0 && tid == 0) p.counters[(p.step + 1) & (kRing - 1)] = 0;
+    if (p.early_exit && p.step >= 2 &&
+        p.counters[(p.step - 1) & (kRing - 1)] == p.counters[(p.step - 2) & (kRing - 1)]) {
+        if (blockIdx.x == 0 && tid == 0) p.counters[p.step & (kRing - 1)] = p.counters[(p.step - 1) & (kRing - 1)];
+        return;
+    }
+    if (tid == 0) s_bits = 0;
+    __syncthreads();
+    uint32_t my_bits = 0;
+    constexpr int kLog2GC = GC == 8 ? 3 : GC == 4 ? 2 : GC == 2 ? 1 : 0;
+    const int32_t log2G = p.log2W - 6 - kLog2GC;  // items per row = W / (64 GC)
+    const int64_t n_items = (int64_t)(p.total >> p.log2W) << log2G;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); it < n_items;
+         it += waves) {
+        const int32_t row = (int32_t)(it >> log2G);
+        const int64_t w0 = ((it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
+        const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
+        const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
+        uint64_t acc[GC];
+#pragma unroll
+        for (int k = 0; k < GC; ++k) acc[k] = is_and ? ~0ull : 0ull;
+        for (int32_t i = s; i < e; i += E) {
+            // entries past the row's end reload its last entry (the same word: AND and OR are idempotent)
+            uint64_t x[E][GC];
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int64_t c = p.col[i + j < e ? i + j : e - 1];
+#pragma unroll
+                for (int k = 0; k < GC; ++k) x[j][k] = p.V[(c << p.log2W) + w0 + 64 * k];
+            }
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+#pragma unroll
+                for (int k = 0; k < GC; ++k) acc[k] = is_and ? (acc[k] & x[j][k]) : (acc[k] | x[j][k]);
+        }
+#pragma unroll
+        for (int k = 0; k < GC; ++k) {
+            const uint64_t a = s == e ? 0ull : acc[k];
+            my_bits += (uint32_t)__popcll(a);
+            p.U[((int64_t)row << p.log2W) + w0 + 64 * k] = a;
+        }
     }
     my_bits = wave_sum(my_bits);
     if ((tid & 63) == 0 && my_bits) atomicAdd(&s_bits, my_bits);
@@ -156,10 +214,19 @@ static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st) {
     const unsigned grid = std::max(1u, std::min(blocks_for(p.total), (unsigned)std::max(1, max_grid)));
-    if (p.log2W >= 6)
-        hipLaunchKernelGGL((spmm_step_kernel<true>), dim3(grid), dim3(kBlock), 0, st, p);
+    // chunks per item, measured at W = 1,024 (16 negated atoms): 8 chunks 113 us per product,
+    // 4 chunks 119 us, one chunk and one entry at a time 148 us; 4 entries per pass were slower
+    // than 2 (rows name about three others, so more entries reload the last one more often)
+    if (p.log2W >= 9)
+        hipLaunchKernelGGL((spmm_step_wide_kernel<8, 2>), dim3(grid), dim3(kBlock), 0, st, p);
+    else if (p.log2W == 8)
+        hipLaunchKernelGGL((spmm_step_wide_kernel<4, 2>), dim3(grid), dim3(kBlock), 0, st, p);
+    else if (p.log2W == 7)
+        hipLaunchKernelGGL((spmm_step_wide_kernel<2, 2>), dim3(grid), dim3(kBlock), 0, st, p);
+    else if (p.log2W == 6)
+        hipLaunchKernelGGL((spmm_step_wide_kernel<1, 2>), dim3(grid), dim3(kBlock), 0, st, p);
     else
-        hipLaunchKernelGGL((spmm_step_kernel<false>), dim3(grid), dim3(kBlock), 0, st, p);
+        hipLaunchKernelGGL(spmm_step_kernel, dim3(grid), dim3(kBlock), 0, st, p);
     return hipGetLastError();
 }
 

@@ -325,11 +325,15 @@ def odd_loop() -> Program:
     return from_rules(1, [(0, [neg(0)])], kind="odd_loop")
 
 
-def transitive_closure(n_vertices: int, edges) -> Program:
+def transitive_closure(n_vertices: int, edges, grounding: str = "edges") -> Program:
     """Ground path/edge program: path(x,y) <- edge(x,y);
     path(x,y) <- edge(x,z) and path(z,y).
 
     Atom edge(x,y) = x*V + y, path(x,y) = V*V + x*V + y. Edge atoms are facts.
+    grounding "edges" instantiates the rules only where edge(x, .) is a fact;
+    "all" instantiates them for every x, y, z (V^3 + V^2 rules), the naive
+    grounding whose matrix sizes match the transitive-closure table of the
+    paper's section 4 (n' about V^3).
     """
     V = n_vertices
     E = V * V
@@ -340,6 +344,22 @@ def transitive_closure(n_vertices: int, edges) -> Program:
     def p(x, y):
         return E + x * V + y
 
+    if grounding == "all":
+        xs, ys = np.meshgrid(np.arange(V), np.arange(V), indexing="ij")
+        xs, ys = xs.ravel(), ys.ravel()
+        ed = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+        n_e = ed.shape[0]
+        heads = [ed[:, 0] * V + ed[:, 1], E + xs * V + ys]               # facts, base rules
+        bodies = [np.zeros((n_e, 2), np.int64), np.stack([xs * V + ys, np.zeros_like(xs)], 1)]
+        lengths = [np.zeros(n_e, np.int64), np.ones(V * V, np.int64)]
+        x3, z3, y3 = (a.ravel() for a in np.meshgrid(np.arange(V), np.arange(V), np.arange(V), indexing="ij"))
+        heads.append(E + x3 * V + y3)
+        bodies.append(np.stack([x3 * V + z3, E + z3 * V + y3], 1))
+        lengths.append(np.full(V ** 3, 2, np.int64))
+        return _assemble(2 * E, np.concatenate(heads), np.concatenate(lengths), np.concatenate(bodies),
+                         dict(kind="transitive_closure", n_vertices=V, grounding="all"))
+    if grounding != "edges":
+        raise ValueError("grounding is 'edges' or 'all'")
     rules = []
     for (x, y) in edges:
         rules.append((e(x, y), []))
@@ -349,6 +369,52 @@ def transitive_closure(n_vertices: int, edges) -> Program:
         for y in range(V):
             rules.append((p(x, y), [e(x, z), p(z, y)]))
     return from_rules(2 * E, rules, kind="transitive_closure", n_vertices=V)
+
+
+# Body-length proportions of the non-fact rules in the paper's random
+# programs (section 4, the table of rule proportions by body length 1..8).
+PAPER_BODY_PROPORTIONS = (0.04, 0.04, 0.10, 0.40, 0.35, 0.04, 0.02, 0.01)
+
+
+def paper_definite(seed: int, n_atoms: int, n_rules: int) -> Program:
+    """Random definite program shaped like the paper's section 4 experiments:
+    n = |B_P| atoms, m = |P| rules; fewer than n/3 facts (read as a count:
+    floor((n - 1) / 3) fact rules with distinct heads); the other rules have
+    uniform heads and body lengths 1..8 in the proportions of
+    PAPER_BODY_PROPORTIONS (counts rounded, the remainder to length 4), body
+    atoms distinct and never the head.
+    """
+    rng = _rng(seed)
+    n_facts = min((n_atoms - 1) // 3, n_rules)
+    n_body = n_rules - n_facts
+    counts = [int(math.floor(q * n_body)) for q in PAPER_BODY_PROPORTIONS]
+    counts[3] += n_body - sum(counts)
+    lengths = np.concatenate([np.zeros(n_facts, np.int64)] +
+                             [np.full(c, L + 1, np.int64) for L, c in enumerate(counts)])
+    rng.shuffle(lengths[n_facts:])
+    heads = np.concatenate([rng.permutation(n_atoms)[:n_facts],
+                            rng.integers(0, n_atoms, size=n_body)]).astype(np.int64)
+    np.minimum(lengths, max(n_atoms - 1, 0), out=lengths)
+    bodies = _draw_bodies(rng, heads, lengths, 8, n_atoms)
+    return _assemble(n_atoms, heads, lengths, bodies,
+                     dict(kind="paper_definite", seed=seed, gen_version=GEN_VERSION))
+
+
+def paper_normal(seed: int, n_atoms: int, n_rules: int, k: int) -> Program:
+    """paper_definite with k body literals (distinct positions, uniform over
+    all body literals) changed to negations, as in the paper's normal
+    programs (4 <= k <= 8). The negated atoms are the atoms at those
+    positions, so K <= k distinct atoms appear negated.
+    """
+    prog = paper_definite(seed, n_atoms, n_rules)
+    rng = _rng(seed + 0x5EED)
+    lits = prog.body_lit.copy()
+    if k > lits.shape[0]:
+        raise ValueError("more negations than body literals")
+    pos = rng.choice(lits.shape[0], size=k, replace=False)
+    lits[pos] = -lits[pos] - 1
+    meta = dict(prog.meta, kind="paper_normal", k=k)
+    return Program(prog.n_atoms, prog.head, prog.body_ptr, lits, meta)
 
 
 def random_graph_edges(seed: int, n_vertices: int, n_edges: int):

@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+import oracle
 from paper_2009_10247_amd import gen, serve
 
 
@@ -51,3 +52,40 @@ def test_zipf_weights():
     w = serve.zipf_weights(256)
     assert abs(w.sum() - 1.0) < 1e-12 and (np.diff(w) < 0).all()
     assert abs(w[0] / w[1] - 2.0) < 1e-12
+
+
+def test_paper_definite_shape():
+    p = gen.paper_definite(3, 2000, 36000)
+    L = np.diff(p.body_ptr)
+    n_facts = int((L == 0).sum())
+    assert n_facts == (2000 - 1) // 3 and n_facts < 2000 / 3
+    assert len(set(p.head[L == 0].tolist())) == n_facts  # distinct fact atoms
+    body = L[L > 0]
+    for length, q in enumerate(gen.PAPER_BODY_PROPORTIONS, 1):
+        assert abs((body == length).mean() - q) < 0.002, length
+    for r in range(0, p.n_rules, 97):  # bodies: distinct atoms, never the head
+        lits = p.body_lit[p.body_ptr[r]:p.body_ptr[r + 1]]
+        assert len(set(lits.tolist())) == lits.shape[0] and p.head[r] not in lits and (lits >= 0).all()
+
+
+def test_paper_normal_negations():
+    p = gen.paper_normal(4, 1000, 5000, 7)
+    assert int((p.body_lit < 0).sum()) == 7
+    base = gen.paper_definite(4, 1000, 5000)
+    assert np.array_equal(np.where(p.body_lit < 0, -p.body_lit - 1, p.body_lit), base.body_lit)
+
+
+def test_transitive_closure_all_grounding_is_warshall():
+    # the all-triples grounding of path/edge: its least model's path atoms are
+    # the transitive closure (Warshall's algorithm on the adjacency matrix)
+    V = 9
+    edges = gen.random_graph_edges(2, V, 14)
+    p = gen.transitive_closure(V, edges, grounding="all")
+    assert p.n_atoms == 2 * V * V and p.n_rules == V ** 3 + V * V + len(edges)
+    model = oracle.least_model(p)
+    reach = np.zeros((V, V), dtype=bool)
+    for x, y in edges:
+        reach[x, y] = True
+    for z in range(V):
+        reach |= reach[:, [z]] & reach[[z], :]
+    assert np.array_equal(model[V * V:].reshape(V, V).astype(bool), reach)

@@ -356,6 +356,19 @@ def main() -> int:
                       "guesses": H, "ms_per_solve": round(sms, 3), "guesses_per_s": round(H / (sms / 1e3), 1),
                       "n_models": r["n_models"], "products": r["products"]}
         log(f"[bench] stable: {stable}")
+        # guess sampling with local search where 2^K cannot be enumerated: a normal program with
+        # 40 negated atoms (65,536 guesses per round, 4 rounds; every found model is sound)
+        qs = gen.normal_uniform(args.seed, 10_000, 20_000, k_neg=40, p_neg=0.1)
+        with lp.Matrix(qs, stream=stream) as ms:
+            ms.stable_search(n_samples=1024, rounds=1, seed=1, stream=stream)
+            t = time.perf_counter()
+            sr = ms.stable_search(n_samples=65536, rounds=4, seed=2, max_found=4096, stream=stream)
+            sdt = time.perf_counter() - t
+            stable["search"] = {"workload": "normal_uniform: 10,000 atoms, 20,000 rules, 40 negated atoms "
+                                            "(2^40 guesses)", "guesses": 4 * 65536, "rounds": 4,
+                                "ms": round(sdt * 1e3, 3), "guesses_per_s": round(4 * 65536 / sdt, 1),
+                                "models_found": sr["n_found"]}
+        log(f"[bench] stable search: {stable['search']}")
 
     batch = None if args.no_batch else bench_batch(args, torch, gen, lp, stream)
 

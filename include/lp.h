@@ -95,7 +95,8 @@ typedef struct lp_info {
                                (least models: the AND lengths, one entry offset per four
                                words, the AND entries, the OR range table, the long-row
                                segments, one read of v and one write of u; stable models:
-                               CSR, one read of V, one write of U) */
+                               CSR, one read of V, one write of U for all 2^K guesses; 0 when
+                               K exceeds LP_MAX_NEG_ATOMS) */
     double sparsity;        /* equation 5: 1 - sum_r |body(r)| / N^2 */
 } lp_info;
 
@@ -224,6 +225,55 @@ lp_status lp_least_model(const lp_matrix *m, uint8_t *model, int32_t *products,
 lp_status lp_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_models,
                            uint8_t *models, int64_t max_models, uint64_t *interp,
                            int32_t *products, void *hip_stream);
+
+/*
+ * Algorithms 2 and 3 on caller-chosen guesses, for programs whose 2^K guesses
+ * are too many to enumerate (1 <= K <= 64). Column j of the initial matrix
+ * (Definition 8) is guesses[j]: bit t is the initial value of qbar_t, as in
+ * lp_stable_models' guess order; bits at or above K are ignored.
+ * guesses:    uint64[n] host, 1 <= n <= 2^30 (duplicates allowed).
+ * accepted:   uint64[ceil(n/64)] host; bit j%64 of word j/64 = guess j passes
+ *             Algorithm 3's test (so its column is a stable model).
+ * n_accepted: receives the number of accepted entries of guesses.
+ * next:       nullable; uint64[n] host, for each guess the guess its fixpoint
+ *             points to: bit t set iff q_t is false in that fixpoint. An
+ *             accepted guess maps to itself; lp_stable_models_search iterates
+ *             this map.
+ * models:     nullable; uint8[max_models][n_atoms] host, the accepted columns
+ *             restricted to the original atoms, in the order of guesses.
+ * products:   nullable; theta(M_P M) evaluations until no column changed.
+ * Device memory: two interpretation matrices of n_rows x W words, W = the
+ * next power of two >= n/64. Errors: LP_E_INVAL (K = 0, bad arguments),
+ * LP_E_TOO_MANY_GUESSES (K > 64), LP_E_TRUNCATED (more accepted than
+ * max_models; the other outputs are complete), LP_E_NOMEM, LP_E_DEVICE.
+ */
+lp_status lp_stable_models_guesses(const lp_matrix *m, const uint64_t *guesses, int64_t n,
+                                   uint64_t *accepted, int64_t *n_accepted, uint64_t *next,
+                                   uint8_t *models, int64_t max_models, int32_t *products,
+                                   void *hip_stream);
+
+/*
+ * Stable models by guess sampling and local search (the paper's closing
+ * remarks name sampling guesses for programs with many negations as future
+ * work; this is one such search, sound but not complete). rounds rounds of
+ * n_samples guesses through lp_stable_models_guesses: round 0 draws guess j
+ * as SplitMix64 output j of the stream seeded with seed, masked to K bits;
+ * in later rounds a guess that was not accepted flips each bit where it
+ * disagrees with the guess its fixpoint points to with probability 1/2 (a
+ * mask drawn from the stream; at least one bit), and an accepted one is
+ * replaced by the next draw of the stream.
+ * Every accepted guess is a stable model (Algorithm 3); models that no
+ * sampled or repaired guess reaches are missed.
+ * found:    uint64[max_found] host, the distinct accepted guesses, ascending
+ *           (the first max_found of them).
+ * n_found:  receives the number of distinct accepted guesses.
+ * models:   nullable; uint8[max_found][n_atoms] host, the models of found.
+ * Errors: as lp_stable_models_guesses; LP_E_TRUNCATED if more than
+ *   max_found guesses were found.
+ */
+lp_status lp_stable_models_search(const lp_matrix *m, int64_t n_samples, int32_t rounds,
+                                  uint64_t seed, uint64_t *found, int64_t max_found,
+                                  int64_t *n_found, uint8_t *models, void *hip_stream);
 
 /*
  * Least models of count definite programs (Algorithm 1 for each) in one

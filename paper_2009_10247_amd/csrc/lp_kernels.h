@@ -146,6 +146,10 @@ hipError_t launch_frontier_level(const FrontierParams &f, int grid, hipStream_t 
 hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std,
                           const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff,
                           unsigned long long *count, unsigned long long bits, hipStream_t st);
+hipError_t launch_init_guess(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std, int32_t K,
+                             const uint64_t *fact_bits, const uint64_t *guesses, hipStream_t st);
+hipError_t launch_next_guess(const uint64_t *V, int32_t log2W, int64_t n_cols, const int32_t *q_rows, int32_t K,
+                             uint64_t *out, hipStream_t st);
 hipError_t launch_stable_check(const uint64_t *V, int32_t log2W, int64_t W, const int32_t *q_rows, int32_t n_std,
                                int32_t K, int32_t k_eff, uint64_t *accept, unsigned long long *count,
                                hipStream_t st);

@@ -377,10 +377,12 @@ static lp_status upload_matrix(Matrix &m, hipStream_t st) {
     const int64_t vbytes = (m.n_rows + 7) / 8;
     if (m.K == 0) {
         m.info.step_bytes = d.stream_bytes + 2 * vbytes;
-    } else {
+    } else if (m.K_eff <= LP_MAX_NEG_ATOMS) {
         const int keff = m.K_eff;
         const int64_t wbytes = ((((int64_t)1 << keff) + 63) / 64) * 8;
         m.info.step_bytes = 4 * ((int64_t)m.n_rows + 1) + 4 * m.nnz + vbytes + 2 * (int64_t)m.n_rows * wbytes;
+    } else {
+        m.info.step_bytes = 0;  // the guesses cannot be enumerated: the width depends on the guesses given
     }
     return LP_OK;
 }
@@ -825,8 +827,9 @@ static int spmm_grid(const Matrix &m) {
     return 8 * d.n_cu;
 }
 
-static SpmmParams spmm_params(const Matrix &m, unsigned long long *counters) {
-    const int64_t W = ((1ll << m.K_eff) + 63) / 64;
+// log2W < 0: the width of the enumerated guess space (K_eff <= LP_MAX_NEG_ATOMS).
+static SpmmParams spmm_params(const Matrix &m, unsigned long long *counters, int log2W = -1) {
+    const int64_t W = log2W >= 0 ? (1ll << log2W) : ((1ll << m.K_eff) + 63) / 64;
     SpmmParams p{};
     p.row_ptr = m.dev.full_row_ptr;
     p.col = m.dev.full_col;
@@ -842,6 +845,9 @@ static SpmmParams spmm_params(const Matrix &m, unsigned long long *counters) {
 // changes; *fix is the buffer holding the fixpoint. The counters hold the bit
 // count of each product's result (slot 0: the initial matrix); product s
 // changed nothing iff its count equals that of product s - 1.
+static lp_status stable_loop(const Matrix &m, SpmmParams p, hipStream_t st, uint64_t *const buf[2],
+                             unsigned long long *counters, int32_t *products, uint64_t **fix);
+
 static lp_status stable_fixpoint(const Matrix &m, hipStream_t st, uint64_t *const buf[2],
                                  unsigned long long *counters, int32_t *products, uint64_t **fix) {
     SpmmParams p = spmm_params(m, counters);
@@ -851,6 +857,13 @@ static lp_status stable_fixpoint(const Matrix &m, hipStream_t st, uint64_t *cons
     const unsigned long long m0_bits = (unsigned long long)m.info.n_fact_rows * H + (unsigned long long)m.K_eff * (H / 2);
     LP_HIP(launch_init_m0(buf[0], buf[1], p.total, p.log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, m.K_eff,
                           &counters[0], m0_bits, st));
+    return stable_loop(m, p, st, buf, counters, products, fix);
+}
+
+// Products of Algorithm 2 from the initial matrix in buf[0] (and buf[1]),
+// whose bit count is in counters[0], until a product changes no column.
+static lp_status stable_loop(const Matrix &m, SpmmParams p, hipStream_t st, uint64_t *const buf[2],
+                             unsigned long long *counters, int32_t *products, uint64_t **fix) {
     unsigned long long *h = pinned_ring();
     if (!h) {
         set_error("pinned host allocation failed");
@@ -977,6 +990,151 @@ static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_mod
     if (products) *products = prods;
     if (models && (int64_t)nm > max_models) return LP_E_TRUNCATED;
     return LP_OK;
+}
+
+// Algorithms 2 and 3 on caller-given guesses (K <= 64): column j of the
+// initial matrix is guesses[j]. The columns are padded to a power of two of
+// words with copies of guesses[0]; padded columns are ignored.
+// accepted: bits of the n guesses; next (nullable): for each guess, the guess
+// its fixpoint points to (qbar_t = not q_t); models (nullable): the first
+// max_models accepted columns restricted to the original atoms.
+static lp_status guesses_impl(const Matrix &m, const uint64_t *guesses, int64_t n, uint64_t *accepted,
+                              int64_t *n_accepted, uint64_t *next, uint8_t *models, int64_t max_models,
+                              int32_t *products, hipStream_t st) {
+    const int K = m.K;
+    const int64_t W = std::max<int64_t>(1, (int64_t)1 << ilog2((n + 63) / 64));
+    const int64_t cols = W * 64;
+    const int log2W = ilog2(W);
+    const int64_t total = (int64_t)m.n_rows * W;
+    size_t free_b = 0, total_b = 0;
+    LP_HIP(hipMemGetInfo(&free_b, &total_b));
+    double avail = (double)free_b;
+    {
+        DevicePool &P = pool();
+        std::lock_guard<std::mutex> lock(P.mu);
+        avail += (double)P.cached;
+    }
+    const double need = 2.0 * (double)total * 8.0 + 2.0 * (double)cols * 8.0 + (double)W * 8.0 + 4096.0;
+    if (need > avail) {
+        set_error("guess evaluation needs " + std::to_string((long long)need) + " bytes of device memory, " +
+                  std::to_string((long long)avail) + " available");
+        return LP_E_NOMEM;
+    }
+    const uint64_t kmask = K == 64 ? ~0ull : ((1ull << K) - 1ull);
+    std::vector<uint64_t> g((size_t)cols);
+    unsigned long long m0_bits = (unsigned long long)m.info.n_fact_rows * (unsigned long long)cols;
+    for (int64_t j = 0; j < cols; ++j) {
+        g[j] = (j < n ? guesses[j] : guesses[0]) & kmask;
+        m0_bits += (unsigned long long)__builtin_popcountll(g[j]);
+    }
+    Scratch S(st);
+    uint64_t *buf[2], *acc_d, *g_d, *next_d;
+    unsigned long long *counters;
+    lp_status rc;
+    if ((rc = S.get(&buf[0], total)) || (rc = S.get(&buf[1], total)) || (rc = S.get(&acc_d, W)) ||
+        (rc = S.get(&g_d, cols)) || (rc = S.get(&next_d, cols)) || (rc = S.get(&counters, kRing)))
+        return rc;
+    LP_HIP(hipMemcpyAsync(g_d, g.data(), cols * 8, hipMemcpyHostToDevice, st));
+    LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
+    LP_HIP(launch_init_guess(buf[0], buf[1], total, log2W, m.n_std, K, m.dev.fact_bits, g_d, st));
+    LP_HIP(hipMemcpyAsync(counters, &m0_bits, 8, hipMemcpyHostToDevice, st));
+    SpmmParams p = spmm_params(m, counters, log2W);
+    int32_t prods = -1;
+    uint64_t *fix = nullptr;
+    if ((rc = stable_loop(m, p, st, buf, counters, &prods, &fix))) return rc;
+    unsigned long long *cnt_d = counters;
+    LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
+    LP_HIP(launch_stable_check(fix, log2W, W, m.dev.q_rows, m.n_std, K, 6, acc_d, cnt_d, st));
+    if (next) LP_HIP(launch_next_guess(fix, log2W, cols, m.dev.q_rows, K, next_d, st));
+    std::vector<uint64_t> acc_h(W);
+    LP_HIP(hipMemcpyAsync(acc_h.data(), acc_d, W * 8, hipMemcpyDeviceToHost, st));
+    if (next) LP_HIP(hipMemcpyAsync(next, next_d, n * 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    std::memset(accepted, 0, sizeof(uint64_t) * (size_t)((n + 63) / 64));
+    std::vector<int64_t> acc_cols;
+    int64_t na = 0;
+    for (int64_t j = 0; j < n; ++j)
+        if ((acc_h[j >> 6] >> (j & 63)) & 1ull) {
+            accepted[j >> 6] |= 1ull << (j & 63);
+            ++na;
+            if (models && (int64_t)acc_cols.size() < max_models) acc_cols.push_back(j);
+        }
+    *n_accepted = na;
+    if (models && !acc_cols.empty() && m.n_atoms) {
+        int64_t *cols_d;
+        uint8_t *out_d;
+        const int64_t nb = (int64_t)acc_cols.size() * m.n_atoms;
+        if ((rc = S.get(&cols_d, acc_cols.size())) || (rc = S.get(&out_d, nb))) return rc;
+        LP_HIP(hipMemcpyAsync(cols_d, acc_cols.data(), acc_cols.size() * 8, hipMemcpyHostToDevice, st));
+        LP_HIP(launch_extract(fix, log2W, cols_d, (int64_t)acc_cols.size(), m.n_atoms, out_d, st));
+        LP_HIP(hipMemcpyAsync(models, out_d, nb, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+    }
+    if (products) *products = prods;
+    if (models && na > max_models) return LP_E_TRUNCATED;
+    return LP_OK;
+}
+
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): output number i of the stream with the given seed.
+static inline uint64_t splitmix64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Guess sampling with local search (for K too large to enumerate): rounds of
+// n_samples guesses. Round 0 draws them from splitmix64(seed, j). Afterwards a
+// column that was not accepted continues with its guess where each bit that
+// disagrees with the guess its fixpoint points to (qbar_t = not q_t) is
+// flipped with probability 1/2 (a random mask from the same stream; at least
+// one bit flips): flipping all of them can oscillate, as in an even loop
+// a <- not b, b <- not a, where assuming both or neither maps to the other.
+// An accepted column continues with a fresh draw. Every accepted guess is a
+// stable model (Algorithm 3's test); the search is not complete. found: the
+// distinct accepted guesses, ascending, the first max_found of them.
+static lp_status search_impl(const Matrix &m, int64_t n_samples, int32_t rounds, uint64_t seed, uint64_t *found,
+                             int64_t max_found, int64_t *n_found, uint8_t *models, hipStream_t st) {
+    const int K = m.K;
+    const uint64_t kmask = K == 64 ? ~0ull : ((1ull << K) - 1ull);
+    std::vector<uint64_t> g((size_t)n_samples), nx((size_t)n_samples), acc((size_t)(n_samples + 63) / 64);
+    uint64_t draws = 0;
+    for (int64_t j = 0; j < n_samples; ++j) g[j] = splitmix64(seed, draws++) & kmask;
+    std::vector<uint64_t> hits;
+    for (int32_t r = 0; r < rounds; ++r) {
+        int64_t na = 0;
+        lp_status rc = guesses_impl(m, g.data(), n_samples, acc.data(), &na, nx.data(), nullptr, 0, nullptr, st);
+        if (rc) return rc;
+        for (int64_t j = 0; j < n_samples; ++j) {
+            const bool ok = (acc[j >> 6] >> (j & 63)) & 1ull;
+            if (ok) hits.push_back(g[j]);
+            const uint64_t diff = g[j] ^ nx[j];  // 0 iff accepted
+            if (ok || diff == 0) {
+                g[j] = splitmix64(seed, draws++) & kmask;
+            } else {
+                uint64_t flip = diff & splitmix64(seed, draws++);
+                if (flip == 0) flip = diff & (~diff + 1);  // the lowest disagreeing bit
+                g[j] ^= flip;
+            }
+        }
+    }
+    std::sort(hits.begin(), hits.end());
+    hits.erase(std::unique(hits.begin(), hits.end()), hits.end());
+    *n_found = (int64_t)hits.size();
+    const int64_t keep = std::min<int64_t>((int64_t)hits.size(), max_found);
+    if (keep > 0) std::memcpy(found, hits.data(), sizeof(uint64_t) * (size_t)keep);
+    if (models && keep > 0) {
+        std::vector<uint64_t> acc2((size_t)(keep + 63) / 64);
+        int64_t na = 0;
+        lp_status rc = guesses_impl(m, hits.data(), keep, acc2.data(), &na, nullptr, models, keep, nullptr, st);
+        if (rc && rc != LP_E_TRUNCATED) return rc;
+        if (na != keep) {
+            set_error("a found guess was not accepted again");
+            return LP_E_INTERNAL;
+        }
+    }
+    return (int64_t)hits.size() > max_found ? LP_E_TRUNCATED : LP_OK;
 }
 
 struct Events {
@@ -1700,6 +1858,46 @@ lp_status lp_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_mo
     }
     DeviceGuard g(m->m.dev.device);
     return stable_impl(m->m, accepted, n_models, models, max_models, interp, products, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_stable_models_guesses(const lp_matrix *m, const uint64_t *guesses, int64_t n, uint64_t *accepted,
+                                   int64_t *n_accepted, uint64_t *next, uint8_t *models, int64_t max_models,
+                                   int32_t *products, void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K == 0 || m->m.K > 64) {
+        set_error("guess evaluation needs 1 to 64 negated atoms, the program has " + std::to_string(m->m.K));
+        return m->m.K > 64 ? LP_E_TOO_MANY_GUESSES : LP_E_INVAL;
+    }
+    if (!guesses || n < 1 || n > (1ll << 30) || !accepted || !n_accepted || max_models < 0) {
+        set_error("guesses and accepted must be non-NULL, 1 <= n <= 2^30, max_models >= 0");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return guesses_impl(m->m, guesses, n, accepted, n_accepted, next, models, max_models, products,
+                        (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_stable_models_search(const lp_matrix *m, int64_t n_samples, int32_t rounds, uint64_t seed,
+                                  uint64_t *found, int64_t max_found, int64_t *n_found, uint8_t *models,
+                                  void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K == 0 || m->m.K > 64) {
+        set_error("guess search needs 1 to 64 negated atoms, the program has " + std::to_string(m->m.K));
+        return m->m.K > 64 ? LP_E_TOO_MANY_GUESSES : LP_E_INVAL;
+    }
+    if (n_samples < 1 || n_samples > (1ll << 30) || rounds < 1 || !n_found || max_found < 0 ||
+        (max_found > 0 && !found)) {
+        set_error("1 <= n_samples <= 2^30, rounds >= 1, n_found non-NULL, found non-NULL if max_found > 0");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return search_impl(m->m, n_samples, rounds, seed, found, max_found, n_found, models, (hipStream_t)hip_stream);
     LP_GUARD_END
 }
 

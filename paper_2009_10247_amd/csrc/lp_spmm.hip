@@ -180,6 +180,43 @@ __global__ __launch_bounds__(kBlock) void init_m0_kernel(uint64_t *V, uint64_t *
     if (g < total) init_m0_word(V, U, g, log2W, n_std, fact_bits, guess_pos, k_eff);
 }
 
+// Initial matrix for explicit guesses (word g, both buffers): column j is
+// guess j of the caller's list, bit t of guesses[j] the initial value of
+// qbar_t (row n_std + t); fact rows are all ones; every other row is 0.
+__global__ __launch_bounds__(kBlock) void init_guess_kernel(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W,
+                                                            int32_t n_std, int32_t K, const uint64_t *fact_bits,
+                                                            const uint64_t *guesses) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= total) return;
+    const int32_t row = (int32_t)(g >> log2W);
+    const int64_t w = g & ((1ll << log2W) - 1);
+    uint64_t x = 0;
+    if ((fact_bits[row >> 6] >> (row & 63)) & 1ull) {
+        x = ~0ull;
+    } else if (row >= n_std && row - n_std < K) {
+        const int t = row - n_std;
+        const uint64_t *gw = guesses + w * 64;
+        for (int b = 0; b < 64; ++b) x |= ((gw[b] >> t) & 1ull) << b;
+    }
+    V[g] = x;
+    U[g] = x;
+}
+
+// The guess each column's fixpoint points to: bit t set iff q_t is false in
+// the column (then assuming qbar_t is the consistent choice). A column that
+// Algorithm 3 accepts maps to its own guess.
+__global__ __launch_bounds__(kBlock) void next_guess_kernel(const uint64_t *V, int32_t log2W, int64_t n_cols,
+                                                            const int32_t *q_rows, int32_t K, uint64_t *out) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n_cols) return;
+    const int64_t w = j >> 6;
+    const int b = (int)(j & 63);
+    uint64_t g = 0;
+    for (int32_t t = 0; t < K; ++t)
+        if (!((V[((int64_t)q_rows[t] << log2W) + w] >> b) & 1ull)) g |= 1ull << t;
+    out[j] = g;
+}
+
 // Algorithm 3: column j is accepted iff for every negated atom q_t exactly
 // one of row q_t and row qbar_t is 1 (a_l + a_j = 1), i.e. their XOR is 1.
 __global__ __launch_bounds__(kBlock) void stable_check_kernel(const uint64_t *V, int32_t log2W, int64_t W,
@@ -235,6 +272,20 @@ hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W
                           unsigned long long *count, unsigned long long bits, hipStream_t st) {
     hipLaunchKernelGGL(init_m0_kernel, dim3(blocks_for(total)), dim3(kBlock), 0, st, V, U, total, log2W, n_std,
                        fact_bits, guess_pos, k_eff, count, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_guess(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std, int32_t K,
+                             const uint64_t *fact_bits, const uint64_t *guesses, hipStream_t st) {
+    hipLaunchKernelGGL(init_guess_kernel, dim3(blocks_for(total)), dim3(kBlock), 0, st, V, U, total, log2W, n_std, K,
+                       fact_bits, guesses);
+    return hipGetLastError();
+}
+
+hipError_t launch_next_guess(const uint64_t *V, int32_t log2W, int64_t n_cols, const int32_t *q_rows, int32_t K,
+                             uint64_t *out, hipStream_t st) {
+    hipLaunchKernelGGL(next_guess_kernel, dim3(blocks_for(n_cols)), dim3(kBlock), 0, st, V, log2W, n_cols, q_rows, K,
+                       out);
     return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ LP_STEP_GLOBAL = 1
 LP_STEP_LDS = 2
 
 EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg_atoms",
-           "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_least_model_batch",
+           "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_stable_models_guesses",
+           "lp_stable_models_search", "lp_least_model_batch",
            "lp_batch_create", "lp_batch_run", "lp_batch_results", "lp_batch_tune",
            "lp_batch_get_info", "lp_batch_free", "lp_matrix_evict", "lp_matrix_upload",
            "lp_server_create", "lp_server_add_program", "lp_server_submit", "lp_server_wait_any",
@@ -128,6 +129,8 @@ def load():
         "lp_matrix_csr": [P, P, P, P, P],
         "lp_least_model": [P, P, P, P, P],
         "lp_stable_models": [P, P, P, P, i64, P, P, P],
+        "lp_stable_models_guesses": [P, P, i64, P, ctypes.POINTER(i64), P, P, i64, P, P],
+        "lp_stable_models_search": [P, i64, i32, ctypes.c_uint64, P, i64, ctypes.POINTER(i64), P, P],
         "lp_least_model_batch": [P, i32, P, P, P, P],
         "lp_batch_create": [P, i32, P, P, ctypes.POINTER(P)],
         "lp_batch_run": [P, P],
@@ -305,6 +308,44 @@ class Matrix:
         _check(load().lp_bench_step(self._h, ctypes.byref(sched) if sched is not None else None,
                                     int(reps), ctypes.byref(ms), _stream(stream)))
         return ms.value
+
+    def stable_guesses(self, guesses, max_models: int = 0, want_next: bool = True, stream=None) -> dict:
+        """Algorithms 2 and 3 on given guesses (lp_stable_models_guesses): dict(accepted=bool[n],
+        n_accepted, next=uint64[n] or None, models=uint8[m][n_atoms], products, truncated)."""
+        g = np.ascontiguousarray(guesses, dtype=np.uint64)
+        n = int(g.shape[0])
+        acc = np.zeros(max((n + 63) // 64, 1), dtype=np.uint64)
+        na = ctypes.c_int64(0)
+        prods = ctypes.c_int32(0)
+        nxt = np.zeros(max(n, 1), dtype=np.uint64) if want_next else None
+        models = np.zeros((max(max_models, 1), max(self.n_atoms, 1)), dtype=np.uint8) if max_models else None
+        rc = _check(load().lp_stable_models_guesses(
+            self._h, g.ctypes.data, n, acc.ctypes.data, ctypes.byref(na),
+            nxt.ctypes.data if nxt is not None else None, models.ctypes.data if models is not None else None,
+            int(max_models), ctypes.addressof(prods), _stream(stream)), allow=(LP_E_TRUNCATED,))
+        bits = np.unpackbits(acc.view(np.uint8), bitorder="little")[:n].astype(bool)
+        out = dict(accepted=bits, n_accepted=na.value, next=nxt[:n] if nxt is not None else None,
+                   products=prods.value, truncated=rc == LP_E_TRUNCATED)
+        if models is not None:
+            out["models"] = models[: min(na.value, max_models), : self.n_atoms]
+        return out
+
+    def stable_search(self, n_samples: int = 4096, rounds: int = 4, seed: int = 0, max_found: int = 1024,
+                      want_models: bool = True, stream=None) -> dict:
+        """Guess sampling with local search (lp_stable_models_search): dict(found=uint64[k] ascending,
+        n_found, models=uint8[k][n_atoms], truncated)."""
+        found = np.zeros(max(max_found, 1), dtype=np.uint64)
+        nf = ctypes.c_int64(0)
+        models = np.zeros((max(max_found, 1), max(self.n_atoms, 1)), dtype=np.uint8) if want_models else None
+        rc = _check(load().lp_stable_models_search(
+            self._h, int(n_samples), int(rounds), ctypes.c_uint64(seed), found.ctypes.data, int(max_found),
+            ctypes.byref(nf), models.ctypes.data if models is not None else None, _stream(stream)),
+            allow=(LP_E_TRUNCATED,))
+        k = min(nf.value, max_found)
+        out = dict(found=found[:k], n_found=nf.value, truncated=rc == LP_E_TRUNCATED)
+        if models is not None:
+            out["models"] = models[:k, : self.n_atoms]
+        return out
 
     def bench_spmm(self, reps: int = 20, stream=None):
         """(average ms of one stable-model step on the fixpoint, fixpoint products)."""

@@ -14,7 +14,8 @@ Also reported: the dominant kernel (one full-sweep T_P step) against the HBM
 roofline, the CPU oracle timed on this host, stable-model guesses/s on a
 normal program with 10,000 atoms, 20,000 rules and 16 negated atoms, and 512
 programs of 1e3-1e5 atoms solved by one batch launch against 512 sequential
-single-program solves.
+single-program solves, and the dense-matrix method (the paper's third method)
+beside the sparse engine on the same programs.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
@@ -173,6 +174,82 @@ def copy_probe(torch, dev, stream, mib: int = 1024) -> float:
     return 2 * (mib << 20) / (ms / 1e3) / 1e9
 
 
+MFMA_INT8_PEAK_TOPS = 5000.0
+
+
+def dense_roofline(n_rows: int, columns: int, ms: float) -> dict:
+    """Roofline of one dense product: the method reads every one of the n'^2
+    matrix entries (one byte each) and reads and writes n' bytes per column;
+    a product with c columns is 2 n'^2 c int8 operations. The bound is the
+    larger of the two times at peak (HBM 8 TB/s, int8 matrix cores 5.0 POP/s)."""
+    ops = 2.0 * n_rows * n_rows * columns
+    nbytes = float(n_rows) * n_rows + 2.0 * n_rows * columns
+    secs = ms / 1e3
+    if columns > 1 and ops / (MFMA_INT8_PEAK_TOPS * 1e12) >= nbytes / (HBM_PEAK_GBS * 1e9):
+        ach = ops / secs / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 1), "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": round(ach / MFMA_INT8_PEAK_TOPS, 4), "ops_per_launch": ops}
+    ach = nbytes / secs / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes}
+
+
+def bench_dense(gen, lp, stream) -> dict:
+    """The dense-matrix method against the sparse engine on the same programs:
+    the sixth rows of the paper's definite- and normal-program tables (2,000
+    atoms, 40,000 rules; the normal one with 8 negated body literals), and the
+    normal program with 16 negated atoms (65,536 guess columns), where the
+    dense product is bound by the matrix cores."""
+    import numpy as np
+
+    from paper_2009_10247_amd import paper_tables as pt
+
+    out = {}
+    cases = (("definite_2k_40k", gen.paper_definite(0, 2000, 40000), False, ("definite", 6)),
+             ("normal_2k_40k_k8", gen.paper_normal(0, 2000, 40000, 8), True, ("normal", 6)),
+             ("normal_10k_k16", gen.normal_uniform(0), True, None))
+    for name, p, stable, paper in cases:
+        with lp.Matrix(p, stream=stream) as m:
+            n = m.info["n_rows"]
+            K = m.info["n_neg"]
+            # first call warms up; the second is timed (solve includes building the dense matrix)
+            if stable:
+                m.dense_stable_models(max_models=16, stream=stream)
+                t = time.perf_counter()
+                r = m.dense_stable_models(max_models=16, stream=stream)
+                dense_s = time.perf_counter() - t
+                prods, kms = r["products"], r["kernel_ms"]
+                m.stable_models(max_models=16, stream=stream)
+                t = time.perf_counter()
+                rs = m.stable_models(max_models=16, stream=stream)
+                sparse_s = time.perf_counter() - t
+                assert np.array_equal(r["accepted"], rs["accepted"]) and r["products"] == rs["products"]
+                cols = 1 << K
+            else:
+                m.dense_least_model(stream=stream)
+                t = time.perf_counter()
+                model, prods, kms = m.dense_least_model(stream=stream)
+                dense_s = time.perf_counter() - t
+                m.least_model(stream=stream)
+                t = time.perf_counter()
+                smodel, sprods = m.least_model(stream=stream)
+                sparse_s = time.perf_counter() - t
+                assert np.array_equal(model, smodel) and prods == sprods
+                cols = 1
+        kern = "dense_gemm_kernel" if stable else "dense_gemv_kernel"
+        row = {"n_rows": n, "negated_atoms": K, "columns": cols, "products": prods,
+               "dense_solve_ms": round(dense_s * 1e3, 3), "sparse_solve_ms": round(sparse_s * 1e3, 3),
+               "dense_over_sparse": round(dense_s / sparse_s, 1), "kernel": kern,
+               "us_per_launch": round(kms * 1e3, 2), "roofline": dense_roofline(n, cols, kms)}
+        if paper:
+            row["paper_dense_s"] = pt.PAPER_DENSE_S[paper[0]][paper[1]]
+            spec = (pt.DEFINITE_ROWS if paper[0] == "definite" else pt.NORMAL_ROWS)[paper[1] - 1]
+            row["paper_sparse_s"] = spec[3] if paper[0] == "definite" else spec[4]
+        out[name] = row
+        log(f"[bench] dense {name}: {row}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +261,9 @@ def main() -> int:
     ap.add_argument("--no-stable", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-frontier", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="run only the dense-matrix contrast and print its JSON")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true", help="time every step shape (diagnostic)")
     ap.add_argument("--tune-reps", type=int, default=20)
@@ -215,6 +295,10 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+
+    if args.dense_only:
+        print(json.dumps(bench_dense(gen, lp, stream)), flush=True)
+        return 0
 
     t = time.perf_counter()
     n_atoms, n_rules = 1_000_000 * args.scale_atoms, 5_000_000 * args.scale_rules
@@ -371,6 +455,7 @@ def main() -> int:
         log(f"[bench] stable search: {stable['search']}")
 
     batch = None if args.no_batch else bench_batch(args, torch, gen, lp, stream)
+    dense = None if args.no_dense else bench_dense(gen, lp, stream)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -414,6 +499,7 @@ def main() -> int:
         "stable_models": stable,
         "batch": batch,
         "frontier": frontier,
+        "dense": dense,
         "schedule": lp.schedule_dict(sched),
         "step_us_per_shape": variants or None,
     }

@@ -381,6 +381,40 @@ lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t re
 lp_status lp_bench_spmm(const lp_matrix *m, int32_t reps, float *avg_ms, int32_t *products, void *hip_stream);
 
 /*
+ * The dense-matrix method that the paper's experiments (Section 4) set
+ * against the sparse one: Algorithms 1 and 2 (and 3) with the program matrix
+ * of Definitions 2 and 7 expanded on the device to an n' x n' byte matrix,
+ * n' = lp_info.n_rows rounded up to a multiple of 1024, so that every product
+ * reads all n'^2 entries. It computes the same models and the same product
+ * counts as lp_least_model and lp_stable_models; it exists to measure what
+ * the sparse form saves. The dense matrix is built on hip_stream at each call
+ * and released before the call returns.
+ *
+ * lp_dense_least_model: Algorithm 1, a byte-vector product per iteration.
+ *   model (uint8[n_atoms] host) and products as in lp_least_model.
+ * lp_dense_stable_models: Algorithms 2 and 3 over all 2^K guesses (the guess
+ *   order of lp_stable_models, with no pruning): the interpretation matrix is
+ *   held as 2^K columns of n' bytes (columns padded to a multiple of 128) and
+ *   each product runs on the int8 matrix cores. accepted (uint64[ceil(2^K/64)]
+ *   host), n_models, models (nullable, uint8[max_models][n_atoms] host, the
+ *   first max_models models in guess order) and products as in
+ *   lp_stable_models. K = 0 gives the least model as the one stable model.
+ * kernel_ms: nullable; receives the mean time of one product launch,
+ *   measured with HIP events on hip_stream.
+ * Device memory: n'^2 + 2 n' bytes, plus two interpretation matrices of
+ *   (2^K rounded up to 128) x n' bytes for stable models.
+ * Errors: LP_E_NEGATION (lp_dense_least_model on a program with negative
+ *   literals), LP_E_TOO_MANY_GUESSES (K > LP_MAX_NEG_ATOMS), LP_E_NOMEM (the
+ *   dense form does not fit in free device memory; checked before any
+ *   allocation), LP_E_TRUNCATED (more models than max_models; other outputs
+ *   complete), LP_E_INVAL, LP_E_HOST_ONLY, LP_E_DEVICE.
+ */
+lp_status lp_dense_least_model(const lp_matrix *m, uint8_t *model, int32_t *products, float *kernel_ms,
+                               void *hip_stream);
+lp_status lp_dense_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
+                                 int64_t max_models, int32_t *products, float *kernel_ms, void *hip_stream);
+
+/*
  * Autotuner for least-model solves of m (a definite program). Times every
  * supported step shape (LP_STEP_LDS / LP_STEP_GLOBAL, 4 or 8 words per super-block,
  * 4/8/16 chunks in flight) over reps full-sweep steps on m's own fixpoint

@@ -14,8 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblp.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("lp_build.cpp", "lp_step.hip", "lp_batch.hip", "lp_spmm.hip", "lp_frontier.hip", "lp_runtime.hip",
-            "lp_server.cpp")]
+           ("lp_build.cpp", "lp_step.hip", "lp_batch.hip", "lp_spmm.hip", "lp_frontier.hip", "lp_dense.hip",
+            "lp_runtime.hip", "lp_server.cpp")]
 ARCH = os.environ.get("LP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -156,4 +156,22 @@ hipError_t launch_stable_check(const uint64_t *V, int32_t log2W, int64_t W, cons
 hipError_t launch_extract(const uint64_t *V, int32_t log2W, const int64_t *cols, int64_t n_models, int32_t n_atoms,
                           uint8_t *out, hipStream_t st);
 
+// Dense-matrix products (lp_dense.hip). The dense matrix is ld x ld bytes with
+// ld = n_rows rounded up to kDenseAlign; interpretation matrices are hp x ld
+// bytes (guess-major) with hp = 2^K rounded up to kDenseColAlign.
+constexpr int64_t kDenseAlign = 1024;
+constexpr int64_t kDenseColAlign = 128;
+hipError_t launch_dense_scatter(uint8_t *M, int64_t ld, const int32_t *row_ptr, const int32_t *col, int32_t n_rows,
+                                hipStream_t st);
+hipError_t launch_dense_gemv(const uint8_t *M, int64_t ld, const uint8_t *v, uint8_t *u, const int32_t *thr,
+                             unsigned long long *changed, hipStream_t st);
+hipError_t launch_dense_gemm(const uint8_t *M, const uint8_t *Vt, uint8_t *Ut, int64_t ld, int64_t hp,
+                             const int32_t *thr, unsigned long long *changed, hipStream_t st);
+hipError_t launch_dense_init(uint8_t *V, int64_t ld, int64_t h, int64_t hp, const uint8_t *fact, int32_t n_std,
+                             int32_t K, hipStream_t st);
+hipError_t launch_dense_check(const uint8_t *V, int64_t ld, int64_t h, const int32_t *q_rows, int32_t n_std,
+                              int32_t K, uint64_t *accept, unsigned long long *count, hipStream_t st);
+hipError_t launch_dense_gather(const uint8_t *V, int64_t ld, const int64_t *cols, int64_t n, int32_t n_atoms,
+                               uint8_t *out, hipStream_t st);
+
 }  // namespace lp

@@ -159,6 +159,25 @@ static void dev_free(void *p, hipStream_t st) {
     P.live.erase(it);
 }
 
+// LP_E_NOMEM unless `need` bytes fit in the device's free memory plus the
+// pool's cached blocks (which are reused or trimmed before an allocation fails).
+static lp_status check_device_memory(double need, const char *what) {
+    size_t free_b = 0, total_b = 0;
+    LP_HIP(hipMemGetInfo(&free_b, &total_b));
+    double avail = (double)free_b;
+    {
+        DevicePool &P = pool();
+        std::lock_guard<std::mutex> lock(P.mu);
+        avail += (double)P.cached;
+    }
+    if (need > avail) {
+        set_error(std::string(what) + " need " + std::to_string((long long)need) + " bytes of device memory, " +
+                  std::to_string((long long)avail) + " available");
+        return LP_E_NOMEM;
+    }
+    return LP_OK;
+}
+
 // RAII list of device buffers of one call.
 struct Scratch {
     hipStream_t st;
@@ -922,26 +941,12 @@ static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_mod
     const int64_t W = (H + 63) / 64;
     const int log2W = ilog2(W);
     const int64_t total = (int64_t)m.n_rows * W;
-    // memory check before any launch
-    size_t free_b = 0, total_b = 0;
-    LP_HIP(hipMemGetInfo(&free_b, &total_b));
-    double avail = (double)free_b;
-    {
-        DevicePool &P = pool();
-        std::lock_guard<std::mutex> lock(P.mu);
-        avail += (double)P.cached;  // cached blocks are reused or trimmed before an allocation fails
-    }
-    const double need = 2.0 * (double)total * 8.0 + (double)W * 8.0 + 4096.0;
-    if (need > avail) {
-        set_error("stable models need " + std::to_string((long long)need) + " bytes of device memory, " +
-                  std::to_string((long long)avail) + " available");
-        return LP_E_NOMEM;
-    }
+    lp_status rc = check_device_memory(2.0 * (double)total * 8.0 + (double)W * 8.0 + 4096.0, "stable models");
+    if (rc) return rc;
     Scratch S(st);
     uint64_t *buf[2];
     uint64_t *acc_d;
     unsigned long long *counters;
-    lp_status rc;
     if ((rc = S.get(&buf[0], total)) || (rc = S.get(&buf[1], total)) || (rc = S.get(&acc_d, W)) ||
         (rc = S.get(&counters, kRing)))
         return rc;
@@ -1671,6 +1676,182 @@ static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStrea
     return b.use_graph ? batch_capture(b) : LP_OK;
 }
 
+// ------------------------------------------------------------------ dense contrast
+//
+// The dense-matrix method of the paper's experiments (Section 4): the same
+// Algorithms 1 and 2 with M_P expanded to an ld x ld byte matrix (kernels in
+// lp_dense.hip). Built per call, released at its end.
+
+struct DenseMatrix {
+    uint8_t *M = nullptr;   // [ld][ld]
+    int32_t *thr = nullptr; // [ld] count a row needs to fire: AND length, OR 1, padding 1
+    uint8_t *fact = nullptr;// [ld] fact rows (the initial vector of Definition 4)
+    int64_t ld = 0;
+};
+
+static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+static int64_t dense_ld(const Matrix &m) { return round_up(std::max<int64_t>(m.n_rows, 1), kDenseAlign); }
+
+// Checks that the dense matrix plus extra_bytes fit, then builds it on st.
+static lp_status dense_build(const Matrix &m, Scratch &S, hipStream_t st, double extra_bytes, DenseMatrix *D) {
+    const int64_t ld = dense_ld(m);
+    const double need = (double)ld * (double)ld + 5.0 * (double)ld + 4.0 * (double)(m.nnz + m.n_rows + 1) +
+                        extra_bytes + 65536.0;
+    lp_status rc = check_device_memory(need, "the dense matrix and its interpretations");
+    if (rc) return rc;
+    std::vector<int32_t> thr(ld, 1);
+    std::vector<uint8_t> fact(ld, 0);
+    for (int32_t i = 0; i < m.n_rows; ++i) {
+        const int32_t len = m.row_ptr[i + 1] - m.row_ptr[i];
+        if (m.kind[i]) {
+            if (len == 0) {
+                set_error("AND row without entries in the program matrix");
+                return LP_E_INTERNAL;
+            }
+            thr[i] = len;
+        }
+        fact[i] = m.fact[i] ? 1 : 0;
+    }
+    int32_t *row_ptr_d, *col_d;
+    if ((rc = S.get(&D->M, (size_t)(ld * ld))) || (rc = S.get(&D->thr, ld)) || (rc = S.get(&D->fact, ld)) ||
+        (rc = S.get(&row_ptr_d, m.n_rows + 1)) || (rc = S.get(&col_d, std::max<int64_t>(m.nnz, 1))))
+        return rc;
+    D->ld = ld;
+    LP_HIP(hipMemsetAsync(D->M, 0, (size_t)(ld * ld), st));
+    LP_HIP(hipMemcpyAsync(D->thr, thr.data(), ld * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    LP_HIP(hipMemcpyAsync(D->fact, fact.data(), ld, hipMemcpyHostToDevice, st));
+    LP_HIP(hipMemcpyAsync(row_ptr_d, m.row_ptr.data(), (m.n_rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (m.nnz) LP_HIP(hipMemcpyAsync(col_d, m.col.data(), m.nnz * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    LP_HIP(launch_dense_scatter(D->M, ld, row_ptr_d, col_d, m.n_rows, st));
+    LP_HIP(hipStreamSynchronize(st));  // the host vectors above end here
+    return LP_OK;
+}
+
+// Jacobi loop shared by both algorithms: product(in, out, counter) until a
+// product changes nothing. *cur ends as the index of the fixpoint buffer;
+// *kernel_ms gets the mean product time (HIP events around each launch).
+template <class Product>
+static lp_status dense_loop(const Matrix &m, hipStream_t st, Scratch &S, Product product, int *cur, int32_t *products,
+                            float *kernel_ms) {
+    unsigned long long *cnt_d;
+    lp_status rc;
+    if ((rc = S.get(&cnt_d, 1))) return rc;
+    unsigned long long *h = pinned_ring();
+    if (!h) {
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
+    Events ev;
+    if ((rc = ev.init())) return rc;
+    double total_ms = 0.0;
+    int32_t p = 0;
+    int c = 0;
+    for (;;) {
+        if (p > m.n_rows + 1) {
+            set_error("dense fixpoint exceeded n_rows + 1 products");
+            return LP_E_INTERNAL;
+        }
+        LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
+        LP_HIP(hipEventRecord(ev.a, st));
+        LP_HIP(product(c, cnt_d));
+        LP_HIP(hipEventRecord(ev.b, st));
+        LP_HIP(hipMemcpyAsync(h, cnt_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        float ms = 0.f;
+        if ((rc = ev.elapsed(&ms))) return rc;
+        total_ms += ms;
+        ++p;
+        c ^= 1;
+        if (h[0] == 0) break;
+    }
+    *cur = c;
+    if (products) *products = p;
+    if (kernel_ms) *kernel_ms = (float)(total_ms / p);
+    return LP_OK;
+}
+
+static lp_status dense_least_impl(const Matrix &m, uint8_t *model, int32_t *products, float *kernel_ms,
+                                  hipStream_t st) {
+    Scratch S(st);
+    DenseMatrix D;
+    const int64_t ld = dense_ld(m);
+    lp_status rc = dense_build(m, S, st, 2.0 * (double)ld, &D);
+    if (rc) return rc;
+    uint8_t *v[2];
+    if ((rc = S.get(&v[0], ld)) || (rc = S.get(&v[1], ld))) return rc;
+    LP_HIP(hipMemcpyAsync(v[0], D.fact, ld, hipMemcpyDeviceToDevice, st));
+    int cur = 0;
+    auto product = [&](int c, unsigned long long *cnt) {
+        return launch_dense_gemv(D.M, ld, v[c], v[c ^ 1], D.thr, cnt, st);
+    };
+    if ((rc = dense_loop(m, st, S, product, &cur, products, kernel_ms))) return rc;
+    if (m.n_atoms) LP_HIP(hipMemcpyAsync(model, v[cur], m.n_atoms, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+static lp_status dense_stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
+                                   int64_t max_models, int32_t *products, float *kernel_ms, hipStream_t st) {
+    const int K = m.K;
+    if (K == 0) {
+        // definite program: exactly one stable model, the least model
+        std::vector<uint8_t> lm(m.n_atoms ? m.n_atoms : 1);
+        lp_status rc = dense_least_impl(m, lm.data(), products, kernel_ms, st);
+        if (rc) return rc;
+        accepted[0] = 1;
+        *n_models = 1;
+        if (models && max_models >= 1) std::memcpy(models, lm.data(), m.n_atoms);
+        return models && max_models < 1 ? LP_E_TRUNCATED : LP_OK;
+    }
+    const int64_t h = 1ll << K;
+    const int64_t hp = round_up(h, kDenseColAlign);
+    const int64_t W = (h + 63) / 64;
+    const int64_t ld = dense_ld(m);
+    Scratch S(st);
+    DenseMatrix D;
+    lp_status rc = dense_build(m, S, st, 2.0 * (double)hp * (double)ld + 8.0 * (double)W + 4.0 * K, &D);
+    if (rc) return rc;
+    uint8_t *V[2];
+    uint64_t *acc_d;
+    int32_t *q_d;
+    unsigned long long *cnt_d;
+    if ((rc = S.get(&V[0], (size_t)(hp * ld))) || (rc = S.get(&V[1], (size_t)(hp * ld))) || (rc = S.get(&acc_d, W)) ||
+        (rc = S.get(&q_d, K)) || (rc = S.get(&cnt_d, 1)))
+        return rc;
+    LP_HIP(hipMemcpyAsync(q_d, m.neg_atoms.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    LP_HIP(launch_dense_init(V[0], ld, h, hp, D.fact, m.n_std, K, st));
+    int cur = 0;
+    auto product = [&](int c, unsigned long long *cnt) {
+        return launch_dense_gemm(D.M, V[c], V[c ^ 1], ld, hp, D.thr, cnt, st);
+    };
+    if ((rc = dense_loop(m, st, S, product, &cur, products, kernel_ms))) return rc;
+    // Algorithm 3
+    LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
+    LP_HIP(launch_dense_check(V[cur], ld, h, q_d, m.n_std, K, acc_d, cnt_d, st));
+    unsigned long long nm = 0;
+    LP_HIP(hipMemcpyAsync(accepted, acc_d, W * 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(&nm, cnt_d, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    *n_models = (int64_t)nm;
+    if (models && max_models > 0 && nm && m.n_atoms) {
+        std::vector<int64_t> cols;
+        for (int64_t w = 0; w < W && (int64_t)cols.size() < max_models; ++w)
+            for (uint64_t x = accepted[w]; x && (int64_t)cols.size() < max_models; x &= x - 1)
+                cols.push_back(w * 64 + __builtin_ctzll(x));
+        int64_t *cols_d;
+        uint8_t *out_d;
+        const int64_t nb = (int64_t)cols.size() * m.n_atoms;
+        if ((rc = S.get(&cols_d, cols.size())) || (rc = S.get(&out_d, nb))) return rc;
+        LP_HIP(hipMemcpyAsync(cols_d, cols.data(), cols.size() * 8, hipMemcpyHostToDevice, st));
+        LP_HIP(launch_dense_gather(V[cur], ld, cols_d, (int64_t)cols.size(), m.n_atoms, out_d, st));
+        LP_HIP(hipMemcpyAsync(models, out_d, nb, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+    }
+    if (models && (int64_t)nm > max_models) return LP_E_TRUNCATED;
+    return LP_OK;
+}
+
 }  // namespace lp
 
 // ------------------------------------------------------------------ C ABI
@@ -2038,6 +2219,43 @@ lp_status lp_bench_step(const lp_matrix *m, const lp_schedule *sched, int32_t re
     }
     DeviceGuard g(m->m.dev.device);
     return bench_step_impl(m->m, sched, reps, avg_ms, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_dense_least_model(const lp_matrix *m, uint8_t *model, int32_t *products, float *kernel_ms,
+                               void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K) {
+        set_error("the program has negative literals; the least model is defined for definite programs");
+        return LP_E_NEGATION;
+    }
+    if (!model && m->m.n_atoms) {
+        set_error("model must be non-NULL");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return dense_least_impl(m->m, model, products, kernel_ms, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_dense_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
+                                 int64_t max_models, int32_t *products, float *kernel_ms, void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K > LP_MAX_NEG_ATOMS) {
+        set_error("too many negated atoms: " + std::to_string(m->m.K));
+        return LP_E_TOO_MANY_GUESSES;
+    }
+    if (!accepted || !n_models || max_models < 0) {
+        set_error("accepted and n_models must be non-NULL, max_models >= 0");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    return dense_stable_impl(m->m, accepted, n_models, models, max_models, products, kernel_ms,
+                             (hipStream_t)hip_stream);
     LP_GUARD_END
 }
 

@@ -50,7 +50,8 @@ EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg
            "lp_server_create", "lp_server_add_program", "lp_server_submit", "lp_server_wait_any",
            "lp_server_take_result", "lp_server_get_stats", "lp_server_free",
            "lp_memory_stats", "lp_release_cached_memory", "lp_bench_spmm",
-           "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_last_error")
+           "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_dense_least_model",
+           "lp_dense_stable_models", "lp_last_error")
 
 
 class LPError(RuntimeError):
@@ -154,6 +155,8 @@ def load():
         "lp_memory_stats": [ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "lp_release_cached_memory": [],
         "lp_bench_spmm": [P, i32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32), P],
+        "lp_dense_least_model": [P, P, P, P, P],
+        "lp_dense_stable_models": [P, P, ctypes.POINTER(i64), P, i64, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -300,6 +303,37 @@ class Matrix:
             out["models"] = models[: min(nm, max_models), : self.n_atoms]
         if interp is not None:
             out["interp"] = interp[: self.n_atoms]
+        return out
+
+    def dense_least_model(self, stream=None):
+        """Algorithm 1 with the dense matrix (lp_dense_least_model): (model uint8[n_atoms], products,
+        mean ms of one product launch)."""
+        model = np.zeros(max(self.n_atoms, 1), dtype=np.uint8)
+        prods = ctypes.c_int32(0)
+        ms = ctypes.c_float(0)
+        _check(load().lp_dense_least_model(self._h, model.ctypes.data, ctypes.addressof(prods),
+                                           ctypes.addressof(ms), _stream(stream)))
+        return model[: self.n_atoms], prods.value, ms.value
+
+    def dense_stable_models(self, max_models: int = 1024, want_models: bool = True, stream=None) -> dict:
+        """Algorithms 2 and 3 with the dense matrix (lp_dense_stable_models): dict(accepted=uint64[W],
+        n_models, models, products, kernel_ms, truncated)."""
+        K = self.info["n_neg"]
+        Wf = max(((1 << K) + 63) // 64, 1)
+        acc = np.zeros(Wf, dtype=np.uint64)
+        n_models = ctypes.c_int64(0)
+        prods = ctypes.c_int32(0)
+        ms = ctypes.c_float(0)
+        models = np.zeros((max(max_models, 1), max(self.n_atoms, 1)), dtype=np.uint8) if want_models else None
+        rc = _check(load().lp_dense_stable_models(self._h, acc.ctypes.data, ctypes.byref(n_models),
+                                                  models.ctypes.data if models is not None else None,
+                                                  int(max_models), ctypes.addressof(prods), ctypes.addressof(ms),
+                                                  _stream(stream)), allow=(LP_E_TRUNCATED,))
+        nm = n_models.value
+        out = dict(accepted=acc, n_models=nm, products=prods.value, kernel_ms=ms.value,
+                   truncated=rc == LP_E_TRUNCATED)
+        if models is not None:
+            out["models"] = models[: min(nm, max_models), : self.n_atoms]
         return out
 
     def bench_step(self, reps: int = 100, sched=None, stream=None) -> float:

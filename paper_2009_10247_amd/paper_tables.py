@@ -16,7 +16,10 @@ checked here against a breadth-first closure of the graph; the least and
 stable models of the random programs are checked against the CPU oracle in
 tests/test_gpu_paper_shapes.py.
 
-    python -m paper_2009_10247_amd.paper_tables [--only definite,normal,tc] [--reps 5]
+* the dense-matrix method on rows of the first two tables, beside the sparse
+  engine and the paper's dense and sparse seconds.
+
+    python -m paper_2009_10247_amd.paper_tables [--only definite,normal,tc,dense] [--reps 5]
 """
 from __future__ import annotations
 
@@ -43,6 +46,11 @@ NORMAL_ROWS = [
     (10000, 120000, 171967, 6, 0.7124), (10000, 160000, 207432, 7, 0.8424), (16000, 200000, 250194, 5, 1.5603),
     (16000, 220000, 278190, 6, 1.8314), (20000, 280000, 357001, 4, 1.9170), (20000, 320000, 396128, 4, 2.1066),
 ]
+# the paper's dense-matrix seconds for the rows it could run (1-6 of both tables)
+PAPER_DENSE_S = {
+    "definite": {1: 2.0559, 2: 17.9986, 3: 73.3541, 4: 116.1158, 5: 155.4312, 6: 187.6549},
+    "normal": {1: 3.9560, 2: 28.1806, 3: 105.4931, 4: 168.8044, 5: 203.2749, 6: 256.9701},
+}
 # (graph name, |V|, |E|, paper n, paper m, paper n', paper sparse-matrix seconds)
 TC_ROWS = [
     ("Club membership", 65, 95, 1200, 14492, 15600, 0.0255), ("Cattle", 28, 217, 1512, 20629, 21924, 0.0365),
@@ -127,12 +135,42 @@ def run_tc(reps: int, seed: int = 0):
         mat.close()
 
 
+def run_dense(reps: int, seed: int = 0, rows=range(1, 7)):
+    """The dense-matrix method (lp_dense_least_model / lp_dense_stable_models) beside the sparse
+    engine on rows of the definite- and normal-program tables. The dense matrix of row r holds
+    n'^2 bytes (rows 7-12 need 16-157 GB, which one MI355X holds)."""
+    for table, spec in (("definite", DEFINITE_ROWS), ("normal", NORMAL_ROWS)):
+        for i in rows:
+            row = spec[i - 1]
+            p = gen.paper_definite(seed, row[0], row[1]) if table == "definite" else \
+                gen.paper_normal(seed, row[0], row[1], row[3])
+            with lp.Matrix(p) as mat:
+                if table == "definite":
+                    (_, prods, kern_ms), dense = _timed(lambda: mat.dense_least_model(), max(reps // 2, 1))
+                    _, sparse = _timed(lambda: mat.least_model(), reps)
+                else:
+                    r, dense = _timed(lambda: mat.dense_stable_models(max_models=16), max(reps // 2, 1))
+                    prods, kern_ms = r["products"], r["kernel_ms"]
+                    _, sparse = _timed(lambda: mat.stable_models(max_models=16), reps)
+                yield dict(table=f"dense_{table}", row=i, n=row[0], m=row[1], negated_atoms=mat.info["n_neg"],
+                           n_prime=mat.info["n_rows"], products=prods, dense_solve_ms=round(dense * 1e3, 3),
+                           dense_product_us=round(kern_ms * 1e3, 1), sparse_solve_ms=round(sparse * 1e3, 3),
+                           dense_over_sparse=round(dense / sparse, 1),
+                           paper_dense_s=PAPER_DENSE_S[table].get(i),
+                           paper_sparse_s=row[3] if table == "definite" else row[4])
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", default="definite,normal,tc")
+    ap.add_argument("--only", default="definite,normal,tc",
+                    help="comma list of definite, normal, tc, dense")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--dense-rows", default="1-6", help="table rows for the dense method, e.g. 1-6 or 1-12")
     args = ap.parse_args(argv)
-    runs = {"definite": run_definite, "normal": run_normal, "tc": run_tc}
+    lo, _, hi = args.dense_rows.partition("-")
+    dense_rows = range(int(lo), int(hi or lo) + 1)
+    runs = {"definite": run_definite, "normal": run_normal, "tc": run_tc,
+            "dense": lambda reps: run_dense(reps, rows=dense_rows)}
     ok = True
     for name in args.only.split(","):
         for row in runs[name](args.reps):

@@ -30,6 +30,22 @@ __device__ inline uint32_t dense_wave_sum(uint32_t x) {
     return x;
 }
 
+// Adds the workgroup's change count to counter blockIdx % kDenseCounters
+// (each on its own 128-byte line; the host sums them): one atomic per
+// workgroup, spread over several addresses, because same-address atomics
+// from every wave serialize. ch: the wave's count, read from its first lane.
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void add_changes(uint32_t ch, unsigned long long *changed) {
+    __shared__ uint32_t s_ch[8];
+    if ((threadIdx.x & 63) == 0) s_ch[threadIdx.x >> 6] = ch;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) t += s_ch[w];
+        if (t) atomicAdd(changed + (blockIdx.x % kDenseCounters) * kDenseCounterStride, (unsigned long long)t);
+    }
+}
+
 // Number of byte positions where both a and b hold 1 (every byte is 0 or 1).
 __device__ __forceinline__ uint32_t and_count(uint4 a, uint4 b) {
     return __builtin_popcount(a.x & b.x) + __builtin_popcount(a.y & b.y) + __builtin_popcount(a.z & b.z) +
@@ -50,8 +66,8 @@ __global__ __launch_bounds__(kDenseBlock) void dense_scatter_kernel(uint8_t *M, 
 // u = theta(M v) (Algorithm 1's product). Each wave takes kGemvRows
 // consecutive rows; lane l reads bytes [16 l, 16 l + 16) of every 1024-byte
 // chunk of v and of those rows, so each chunk of v serves all of them. The
-// wave's first lane writes the rows' results and adds the number of rows that
-// changed to *changed.
+// wave's first lane writes the rows' results; the number of rows that
+// changed goes to the change counters.
 constexpr int kGemvRows = 8;
 
 __global__ __launch_bounds__(kDenseBlock) void dense_gemv_kernel(const uint8_t *M, int64_t ld, const uint8_t *v,
@@ -73,8 +89,8 @@ __global__ __launch_bounds__(kDenseBlock) void dense_gemv_kernel(const uint8_t *
     }
 #pragma unroll
     for (int r = 0; r < kGemvRows; ++r) c[r] = dense_wave_sum(c[r]);
+    uint32_t ch = 0;
     if (lane == 0) {
-        uint32_t ch = 0;
 #pragma unroll
         for (int h = 0; h < kGemvRows / 4; ++h) {
             const int4 t = *(const int4 *)(thr + r0 + 4 * h);
@@ -84,24 +100,26 @@ __global__ __launch_bounds__(kDenseBlock) void dense_gemv_kernel(const uint8_t *
             ch += __builtin_popcount(word ^ *(const uint32_t *)(v + r0 + 4 * h));
             *(uint32_t *)(u + r0 + 4 * h) = word;
         }
-        if (ch) atomicAdd(changed, (unsigned long long)ch);
     }
+    add_changes(ch, changed);
 }
 
 // Ut = theta(M V) (Algorithm 2's product) on the int8 matrix cores: counts
-// C[i][j] = sum_k M[i][k] Vt[j][k] by v_mfma_i32_16x16x64_i8, a 128 x 128 tile
-// of C per workgroup (four waves of 64 x 64), K in stages of 128 bytes staged
-// through two LDS buffers. Both operands are K-contiguous in memory, so lane
-// l's 16 bytes of an A fragment (row l % 16) and of a B fragment (column
-// l % 16) cover the same 16 values of k, (l / 16) * 16 onwards; the
-// instruction pairs them position by position, so its internal order of k
-// does not matter. Result lane l, element e of a 16 x 16 tile: row
-// 4 (l / 16) + e, column l % 16.
-constexpr int kGT = 128;                  // tile edge (rows of M, columns of V)
-constexpr int kGK = 128;                  // bytes of k per stage
-constexpr int kGRow = kGK + 16;           // LDS row pitch: 16 rows at one k start 36 banks apart
-constexpr int kGStage = 2 * kGT * kGRow;  // A and B tiles of one stage
-constexpr int kGroupM = 8;                // row tiles per group of the tile order
+// C[i][j] = sum_k M[i][k] Vt[j][k] by v_mfma_i32_16x16x64_i8. A workgroup of
+// 2 x NWN waves computes a 128 x 64 NWN tile of C (each wave 64 x 64), K in
+// stages of 128 bytes staged through two LDS buffers. Both operands are
+// K-contiguous in memory, so lane l's 16 bytes of an A fragment (row l % 16)
+// and of a B fragment (column l % 16) cover the same 16 values of k,
+// (l / 16) * 16 onwards; the instruction pairs them position by position, so
+// its internal order of k does not matter. Result lane l, element e of a
+// 16 x 16 tile: row 4 (l / 16) + e, column l % 16.
+constexpr int kGT = 128;         // rows of M per tile
+constexpr int kGK = 128;         // bytes of k per stage
+constexpr int kGRow = kGK + 16;  // LDS row pitch: 16 rows at one k start 36 banks apart
+constexpr int kGroupM = 8;       // row tiles per group of the tile order
+
+template <int NWN>
+constexpr int gemm_stage_bytes() { return (kGT + 64 * NWN) * kGRow; }
 
 // Workgroup b runs on XCD b % 8; give consecutive logical tiles to one XCD so
 // that tiles sharing rows of M share its L2.
@@ -110,73 +128,88 @@ __device__ __forceinline__ int32_t xcd_order(int32_t b, int32_t nb) {
     return xcd * base + (xcd < rem ? xcd : rem) + local;
 }
 
-__global__ __launch_bounds__(kDenseBlock) void dense_gemm_kernel(const uint8_t *M, const uint8_t *Vt, uint8_t *Ut,
-                                                                int64_t ld, int32_t m_tiles, int32_t n_tiles,
-                                                                const int32_t *thr, unsigned long long *changed) {
+// With splits > 1 (few tiles: too few workgroups to keep enough loads in
+// flight), workgroup (tile, s) sums only k-stages [s nk / splits, (s + 1) nk /
+// splits) and writes its raw counts to partial[s][column][row]; then
+// dense_theta_kernel adds the slices and applies theta.
+template <int NWN>
+__global__ __launch_bounds__(128 * NWN) void dense_gemm_kernel(const uint8_t *M, const uint8_t *Vt, uint8_t *Ut,
+                                                              int64_t ld, int64_t hp, int32_t splits,
+                                                              int32_t *partial, const int32_t *thr,
+                                                              unsigned long long *changed) {
+    constexpr int kThreads = 128 * NWN;
+    constexpr int BN = 64 * NWN;                         // columns per tile
+    constexpr int kAP = kGT * (kGK / 16) / kThreads;     // 16-byte pieces of A per thread and stage
+    constexpr int kBP = BN * (kGK / 16) / kThreads;      // and of B
+    constexpr int kStage = gemm_stage_bytes<NWN>();
     extern __shared__ __attribute__((aligned(16))) uint8_t s_dense[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // tile order: groups of kGroupM row tiles, row tile fastest inside a group
-    const int32_t L = xcd_order((int32_t)blockIdx.x, m_tiles * n_tiles);
-    const int32_t per_group = kGroupM * n_tiles;
-    const int32_t first_m = (L / per_group) * kGroupM;
-    const int32_t gsize = min(kGroupM, m_tiles - first_m);
-    const int32_t in_group = L - (L / per_group) * per_group;
-    const int32_t mt = first_m + in_group % gsize, nt = in_group / gsize;
+    const int32_t m_tiles = (int32_t)(ld / kGT), n_tiles = (int32_t)(hp / BN);
+    const int32_t L = xcd_order((int32_t)blockIdx.x, m_tiles * n_tiles * splits);
+    int32_t mt, nt, split = 0;
+    if (splits == 1) {
+        // groups of kGroupM row tiles, row tile fastest inside a group
+        const int32_t per_group = kGroupM * n_tiles;
+        const int32_t first_m = (L / per_group) * kGroupM;
+        const int32_t gsize = min(kGroupM, m_tiles - first_m);
+        const int32_t in_group = L - (L / per_group) * per_group;
+        mt = first_m + in_group % gsize;
+        nt = in_group / gsize;
+    } else {
+        // column tile fastest, so the tiles that share rows of M run side by side
+        nt = L % n_tiles;
+        split = (L / n_tiles) % splits;
+        mt = L / (n_tiles * splits);
+    }
+    const int32_t nk = (int32_t)(ld / kGK) / splits;
+    const int64_t kbase = (int64_t)split * nk * kGK;
 
-    const uint8_t *Ag = M + (int64_t)mt * kGT * ld;
-    const uint8_t *Bg = Vt + (int64_t)nt * kGT * ld;
-    // staging: 16-byte piece c = tid + 256 s of a stage, s < 4: row c / 8,
+    const uint8_t *Ag = M + (int64_t)mt * kGT * ld + kbase;
+    const uint8_t *Bg = Vt + (int64_t)nt * BN * ld + kbase;
+    // staging: 16-byte piece c = tid + kThreads s of a stage: row c / 8,
     // bytes 16 (c % 8) onwards, in global memory and in LDS
-    int64_t goff[4];
-    int loff[4];
+    int64_t ga[kAP], gb[kBP];
+    int la[kAP], lb[kBP];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int c = tid + kDenseBlock * s;
-        goff[s] = (int64_t)(c >> 3) * ld + (c & 7) * 16;
-        loff[s] = (c >> 3) * kGRow + (c & 7) * 16;
+    for (int s = 0; s < kAP; ++s) {
+        const int c = tid + kThreads * s;
+        ga[s] = (int64_t)(c >> 3) * ld + (c & 7) * 16;
+        la[s] = (c >> 3) * kGRow + (c & 7) * 16;
     }
-    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-#define LP_DENSE_GLOAD(k0)                                  \
-    ra0 = *(const uint4 *)(Ag + goff[0] + (k0));            \
-    ra1 = *(const uint4 *)(Ag + goff[1] + (k0));            \
-    ra2 = *(const uint4 *)(Ag + goff[2] + (k0));            \
-    ra3 = *(const uint4 *)(Ag + goff[3] + (k0));            \
-    rb0 = *(const uint4 *)(Bg + goff[0] + (k0));            \
-    rb1 = *(const uint4 *)(Bg + goff[1] + (k0));            \
-    rb2 = *(const uint4 *)(Bg + goff[2] + (k0));            \
-    rb3 = *(const uint4 *)(Bg + goff[3] + (k0));
-#define LP_DENSE_LSTORE(buf)                                \
-    {                                                       \
-        uint8_t *A_ = s_dense + (buf) * kGStage;            \
-        uint8_t *B_ = A_ + kGT * kGRow;                     \
-        *(uint4 *)(A_ + loff[0]) = ra0;                     \
-        *(uint4 *)(A_ + loff[1]) = ra1;                     \
-        *(uint4 *)(A_ + loff[2]) = ra2;                     \
-        *(uint4 *)(A_ + loff[3]) = ra3;                     \
-        *(uint4 *)(B_ + loff[0]) = rb0;                     \
-        *(uint4 *)(B_ + loff[1]) = rb1;                     \
-        *(uint4 *)(B_ + loff[2]) = rb2;                     \
-        *(uint4 *)(B_ + loff[3]) = rb3;                     \
+#pragma unroll
+    for (int s = 0; s < kBP; ++s) {
+        const int c = tid + kThreads * s;
+        gb[s] = (int64_t)(c >> 3) * ld + (c & 7) * 16;
+        lb[s] = (kGT + (c >> 3)) * kGRow + (c & 7) * 16;
     }
+    v4i ra[kAP], rb[kBP];  // native vectors: arrays of them stay in registers
     v4i acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4i{0, 0, 0, 0};
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave / NWN) * 64, wn = (wave % NWN) * 64;
     const int fr = lane & 15, fk = (lane >> 4) * 16;
-    const int32_t nk = (int32_t)(ld / kGK);
-    LP_DENSE_GLOAD(0)
-    LP_DENSE_LSTORE(0)
+#pragma unroll
+    for (int s = 0; s < kAP; ++s) ra[s] = *(const v4i *)(Ag + ga[s]);
+#pragma unroll
+    for (int s = 0; s < kBP; ++s) rb[s] = *(const v4i *)(Bg + gb[s]);
+#pragma unroll
+    for (int s = 0; s < kAP; ++s) *(v4i *)(s_dense + la[s]) = ra[s];
+#pragma unroll
+    for (int s = 0; s < kBP; ++s) *(v4i *)(s_dense + lb[s]) = rb[s];
     __syncthreads();
     for (int32_t kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) {
             const int64_t k0 = (int64_t)(kt + 1) * kGK;
-            LP_DENSE_GLOAD(k0)
+#pragma unroll
+            for (int s = 0; s < kAP; ++s) ra[s] = *(const v4i *)(Ag + ga[s] + k0);
+#pragma unroll
+            for (int s = 0; s < kBP; ++s) rb[s] = *(const v4i *)(Bg + gb[s] + k0);
         }
-        const uint8_t *A = s_dense + cur * kGStage;
+        const uint8_t *A = s_dense + cur * kStage;
         const uint8_t *B = A + kGT * kGRow;
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 64) {
@@ -192,17 +225,29 @@ __global__ __launch_bounds__(kDenseBlock) void dense_gemm_kernel(const uint8_t *
                     acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         // the other buffer was last read before the previous barrier
-        if (more) LP_DENSE_LSTORE(cur ^ 1)
+        if (more) {
+            uint8_t *Nb = s_dense + (cur ^ 1) * kStage;
+#pragma unroll
+            for (int s = 0; s < kAP; ++s) *(v4i *)(Nb + la[s]) = ra[s];
+#pragma unroll
+            for (int s = 0; s < kBP; ++s) *(v4i *)(Nb + lb[s]) = rb[s];
+        }
         __syncthreads();
     }
-#undef LP_DENSE_GLOAD
-#undef LP_DENSE_LSTORE
     // theta, the change count against the input, and the store: element e of
     // tile (i, j) is row rr + e, column cc; four rows of one column are four
     // consecutive bytes of Ut.
     uint32_t ch = 0;
     const int64_t row0 = (int64_t)mt * kGT + wm + 4 * (lane >> 4);
-    const int64_t col0 = (int64_t)nt * kGT + wn + fr;
+    const int64_t col0 = (int64_t)nt * BN + wn + fr;
+    if (splits > 1) {
+        int32_t *P = partial + (int64_t)split * hp * ld;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) *(v4i *)(P + (col0 + 16 * j) * ld + row0 + 16 * i) = acc[i][j];
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int64_t rr = row0 + 16 * i;
@@ -217,8 +262,30 @@ __global__ __launch_bounds__(kDenseBlock) void dense_gemm_kernel(const uint8_t *
             *(uint32_t *)(Ut + at) = word;
         }
     }
-    ch = dense_wave_sum(ch);
-    if (lane == 0 && ch) atomicAdd(changed, (unsigned long long)ch);
+    add_changes(dense_wave_sum(ch), changed);
+}
+
+// Adds the splits slices of partial counts and applies theta: four rows of
+// one column per thread; the change count as in dense_gemm_kernel.
+__global__ __launch_bounds__(kDenseBlock) void dense_theta_kernel(const int32_t *partial, int32_t splits,
+                                                                 const uint8_t *Vt, uint8_t *Ut, int64_t ld,
+                                                                 int64_t hp, const int32_t *thr,
+                                                                 unsigned long long *changed) {
+    const int64_t g = (int64_t)blockIdx.x * kDenseBlock + threadIdx.x;
+    const int64_t per_col = ld >> 2;
+    uint32_t ch = 0;
+    if (g < hp * per_col) {
+        const int64_t at = g * 4;  // column g / per_col, rows 4 (g % per_col) onwards
+        const int64_t slice = hp * ld;
+        v4i s = *(const v4i *)(partial + at);
+        for (int32_t k = 1; k < splits; ++k) s += *(const v4i *)(partial + k * slice + at);
+        const int4 t = *(const int4 *)(thr + (at % ld));
+        const uint32_t word = (uint32_t)(s.x >= t.x) | ((uint32_t)(s.y >= t.y) << 8) |
+                              ((uint32_t)(s.z >= t.z) << 16) | ((uint32_t)(s.w >= t.w) << 24);
+        ch = __builtin_popcount(word ^ *(const uint32_t *)(Vt + at));
+        *(uint32_t *)(Ut + at) = word;
+    }
+    add_changes(dense_wave_sum(ch), changed);
 }
 
 // Initial matrix of Definition 8, guess-major: column j < h has 1 in the fact
@@ -277,10 +344,9 @@ unsigned dense_blocks(int64_t n) { return (unsigned)((n + kDenseBlock - 1) / kDe
 
 }  // namespace
 
-static_assert(kDenseColAlign == kGT && kDenseAlign % kGK == 0 && kDenseAlign % kGT == 0 &&
+static_assert(kDenseColAlign == 128 && kDenseAlign % (kGK * kDenseMaxSplits) == 0 && kDenseAlign % kGT == 0 &&
                   kDenseAlign % (kGemvRows * (kDenseBlock / 64)) == 0,
               "dense padding must cover the kernels' tiles");
-static const size_t kDenseGemmLds = 2 * (size_t)kGStage;
 
 hipError_t launch_dense_scatter(uint8_t *M, int64_t ld, const int32_t *row_ptr, const int32_t *col, int32_t n_rows,
                                 hipStream_t st) {
@@ -298,16 +364,41 @@ hipError_t launch_dense_gemv(const uint8_t *M, int64_t ld, const uint8_t *v, uin
     return hipGetLastError();
 }
 
-hipError_t launch_dense_gemm(const uint8_t *M, const uint8_t *Vt, uint8_t *Ut, int64_t ld, int64_t hp,
-                             const int32_t *thr, unsigned long long *changed, hipStream_t st) {
-    if (ld <= 0 || ld % kDenseAlign || hp <= 0 || hp % kGT) return hipErrorInvalidValue;
-    static const hipError_t lds_ok = hipFuncSetAttribute(
-        (const void *)dense_gemm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDenseGemmLds);
+// Tiles 128 columns wide (NWN = 2). Tiles of 256 columns (NWN = 4, M read
+// once per 256 columns) measured slower on both the 256- and the
+// 65,536-column products: their 110 KB of LDS leaves one workgroup per CU.
+static int gemm_nwn(int64_t) { return 2; }
+
+int dense_gemm_splits(int64_t ld, int64_t hp) {
+    const int64_t tiles = (ld / kGT) * (hp / (64 * gemm_nwn(hp)));
+    int s = 1;
+    while (s < kDenseMaxSplits && tiles * s < kDenseSplitTarget) s *= 2;
+    return s;
+}
+
+template <int NWN>
+static hipError_t gemm_launch(const uint8_t *M, const uint8_t *Vt, uint8_t *Ut, int64_t ld, int64_t hp, int splits,
+                              int32_t *partial, const int32_t *thr, unsigned long long *changed, hipStream_t st) {
+    constexpr size_t lds = 2 * (size_t)gemm_stage_bytes<NWN>();
+    static const hipError_t lds_ok = hipFuncSetAttribute((const void *)dense_gemm_kernel<NWN>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (lds_ok != hipSuccess) return lds_ok;
-    const int64_t tiles = (ld / kGT) * (hp / kGT);
-    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(dense_gemm_kernel, dim3((unsigned)tiles), dim3(kDenseBlock), kDenseGemmLds, st, M, Vt, Ut, ld,
-                       (int32_t)(ld / kGT), (int32_t)(hp / kGT), thr, changed);
+    const int64_t blocks = (ld / kGT) * (hp / (64 * NWN)) * splits;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(dense_gemm_kernel<NWN>, dim3((unsigned)blocks), dim3(128 * NWN), lds, st, M, Vt, Ut, ld, hp,
+                       (int32_t)splits, partial, thr, changed);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_gemm(const uint8_t *M, const uint8_t *Vt, uint8_t *Ut, int64_t ld, int64_t hp,
+                             int32_t *partial, const int32_t *thr, unsigned long long *changed, hipStream_t st) {
+    if (ld <= 0 || ld % kDenseAlign || hp <= 0 || hp % kDenseColAlign) return hipErrorInvalidValue;
+    const int splits = dense_gemm_splits(ld, hp);
+    if (splits > 1 && !partial) return hipErrorInvalidValue;
+    hipError_t e = gemm_launch<2>(M, Vt, Ut, ld, hp, splits, partial, thr, changed, st);
+    if (e != hipSuccess || splits == 1) return e;
+    hipLaunchKernelGGL(dense_theta_kernel, dim3(dense_blocks(hp * (ld >> 2))), dim3(kDenseBlock), 0, st, partial,
+                       (int32_t)splits, Vt, Ut, ld, hp, thr, changed);
     return hipGetLastError();
 }
 

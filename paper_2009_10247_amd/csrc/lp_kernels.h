@@ -161,12 +161,22 @@ hipError_t launch_extract(const uint64_t *V, int32_t log2W, const int64_t *cols,
 // bytes (guess-major) with hp = 2^K rounded up to kDenseColAlign.
 constexpr int64_t kDenseAlign = 1024;
 constexpr int64_t kDenseColAlign = 128;
+// A product with fewer than kDenseSplitTarget tiles of 128 x 128 is split
+// along k into up to kDenseMaxSplits slices; dense_gemm_splits gives the
+// count, and the caller passes a partial-count buffer of splits x hp x ld int32.
+constexpr int kDenseMaxSplits = 8;
+// The products' change counts: kDenseCounters counters, kDenseCounterStride
+// words apart; a product changed nothing iff all are 0.
+constexpr int kDenseCounters = 32;
+constexpr int kDenseCounterStride = 16;
+constexpr int64_t kDenseSplitTarget = 1024;
+int dense_gemm_splits(int64_t ld, int64_t hp);
 hipError_t launch_dense_scatter(uint8_t *M, int64_t ld, const int32_t *row_ptr, const int32_t *col, int32_t n_rows,
                                 hipStream_t st);
 hipError_t launch_dense_gemv(const uint8_t *M, int64_t ld, const uint8_t *v, uint8_t *u, const int32_t *thr,
                              unsigned long long *changed, hipStream_t st);
 hipError_t launch_dense_gemm(const uint8_t *M, const uint8_t *Vt, uint8_t *Ut, int64_t ld, int64_t hp,
-                             const int32_t *thr, unsigned long long *changed, hipStream_t st);
+                             int32_t *partial, const int32_t *thr, unsigned long long *changed, hipStream_t st);
 hipError_t launch_dense_init(uint8_t *V, int64_t ld, int64_t h, int64_t hp, const uint8_t *fact, int32_t n_std,
                              int32_t K, hipStream_t st);
 hipError_t launch_dense_check(const uint8_t *V, int64_t ld, int64_t h, const int32_t *q_rows, int32_t n_std,

@@ -1734,14 +1734,11 @@ static lp_status dense_build(const Matrix &m, Scratch &S, hipStream_t st, double
 template <class Product>
 static lp_status dense_loop(const Matrix &m, hipStream_t st, Scratch &S, Product product, int *cur, int32_t *products,
                             float *kernel_ms) {
+    constexpr size_t n_cnt = (size_t)kDenseCounters * kDenseCounterStride;
     unsigned long long *cnt_d;
     lp_status rc;
-    if ((rc = S.get(&cnt_d, 1))) return rc;
-    unsigned long long *h = pinned_ring();
-    if (!h) {
-        set_error("pinned host allocation failed");
-        return LP_E_NOMEM;
-    }
+    if ((rc = S.get(&cnt_d, n_cnt))) return rc;
+    std::vector<unsigned long long> h(n_cnt);
     Events ev;
     if ((rc = ev.init())) return rc;
     double total_ms = 0.0;
@@ -1752,18 +1749,20 @@ static lp_status dense_loop(const Matrix &m, hipStream_t st, Scratch &S, Product
             set_error("dense fixpoint exceeded n_rows + 1 products");
             return LP_E_INTERNAL;
         }
-        LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
+        LP_HIP(hipMemsetAsync(cnt_d, 0, n_cnt * sizeof(unsigned long long), st));
         LP_HIP(hipEventRecord(ev.a, st));
         LP_HIP(product(c, cnt_d));
         LP_HIP(hipEventRecord(ev.b, st));
-        LP_HIP(hipMemcpyAsync(h, cnt_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        LP_HIP(hipMemcpyAsync(h.data(), cnt_d, n_cnt * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         LP_HIP(hipStreamSynchronize(st));
         float ms = 0.f;
         if ((rc = ev.elapsed(&ms))) return rc;
         total_ms += ms;
         ++p;
         c ^= 1;
-        if (h[0] == 0) break;
+        unsigned long long changed = 0;
+        for (int i = 0; i < kDenseCounters; ++i) changed += h[(size_t)i * kDenseCounterStride];
+        if (changed == 0) break;
     }
     *cur = c;
     if (products) *products = p;
@@ -1808,22 +1807,25 @@ static lp_status dense_stable_impl(const Matrix &m, uint64_t *accepted, int64_t 
     const int64_t hp = round_up(h, kDenseColAlign);
     const int64_t W = (h + 63) / 64;
     const int64_t ld = dense_ld(m);
+    const int splits = dense_gemm_splits(ld, hp);
+    const int64_t n_partial = splits > 1 ? splits * hp * ld : 0;
     Scratch S(st);
     DenseMatrix D;
-    lp_status rc = dense_build(m, S, st, 2.0 * (double)hp * (double)ld + 8.0 * (double)W + 4.0 * K, &D);
+    lp_status rc = dense_build(m, S, st, 2.0 * (double)hp * (double)ld + 4.0 * (double)n_partial + 8.0 * (double)W +
+                                             4.0 * K, &D);
     if (rc) return rc;
     uint8_t *V[2];
     uint64_t *acc_d;
-    int32_t *q_d;
+    int32_t *q_d, *partial = nullptr;
     unsigned long long *cnt_d;
     if ((rc = S.get(&V[0], (size_t)(hp * ld))) || (rc = S.get(&V[1], (size_t)(hp * ld))) || (rc = S.get(&acc_d, W)) ||
-        (rc = S.get(&q_d, K)) || (rc = S.get(&cnt_d, 1)))
+        (rc = S.get(&q_d, K)) || (rc = S.get(&cnt_d, 1)) || (n_partial && (rc = S.get(&partial, n_partial))))
         return rc;
     LP_HIP(hipMemcpyAsync(q_d, m.neg_atoms.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
     LP_HIP(launch_dense_init(V[0], ld, h, hp, D.fact, m.n_std, K, st));
     int cur = 0;
     auto product = [&](int c, unsigned long long *cnt) {
-        return launch_dense_gemm(D.M, V[c], V[c ^ 1], ld, hp, D.thr, cnt, st);
+        return launch_dense_gemm(D.M, V[c], V[c ^ 1], ld, hp, partial, D.thr, cnt, st);
     };
     if ((rc = dense_loop(m, st, S, product, &cur, products, kernel_ms))) return rc;
     // Algorithm 3

@@ -128,7 +128,9 @@ typedef struct lp_schedule {
                                 wave, 1, 2 or 4 (0: default) */
     int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16 (0: default) */
     int32_t block;           /* batch kernel: threads per workgroup, 256, 512 or 1024 (0: 512) */
-    int32_t reserved;
+    int32_t team;            /* batch plans: 0 teams chosen by size, 1 no teams, k >= 2 every
+                                program solved by a team of k workgroups (at most 8 and half the
+                                grid) */
 } lp_schedule;
 
 /*
@@ -313,17 +315,26 @@ typedef struct lp_batch_info {
     int64_t nnz;            /* sum of the programs' stored nonzeros */
     int64_t step_bytes;     /* sum of the programs' lp_info.step_bytes */
     float tuned_ms;         /* time per run found by lp_batch_tune, 0 before */
-    int32_t reserved;
+    int32_t n_teams;        /* programs solved by a team of workgroups */
+    int32_t team_members;   /* workgroups in those teams */
+    int32_t team_fallbacks; /* team programs re-solved alone by lp_batch_results since the plan was made
+                               (a team whose bounded barrier gave up); 0 normally */
 } lp_batch_info;
 
 /*
  * Plan for ms[0..count) (definite programs on one device). sched (nullable):
  * wpw, unroll, block and grid select the batch kernel's shape (0: defaults,
- * grid: as many workgroups as are resident at once, at most count); the whole
- * schedule is used for the programs solved by the single-program drivers.
+ * grid: as many workgroups as are resident at once, at most the number of
+ * queue positions); the whole schedule is used for the programs solved by the
+ * single-program drivers. A program whose work exceeds a workgroup's share of
+ * the batch is solved by a team of up to 8 workgroups (sched->team); every
+ * team's members fit in one grid, and a team whose bounded barrier gives up
+ * (its members could not run together) has its program solved alone by
+ * lp_batch_results. Results and product counts do not depend on teams.
  * Uploads the descriptors on hip_stream and synchronizes it.
  * Errors: LP_E_NEGATION, LP_E_HOST_ONLY, LP_E_INVAL (NULL matrix, mixed
- * devices, unsupported shape), LP_E_NOMEM, LP_E_DEVICE.
+ * devices, unsupported shape, a grid smaller than a team), LP_E_NOMEM,
+ * LP_E_DEVICE.
  */
 lp_status lp_batch_create(const lp_matrix *const *ms, int32_t count, const lp_schedule *sched, void *hip_stream,
                           lp_batch **out);

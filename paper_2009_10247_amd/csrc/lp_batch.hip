@@ -15,6 +15,15 @@
 // LDS, ballots, one window fold per row), OR rows as child bit ranges, long
 // rows by segments. Results are ORed into the buffer holding v_{t-1}
 // (monotone), and the new-bit count decides the loop.
+//
+// A program much larger than a workgroup's share of the batch is solved by a
+// team of G workgroups (its G queue positions come first, so all members
+// start at once). Member m evaluates every G-th super-block, OR row and
+// segment; after each product the members OR their result buffers into a
+// global copy of the interpretation, meet at a bounded team barrier and load
+// the union. The result of product t goes to global buffer t mod 2, which
+// holds v_{t-2}, a subset of v_t, so after the barrier it is exactly v_t and
+// the products are those of the one-workgroup loop.
 #include <hip/hip_runtime.h>
 
 #include "lp_dev.h"
@@ -91,24 +100,26 @@ __device__ __forceinline__ void wg_load_super_block(const GProg &d, int64_t sb, 
 }
 
 // AND rows of the block pass (see BlockPass in lp_step.hip).
+// Member `member` of a team of `team` workgroups takes every team-th share.
 template <int WPW, int U>
 __device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 *v, lds_u64 *u,
-                                                  lds_u64 *s_ball) {
+                                                  lds_u64 *s_ball, int32_t member, int32_t team) {
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
+    const int64_t stride = (int64_t)team * waves;
     const int64_t n_words = ((int64_t)d.n_rows + 63) >> 6;
     const int64_t n_sb = (n_words + WPW - 1) / WPW;
     const lds_u8 *v8 = (const lds_u8 *)v;
     const lds_u32 *b32 = (const lds_u32 *)s_ball;
     uint32_t my_new = 0;
-    int64_t sb = threadIdx.x >> 6;
+    int64_t sb = (int64_t)member * waves + (threadIdx.x >> 6);
     if (sb >= n_sb) return 0;
     WgSuperBlock<WPW> cur;
     wg_load_super_block<WPW>(d, sb, n_words, cur);
-    for (; sb < n_sb; sb += waves) {
+    for (; sb < n_sb; sb += stride) {
         WgSuperBlock<WPW> nxt;
-        const bool more = sb + waves < n_sb;
-        if (more) wg_load_super_block<WPW>(d, sb + waves, n_words, nxt);
+        const bool more = sb + stride < n_sb;
+        if (more) wg_load_super_block<WPW>(d, sb + stride, n_words, nxt);
         const int64_t w0 = sb * WPW;
         bool acc[WPW];
         int32_t st[WPW], en[WPW];
@@ -165,17 +176,18 @@ __device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 
 
 // OR rows (one lane each) and long rows (one wave per OR segment, one wave per
 // whole long AND row, looping over its segments).
-__device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const lds_u64 *v, lds_u64 *u) {
+__device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const lds_u64 *v, lds_u64 *u,
+                                                        int32_t member, int32_t team) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const lds_u8 *v8 = (const lds_u8 *)v;
     uint32_t my_new = 0;
-    for (int64_t j = threadIdx.x; j < d.n_or; j += blockDim.x) {
+    for (int64_t j = (int64_t)member * blockDim.x + threadIdx.x; j < d.n_or; j += (int64_t)team * blockDim.x) {
         const int32_t row = d.or_row[j];
         if (row >= 0 && lds_any_in_range(v, d.or_c0[j], d.or_c0[j + 1])) my_new += lds_set_bit(u, v, row);
     }
-    for (int64_t si = wave; si < d.n_segs; si += waves) {
+    for (int64_t si = (int64_t)member * waves + wave; si < d.n_segs; si += (int64_t)team * waves) {
         const gp<LongSeg> sg = d.segs + si;
         bool fire = false;
         if (!sg->is_and) {
@@ -205,6 +217,38 @@ __device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const ld
     return my_new;
 }
 
+// Barrier of one team: every wave first waits for its own global stores and
+// atomics to complete (a workgroup barrier does not), then the first thread
+// adds 1 to *count with an agent-scope release (the workgroup's global writes
+// are written back past its XCD's L2), polls with relaxed agent-scope loads
+// until *count reaches target and ends with one agent-scope acquire fence.
+// Bounded: after kTeamPolls reads, or when a member has given up (*abort), it
+// sets *abort and returns false in every thread of the workgroup.
+constexpr uint32_t kTeamPolls = 1u << 22;
+
+__device__ __forceinline__ bool team_barrier(uint32_t *count, uint32_t target, uint32_t *abort, lds_u32 *s_flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (uint32_t polls = 0;; ++polls) {
+            if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (polls >= kTeamPolls ||
+                ((polls & 63) == 63 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_flag = ok;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
 }  // namespace
 
 template <int WPW, int U>
@@ -216,6 +260,7 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     // so one barrier per product suffices.
     __shared__ uint32_t s_new[3];
     __shared__ int32_t s_item;
+    __shared__ uint32_t s_flag;
     lds_u64 *buf0 = (lds_u64 *)s_dyn;
     lds_u64 *buf1 = buf0 + b.lds_words;
     lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * (U + 1);
@@ -225,8 +270,10 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
         if (threadIdx.x < 3) s_new[threadIdx.x] = 0;
         __syncthreads();
         const int32_t item = s_item;
-        if (item >= b.n_progs) break;
+        if (item >= b.n_items) break;
         const ProgDesc pd = b.progs[b.order[item]];
+        const int32_t team = pd.team_size;
+        const int32_t member = team > 1 ? b.member[item] : 0;
         GProg d;
         d.words = as_global(pd.words);
         d.and_len = as_global(pd.and_len);
@@ -250,34 +297,96 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
         lds_u64 *cur = buf0, *nxt = buf1;  // cur holds v_t, nxt holds v_{t-1}
         int32_t step = 1, slot = 1;        // slot = step mod 3
         uint32_t changed = 0;
-        for (;;) {
-            if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
-            uint32_t my_new = wg_or_and_long_rows(d, cur, nxt);
-            my_new += wg_block_rows<WPW, U>(d, cur, nxt, my_ball);
-            my_new = wave_sum(my_new);
-            if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
-            __syncthreads();
-            changed = s_new[slot];
-            if (changed == 0 || step > d.n_rows) break;
-            lds_u64 *t = cur;
-            cur = nxt;
-            nxt = t;
-            ++step;
-            slot = slot == 2 ? 0 : slot + 1;
-        }
-        // nxt holds the last product, equal to cur at the fixpoint
         typedef __attribute__((address_space(1))) uint64_t g_u64;
         typedef __attribute__((address_space(1))) int32_t g_i32;
-        g_u64 *out = (g_u64 *)pd.out_bits;
-        const int32_t out_words = (pd.n_atoms + 63) >> 6;
-        for (int32_t i = threadIdx.x; i < out_words; i += blockDim.x) out[i] = nxt[i];
-        if (threadIdx.x == 0) *(g_i32 *)pd.out_products = changed == 0 ? step : -1;
+        int32_t result;
+        if (team == 1) {
+            for (;;) {
+                if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
+                uint32_t my_new = wg_or_and_long_rows(d, cur, nxt, 0, 1);
+                my_new += wg_block_rows<WPW, U>(d, cur, nxt, my_ball, 0, 1);
+                my_new = wave_sum(my_new);
+                if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
+                __syncthreads();
+                changed = s_new[slot];
+                if (changed == 0 || step > d.n_rows) break;
+                lds_u64 *t = cur;
+                cur = nxt;
+                nxt = t;
+                ++step;
+                slot = slot == 2 ? 0 : slot + 1;
+            }
+            result = changed == 0 ? step : -1;
+            // nxt holds the last product, equal to cur at the fixpoint
+            cur = nxt;
+        } else {
+            uint32_t *T = pd.team;  // [0] arrivals, [1] abort, [2 + t mod 3] new bits of product t
+            // member 0 starts both exchange buffers at the facts (subsets of
+            // v_1 and v_2) and clears product 1's count before the first meeting
+            if (member == 0) {
+                for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
+                    const uint64_t f = fact_bits[i];
+                    pd.xch[i] = f;
+                    pd.xch[n_words + i] = f;
+                }
+                if (threadIdx.x == 0) __hip_atomic_store(&T[2 + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            bool ok = team_barrier(&T[0], (uint32_t)team, &T[1], (lds_u32 *)&s_flag);
+            result = -2;
+            while (ok) {
+                // the count of product t+1 is cleared during product t, after
+                // every member has read it for product t-2
+                if (member == 0 && threadIdx.x == 0)
+                    __hip_atomic_store(&T[2 + (slot == 2 ? 0 : slot + 1)], 0u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t my_new = wg_or_and_long_rows(d, cur, nxt, member, team);
+                my_new += wg_block_rows<WPW, U>(d, cur, nxt, my_ball, member, team);
+                my_new = wave_sum(my_new);
+                if ((threadIdx.x & 63) == 0 && my_new)
+                    __hip_atomic_fetch_add(&T[2 + slot], my_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                // publish: the member's rows of v_step (with v_{step-2}) into buffer step mod 2
+                uint64_t *Xs = pd.xch + ((step & 1) ? n_words : 0);
+                for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
+                    const uint64_t w = nxt[i];
+                    if (w) __hip_atomic_fetch_or(&Xs[i], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                ok = team_barrier(&T[0], (uint32_t)team * (uint32_t)(step + 1), &T[1], (lds_u32 *)&s_flag);
+                if (!ok) break;
+                changed = __hip_atomic_load(&T[2 + slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (changed == 0 || step > d.n_rows) {
+                    result = changed == 0 ? step : -1;
+                    break;
+                }
+                // nxt <- v_step from the union; then v_step is current and v_{step-1} the older buffer
+                const gp<uint64_t> Xg = as_global((const uint64_t *)Xs);
+                for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) nxt[i] = Xg[i];
+                __syncthreads();
+                lds_u64 *t = cur;
+                cur = nxt;
+                nxt = t;
+                ++step;
+                slot = slot == 2 ? 0 : slot + 1;
+            }
+            // at the fixpoint cur (v_{step-1}) equals v_step
+        }
+        if (member == 0) {
+            g_u64 *out = (g_u64 *)pd.out_bits;
+            const int32_t out_words = (pd.n_atoms + 63) >> 6;
+            for (int32_t i = threadIdx.x; i < out_words; i += blockDim.x) out[i] = cur[i];
+            if (threadIdx.x == 0) *(g_i32 *)pd.out_products = result;
+        }
         __syncthreads();  // the buffers, s_item and s_new are reused by the next program
     }
-    // The last workgroup to finish rewinds the queue for the next launch.
+    // The last workgroup to finish rewinds the queue and clears the team
+    // states for the next launch (every other workgroup has left by then).
     if (threadIdx.x == 0) {
         __threadfence();
         if (atomicAdd(&b.queue[1], 1u) == gridDim.x - 1) {
+            for (int32_t t = 0; t < b.n_teams; ++t)
+                for (int k = 0; k < 5; ++k)
+                    __hip_atomic_store(&b.teams[(int64_t)t * kTeamStateWords + k], 0u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             atomicExch(&b.queue[0], 0u);
             atomicExch(&b.queue[1], 0u);
         }

@@ -89,19 +89,28 @@ struct ProgDesc {
     const int32_t *long_col;
     const uint64_t *fact_bits;
     uint64_t *out_bits;      // [ceil(n_atoms / 64)] fixpoint restricted to the first words
-    int32_t *out_products;   // products, or -1 if the product bound was exceeded
+    int32_t *out_products;   // products; -1 if the product bound was exceeded; -2 if a team gave up
+    uint64_t *xch;           // team programs: two interpretations of n_words, exchanged between members
+    uint32_t *team;          // team programs: kTeamStateWords words of barrier and count state
     int32_t n_rows;
     int32_t n_atoms;
     int32_t n_or;
     int32_t n_segs;
     int32_t and_end;
-    int32_t pad;
+    int32_t team_size;       // workgroups that solve this program together (1: one workgroup alone)
 };
+// Team state: [0] barrier arrivals, [1] abort flag, [2..4] new-bit counts by
+// product index mod 3; one 128-byte line per team. Zero between launches.
+constexpr int kTeamStateWords = 32;
+constexpr int kMaxTeam = 8;
 struct BatchParams {
     const ProgDesc *progs;
-    const int32_t *order;    // queue position -> program, largest first
+    const int32_t *order;    // queue position -> program: team members first, then largest first
+    const int32_t *member;   // queue position -> member index within the program's team
     unsigned int *queue;     // [0] next position, [1] finished workgroups; zero between launches
-    int32_t n_progs;
+    uint32_t *teams;         // n_teams x kTeamStateWords, reset by the last workgroup to finish
+    int32_t n_items;         // queue positions
+    int32_t n_teams;
     int32_t lds_words;       // words of each of the two LDS buffers
 };
 bool batch_shape_supported(int wpw, int unroll);

@@ -1391,11 +1391,23 @@ struct BatchShape {
     size_t lds_bytes = 0;
 };
 
+// Smallest program work (stored entries + rows) that a team is formed for: below
+// it a product takes a workgroup a few microseconds, about a team barrier.
+constexpr int64_t kTeamMinWork = 1 << 16;
+
 struct BatchPlan {
     int device = -1;
     std::vector<const Matrix *> ms;
-    std::vector<int32_t> order;      // queue position -> program (resident programs only)
+    std::vector<int32_t> order;      // resident programs: team programs first, then largest first
     std::vector<int32_t> large;      // programs solved by the single-program drivers
+    std::vector<int32_t> team;       // workgroups per resident program (1: alone), by program index
+    std::vector<int32_t> item_prog;  // queue position -> program
+    std::vector<int32_t> item_member;// queue position -> member of the program's team
+    int32_t n_teams = 0;
+    int32_t team_fallbacks = 0;      // team programs re-solved alone after a team gave up
+    uint64_t *d_xch = nullptr;
+    uint32_t *d_teams = nullptr;
+    int32_t *d_member = nullptr;
     std::vector<int64_t> out_off;    // first output word of each resident program, -1 otherwise
     int64_t out_words = 0;
     int32_t lds_words = 0;
@@ -1417,8 +1429,11 @@ static void batch_release(BatchPlan &b) {
     if (b.graph) (void)hipGraphDestroy(b.graph);
     b.exec = nullptr;
     b.graph = nullptr;
-    void *ps[] = {b.d_progs, b.d_order, b.d_queue, b.d_out, b.d_prod};
+    void *ps[] = {b.d_progs, b.d_order, b.d_queue, b.d_out, b.d_prod, b.d_xch, b.d_teams, b.d_member};
     for (void *p : ps) dev_free(p, nullptr);
+    b.d_xch = nullptr;
+    b.d_teams = nullptr;
+    b.d_member = nullptr;
     b.d_progs = nullptr;
     b.d_order = nullptr;
     b.d_queue = nullptr;
@@ -1430,14 +1445,17 @@ static BatchParams batch_params(const BatchPlan &b) {
     BatchParams q{};
     q.progs = b.d_progs;
     q.order = b.d_order;
+    q.member = b.d_member;
     q.queue = b.d_queue;
-    q.n_progs = (int32_t)b.order.size();
+    q.teams = b.d_teams;
+    q.n_items = (int32_t)b.item_prog.size();
+    q.n_teams = b.n_teams;
     q.lds_words = b.lds_words;
     return q;
 }
 
 // Fills in lds_bytes and grid: as many workgroups as fit on the device at
-// once, but no more than there are programs.
+// once, but no more than there are queue positions.
 static lp_status batch_fit_shape(const BatchPlan &b, BatchShape *s) {
     if (!batch_shape_supported(s->wpw, s->unroll) || (s->block != 256 && s->block != 512 && s->block != 1024)) {
         set_error("unsupported batch shape (wpw/unroll 1/8, 2/8, 4/4, 1/16, 2/16; block 256, 512 or 1024)");
@@ -1455,7 +1473,15 @@ static lp_status batch_fit_shape(const BatchPlan &b, BatchShape *s) {
     }
     const int64_t resident = (int64_t)per_cu * d.n_cu;
     const int64_t want = s->grid > 0 ? s->grid : resident;
-    s->grid = (int)std::max<int64_t>(1, std::min<int64_t>({want, resident, (int64_t)b.order.size()}));
+    s->grid = (int)std::max<int64_t>(1, std::min<int64_t>({want, resident, (int64_t)b.item_prog.size()}));
+    int32_t max_team = 1;
+    for (int32_t i : b.order) max_team = std::max(max_team, b.team[i]);
+    if (s->grid < max_team) {
+        // a team waits for all of its members: they must be able to run at once
+        set_error("batch grid of " + std::to_string(s->grid) + " workgroups is smaller than a team of " +
+                  std::to_string(max_team));
+        return LP_E_INVAL;
+    }
     return LP_OK;
 }
 
@@ -1521,12 +1547,51 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
         if (n_words_of(b.ms[i]->n_rows) <= cap_words) idx.push_back(i);
         else b.large.push_back(i);
     }
-    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
-        const Matrix &a = *b.ms[x], &c = *b.ms[y];
-        const int64_t wa = a.dev.and_nnz + a.dev.long_nnz + a.n_rows, wc = c.dev.and_nnz + c.dev.long_nnz + c.n_rows;
-        return wa > wc;
-    });
+    auto work = [&](int32_t i) {
+        const Matrix &a = *b.ms[i];
+        return a.dev.and_nnz + a.dev.long_nnz + a.n_rows;
+    };
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
+    // Teams: a program whose work (stored entries + rows) exceeds a workgroup's
+    // share of the batch (total / CUs) and kTeamMinWork gets ceil(work / share)
+    // workgroups, at most kMaxTeam and half the grid; the share grows until all
+    // members fit in one grid's worth of workgroups, so every team starts at once.
+    // sched->team: 0 automatic, 1 no teams, k >= 2 every program in teams of k.
+    b.team.assign(count, 1);
+    {
+        const int32_t opt = sched ? sched->team : 0;
+        const int64_t grid_cap = (sched && sched->grid > 0) ? sched->grid : (int64_t)d.n_cu;
+        const int32_t gmax = (int32_t)std::min<int64_t>(kMaxTeam, grid_cap / 2);
+        if (opt >= 2 && gmax >= 2) {
+            for (int32_t i : idx) b.team[i] = std::min(opt, gmax);
+        } else if (opt == 0 && gmax >= 2 && !idx.empty()) {
+            double total = 0;
+            for (int32_t i : idx) total += (double)work(i);
+            double share = total / (double)d.n_cu;
+            for (;;) {
+                int64_t members = 0;
+                for (int32_t i : idx) {
+                    const double w = (double)work(i);
+                    b.team[i] = (w > share && w >= (double)kTeamMinWork)
+                                    ? (int32_t)std::min<double>(gmax, std::ceil(w / share))
+                                    : 1;
+                    if (b.team[i] > 1) members += b.team[i];
+                }
+                if (members <= grid_cap) break;
+                share *= 1.25;
+            }
+        }
+    }
+    std::stable_partition(idx.begin(), idx.end(), [&](int32_t i) { return b.team[i] > 1; });
     b.order = idx;
+    b.item_prog.clear();
+    b.item_member.clear();
+    b.n_teams = 0;
+    for (int32_t i : idx)
+        for (int32_t k = 0; k < b.team[i]; ++k) {
+            b.item_prog.push_back(i);
+            b.item_member.push_back(k);
+        }
     b.out_off.assign(count, -1);
     std::vector<ProgDesc> desc(count ? count : 1);
     int64_t off = 0;
@@ -1540,6 +1605,20 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
     b.lds_words = maxw;
     if ((rc = dev_alloc((void **)&b.d_out, (size_t)std::max<int64_t>(1, off) * 8, st))) return rc;
     if ((rc = dev_alloc((void **)&b.d_prod, sizeof(int32_t) * std::max(1, count), st))) return rc;
+    // exchange buffers and states of the teams
+    std::vector<int64_t> xoff(count, -1);
+    int64_t xwords = 0;
+    for (int32_t i : idx)
+        if (b.team[i] > 1) {
+            xoff[i] = xwords;
+            xwords += 2 * n_words_of(b.ms[i]->n_rows);
+            ++b.n_teams;
+        }
+    if ((rc = dev_alloc((void **)&b.d_xch, (size_t)std::max<int64_t>(1, xwords) * 8, st))) return rc;
+    if ((rc = dev_alloc((void **)&b.d_teams, sizeof(uint32_t) * kTeamStateWords * std::max(1, b.n_teams), st)))
+        return rc;
+    LP_HIP(hipMemsetAsync(b.d_teams, 0, sizeof(uint32_t) * kTeamStateWords * std::max(1, b.n_teams), st));
+    int32_t team_no = 0;
     for (int32_t i : idx) {
         const Matrix &m = *b.ms[i];
         const DeviceMatrix &dm = m.dev;
@@ -1559,12 +1638,17 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
         g.n_or = dm.n_or;
         g.n_segs = dm.n_segs;
         g.and_end = (int32_t)dm.and_nnz;
+        g.team_size = b.team[i];
+        g.xch = b.team[i] > 1 ? b.d_xch + xoff[i] : nullptr;
+        g.team = b.team[i] > 1 ? b.d_teams + (int64_t)kTeamStateWords * team_no++ : nullptr;
     }
     int64_t dummy = 0;
     if ((rc = upload(&b.d_progs, desc.data(), desc.size(), st, &dummy))) return rc;
-    std::vector<int32_t> ord(b.order);
+    std::vector<int32_t> ord(b.item_prog), mem(b.item_member);
     if (ord.empty()) ord.push_back(0);
+    if (mem.empty()) mem.push_back(0);
     if ((rc = upload(&b.d_order, ord.data(), ord.size(), st, &dummy))) return rc;
+    if ((rc = upload(&b.d_member, mem.data(), mem.size(), st, &dummy))) return rc;
     if ((rc = dev_alloc((void **)&b.d_queue, sizeof(unsigned int) * 2, st))) return rc;
     LP_HIP(hipMemsetAsync(b.d_queue, 0, sizeof(unsigned int) * 2, st));
     LP_HIP(hipStreamSynchronize(st));
@@ -1605,7 +1689,14 @@ static lp_status batch_results(const BatchPlan &b, uint8_t *const *models, int32
     if (b.out_words) LP_HIP(hipMemcpyAsync(hb.data(), b.d_out, b.out_words * 8, hipMemcpyDeviceToHost, st));
     if (count) LP_HIP(hipMemcpyAsync(hp.data(), b.d_prod, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
     LP_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> alone(b.large);
     for (int32_t i : b.order) {
+        if (hp[i] == -2) {
+            // a team gave up waiting for a member (bounded barrier): solve it alone
+            alone.push_back(i);
+            ++const_cast<BatchPlan &>(b).team_fallbacks;
+            continue;
+        }
         if (hp[i] < 1) {
             set_error("fixpoint of batch program " + std::to_string(i) + " not reached within n_rows+1 products");
             return LP_E_INTERNAL;
@@ -1613,7 +1704,7 @@ static lp_status batch_results(const BatchPlan &b, uint8_t *const *models, int32
         if (models && models[i]) unpack_model(hb.data() + b.out_off[i], b.ms[i]->n_atoms, models[i]);
         if (products) products[i] = hp[i];
     }
-    for (int32_t i : b.large) {
+    for (int32_t i : alone) {
         int32_t pr = 0;
         std::vector<uint8_t> tmp;
         uint8_t *dst = models ? models[i] : nullptr;
@@ -2192,6 +2283,10 @@ lp_status lp_batch_get_info(const lp_batch *b, lp_batch_info *out) {
         I.step_bytes += m->info.step_bytes;
     }
     I.tuned_ms = p.tuned_ms;
+    I.n_teams = p.n_teams;
+    for (int32_t i : p.order)
+        if (p.team[i] > 1) I.team_members += p.team[i];
+    I.team_fallbacks = p.team_fallbacks;
     *out = I;
     return LP_OK;
     LP_GUARD_END

@@ -75,7 +75,7 @@ class lp_schedule(ctypes.Structure):
     _fields_ = [("driver", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("wpw", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("team", ctypes.c_int32)]
 
 
 class lp_batch_info(ctypes.Structure):
@@ -84,7 +84,8 @@ class lp_batch_info(ctypes.Structure):
                 ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("step_bytes", ctypes.c_int64), ("tuned_ms", ctypes.c_float),
-                ("reserved", ctypes.c_int32)]
+                ("n_teams", ctypes.c_int32), ("team_members", ctypes.c_int32),
+                ("team_fallbacks", ctypes.c_int32)]
 
 
 class lp_server_config(ctypes.Structure):
@@ -187,9 +188,10 @@ def _ptr(a):
 
 
 def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, variant=LP_STEP_AUTO, grid=0, wpw=0, unroll=0,
-                  block=0):
+                  block=0, team=0):
     s = lp_schedule()
     s.block = block
+    s.team = team
     s.driver = driver
     s.steps_per_sync = steps_per_sync
     s.variant = variant

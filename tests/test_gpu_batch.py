@@ -57,11 +57,14 @@ def test_batch_config_512_programs_vs_oracle():
         with lp.Batch(mats) as b:
             info = b.info()
             assert info["count"] == 512 and info["n_resident"] == 512
+            # the largest programs are split among teams of workgroups
+            assert info["n_teams"] > 0 and info["team_members"] <= 256
             b.run()
             _assert_equal(b.results(), want, "default")
             b.tune(reps=1)
             b.run()
             _assert_equal(b.results(), want, "tuned")
+            assert b.info()["team_fallbacks"] == 0
         _assert_equal(lp.least_model_batch(mats), want, "one call")
     finally:
         for m in mats:
@@ -177,3 +180,76 @@ def test_batch_unsupported_shape_rejected():
         with pytest.raises(lp.LPError) as e:
             lp.least_model_batch([m], sched=lp.make_schedule(block=128))
         assert e.value.code == lp.LP_E_INVAL
+
+
+# ---------------------------------------------------------------- teams
+
+@pytest.mark.parametrize("team", [2, 3, 8])
+@pytest.mark.parametrize("wpw,unroll,block", [(2, 8, 1024), (1, 16, 256)])
+def test_batch_forced_teams(team, wpw, unroll, block):
+    # every program solved by a team of `team` workgroups: members take every
+    # team-th super-block, OR row and segment, and meet after each product
+    progs = gen.batch_programs(7, count=24, lo=50, hi=40_000) + _edge_programs()
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        sched = lp.make_schedule(wpw=wpw, unroll=unroll, block=block, team=team)
+        with lp.Batch(mats, sched=sched) as b:
+            info = b.info()
+            assert info["n_teams"] == len(progs) and info["team_members"] == team * len(progs)
+            for rep in range(2):
+                b.run()
+                _assert_equal(b.results(), want, (team, rep))
+            assert b.info()["team_fallbacks"] == 0
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_batch_team_graph_replays_with_work_between():
+    # team states are cleared by the last workgroup of each launch; replays of
+    # the captured graph, with eager solves between them, give the same results
+    progs = gen.batch_programs(23, count=16, lo=20_000, hi=60_000)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    other = gen.definite_uniform(98, 4000, 9000, 0.02, 5)
+    try:
+        with lp.Batch(mats, sched=lp.make_schedule(team=4)) as b, lp.Matrix(other) as mo:
+            w_other = oracle.sd_fixpoint(other)[:2]
+            for rep in range(3):
+                b.run()
+                _assert_equal(b.results(), want, rep)
+                g, pr = mo.least_model()
+                assert np.array_equal(g, w_other[0]) and pr == w_other[1]
+            for rep in range(3):
+                b.run()
+            _assert_equal(b.results(), want, "back-to-back")
+            assert b.info()["team_fallbacks"] == 0
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_batch_teams_off_and_small_grids():
+    progs = gen.batch_programs(11, count=12, lo=1000, hi=80_000)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        with lp.Batch(mats, sched=lp.make_schedule(team=1)) as b:
+            assert b.info()["n_teams"] == 0
+            b.run()
+            _assert_equal(b.results(), want, "off")
+        # a grid of 4 workgroups allows teams of at most 2
+        with lp.Batch(mats, sched=lp.make_schedule(grid=4, team=8)) as b:
+            info = b.info()
+            assert info["grid"] == 4 and info["team_members"] == 2 * len(progs)
+            b.run()
+            _assert_equal(b.results(), want, "grid 4")
+        # one large program alone: a team of 8
+        with lp.Batch(mats[:1]) as b:
+            assert b.info()["team_members"] in (0, 8)
+            b.run()
+            _assert_equal(b.results(), want[:1], "alone")
+    finally:
+        for m in mats:
+            m.close()

@@ -813,8 +813,26 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     }
 }
 
+// Bit-packed interpretation -> one byte per atom. Eight atoms at a time: byte
+// j of the packed words (bits 8j..8j+7, little-endian) expands through a
+// 256-entry table to eight 0/1 bytes.
+static const uint64_t *byte_expand_table() {
+    static const std::vector<uint64_t> t = [] {
+        std::vector<uint64_t> v(256);
+        for (int b = 0; b < 256; ++b)
+            for (int k = 0; k < 8; ++k)
+                if ((b >> k) & 1) v[b] |= 1ull << (8 * k);
+        return v;
+    }();
+    return t.data();
+}
+
 static void unpack_model(const uint64_t *bits, int32_t n, uint8_t *model) {
-    for (int32_t a = 0; a < n; ++a) model[a] = (uint8_t)((bits[a >> 6] >> (a & 63)) & 1ull);
+    const uint64_t *T = byte_expand_table();
+    const uint8_t *by = reinterpret_cast<const uint8_t *>(bits);
+    int32_t a = 0;
+    for (; a + 8 <= n; a += 8) std::memcpy(model + a, &T[by[a >> 3]], 8);
+    for (; a < n; ++a) model[a] = (uint8_t)((bits[a >> 6] >> (a & 63)) & 1ull);
 }
 
 static lp_status least_model_impl(const Matrix &m, uint8_t *model, int32_t *products, const lp_schedule *sched,
@@ -1552,10 +1570,12 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
         return a.dev.and_nnz + a.dev.long_nnz + a.n_rows;
     };
     std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
-    // Teams: a program whose work (stored entries + rows) exceeds a workgroup's
-    // share of the batch (total / CUs) and kTeamMinWork gets ceil(work / share)
-    // workgroups, at most kMaxTeam and half the grid; the share grows until all
-    // members fit in one grid's worth of workgroups, so every team starts at once.
+    // Teams: a program whose work (stored entries + rows) exceeds a share of
+    // the batch (total / (1.5 CUs): product counts differ, so a share a little
+    // under a CU's keeps the long programs off the critical path) and
+    // kTeamMinWork gets ceil(work / share) workgroups, at most kMaxTeam and half
+    // the grid; the share grows by 10% until all members fit in one grid's worth
+    // of workgroups, so every team starts at once.
     // sched->team: 0 automatic, 1 no teams, k >= 2 every program in teams of k.
     b.team.assign(count, 1);
     {
@@ -1567,7 +1587,7 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
         } else if (opt == 0 && gmax >= 2 && !idx.empty()) {
             double total = 0;
             for (int32_t i : idx) total += (double)work(i);
-            double share = total / (double)d.n_cu;
+            double share = total / (1.5 * (double)d.n_cu);
             for (;;) {
                 int64_t members = 0;
                 for (int32_t i : idx) {
@@ -1578,7 +1598,7 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
                     if (b.team[i] > 1) members += b.team[i];
                 }
                 if (members <= grid_cap) break;
-                share *= 1.25;
+                share *= 1.1;
             }
         }
     }

@@ -84,6 +84,14 @@ def csr_step_bytes(info: dict) -> int:
     return 4 * (n + 1) + 4 * nnz + 3 * ((n + 7) // 8)
 
 
+def cpu_threads() -> int:
+    """Host threads the oracle baselines use: OMP_NUM_THREADS if set, else all CPUs."""
+    try:
+        return max(1, int(os.environ.get("OMP_NUM_THREADS", "")))
+    except ValueError:
+        return max(1, os.cpu_count() or 1)
+
+
 def bench_batch(args, torch, gen, lp, stream) -> dict:
     """Many programs at once: 512 definite programs (atoms log-uniform in
     1e3..1e5, 2x rules, bodies 1..6, 2% facts) solved by one launch of the
@@ -144,7 +152,30 @@ def bench_batch(args, torch, gen, lp, stream) -> dict:
                "speedup_vs_sequential_plain": round(seq["plain"] / e2e_ms, 2),
                "speedup_vs_sequential_default": round(seq["default"] / e2e_ms, 2),
                "shape": {k: binfo[k] for k in ("wpw", "unroll", "block", "grid", "lds_bytes")},
+               "teams": {k: binfo[k] for k in ("n_teams", "team_members", "team_fallbacks")},
                "tuned_ms": round(tuned_ms, 3)}
+        if not args.no_cpu_baseline:
+            # the oracle's forward chaining per program: one thread on a sample of 128 programs
+            # (scaled to 512), and every program over a pool of host threads
+            import oracle
+            from concurrent.futures import ThreadPoolExecutor
+
+            t = time.perf_counter()
+            for p in progs[:128]:
+                oracle.sd_fixpoint(p)
+            one = (time.perf_counter() - t) * 512 / 128
+            thr = cpu_threads()
+            t = time.perf_counter()
+            with ThreadPoolExecutor(thr) as ex:
+                ores = list(ex.map(oracle.sd_fixpoint, progs))
+            alls = time.perf_counter() - t
+            for (g, pr), o in zip(res, ores):
+                assert pr == o[1] and (g == o[0]).all(), "batch result differs from the oracle"
+            out["cpu_baseline"] = {"kind": "oracle", "unit": "ms per 512 programs",
+                                   "one_thread": {"value": round(one * 1e3, 1), "cores": 1,
+                                                  "sample": "programs 0-127 in generation order, scaled to 512"},
+                                   "all_cores": {"value": round(alls * 1e3, 1), "cores": thr,
+                                                 "sample": "all 512 programs, one per host thread at a time"}}
         log(f"[bench] batch: {out}")
         plan.close()
         return out
@@ -347,14 +378,19 @@ def main() -> int:
     t0 = time.perf_counter()
     e0.record(stream)
     prods = []
+    marks = []
     for i in range(args.steps):
         model, products = m.least_model(sched=sched, stream=stream)
         prods.append(products)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(stream)
+        marks.append(ev)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     ms_per_step = ev_ms / max(args.steps, 1)
+    per_solve = [(e0 if i == 0 else marks[i - 1]).elapsed_time(marks[i]) for i in range(len(marks))]
     products = prods[-1]
     assert all(p == products for p in prods)
     entries = info["nnz"] * products
@@ -439,6 +475,25 @@ def main() -> int:
             stable = {"workload": "normal_uniform: 10,000 atoms, 20,000 rules, bodies 1-5, 16 negated atoms",
                       "guesses": H, "ms_per_solve": round(sms, 3), "guesses_per_s": round(H / (sms / 1e3), 1),
                       "n_models": r["n_models"], "products": r["products"]}
+            if not args.no_cpu_baseline:
+                # the oracle's per-guess least models and Algorithm 3 test: one thread on guesses
+                # 0..8191, and all 65,536 guesses over the host's threads (OpenMP)
+                import oracle
+
+                t = time.perf_counter()
+                oracle.stable(q, guess_begin=0, guess_count=8192, threads=1)
+                one = time.perf_counter() - t
+                thr = cpu_threads()
+                t = time.perf_counter()
+                ro = oracle.stable(q, threads=thr)
+                alls = time.perf_counter() - t
+                assert np.array_equal(np.nonzero(ro["accept"])[0], lp.accepted_indices(r["accepted"])), \
+                    "stable models differ from the oracle"
+                stable["cpu_baseline"] = {"kind": "oracle", "unit": "guesses/s",
+                                          "one_thread": {"value": round(8192 / one, 1), "cores": 1,
+                                                         "sample": "guesses 0-8191"},
+                                          "all_cores": {"value": round(H / alls, 1), "cores": thr,
+                                                        "sample": "all 65,536 guesses"}}
         log(f"[bench] stable: {stable}")
         # guess sampling with local search where 2^K cannot be enumerated: a normal program with
         # 40 negated atoms (65,536 guesses per round, 4 rounds; every found model is sound)
@@ -493,7 +548,9 @@ def main() -> int:
                                f"{n_rules:,} rules, bodies 1-8, "
                                "1% facts, Zipf(1.1) heads, 2,000-long chain; least model, full-sweep products",
                    "seed": args.seed, "n_rows": info["n_rows"], "nnz": info["nnz"], "products": products,
-                   "build_s": round(build_s, 3), "us_per_product": round(ms_per_step * 1e3 / products, 3)},
+                   "build_s": round(build_s, 3), "us_per_product": round(ms_per_step * 1e3 / products, 3),
+                   "ms_per_step_p50": round(float(np.median(per_solve)), 4) if per_solve else None,
+                   "ms_per_step_min": round(min(per_solve), 4) if per_solve else None},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stable_models": stable,

@@ -71,7 +71,12 @@ enum {
     LP_PRUNE_FACT_GUESSES = 1u << 0,
     /* Build the host-side CSR only (no device memory, no HIP call). Used to
      * inspect the matrix; solve calls then return LP_E_HOST_ONLY. */
-    LP_BUILD_HOST_ONLY = 1u << 1
+    LP_BUILD_HOST_ONLY = 1u << 1,
+    /* Stable-model products (Algorithm 2) evaluate every row each time. By
+     * default a product evaluates only the rows that name a row changed by the
+     * previous product (the others cannot change); the products, their count
+     * and the models are the same either way. */
+    LP_STABLE_FULL_SWEEP = 1u << 2
 };
 
 typedef struct lp_matrix lp_matrix;
@@ -151,7 +156,7 @@ typedef struct lp_schedule {
  * row holds its own atom (a_ii = 1) and is set in the initial vector; an atom
  * with no rule has an empty OR row and is never true.
  *
- * flags: LP_PRUNE_FACT_GUESSES, LP_BUILD_HOST_ONLY.
+ * flags: LP_PRUNE_FACT_GUESSES, LP_BUILD_HOST_ONLY, LP_STABLE_FULL_SWEEP.
  * On success *out owns host metadata and (unless host-only) device buffers,
  * uploaded on hip_stream, until lp_free_matrix.
  * Errors: LP_E_INVAL (bad ids, body_ptr not monotone, NULL arrays with

@@ -134,6 +134,32 @@ struct SpmmParams {
 };
 // max_grid: workgroups of 256 threads (grid-stride loop over the items).
 hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st);
+// Stable-model products by dirty rows (lp_spmm.hip): one launch pair per
+// product t; see spmm_dirty_eval_kernel.
+constexpr int kDirtyRing = 4;    // |C_t| and |D_t| by t mod kDirtyRing
+constexpr int kDirtyHist = 128;  // |C_t| by t mod kDirtyHist, read by the host
+struct DirtyParams {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint64_t *and_bits;
+    const int32_t *occ_ptr;      // transposed matrix: rows naming each row
+    const int32_t *occ;
+    const uint64_t *V;           // v_{t-1}
+    uint64_t *U;                 // result of product t (holds v_{t-2} outside D_t's rows on entry)
+    uint64_t *next;              // the buffer product t+1 writes (holds v_{t-1})
+    const int32_t *dirty;        // D_t (unused for t = 1: every row)
+    int32_t *changed_out;        // C_t
+    int32_t *dirty_out;          // D_{t+1}
+    int32_t *cmark;              // [n_rows] last product a row was appended to C
+    int32_t *dmark;              // [n_rows] last product a row was appended to D
+    uint32_t *n_changed;         // [kDirtyRing]
+    uint32_t *n_dirty;           // [kDirtyRing]
+    int32_t *hist;               // [kDirtyHist]
+    int32_t n_rows;
+    int32_t log2W;
+    int32_t step;
+};
+hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st);
 // Frontier (semi-naive) least models: one launch per level. occ_ptr/occ is
 // the transposed matrix (for each row, the rows whose entries name it); cnt
 // holds each row's count of entries still false (an OR row starts at 1).

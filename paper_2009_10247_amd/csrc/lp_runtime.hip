@@ -897,10 +897,75 @@ static lp_status stable_fixpoint(const Matrix &m, hipStream_t st, uint64_t *cons
     return stable_loop(m, p, st, buf, counters, products, fix);
 }
 
+static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
+
+// Products of Algorithm 2 by dirty rows (spmm_dirty_eval_kernel): product t
+// evaluates only the rows naming a row that changed in product t-1; the same
+// products and fixpoint as the full sweep. Products are issued eight at a time
+// between host reads of |C_t|.
+static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStream_t st, uint64_t *const buf[2],
+                                   int32_t *products, uint64_t **fix) {
+    lp_status rc;
+    if ((rc = ensure_frontier(m, st))) return rc;
+    const int32_t n = std::max(m.n_rows, 1);
+    Scratch S(st);
+    int32_t *dirty, *changed, *cmark, *dmark, *hist;
+    uint32_t *ring;
+    if ((rc = S.get(&dirty, n)) || (rc = S.get(&changed, n)) || (rc = S.get(&cmark, n)) || (rc = S.get(&dmark, n)) ||
+        (rc = S.get(&hist, kDirtyHist)) || (rc = S.get(&ring, 2 * kDirtyRing)))
+        return rc;
+    LP_HIP(hipMemsetAsync(cmark, 0, sizeof(int32_t) * n, st));
+    LP_HIP(hipMemsetAsync(dmark, 0, sizeof(int32_t) * n, st));
+    LP_HIP(hipMemsetAsync(ring, 0, sizeof(uint32_t) * 2 * kDirtyRing, st));
+    std::vector<int32_t> hh(kDirtyHist);
+    DirtyParams p{};
+    p.row_ptr = sp.row_ptr;
+    p.col = sp.col;
+    p.and_bits = sp.and_bits;
+    p.occ_ptr = m.dev.fr_ptr;
+    p.occ = m.dev.fr_occ;
+    p.dirty = dirty;
+    p.changed_out = changed;
+    p.dirty_out = dirty;
+    p.cmark = cmark;
+    p.dmark = dmark;
+    p.n_changed = ring;
+    p.n_dirty = ring + kDirtyRing;
+    p.hist = hist;
+    p.n_rows = m.n_rows;
+    p.log2W = sp.log2W;
+    const int grid = spmm_grid(m);
+    const int batch = 8;
+    const int64_t limit = (int64_t)m.n_rows + 1;
+    for (int64_t t0 = 1;; t0 += batch) {
+        for (int64_t t = t0; t < t0 + batch; ++t) {
+            p.step = (int32_t)t;
+            p.V = buf[(t - 1) & 1];
+            p.U = buf[t & 1];
+            p.next = buf[(t + 1) & 1];
+            LP_HIP(launch_dirty_product(p, grid, st));
+        }
+        LP_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * kDirtyHist, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        for (int64_t t = t0; t < t0 + batch; ++t) {
+            if (hh[t & (kDirtyHist - 1)] == 0) {
+                *products = (int32_t)t;
+                *fix = buf[t & 1];
+                return LP_OK;
+            }
+        }
+        if (t0 + batch > limit) {
+            set_error("fixpoint not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
+    }
+}
+
 // Products of Algorithm 2 from the initial matrix in buf[0] (and buf[1]),
 // whose bit count is in counters[0], until a product changes no column.
 static lp_status stable_loop(const Matrix &m, SpmmParams p, hipStream_t st, uint64_t *const buf[2],
                              unsigned long long *counters, int32_t *products, uint64_t **fix) {
+    if (!(m.flags & LP_STABLE_FULL_SWEEP) && m.n_rows > 0) return stable_dirty_loop(m, p, st, buf, products, fix);
     unsigned long long *h = pinned_ring();
     if (!h) {
         set_error("pinned host allocation failed");

@@ -139,6 +139,138 @@ __global__ __launch_bounds__(kBlock) void spmm_step_wide_kernel(SpmmParams p) {
     if (tid == 0 && s_bits) atomicAdd(&p.counters[p.step & (kRing - 1)], (unsigned long long)s_bits);
 }
 
+// ---------------------------------------------------------------- dirty rows
+//
+// Algorithm 2 by dirty rows. A row's value in product t can differ from its
+// value in product t-1 only if a row it names changed in product t-1, so
+// product t evaluates only those rows (D_t; every row in product 1). The
+// result buffer of product t holds v_{t-2}; the rows that changed in product
+// t-1 (C_{t-1}) were copied into it when C_{t-1} was propagated, so every row
+// outside D_t already holds its product-t value there and the products are
+// those of the full sweep. Per product: spmm_dirty_eval_kernel evaluates D_t
+// and appends each row whose words changed to C_t (once: an atomic max of the
+// product index on the row's mark); spmm_dirty_push_kernel copies the rows of
+// C_t into the other buffer and appends every row that names one of them to
+// D_{t+1}. Ring slots t mod kDirtyRing hold |C_t| and |D_t|; hist[t mod
+// kDirtyHist] gets |C_t| for the host. A product after the one that changed
+// nothing returns at once.
+
+// One wave per (dirty row, chunk of 64 GC words); W >= 64 (log2W >= 6).
+template <int GC>
+__global__ __launch_bounds__(kBlock) void spmm_dirty_eval_kernel(DirtyParams p) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int32_t t = p.step;
+    if (t >= 2 && p.n_changed[(t - 1) & (kDirtyRing - 1)] == 0) return;
+    const int64_t n_rows = t == 1 ? (int64_t)p.n_rows : (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
+    constexpr int kLog2GC = GC == 8 ? 3 : GC == 4 ? 2 : GC == 2 ? 1 : 0;
+    const int32_t log2G = p.log2W - 6 - kLog2GC;
+    const int64_t n_items = n_rows << log2G;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); it < n_items;
+         it += waves) {
+        const int64_t pos = it >> log2G;
+        const int32_t row = t == 1 ? (int32_t)pos : p.dirty[pos];
+        const int64_t w0 = ((it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
+        const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
+        const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
+        uint64_t acc[GC];
+#pragma unroll
+        for (int k = 0; k < GC; ++k) acc[k] = is_and ? ~0ull : 0ull;
+        for (int32_t i = s; i < e; i += 2) {
+            uint64_t x[2][GC];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int64_t c = p.col[i + j < e ? i + j : e - 1];
+#pragma unroll
+                for (int k = 0; k < GC; ++k) x[j][k] = p.V[(c << p.log2W) + w0 + 64 * k];
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int k = 0; k < GC; ++k) acc[k] = is_and ? (acc[k] & x[j][k]) : (acc[k] | x[j][k]);
+        }
+        bool diff = false;
+#pragma unroll
+        for (int k = 0; k < GC; ++k) {
+            const int64_t at = ((int64_t)row << p.log2W) + w0 + 64 * k;
+            const uint64_t a = s == e ? 0ull : acc[k];
+            diff |= a != p.V[at];
+            p.U[at] = a;
+        }
+        if (__ballot(diff) != 0 && lane == 0 && atomicMax(&p.cmark[row], t) < t)
+            p.changed_out[atomicAdd(&p.n_changed[t & (kDirtyRing - 1)], 1u)] = row;
+    }
+}
+
+// W < 64: one thread per word; the W lanes of a row are consecutive in the
+// wave (W divides 64), and the row's first lane appends it.
+__global__ __launch_bounds__(kBlock) void spmm_dirty_eval_small_kernel(DirtyParams p) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int32_t t = p.step;
+    if (t >= 2 && p.n_changed[(t - 1) & (kDirtyRing - 1)] == 0) return;
+    const int64_t n_rows = t == 1 ? (int64_t)p.n_rows : (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
+    const int32_t W = 1 << p.log2W;
+    const int64_t total = n_rows << p.log2W;
+    // whole waves iterate together so the ballot sees every lane of a row
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t g0 = (int64_t)blockIdx.x * kBlock + (tid & ~63); g0 < total; g0 += stride) {
+        const int64_t g = g0 + lane;
+        bool diff = false;
+        int32_t row = -1;
+        if (g < total) {
+            const int64_t pos = g >> p.log2W;
+            row = t == 1 ? (int32_t)pos : p.dirty[pos];
+            const int64_t w = g & (W - 1);
+            const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
+            const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
+            uint64_t acc = is_and ? ~0ull : 0ull;
+            for (int32_t i = s; i < e; ++i) {
+                const uint64_t x = p.V[((int64_t)p.col[i] << p.log2W) + w];
+                acc = is_and ? (acc & x) : (acc | x);
+            }
+            if (s == e) acc = 0;
+            const int64_t at = ((int64_t)row << p.log2W) + w;
+            diff = acc != p.V[at];
+            p.U[at] = acc;
+        }
+        const uint64_t b = __ballot(diff);
+        const uint64_t mine = ((W >= 64) ? ~0ull : ((1ull << W) - 1ull)) << (lane & ~(W - 1));
+        if (row >= 0 && (lane & (W - 1)) == 0 && (b & mine) && atomicMax(&p.cmark[row], t) < t)
+            p.changed_out[atomicAdd(&p.n_changed[t & (kDirtyRing - 1)], 1u)] = row;
+    }
+}
+
+// One wave per changed row of product t: copy the row into the buffer product
+// t+1 writes, and append the rows naming it to D_{t+1}.
+__global__ __launch_bounds__(kBlock) void spmm_dirty_push_kernel(DirtyParams p) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int32_t t = p.step;
+    const uint32_t n_ch = p.n_changed[t & (kDirtyRing - 1)];
+    if (blockIdx.x == 0 && tid == 0) {
+        p.hist[t & (kDirtyHist - 1)] = (int32_t)n_ch;
+        // slots appended to in product t+1 (C_{t+1}) and by the next push (D_{t+2})
+        p.n_changed[(t + 1) & (kDirtyRing - 1)] = 0;
+        p.n_dirty[(t + 2) & (kDirtyRing - 1)] = 0;
+    }
+    const int64_t W = 1ll << p.log2W;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); q < n_ch;
+         q += waves) {
+        const int32_t row = p.changed_out[q];
+        const int64_t base = (int64_t)row << p.log2W;
+        for (int64_t w = lane; w < W; w += 64) p.next[base + w] = p.U[base + w];
+        const int32_t o0 = p.occ_ptr[row], o1 = p.occ_ptr[row + 1];
+        for (int32_t j = o0 + lane; j < o1; j += 64) {
+            const int32_t r = p.occ[j];
+            if (atomicMax(&p.dmark[r], t + 1) < t + 1)
+                p.dirty_out[atomicAdd(&p.n_dirty[(t + 1) & (kDirtyRing - 1)], 1u)] = r;
+        }
+    }
+}
+
 // Word g of the initial matrix (Definition 8), written to both buffers.
 // Column j of the compressed guess space: bit pos of j
 // is the value of the qbar row whose guess sits at bit pos. Fact rows are all
@@ -264,6 +396,24 @@ hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st) {
         hipLaunchKernelGGL((spmm_step_wide_kernel<1, 2>), dim3(grid), dim3(kBlock), 0, st, p);
     else
         hipLaunchKernelGGL(spmm_step_kernel, dim3(grid), dim3(kBlock), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st) {
+    const unsigned grid = (unsigned)std::max(1, max_grid);
+    if (p.log2W >= 9)
+        hipLaunchKernelGGL((spmm_dirty_eval_kernel<8>), dim3(grid), dim3(kBlock), 0, st, p);
+    else if (p.log2W == 8)
+        hipLaunchKernelGGL((spmm_dirty_eval_kernel<4>), dim3(grid), dim3(kBlock), 0, st, p);
+    else if (p.log2W == 7)
+        hipLaunchKernelGGL((spmm_dirty_eval_kernel<2>), dim3(grid), dim3(kBlock), 0, st, p);
+    else if (p.log2W == 6)
+        hipLaunchKernelGGL((spmm_dirty_eval_kernel<1>), dim3(grid), dim3(kBlock), 0, st, p);
+    else
+        hipLaunchKernelGGL(spmm_dirty_eval_small_kernel, dim3(grid), dim3(kBlock), 0, st, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(spmm_dirty_push_kernel, dim3(grid), dim3(kBlock), 0, st, p);
     return hipGetLastError();
 }
 

@@ -309,8 +309,39 @@ def test_truncation_reports_all_models():
     assert res["truncated"] and res["n_models"] == 32 and res["models"].shape[0] == 7
 
 
+@pytest.mark.parametrize("k", [1, 3, 6, 7, 9, 12])
+def test_stable_dirty_rows_equal_full_sweep(k):
+    # products by dirty rows (default) and full sweeps (LP_STABLE_FULL_SWEEP):
+    # the same fixpoint matrix, product count and models, equal to the oracle's
+    p = gen.normal_uniform(100 + k, 800, 1600, 5, k_neg=k, p_neg=0.25)
+    ref = oracle.stable(p, want_interp=True)
+    out = {}
+    for flags in (0, lp.LP_STABLE_FULL_SWEEP):
+        with lp.Matrix(p, flags=flags) as m:
+            out[flags] = m.stable_models(max_models=4096, want_interp=True)
+    a, b = out[0], out[lp.LP_STABLE_FULL_SWEEP]
+    assert np.array_equal(a["interp"], b["interp"]) and np.array_equal(a["interp"], ref["interp"])
+    assert a["products"] == b["products"] == ref["products"]
+    assert np.array_equal(a["accepted"], b["accepted"]) and np.array_equal(a["models"], b["models"])
+
+
+def test_stable_dirty_rows_chain_and_loops():
+    # a long derivation chain through negation-free rows (many products, one
+    # row changing per product) and even loops (many models)
+    rules = [(0, [gen.neg(1)]), (1, [gen.neg(0)])] + [(i, [i - 1]) for i in range(2, 400)]
+    for p in (gen.from_rules(400, rules), gen.even_loops(6)):
+        ref = oracle.stable(p, want_interp=True)
+        with lp.Matrix(p) as m:
+            res = m.stable_models(max_models=4096, want_interp=True)
+        assert np.array_equal(res["interp"], ref["interp"]) and res["products"] == ref["products"]
+
+
 def test_normal_10k_atoms_16_negated_full_width():
     # 10,000 atoms, 20,000 rules, 16 negated atoms: all 65,536 guesses, every
-    # per-guess fixpoint compared with the oracle
+    # per-guess fixpoint compared with the oracle (products by dirty rows), and
+    # the full-sweep products giving the same matrix
     p = gen.normal_uniform(0)
-    _check_stable(p, threads=16)
+    res = _check_stable(p, threads=16)
+    with lp.Matrix(p, flags=lp.LP_STABLE_FULL_SWEEP) as m:
+        full = m.stable_models(max_models=4096, want_interp=True)
+    assert np.array_equal(full["interp"], res["interp"]) and full["products"] == res["products"]

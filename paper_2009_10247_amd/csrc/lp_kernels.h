@@ -155,7 +155,9 @@ struct DirtyParams {
     uint32_t *n_changed;         // [kDirtyRing]
     uint32_t *n_dirty;           // [kDirtyRing]
     int32_t *hist;               // [kDirtyHist]
+    const uint64_t *fact_bits;   // fact rows (constant, like the qbar rows from n_std on)
     int32_t n_rows;
+    int32_t n_std;
     int32_t log2W;
     int32_t step;
 };

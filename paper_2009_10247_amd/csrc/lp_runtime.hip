@@ -932,9 +932,13 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
     p.n_changed = ring;
     p.n_dirty = ring + kDirtyRing;
     p.hist = hist;
+    p.fact_bits = m.dev.fact_bits;
     p.n_rows = m.n_rows;
+    p.n_std = m.n_std;
     p.log2W = sp.log2W;
-    const int grid = spmm_grid(m);
+    // product 1 sweeps every row; later dirty sets are small, and a launch of
+    // eight workgroups per CU that mostly exit costs dispatch time
+    const int grid = spmm_grid(m), grid_small = std::max(1, grid / 4);
     const int batch = 8;
     const int64_t limit = (int64_t)m.n_rows + 1;
     for (int64_t t0 = 1;; t0 += batch) {
@@ -943,7 +947,7 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
             p.V = buf[(t - 1) & 1];
             p.U = buf[t & 1];
             p.next = buf[(t + 1) & 1];
-            LP_HIP(launch_dirty_product(p, grid, st));
+            LP_HIP(launch_dirty_product(p, t == 1 ? grid : grid_small, st));
         }
         LP_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * kDirtyHist, hipMemcpyDeviceToHost, st));
         LP_HIP(hipStreamSynchronize(st));

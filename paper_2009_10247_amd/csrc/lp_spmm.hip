@@ -153,7 +153,10 @@ __global__ __launch_bounds__(kBlock) void spmm_step_wide_kernel(SpmmParams p) {
 // C_t into the other buffer and appends every row that names one of them to
 // D_{t+1}. Ring slots t mod kDirtyRing hold |C_t| and |D_t|; hist[t mod
 // kDirtyHist] gets |C_t| for the host. A product after the one that changed
-// nothing returns at once.
+// nothing returns at once. Product 1 needs no read of the initial matrix: it
+// is 0 in every row other than the fact and qbar rows, and those rows (their
+// own only entry) never change, so a row changes in product 1 iff it is
+// another row and its result is not 0.
 
 // One wave per (dirty row, chunk of 64 GC words); W >= 64 (log2W >= 6).
 template <int GC>
@@ -191,11 +194,12 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_kernel(DirtyParams p) 
                 for (int k = 0; k < GC; ++k) acc[k] = is_and ? (acc[k] & x[j][k]) : (acc[k] | x[j][k]);
         }
         bool diff = false;
+        const bool first_varies = row < p.n_std && !((p.fact_bits[row >> 6] >> (row & 63)) & 1ull);
 #pragma unroll
         for (int k = 0; k < GC; ++k) {
             const int64_t at = ((int64_t)row << p.log2W) + w0 + 64 * k;
             const uint64_t a = s == e ? 0ull : acc[k];
-            diff |= a != p.V[at];
+            diff |= t == 1 ? (first_varies && a != 0ull) : (a != p.V[at]);
             p.U[at] = a;
         }
         if (__ballot(diff) != 0 && lane == 0 && atomicMax(&p.cmark[row], t) < t)
@@ -232,7 +236,10 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_small_kernel(DirtyPara
             }
             if (s == e) acc = 0;
             const int64_t at = ((int64_t)row << p.log2W) + w;
-            diff = acc != p.V[at];
+            if (t == 1)
+                diff = row < p.n_std && !((p.fact_bits[row >> 6] >> (row & 63)) & 1ull) && acc != 0ull;
+            else
+                diff = acc != p.V[at];
             p.U[at] = acc;
         }
         const uint64_t b = __ballot(diff);

@@ -878,6 +878,9 @@ static SpmmParams spmm_params(const Matrix &m, unsigned long long *counters, int
     return p;
 }
 
+// Stable-model products by dirty rows (the default) or full sweeps.
+static bool dirty_products(const Matrix &m) { return !(m.flags & LP_STABLE_FULL_SWEEP) && m.n_rows > 0; }
+
 // Algorithm 2's loop from the initial matrix (Definition 8) until no column
 // changes; *fix is the buffer holding the fixpoint. The counters hold the bit
 // count of each product's result (slot 0: the initial matrix); product s
@@ -892,12 +895,15 @@ static lp_status stable_fixpoint(const Matrix &m, hipStream_t st, uint64_t *cons
     // |M0|: every fact row holds all 2^K_eff guesses, every guessed qbar row half of them
     const unsigned long long H = 1ull << m.K_eff;
     const unsigned long long m0_bits = (unsigned long long)m.info.n_fact_rows * H + (unsigned long long)m.K_eff * (H / 2);
-    LP_HIP(launch_init_m0(buf[0], buf[1], p.total, p.log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, m.K_eff,
+    // products by dirty rows read only buf[0] before product 1 writes every row of buf[1]
+    uint64_t *second = dirty_products(m) ? nullptr : buf[1];
+    LP_HIP(launch_init_m0(buf[0], second, p.total, p.log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, m.K_eff,
                           &counters[0], m0_bits, st));
     return stable_loop(m, p, st, buf, counters, products, fix);
 }
 
 static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
+
 
 // Products of Algorithm 2 by dirty rows (spmm_dirty_eval_kernel): product t
 // evaluates only the rows naming a row that changed in product t-1; the same
@@ -909,14 +915,14 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
     if ((rc = ensure_frontier(m, st))) return rc;
     const int32_t n = std::max(m.n_rows, 1);
     Scratch S(st);
-    int32_t *dirty, *changed, *cmark, *dmark, *hist;
-    uint32_t *ring;
-    if ((rc = S.get(&dirty, n)) || (rc = S.get(&changed, n)) || (rc = S.get(&cmark, n)) || (rc = S.get(&dmark, n)) ||
-        (rc = S.get(&hist, kDirtyHist)) || (rc = S.get(&ring, 2 * kDirtyRing)))
+    int32_t *dirty, *changed, *marks, *hist;
+    if ((rc = S.get(&dirty, n)) || (rc = S.get(&changed, n)) || (rc = S.get(&hist, kDirtyHist)) ||
+        (rc = S.get(&marks, 2 * (int64_t)n + 2 * kDirtyRing)))
         return rc;
-    LP_HIP(hipMemsetAsync(cmark, 0, sizeof(int32_t) * n, st));
-    LP_HIP(hipMemsetAsync(dmark, 0, sizeof(int32_t) * n, st));
-    LP_HIP(hipMemsetAsync(ring, 0, sizeof(uint32_t) * 2 * kDirtyRing, st));
+    // the two row marks and the size rings, cleared together
+    int32_t *cmark = marks, *dmark = marks + n;
+    uint32_t *ring = reinterpret_cast<uint32_t *>(marks + 2 * (int64_t)n);
+    LP_HIP(hipMemsetAsync(marks, 0, sizeof(int32_t) * (2 * (size_t)n + 2 * kDirtyRing), st));
     std::vector<int32_t> hh(kDirtyHist);
     DirtyParams p{};
     p.row_ptr = sp.row_ptr;
@@ -969,7 +975,7 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
 // whose bit count is in counters[0], until a product changes no column.
 static lp_status stable_loop(const Matrix &m, SpmmParams p, hipStream_t st, uint64_t *const buf[2],
                              unsigned long long *counters, int32_t *products, uint64_t **fix) {
-    if (!(m.flags & LP_STABLE_FULL_SWEEP) && m.n_rows > 0) return stable_dirty_loop(m, p, st, buf, products, fix);
+    if (dirty_products(m)) return stable_dirty_loop(m, p, st, buf, products, fix);
     unsigned long long *h = pinned_ring();
     if (!h) {
         set_error("pinned host allocation failed");
@@ -1128,7 +1134,8 @@ static lp_status guesses_impl(const Matrix &m, const uint64_t *guesses, int64_t 
         return rc;
     LP_HIP(hipMemcpyAsync(g_d, g.data(), cols * 8, hipMemcpyHostToDevice, st));
     LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
-    LP_HIP(launch_init_guess(buf[0], buf[1], total, log2W, m.n_std, K, m.dev.fact_bits, g_d, st));
+    LP_HIP(launch_init_guess(buf[0], dirty_products(m) ? nullptr : buf[1], total, log2W, m.n_std, K, m.dev.fact_bits,
+                             g_d, st));
     LP_HIP(hipMemcpyAsync(counters, &m0_bits, 8, hipMemcpyHostToDevice, st));
     SpmmParams p = spmm_params(m, counters, log2W);
     int32_t prods = -1;

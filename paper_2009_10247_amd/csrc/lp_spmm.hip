@@ -278,7 +278,8 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_push_kernel(DirtyParams p) 
     }
 }
 
-// Word g of the initial matrix (Definition 8), written to both buffers.
+// Word g of the initial matrix (Definition 8), written to V and, unless it is
+// null, to U.
 // Column j of the compressed guess space: bit pos of j
 // is the value of the qbar row whose guess sits at bit pos. Fact rows are all
 // ones; qbar rows of a pruned guess and all other rows are 0.
@@ -304,7 +305,7 @@ __device__ __forceinline__ void init_m0_word(uint64_t *V, uint64_t *U, int64_t g
         x &= valid;
     }
     V[g] = x;
-    U[g] = x;
+    if (U) U[g] = x;
 }
 
 // The initial matrix; *count receives its bit count, which has a closed form
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void init_m0_kernel(uint64_t *V, uint64_t *
     if (g < total) init_m0_word(V, U, g, log2W, n_std, fact_bits, guess_pos, k_eff);
 }
 
-// Initial matrix for explicit guesses (word g, both buffers): column j is
+// Initial matrix for explicit guesses (word g, V and U unless null): column j is
 // guess j of the caller's list, bit t of guesses[j] the initial value of
 // qbar_t (row n_std + t); fact rows are all ones; every other row is 0.
 __global__ __launch_bounds__(kBlock) void init_guess_kernel(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W,
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void init_guess_kernel(uint64_t *V, uint64_
         for (int b = 0; b < 64; ++b) x |= ((gw[b] >> t) & 1ull) << b;
     }
     V[g] = x;
-    U[g] = x;
+    if (U) U[g] = x;
 }
 
 // The guess each column's fixpoint points to: bit t set iff q_t is false in

@@ -84,6 +84,41 @@ def csr_step_bytes(info: dict) -> int:
     return 4 * (n + 1) + 4 * nnz + 3 * ((n + 7) // 8)
 
 
+def bench_small(gen, lp, stream) -> dict:
+    """The 1,000-atom definite program (2,000 rules, 5% facts, bodies 1-4): a
+    solve is about 15 products of a 45 KB layout, so it is bound by launch and
+    memory latency, not bandwidth. Wall-clock microseconds per solve (model in
+    host memory) with the default driver, the persistent driver, and a
+    one-program batch plan (the whole loop in one workgroup's LDS)."""
+    import numpy as np
+
+    p = gen.definite_uniform(0, 1000, 2000, 0.05, 4)
+    out = {"workload": "definite_uniform: 1,000 atoms, 2,000 rules, 5% facts, bodies 1-4", "unit": "us per solve"}
+    with lp.Matrix(p, stream=stream) as m:
+        ref = m.least_model(stream=stream)
+        out["n_rows"] = m.info["n_rows"]
+        out["products"] = ref[1]
+        reps = 50
+        for name, sched in (("default", None), ("persistent", lp.make_schedule(driver=lp.LP_DRIVER_PERSISTENT))):
+            m.least_model(sched=sched, stream=stream)
+            t = time.perf_counter()
+            for _ in range(reps):
+                r = m.least_model(sched=sched, stream=stream)
+            out[name] = round((time.perf_counter() - t) * 1e6 / reps, 1)
+            assert np.array_equal(r[0], ref[0]) and r[1] == ref[1]
+        with lp.Batch([m], stream=stream) as plan:
+            plan.run(stream=stream)
+            plan.results(stream=stream)
+            t = time.perf_counter()
+            for _ in range(reps):
+                plan.run(stream=stream)
+                r = plan.results(stream=stream)[0]
+            out["batch_plan"] = round((time.perf_counter() - t) * 1e6 / reps, 1)
+            assert np.array_equal(r[0], ref[0]) and r[1] == ref[1]
+    log(f"[bench] small program: {out}")
+    return out
+
+
 def cpu_threads() -> int:
     """Host threads the oracle baselines use: OMP_NUM_THREADS if set, else all CPUs."""
     try:
@@ -511,6 +546,7 @@ def main() -> int:
 
     batch = None if args.no_batch else bench_batch(args, torch, gen, lp, stream)
     dense = None if args.no_dense else bench_dense(gen, lp, stream)
+    small = bench_small(gen, lp, stream)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -557,6 +593,7 @@ def main() -> int:
         "batch": batch,
         "frontier": frontier,
         "dense": dense,
+        "small_program": small,
         "schedule": lp.schedule_dict(sched),
         "step_us_per_shape": variants or None,
     }

@@ -108,7 +108,10 @@ typedef struct lp_info {
 /* Device-side schedule of the fixpoint loop. Zero-initialize and set what you
  * need: 0 in any field selects the library default. */
 enum {
-    LP_DRIVER_AUTO = 0,
+    LP_DRIVER_AUTO = 0,       /* least models: with every other field 0 (or no schedule), programs
+                                 of at most 131,072 stored entries + rows run the whole loop in one
+                                 workgroup with the interpretations in LDS (one launch); otherwise
+                                 BATCHED */
     LP_DRIVER_PLAIN = 1,      /* one launch per product, host reads the change count each time */
     LP_DRIVER_BATCHED = 2,    /* steps_per_sync launches between host reads of the change counts */
     LP_DRIVER_PERSISTENT = 3, /* one launch; the loop runs on the device with a grid barrier */

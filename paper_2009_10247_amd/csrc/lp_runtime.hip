@@ -612,6 +612,71 @@ static lp_status run_persistent(const Matrix &m, const StepParams &p, const Step
 // the fixpoint (one of bufs[0..1]).
 static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products);
 
+// Small programs under the automatic driver: the whole Algorithm 1 loop in
+// one workgroup with both interpretations in LDS (tp_batch_kernel on a
+// one-program queue): one launch and no grid-wide synchronization, where the
+// other drivers pay a launch or a grid barrier per product. Everything the
+// kernel reads or writes is allocated per call, so concurrent solves of one
+// matrix on several streams stay independent.
+constexpr int64_t kLdsLoopMaxWork = 1 << 17;  // stored entries + rows
+
+static bool lds_loop_fits(const Matrix &m) {
+    return m.dev.and_nnz + m.dev.long_nnz + m.n_rows <= kLdsLoopMaxWork && n_words_of(m.n_rows) * 16 <= 48 * 1024;
+}
+
+static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products) {
+    struct Head {
+        ProgDesc desc;
+        int32_t order, member;
+        uint32_t queue[2];
+        int32_t products, pad;
+    };
+    const size_t head = (sizeof(Head) + 255) / 256 * 256;
+    const int64_t Wa = std::max<int64_t>(1, n_words_of(m.n_atoms));
+    uint8_t *blk;
+    lp_status rc;
+    if ((rc = S.get(&blk, head + (size_t)Wa * 8))) return rc;
+    Head *dh = reinterpret_cast<Head *>(blk);
+    uint64_t *bits = reinterpret_cast<uint64_t *>(blk + head);
+    const DeviceMatrix &dm = m.dev;
+    Head h{};
+    h.desc.words = dm.words;
+    h.desc.and_len = dm.and_len;
+    h.desc.col = dm.col;
+    h.desc.or_c0 = dm.or_c0;
+    h.desc.or_row = dm.or_row;
+    h.desc.segs = dm.segs;
+    h.desc.long_col = dm.long_col;
+    h.desc.fact_bits = dm.fact_bits;
+    h.desc.out_bits = bits;
+    h.desc.out_products = &dh->products;
+    h.desc.n_rows = m.n_rows;
+    h.desc.n_atoms = m.n_atoms;
+    h.desc.n_or = dm.n_or;
+    h.desc.n_segs = dm.n_segs;
+    h.desc.and_end = (int32_t)dm.and_nnz;
+    h.desc.team_size = 1;
+    LP_HIP(hipMemcpyAsync(dh, &h, sizeof(Head), hipMemcpyHostToDevice, st));
+    BatchParams q{};
+    q.progs = &dh->desc;
+    q.order = &dh->order;
+    q.member = &dh->member;
+    q.queue = dh->queue;
+    q.n_items = 1;
+    q.lds_words = (int32_t)n_words_of(m.n_rows);
+    LP_HIP(launch_batch(2, 8, 1, 1024, (size_t)q.lds_words * 16, q, st));
+    int32_t prods = 0;
+    LP_HIP(hipMemcpyAsync(&prods, &dh->products, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));  // also ends the host copy of h
+    if (prods < 1) {
+        set_error("fixpoint not reached within n_rows+1 products");
+        return LP_E_INTERNAL;
+    }
+    *products = prods;
+    *out = bits;
+    return LP_OK;
+}
+
 static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipStream_t st, Scratch &S,
                                 uint64_t **out, int32_t *products) {
     if (sched && (sched->driver < LP_DRIVER_AUTO || sched->driver > LP_DRIVER_FRONTIER)) {
@@ -619,6 +684,11 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
         return LP_E_INVAL;
     }
     if (sched && sched->driver == LP_DRIVER_FRONTIER) return frontier_fixpoint(m, st, S, out, products);
+    // the library's own choice only: a schedule that names a step shape gets the step kernel
+    const bool all_default = !sched || (sched->driver == LP_DRIVER_AUTO && sched->steps_per_sync == 0 &&
+                                        sched->variant == 0 && sched->grid == 0 && sched->wpw == 0 &&
+                                        sched->unroll == 0 && sched->block == 0);
+    if (all_default && m.n_rows > 0 && lds_loop_fits(m)) return lds_loop_fixpoint(m, st, S, out, products);
     const int64_t W = n_words_of(m.n_rows);
     uint64_t *buf[2];
     unsigned long long *counters;

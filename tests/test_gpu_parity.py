@@ -192,6 +192,49 @@ def test_concurrent_matrices_do_not_interfere():
             m.close()
 
 
+def test_default_driver_concurrent_solves_of_one_matrix():
+    # small programs take the one-workgroup LDS loop under the default driver;
+    # its descriptor and result buffers are per call, so one matrix solved from
+    # several threads on their own streams gives the oracle's result every time
+    import ctypes
+    import threading
+
+    progs = [gen.definite_uniform(40 + s, 1500 + 400 * s, 3000 + 800 * s, 0.03, 4) for s in range(3)]
+    want = [oracle.sd_fixpoint(p)[:2] for p in progs]
+    mats = [lp.Matrix(p) for p in progs]
+    hip = ctypes.CDLL("libamdhip64.so")  # the HIP runtime the library already loaded
+    streams = []
+    for _ in range(4):
+        h = ctypes.c_void_p()
+        assert hip.hipStreamCreate(ctypes.byref(h)) == 0
+        streams.append(h.value)
+    errors, done = [], []
+
+    def worker(k):
+        try:
+            for it in range(20):
+                i = (k + it) % len(mats)
+                g, pr = mats[i].least_model(stream=streams[k])
+                if not (np.array_equal(g, want[i][0]) and pr == want[i][1]):
+                    errors.append((k, it, i))
+                done.append(k)
+        except BaseException as e:  # noqa: BLE001
+            errors.append(repr(e))
+
+    try:
+        threads = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        assert errors == [] and len(done) == 4 * 20
+    finally:
+        for m in mats:
+            m.close()
+        for h in streams:
+            hip.hipStreamDestroy(ctypes.c_void_p(h))
+
+
 def test_batch_entry_point_equals_single_solves():
     progs = gen.batch_programs(11, count=24, lo=100, hi=5000)
     mats = [lp.Matrix(p) for p in progs]

@@ -842,7 +842,13 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     LP_HIP(hipMemcpyAsync(cnt, d.fr_cnt0, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     DevProps dp;
     if ((rc = dev_props(d.device, &dp))) return rc;
-    const int grid = 4 * std::max(dp.n_cu, 1);
+    // levels of up to kFrontierSmall rows (a long derivation chain) take a few
+    // workgroups: most of a full grid would exit at once, and dispatching it is
+    // most of such a level's time; the size of the next batch's grid follows
+    // the largest frontier of the batch before (every grid gives the same result)
+    constexpr int32_t kFrontierSmall = 4096;
+    const int grid_full = 4 * std::max(dp.n_cu, 1), grid_few = 64;
+    int grid = grid_full;
     unsigned long long *h = pinned_ring();
     if (!h) {
         set_error("pinned host allocation failed");
@@ -870,12 +876,15 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
         }
         LP_HIP(hipMemcpyAsync(hh, hist, sizeof(int32_t) * kFrontierHist, hipMemcpyDeviceToHost, st));
         LP_HIP(hipStreamSynchronize(st));
+        int32_t largest = 0;
         for (int64_t t = t0; t < t0 + kBatch; ++t) {
             if (hh[t % kFrontierHist] == 0) {
                 *products = (int32_t)std::max<int64_t>(t, 1);
                 return LP_OK;
             }
+            largest = std::max(largest, hh[t % kFrontierHist]);
         }
+        grid = largest <= kFrontierSmall ? grid_few : grid_full;
         if (t0 + kBatch > limit) {
             set_error("fixpoint not reached within n_rows+1 products");
             return LP_E_INTERNAL;

@@ -145,9 +145,9 @@ struct DirtyParams {
     const int32_t *occ_ptr;      // transposed matrix: rows naming each row
     const int32_t *occ;
     const uint64_t *V;           // v_{t-1}
-    uint64_t *U;                 // result of product t (holds v_{t-2} outside D_t's rows on entry)
+    uint64_t *U;                 // result of product t (holds v_{t-1} outside D_t's rows on entry)
     uint64_t *next;              // the buffer product t+1 writes (holds v_{t-1})
-    const int32_t *dirty;        // D_t (unused for t = 1: every row)
+    const int32_t *dirty;        // D_t
     int32_t *changed_out;        // C_t
     int32_t *dirty_out;          // D_{t+1}
     int32_t *cmark;              // [n_rows] last product a row was appended to C
@@ -162,6 +162,9 @@ struct DirtyParams {
     int32_t step;
 };
 hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st);
+// D_1 from the fact rows (facts[0..n_facts)) and the qbar rows.
+hipError_t launch_dirty_seed(const DirtyParams &p, const int32_t *facts, int32_t n_facts, int max_grid,
+                             hipStream_t st);
 // Frontier (semi-naive) least models: one launch per level. occ_ptr/occ is
 // the transposed matrix (for each row, the rows whose entries name it); cnt
 // holds each row's count of entries still false (an OR row starts at 1).

@@ -974,9 +974,7 @@ static lp_status stable_fixpoint(const Matrix &m, hipStream_t st, uint64_t *cons
     // |M0|: every fact row holds all 2^K_eff guesses, every guessed qbar row half of them
     const unsigned long long H = 1ull << m.K_eff;
     const unsigned long long m0_bits = (unsigned long long)m.info.n_fact_rows * H + (unsigned long long)m.K_eff * (H / 2);
-    // products by dirty rows read only buf[0] before product 1 writes every row of buf[1]
-    uint64_t *second = dirty_products(m) ? nullptr : buf[1];
-    LP_HIP(launch_init_m0(buf[0], second, p.total, p.log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, m.K_eff,
+    LP_HIP(launch_init_m0(buf[0], buf[1], p.total, p.log2W, m.n_std, m.dev.fact_bits, m.dev.guess_pos, m.K_eff,
                           &counters[0], m0_bits, st));
     return stable_loop(m, p, st, buf, counters, products, fix);
 }
@@ -985,8 +983,9 @@ static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
 
 
 // Products of Algorithm 2 by dirty rows (spmm_dirty_eval_kernel): product t
-// evaluates only the rows naming a row that changed in product t-1; the same
-// products and fixpoint as the full sweep. Products are issued eight at a time
+// evaluates only the rows naming a row that changed in product t-1 (product 1:
+// a fact or qbar row, the rows the initial matrix in both buffers does not
+// hold at 0); the same products and fixpoint as the full sweep. Products are issued eight at a time
 // between host reads of |C_t|.
 static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStream_t st, uint64_t *const buf[2],
                                    int32_t *products, uint64_t **fix) {
@@ -1021,9 +1020,11 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
     p.n_rows = m.n_rows;
     p.n_std = m.n_std;
     p.log2W = sp.log2W;
-    // product 1 sweeps every row; later dirty sets are small, and a launch of
-    // eight workgroups per CU that mostly exit costs dispatch time
+    // product 1's dirty set (rows naming a fact or qbar row) can be large;
+    // later ones are small, and a launch of eight workgroups per CU that mostly
+    // exit costs dispatch time
     const int grid = spmm_grid(m), grid_small = std::max(1, grid / 4);
+    LP_HIP(launch_dirty_seed(p, m.dev.fr_facts, m.dev.fr_n_facts, grid_small, st));
     const int batch = 8;
     const int64_t limit = (int64_t)m.n_rows + 1;
     for (int64_t t0 = 1;; t0 += batch) {
@@ -1213,8 +1214,7 @@ static lp_status guesses_impl(const Matrix &m, const uint64_t *guesses, int64_t 
         return rc;
     LP_HIP(hipMemcpyAsync(g_d, g.data(), cols * 8, hipMemcpyHostToDevice, st));
     LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
-    LP_HIP(launch_init_guess(buf[0], dirty_products(m) ? nullptr : buf[1], total, log2W, m.n_std, K, m.dev.fact_bits,
-                             g_d, st));
+    LP_HIP(launch_init_guess(buf[0], buf[1], total, log2W, m.n_std, K, m.dev.fact_bits, g_d, st));
     LP_HIP(hipMemcpyAsync(counters, &m0_bits, 8, hipMemcpyHostToDevice, st));
     SpmmParams p = spmm_params(m, counters, log2W);
     int32_t prods = -1;

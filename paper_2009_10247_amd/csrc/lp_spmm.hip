@@ -143,7 +143,10 @@ __global__ __launch_bounds__(kBlock) void spmm_step_wide_kernel(SpmmParams p) {
 //
 // Algorithm 2 by dirty rows. A row's value in product t can differ from its
 // value in product t-1 only if a row it names changed in product t-1, so
-// product t evaluates only those rows (D_t; every row in product 1). The
+// product t evaluates only those rows (D_t). The initial matrix is 0 outside
+// the fact and qbar rows, so a row that names none of them is 0 after product
+// 1 as well: D_1 is the set of rows naming a fact or qbar row
+// (spmm_dirty_seed_kernel), with the initial matrix in both buffers. The
 // result buffer of product t holds v_{t-2}; the rows that changed in product
 // t-1 (C_{t-1}) were copied into it when C_{t-1} was propagated, so every row
 // outside D_t already holds its product-t value there and the products are
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_kernel(DirtyParams p) 
     const int lane = tid & 63;
     const int32_t t = p.step;
     if (t >= 2 && p.n_changed[(t - 1) & (kDirtyRing - 1)] == 0) return;
-    const int64_t n_rows = t == 1 ? (int64_t)p.n_rows : (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
+    const int64_t n_rows = (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
     constexpr int kLog2GC = GC == 8 ? 3 : GC == 4 ? 2 : GC == 2 ? 1 : 0;
     const int32_t log2G = p.log2W - 6 - kLog2GC;
     const int64_t n_items = n_rows << log2G;
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_kernel(DirtyParams p) 
     for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); it < n_items;
          it += waves) {
         const int64_t pos = it >> log2G;
-        const int32_t row = t == 1 ? (int32_t)pos : p.dirty[pos];
+        const int32_t row = p.dirty[pos];
         const int64_t w0 = ((it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
         const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
         const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_small_kernel(DirtyPara
     const int lane = tid & 63;
     const int32_t t = p.step;
     if (t >= 2 && p.n_changed[(t - 1) & (kDirtyRing - 1)] == 0) return;
-    const int64_t n_rows = t == 1 ? (int64_t)p.n_rows : (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
+    const int64_t n_rows = (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
     const int32_t W = 1 << p.log2W;
     const int64_t total = n_rows << p.log2W;
     // whole waves iterate together so the ballot sees every lane of a row
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_small_kernel(DirtyPara
         int32_t row = -1;
         if (g < total) {
             const int64_t pos = g >> p.log2W;
-            row = t == 1 ? (int32_t)pos : p.dirty[pos];
+            row = p.dirty[pos];
             const int64_t w = g & (W - 1);
             const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
             const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
@@ -246,6 +249,24 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_small_kernel(DirtyPara
         const uint64_t mine = ((W >= 64) ? ~0ull : ((1ull << W) - 1ull)) << (lane & ~(W - 1));
         if (row >= 0 && (lane & (W - 1)) == 0 && (b & mine) && atomicMax(&p.cmark[row], t) < t)
             p.changed_out[atomicAdd(&p.n_changed[t & (kDirtyRing - 1)], 1u)] = row;
+    }
+}
+
+// D_1: the rows naming a fact row or a qbar row (the rows the initial matrix
+// does not hold at 0). One wave per such row.
+__global__ __launch_bounds__(kBlock) void spmm_dirty_seed_kernel(DirtyParams p, const int32_t *facts, int32_t n_facts) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t n_seed = (int64_t)n_facts + (p.n_rows - p.n_std);
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); q < n_seed;
+         q += waves) {
+        const int32_t row = q < n_facts ? facts[q] : p.n_std + (int32_t)(q - n_facts);
+        const int32_t o0 = p.occ_ptr[row], o1 = p.occ_ptr[row + 1];
+        for (int32_t j = o0 + lane; j < o1; j += 64) {
+            const int32_t r = p.occ[j];
+            if (atomicMax(&p.dmark[r], 1) < 1) p.dirty_out[atomicAdd(&p.n_dirty[1], 1u)] = r;
+        }
     }
 }
 
@@ -404,6 +425,13 @@ hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st) {
         hipLaunchKernelGGL((spmm_step_wide_kernel<1, 2>), dim3(grid), dim3(kBlock), 0, st, p);
     else
         hipLaunchKernelGGL(spmm_step_kernel, dim3(grid), dim3(kBlock), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_dirty_seed(const DirtyParams &p, const int32_t *facts, int32_t n_facts, int max_grid,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(spmm_dirty_seed_kernel, dim3((unsigned)std::max(1, max_grid)), dim3(kBlock), 0, st, p, facts,
+                       n_facts);
     return hipGetLastError();
 }
 

@@ -1577,7 +1577,7 @@ struct BatchPlan {
     std::vector<int32_t> item_prog;  // queue position -> program
     std::vector<int32_t> item_member;// queue position -> member of the program's team
     int32_t n_teams = 0;
-    int32_t team_fallbacks = 0;      // team programs re-solved alone after a team gave up
+    mutable int32_t team_fallbacks = 0;  // team programs re-solved alone after a team gave up (counted by results)
     uint64_t *d_xch = nullptr;
     uint32_t *d_teams = nullptr;
     int32_t *d_member = nullptr;
@@ -1869,7 +1869,7 @@ static lp_status batch_results(const BatchPlan &b, uint8_t *const *models, int32
         if (hp[i] == -2) {
             // a team gave up waiting for a member (bounded barrier): solve it alone
             alone.push_back(i);
-            ++const_cast<BatchPlan &>(b).team_fallbacks;
+            ++b.team_fallbacks;
             continue;
         }
         if (hp[i] < 1) {

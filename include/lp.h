@@ -73,10 +73,15 @@ enum {
      * inspect the matrix; solve calls then return LP_E_HOST_ONLY. */
     LP_BUILD_HOST_ONLY = 1u << 1,
     /* Stable-model products (Algorithm 2) evaluate every row each time. By
-     * default a product evaluates only the rows that name a row changed by the
-     * previous product (the others cannot change); the products, their count
-     * and the models are the same either way. */
-    LP_STABLE_FULL_SWEEP = 1u << 2
+     * default, when the interpretation matrix holds at least 2^19 words
+     * (n_rows x 64-guess words), a product evaluates only the rows that name a
+     * row changed by the previous product (the others cannot change); smaller
+     * matrices are swept in full. The products, their count and the models
+     * are the same either way. */
+    LP_STABLE_FULL_SWEEP = 1u << 2,
+    /* Stable-model products by dirty rows whatever the matrix size (ignored
+     * with LP_STABLE_FULL_SWEEP). */
+    LP_STABLE_DIRTY_ROWS = 1u << 3
 };
 
 typedef struct lp_matrix lp_matrix;
@@ -159,7 +164,8 @@ typedef struct lp_schedule {
  * row holds its own atom (a_ii = 1) and is set in the initial vector; an atom
  * with no rule has an empty OR row and is never true.
  *
- * flags: LP_PRUNE_FACT_GUESSES, LP_BUILD_HOST_ONLY, LP_STABLE_FULL_SWEEP.
+ * flags: LP_PRUNE_FACT_GUESSES, LP_BUILD_HOST_ONLY, LP_STABLE_FULL_SWEEP,
+ * LP_STABLE_DIRTY_ROWS.
  * On success *out owns host metadata and (unless host-only) device buffers,
  * uploaded on hip_stream, until lp_free_matrix.
  * Errors: LP_E_INVAL (bad ids, body_ptr not monotone, NULL arrays with

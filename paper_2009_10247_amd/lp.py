@@ -32,6 +32,7 @@ LP_MAX_NEG_ATOMS = 24
 LP_PRUNE_FACT_GUESSES = 1 << 0
 LP_BUILD_HOST_ONLY = 1 << 1
 LP_STABLE_FULL_SWEEP = 1 << 2
+LP_STABLE_DIRTY_ROWS = 1 << 3
 
 LP_DRIVER_AUTO = 0
 LP_DRIVER_PLAIN = 1

@@ -20,8 +20,9 @@ def _column(interp, j):
     return ((interp[:, w] >> np.uint64(b)) & np.uint64(1)).astype(np.uint8)
 
 
+@pytest.mark.parametrize("flags", [0, lp.LP_STABLE_DIRTY_ROWS])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_given_guesses_match_oracle(seed):
+def test_given_guesses_match_oracle(seed, flags):
     p = gen.normal_uniform(seed, 600, 1200, 5, k_neg=10, p_neg=0.2)
     ref = oracle.stable(p, want_interp=True)
     q = ref["neg_atoms"]
@@ -29,7 +30,7 @@ def test_given_guesses_match_oracle(seed):
     rng = np.random.default_rng(seed)
     acc_idx = np.nonzero(ref["accept"])[0]
     guesses = np.concatenate([rng.integers(0, 1 << K, size=300), acc_idx, acc_idx[:3]]).astype(np.uint64)
-    with lp.Matrix(p) as m:
+    with lp.Matrix(p, flags=flags) as m:
         res = m.stable_guesses(guesses, max_models=len(guesses))
     assert np.array_equal(res["accepted"], ref["accept"][guesses.astype(np.int64)].astype(bool))
     assert res["n_accepted"] == int(res["accepted"].sum())

@@ -296,6 +296,9 @@ def test_tiny_normal_programs_match_brute_force():
         res = _check_stable(p)
         got = sorted(brute.from_vector(m) for m in res["models"])
         assert got == brute.stable_models(p), seed
+        with lp.Matrix(p, flags=lp.LP_STABLE_DIRTY_ROWS) as m:
+            dirty = m.stable_models(max_models=4096)
+        assert np.array_equal(dirty["accepted"], res["accepted"]) and dirty["products"] == res["products"], seed
 
 
 @pytest.mark.parametrize("k", [1, 3, 5, 6, 7, 9, 12])
@@ -354,15 +357,16 @@ def test_truncation_reports_all_models():
 
 @pytest.mark.parametrize("k", [1, 3, 6, 7, 9, 12])
 def test_stable_dirty_rows_equal_full_sweep(k):
-    # products by dirty rows (default) and full sweeps (LP_STABLE_FULL_SWEEP):
-    # the same fixpoint matrix, product count and models, equal to the oracle's
+    # products by dirty rows (LP_STABLE_DIRTY_ROWS; the default only from 2^19
+    # row-words) and full sweeps (LP_STABLE_FULL_SWEEP): the same fixpoint
+    # matrix, product count and models, equal to the oracle's
     p = gen.normal_uniform(100 + k, 800, 1600, 5, k_neg=k, p_neg=0.25)
     ref = oracle.stable(p, want_interp=True)
     out = {}
-    for flags in (0, lp.LP_STABLE_FULL_SWEEP):
+    for flags in (lp.LP_STABLE_DIRTY_ROWS, lp.LP_STABLE_FULL_SWEEP):
         with lp.Matrix(p, flags=flags) as m:
             out[flags] = m.stable_models(max_models=4096, want_interp=True)
-    a, b = out[0], out[lp.LP_STABLE_FULL_SWEEP]
+    a, b = out[lp.LP_STABLE_DIRTY_ROWS], out[lp.LP_STABLE_FULL_SWEEP]
     assert np.array_equal(a["interp"], b["interp"]) and np.array_equal(a["interp"], ref["interp"])
     assert a["products"] == b["products"] == ref["products"]
     assert np.array_equal(a["accepted"], b["accepted"]) and np.array_equal(a["models"], b["models"])
@@ -374,7 +378,7 @@ def test_stable_dirty_rows_chain_and_loops():
     rules = [(0, [gen.neg(1)]), (1, [gen.neg(0)])] + [(i, [i - 1]) for i in range(2, 400)]
     for p in (gen.from_rules(400, rules), gen.even_loops(6)):
         ref = oracle.stable(p, want_interp=True)
-        with lp.Matrix(p) as m:
+        with lp.Matrix(p, flags=lp.LP_STABLE_DIRTY_ROWS) as m:
             res = m.stable_models(max_models=4096, want_interp=True)
         assert np.array_equal(res["interp"], ref["interp"]) and res["products"] == ref["products"]
 

@@ -126,9 +126,13 @@ def test_chain_zipf_full_size():
     want, want_prods, _, _ = oracle.sd_fixpoint(p)
     assert want_prods == 2000
     with lp.Matrix(p) as m:
-        for name in ("batched-global", "persistent", "auto"):
+        for name in ("batched-global", "persistent", "auto", "lds-w4-u16", "lds-w8-u16"):
             got, prods = m.least_model(sched=SCHEDULES[name])
             assert np.array_equal(got, want) and prods == 2000, name
+        # the schedule the benchmark times: the autotuner's choice
+        best, _, _ = m.tune(reps=3)
+        got, prods = m.least_model(sched=best)
+        assert np.array_equal(got, want) and prods == 2000, lp.schedule_dict(best)
 
 
 @pytest.mark.parametrize("variant", ["lds", "global"])

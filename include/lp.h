@@ -144,6 +144,9 @@ typedef struct lp_schedule {
     int32_t team;            /* batch plans: 0 teams chosen by size, 1 no teams, k >= 2 every
                                 program solved by a team of k workgroups (at most 8 and half the
                                 grid) */
+    int32_t team_polls;      /* batch plans: polls after which a team barrier gives up (0: 2^22).
+                                A team that gives up has its program solved alone by
+                                lp_batch_results; small values force that path (tests) */
 } lp_schedule;
 
 /*

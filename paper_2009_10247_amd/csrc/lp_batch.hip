@@ -222,11 +222,10 @@ __device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const ld
 // adds 1 to *count with an agent-scope release (the workgroup's global writes
 // are written back past its XCD's L2), polls with relaxed agent-scope loads
 // until *count reaches target and ends with one agent-scope acquire fence.
-// Bounded: after kTeamPolls reads, or when a member has given up (*abort), it
+// Bounded: after max_polls reads, or when a member has given up (*abort), it
 // sets *abort and returns false in every thread of the workgroup.
-constexpr uint32_t kTeamPolls = 1u << 22;
-
-__device__ __forceinline__ bool team_barrier(uint32_t *count, uint32_t target, uint32_t *abort, lds_u32 *s_flag) {
+__device__ __forceinline__ bool team_barrier(uint32_t *count, uint32_t target, uint32_t *abort, uint32_t max_polls,
+                                             lds_u32 *s_flag) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -234,7 +233,7 @@ __device__ __forceinline__ bool team_barrier(uint32_t *count, uint32_t target, u
         __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         for (uint32_t polls = 0;; ++polls) {
             if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-            if (polls >= kTeamPolls ||
+            if (polls >= max_polls ||
                 ((polls & 63) == 63 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
                 __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
@@ -331,7 +330,7 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
                 }
                 if (threadIdx.x == 0) __hip_atomic_store(&T[2 + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            bool ok = team_barrier(&T[0], (uint32_t)team, &T[1], (lds_u32 *)&s_flag);
+            bool ok = team_barrier(&T[0], (uint32_t)team, &T[1], b.team_polls, (lds_u32 *)&s_flag);
             result = -2;
             while (ok) {
                 // the count of product t+1 is cleared during product t, after
@@ -351,7 +350,8 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
                     const uint64_t w = nxt[i];
                     if (w) __hip_atomic_fetch_or(&Xs[i], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                ok = team_barrier(&T[0], (uint32_t)team * (uint32_t)(step + 1), &T[1], (lds_u32 *)&s_flag);
+                ok = team_barrier(&T[0], (uint32_t)team * (uint32_t)(step + 1), &T[1], b.team_polls,
+                                  (lds_u32 *)&s_flag);
                 if (!ok) break;
                 changed = __hip_atomic_load(&T[2 + slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (changed == 0 || step > d.n_rows) {

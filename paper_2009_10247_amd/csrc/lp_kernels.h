@@ -112,6 +112,7 @@ struct BatchParams {
     int32_t n_items;         // queue positions
     int32_t n_teams;
     int32_t lds_words;       // words of each of the two LDS buffers
+    uint32_t team_polls;     // polls after which a team barrier gives up
 };
 bool batch_shape_supported(int wpw, int unroll);
 hipError_t launch_batch(int wpw, int unroll, int grid, int block, size_t lds_bytes, const BatchParams &b,

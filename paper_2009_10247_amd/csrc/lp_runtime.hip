@@ -1576,6 +1576,9 @@ struct BatchShape {
 // Smallest program work (stored entries + rows) that a team is formed for: below
 // it a product takes a workgroup a few microseconds, about a team barrier.
 constexpr int64_t kTeamMinWork = 1 << 16;
+// Polls after which a team barrier gives up (a few seconds: far beyond any
+// wait of members that run at once).
+constexpr uint32_t kTeamPolls = 1u << 22;
 
 struct BatchPlan {
     int device = -1;
@@ -1633,6 +1636,7 @@ static BatchParams batch_params(const BatchPlan &b) {
     q.n_items = (int32_t)b.item_prog.size();
     q.n_teams = b.n_teams;
     q.lds_words = b.lds_words;
+    q.team_polls = b.sched.team_polls > 0 ? (uint32_t)b.sched.team_polls : kTeamPolls;
     return q;
 }
 

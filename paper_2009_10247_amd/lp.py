@@ -77,7 +77,7 @@ class lp_schedule(ctypes.Structure):
     _fields_ = [("driver", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("wpw", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("team", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("team", ctypes.c_int32), ("team_polls", ctypes.c_int32)]
 
 
 class lp_batch_info(ctypes.Structure):
@@ -190,10 +190,11 @@ def _ptr(a):
 
 
 def make_schedule(driver=LP_DRIVER_AUTO, steps_per_sync=0, variant=LP_STEP_AUTO, grid=0, wpw=0, unroll=0,
-                  block=0, team=0):
+                  block=0, team=0, team_polls=0):
     s = lp_schedule()
     s.block = block
     s.team = team
+    s.team_polls = team_polls
     s.driver = driver
     s.steps_per_sync = steps_per_sync
     s.variant = variant

@@ -253,3 +253,26 @@ def test_batch_teams_off_and_small_grids():
     finally:
         for m in mats:
             m.close()
+
+
+def test_batch_team_that_gives_up_is_solved_alone():
+    # a team barrier bounded at one poll gives up whenever a member is not
+    # already there; lp_batch_results then solves those programs alone, so the
+    # results stay exact (the fallback path, forced from the host)
+    progs = gen.batch_programs(13, count=20, lo=2000, hi=40_000)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        with lp.Batch(mats, sched=lp.make_schedule(team=4, team_polls=1)) as b:
+            for rep in range(2):
+                b.run()
+                _assert_equal(b.results(), want, rep)
+            assert b.info()["team_fallbacks"] > 0
+        # and with the default bound nothing falls back
+        with lp.Batch(mats, sched=lp.make_schedule(team=4)) as b:
+            b.run()
+            _assert_equal(b.results(), want, "default bound")
+            assert b.info()["team_fallbacks"] == 0
+    finally:
+        for m in mats:
+            m.close()

@@ -624,6 +624,8 @@ static bool lds_loop_fits(const Matrix &m) {
     return m.dev.and_nnz + m.dev.long_nnz + m.n_rows <= kLdsLoopMaxWork && n_words_of(m.n_rows) * 16 <= 48 * 1024;
 }
 
+// *out holds the fixpoint's first ceil(n_atoms / 64) words only (the model),
+// not a whole interpretation of n_rows bits.
 static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products) {
     struct Head {
         ProgDesc desc;
@@ -1353,7 +1355,12 @@ struct StepBench {
 
 static lp_status step_bench_init(const Matrix &m, const lp_schedule *sched, hipStream_t st, Scratch &S,
                                  StepBench *B) {
-    lp_status rc = least_fixpoint(m, sched, st, S, &B->fix, &B->products);
+    // the timed steps read and write whole interpretations (n_rows bits); the
+    // automatic driver's one-workgroup loop returns only the original atoms'
+    // bits, so the fixpoint comes from the batched step driver instead
+    lp_schedule fs = sched ? *sched : lp_schedule{};
+    if (fs.driver == LP_DRIVER_AUTO) fs.driver = LP_DRIVER_BATCHED;
+    lp_status rc = least_fixpoint(m, &fs, st, S, &B->fix, &B->products);
     if (rc) return rc;
     const int64_t W = n_words_of(m.n_rows);
     if ((rc = S.get(&B->dst, W)) || (rc = S.get(&B->counters, kRing)) ||

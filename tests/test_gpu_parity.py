@@ -171,6 +171,21 @@ def test_tuned_schedule_gives_the_same_model():
     assert np.array_equal(got, want) and prods == want_prods
 
 
+def test_bench_and_tune_small_program_with_default_schedule():
+    # the default driver solves small programs in one workgroup and keeps only
+    # the model's bits; timing steps needs a whole interpretation, which the
+    # step benchmark and the autotuner take from the batched driver
+    p = gen.definite_uniform(0, 1000, 2000, 0.05, 4)
+    want, want_prods, _, _ = oracle.sd_fixpoint(p)
+    with lp.Matrix(p) as m:
+        assert m.bench_step(reps=5) > 0
+        best, step_ms, solve_ms = m.tune(reps=2)
+        assert step_ms > 0 and solve_ms > 0
+        for sched in (None, best):
+            got, prods = m.least_model(sched=sched)
+            assert np.array_equal(got, want) and prods == want_prods
+
+
 def test_unsupported_shape_is_an_error():
     with lp.Matrix(gen.definite_uniform(0, 100, 200)) as m:
         with pytest.raises(lp.LPError) as e:

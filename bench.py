@@ -497,7 +497,7 @@ def main() -> int:
         with lp.Matrix(q, stream=stream) as mq:
             mq.stable_models(stream=stream)
             torch.cuda.synchronize()
-            reps = 5
+            reps = 20
             s0 = torch.cuda.Event(enable_timing=True)
             s1 = torch.cuda.Event(enable_timing=True)
             s0.record(stream)

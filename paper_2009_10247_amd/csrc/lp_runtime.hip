@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -625,8 +626,10 @@ static bool lds_loop_fits(const Matrix &m) {
 }
 
 // *out holds the fixpoint's first ceil(n_atoms / 64) words only (the model),
-// not a whole interpretation of n_rows bits.
-static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products) {
+// not a whole interpretation of n_rows bits. With host_bits (nullable) those
+// words are also copied to the host, in the same copy as the product count.
+static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products,
+                                  uint64_t *host_bits = nullptr) {
     struct Head {
         ProgDesc desc;
         int32_t order, member;
@@ -668,8 +671,18 @@ static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     q.lds_words = (int32_t)n_words_of(m.n_rows);
     LP_HIP(launch_batch(2, 8, 1, 1024, (size_t)q.lds_words * 16, q, st));
     int32_t prods = 0;
-    LP_HIP(hipMemcpyAsync(&prods, &dh->products, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));  // also ends the host copy of h
+    if (host_bits) {
+        // the product count and the model bits in one copy: [products .. last word of bits]
+        const size_t lead = head - offsetof(Head, products);
+        std::vector<uint8_t> stage(lead + (size_t)Wa * 8);
+        LP_HIP(hipMemcpyAsync(stage.data(), &dh->products, stage.size(), hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));  // also ends the host copy of h
+        std::memcpy(&prods, stage.data(), sizeof(int32_t));
+        std::memcpy(host_bits, stage.data() + lead, (size_t)n_words_of(m.n_atoms) * 8);
+    } else {
+        LP_HIP(hipMemcpyAsync(&prods, &dh->products, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));  // also ends the host copy of h
+    }
     if (prods < 1) {
         set_error("fixpoint not reached within n_rows+1 products");
         return LP_E_INTERNAL;
@@ -679,8 +692,12 @@ static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     return LP_OK;
 }
 
+// With host_bits (nullable), *on_host tells whether the first ceil(n_atoms / 64)
+// words of the fixpoint were already copied there.
 static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipStream_t st, Scratch &S,
-                                uint64_t **out, int32_t *products) {
+                                uint64_t **out, int32_t *products, uint64_t *host_bits = nullptr,
+                                bool *on_host = nullptr) {
+    if (on_host) *on_host = false;
     if (sched && (sched->driver < LP_DRIVER_AUTO || sched->driver > LP_DRIVER_FRONTIER)) {
         set_error("unknown driver " + std::to_string(sched->driver));
         return LP_E_INVAL;
@@ -690,7 +707,11 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
     const bool all_default = !sched || (sched->driver == LP_DRIVER_AUTO && sched->steps_per_sync == 0 &&
                                         sched->variant == 0 && sched->grid == 0 && sched->wpw == 0 &&
                                         sched->unroll == 0 && sched->block == 0);
-    if (all_default && m.n_rows > 0 && lds_loop_fits(m)) return lds_loop_fixpoint(m, st, S, out, products);
+    if (all_default && m.n_rows > 0 && lds_loop_fits(m)) {
+        lp_status rc = lds_loop_fixpoint(m, st, S, out, products, host_bits);
+        if (rc == LP_OK && on_host) *on_host = host_bits != nullptr;
+        return rc;
+    }
     const int64_t W = n_words_of(m.n_rows);
     uint64_t *buf[2];
     unsigned long long *counters;
@@ -921,12 +942,15 @@ static lp_status least_model_impl(const Matrix &m, uint8_t *model, int32_t *prod
     Scratch S(st);
     uint64_t *fix = nullptr;
     int32_t prods = 0;
-    lp_status rc = least_fixpoint(m, sched, st, S, &fix, &prods);
-    if (rc) return rc;
     const int64_t Wn = n_words_of(m.n_atoms);
     std::vector<uint64_t> hb(Wn ? Wn : 1);
-    if (Wn) LP_HIP(hipMemcpyAsync(hb.data(), fix, Wn * 8, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
+    bool on_host = false;
+    lp_status rc = least_fixpoint(m, sched, st, S, &fix, &prods, hb.data(), &on_host);
+    if (rc) return rc;
+    if (!on_host) {
+        if (Wn) LP_HIP(hipMemcpyAsync(hb.data(), fix, Wn * 8, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+    }
     unpack_model(hb.data(), m.n_atoms, model);
     if (products) *products = prods;
     return LP_OK;

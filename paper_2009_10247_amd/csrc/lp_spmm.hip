@@ -157,9 +157,9 @@ __global__ __launch_bounds__(kBlock) void spmm_step_wide_kernel(SpmmParams p) {
 // D_{t+1}. Ring slots t mod kDirtyRing hold |C_t| and |D_t|; hist[t mod
 // kDirtyHist] gets |C_t| for the host. A product after the one that changed
 // nothing returns at once. Product 1 needs no read of the initial matrix: it
-// is 0 in every row other than the fact and qbar rows, and those rows (their
-// own only entry) never change, so a row changes in product 1 iff it is
-// another row and its result is not 0.
+// is 0 in every row other than the fact and qbar rows, and those rows keep
+// their initial values in every product, so a row changes in product 1 iff it
+// is another row and its result is not 0.
 
 // One wave per (dirty row, chunk of 64 GC words); W >= 64 (log2W >= 6).
 template <int GC>

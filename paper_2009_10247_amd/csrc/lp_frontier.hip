@@ -22,38 +22,35 @@ namespace {
 
 constexpr int kFrontierBlock = 256;
 constexpr int kFrontierWaves = kFrontierBlock / 64;
+constexpr int kFrontierLoopBlock = 1024;
 
-// One level. The waves take the frontier 64 rows at a time (grid-stride). For
-// a chunk, a wave scans the lengths of the 64 rows' occurrence lists and walks
-// their concatenation 64 entries per pass, each lane finding the row its
-// entry belongs to by a binary search over the scan in LDS, so a long list
-// is shared by the whole wave. Rows that fire are appended to the next
-// frontier with one atomic per wave and pass.
-__global__ __launch_bounds__(kFrontierBlock) void frontier_level_kernel(FrontierParams f) {
-    __shared__ int32_t s_excl[kFrontierWaves][64];
-    __shared__ int32_t s_start[kFrontierWaves][64];
-    const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t n_in = f.sizes[f.level % kFrontierRing];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        f.sizes[(f.level + 2) % kFrontierRing] = 0;  // the size the level after the next adds to
-        f.hist[f.level % kFrontierHist] = (int32_t)n_in;
-    }
-    if (n_in == 0) return;
-    uint32_t *n_out = &f.sizes[(f.level + 1) % kFrontierRing];
-    const int64_t waves = (int64_t)gridDim.x * kFrontierWaves;
-    for (int64_t c0 = ((int64_t)blockIdx.x * kFrontierWaves + wid) * 64; c0 < n_in; c0 += waves * 64) {
+// Pushes one frontier: the waves take its n_in rows 64 at a time
+// (grid-stride from wave `wave` over `waves` waves). For a chunk, a wave scans
+// the lengths of the 64 rows' occurrence lists and walks their concatenation
+// 64 entries per pass, each lane finding the row its entry belongs to by a
+// binary search over the scan in LDS, so a long list is shared by the whole
+// wave. Rows that fire are appended to `out` with one atomic on n_out per wave
+// and pass. With FROM_L2 the frontier's rows are read with L2-coherent loads:
+// the looped kernel reads rows that other waves of its workgroup stored in the
+// level before.
+template <bool FROM_L2>
+__device__ __forceinline__ void push_frontier(const FrontierParams &f, const int32_t *in, uint32_t n_in, int32_t *out,
+                                              uint32_t *n_out, int64_t wave, int64_t waves, int32_t *s_excl,
+                                              int32_t *s_start, int lane) {
+    for (int64_t c0 = wave * 64; c0 < n_in; c0 += waves * 64) {
         const int64_t j = c0 + lane;
         int32_t s = 0, len = 0;
         if (j < n_in) {
-            const int32_t a = f.in[j];
+            const int32_t a = FROM_L2 ? __hip_atomic_load(const_cast<int32_t *>(in + j), __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : in[j];
             s = f.occ_ptr[a];
             len = f.occ_ptr[a + 1] - s;
         }
         const int32_t ex = wave_exclusive_scan(len);
         const int32_t total = __builtin_amdgcn_readlane(ex + len, 63);
-        s_excl[wid][lane] = ex;
-        s_start[wid][lane] = s;
+        s_excl[lane] = ex;
+        s_start[lane] = s;
         __builtin_amdgcn_wave_barrier();
         for (int32_t i0 = 0; i0 < total; i0 += 64) {
             const int32_t i = i0 + lane;
@@ -65,8 +62,8 @@ __global__ __launch_bounds__(kFrontierBlock) void frontier_level_kernel(Frontier
                 int32_t lo = 0;
 #pragma unroll
                 for (int step = 32; step > 0; step >>= 1)
-                    if (s_excl[wid][lo + step] <= i) lo += step;
-                r = f.occ[s_start[wid][lo] + (i - s_excl[wid][lo])];
+                    if (s_excl[lo + step] <= i) lo += step;
+                r = f.occ[s_start[lo] + (i - s_excl[lo])];
                 fire = atomicSub(&f.cnt[r], 1) == 1;
                 if (fire) atomicOr((unsigned long long *)&f.v[r >> 6], 1ull << (r & 63));
             }
@@ -75,18 +72,83 @@ __global__ __launch_bounds__(kFrontierBlock) void frontier_level_kernel(Frontier
                 uint32_t base = 0;
                 if (lane == 0) base = atomicAdd(n_out, (uint32_t)__popcll(m));
                 base = (uint32_t)__builtin_amdgcn_readfirstlane(base);
-                if (fire) f.out[base + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = r;
+                if (fire) out[base + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = r;
             }
         }
         __builtin_amdgcn_wave_barrier();
     }
 }
 
+// One level, f.level, from f.in to f.out over the whole grid.
+__global__ __launch_bounds__(kFrontierBlock) void frontier_level_kernel(FrontierParams f) {
+    __shared__ int32_t s_excl[kFrontierWaves][64];
+    __shared__ int32_t s_start[kFrontierWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t n_in = f.sizes[f.level % kFrontierRing];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        f.sizes[(f.level + 2) % kFrontierRing] = 0;  // the size the level after the next adds to
+        f.hist[f.level % kFrontierHist] = (int32_t)n_in;
+    }
+    if (n_in == 0) return;
+    push_frontier<false>(f, f.in, n_in, f.out, &f.sizes[(f.level + 1) % kFrontierRing],
+                         (int64_t)blockIdx.x * kFrontierWaves + wid, (int64_t)gridDim.x * kFrontierWaves,
+                         s_excl[wid], s_start[wid], lane);
+}
+
+// Levels f.level .. f.level + n_levels - 1 in one workgroup, with a workgroup
+// barrier between levels in place of a launch: for the long stretches of
+// small frontiers (a derivation chain), where a launch per level costs more
+// than the level's work. Level t reads F_t from q[t & 1] (the fact rows at
+// t = 0) and writes F_{t+1} to q[(t + 1) & 1], as the launches do. The loop
+// ends at the first empty frontier (its size recorded, so the host sees the
+// fixpoint) or before pushing a frontier of more than `cap` rows, which the
+// host then gives to the full grid; ctl[0] gets the first level not pushed.
+// At most n_levels iterations, none of them waiting on another workgroup.
+__global__ __launch_bounds__(kFrontierLoopBlock) void frontier_levels_kernel(FrontierParams f, const int32_t *facts,
+                                                                              int32_t *q0, int32_t *q1,
+                                                                              int32_t n_levels, uint32_t cap,
+                                                                              int32_t *ctl) {
+    constexpr int NW = kFrontierLoopBlock / 64;
+    __shared__ int32_t s_excl[NW][64];
+    __shared__ int32_t s_start[NW][64];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int32_t t = f.level;
+    const int32_t t_end = f.level + n_levels;
+    for (; t < t_end; ++t) {
+        // every atomic on this slot was made before the barrier that ended
+        // level t - 1, and nothing writes it during level t
+        const uint32_t n_in = __hip_atomic_load(&f.sizes[t % kFrontierRing], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        if (n_in > cap) break;
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(&f.sizes[(t + 2) % kFrontierRing], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            f.hist[t % kFrontierHist] = (int32_t)n_in;
+        }
+        if (n_in == 0) {
+            ++t;
+            break;
+        }
+        push_frontier<true>(f, t == 0 ? facts : ((t & 1) ? q1 : q0), n_in, (t & 1) ? q0 : q1,
+                            &f.sizes[(t + 1) % kFrontierRing], wid, NW, s_excl[wid], s_start[wid], lane);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl[0] = t;
+}
+
 }  // namespace
 
 hipError_t launch_frontier_level(const FrontierParams &f, int grid, hipStream_t st) {
     hipLaunchKernelGGL(frontier_level_kernel, dim3(grid), dim3(kFrontierBlock), 0, st, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_frontier_levels(const FrontierParams &f, const int32_t *facts, int32_t *q0, int32_t *q1,
+                                  int32_t n_levels, uint32_t cap, int32_t *ctl, hipStream_t st) {
+    hipLaunchKernelGGL(frontier_levels_kernel, dim3(1), dim3(kFrontierLoopBlock), 0, st, f, facts, q0, q1, n_levels,
+                       cap, ctl);
     return hipGetLastError();
 }
 

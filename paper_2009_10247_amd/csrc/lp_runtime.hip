@@ -853,8 +853,10 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     uint64_t *v;
     int32_t *cnt, *q[2], *hist;
     uint32_t *sizes;
+    // hist holds the |F_t| history and, after it, the looped kernel's stop level
     if ((rc = S.get(&v, W)) || (rc = S.get(&cnt, std::max(n, 1))) || (rc = S.get(&q[0], std::max(n, 1))) ||
-        (rc = S.get(&q[1], std::max(n, 1))) || (rc = S.get(&sizes, kFrontierRing)) || (rc = S.get(&hist, kFrontierHist)))
+        (rc = S.get(&q[1], std::max(n, 1))) || (rc = S.get(&sizes, kFrontierRing)) ||
+        (rc = S.get(&hist, kFrontierHist + 2)))
         return rc;
     LP_HIP(hipMemcpyAsync(v, d.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
     *out = v;
@@ -865,19 +867,21 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     LP_HIP(hipMemcpyAsync(cnt, d.fr_cnt0, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     DevProps dp;
     if ((rc = dev_props(d.device, &dp))) return rc;
-    // levels of up to kFrontierSmall rows (a long derivation chain) take a few
-    // workgroups: most of a full grid would exit at once, and dispatching it is
-    // most of such a level's time; the size of the next batch's grid follows
-    // the largest frontier of the batch before (every grid gives the same result)
+    // The next batch's launch shape follows the largest frontier of the batch
+    // before (every shape gives the same result): above kFrontierSmall rows a
+    // launch per level over the full grid; otherwise (a long derivation
+    // chain) one workgroup runs the batch's levels in a loop, with no launch
+    // per level, until a frontier above kFrontierSmall rows stops it and the
+    // full grid takes over from that level.
     constexpr int32_t kFrontierSmall = 4096;
-    const int grid_full = 4 * std::max(dp.n_cu, 1), grid_few = 64;
-    int grid = grid_full;
+    const int grid_full = 4 * std::max(dp.n_cu, 1);
+    bool looped = false;
     unsigned long long *h = pinned_ring();
     if (!h) {
         set_error("pinned host allocation failed");
         return LP_E_NOMEM;
     }
-    int32_t *hh = reinterpret_cast<int32_t *>(h);  // kRing x 8 bytes >= kFrontierHist x 4 bytes
+    int32_t *hh = reinterpret_cast<int32_t *>(h);  // kRing x 8 bytes >= (kFrontierHist + 2) x 4 bytes
     // sizes = {|F_0|, 0, ...}, copied from the pinned buffer (written again only by a later copy on st)
     for (int i = 0; i < kFrontierRing; ++i) hh[i] = i == 0 ? d.fr_n_facts : 0;
     LP_HIP(hipMemcpyAsync(sizes, hh, sizeof(uint32_t) * kFrontierRing, hipMemcpyHostToDevice, st));
@@ -890,25 +894,38 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     f.v = v;
     f.sizes = sizes;
     f.hist = hist;
-    for (int64_t t0 = 0;; t0 += kBatch) {
-        for (int64_t t = t0; t < t0 + kBatch; ++t) {
-            f.level = (int32_t)t;
-            f.in = t == 0 ? d.fr_facts : q[t & 1];
-            f.out = q[(t + 1) & 1];
-            LP_HIP(launch_frontier_level(f, grid, st));
+    for (int64_t t0 = 0;;) {
+        if (looped) {
+            f.level = (int32_t)t0;
+            LP_HIP(launch_frontier_levels(f, d.fr_facts, q[0], q[1], kBatch, (uint32_t)kFrontierSmall,
+                                          hist + kFrontierHist, st));
+        } else {
+            for (int64_t t = t0; t < t0 + kBatch; ++t) {
+                f.level = (int32_t)t;
+                f.in = t == 0 ? d.fr_facts : q[t & 1];
+                f.out = q[(t + 1) & 1];
+                LP_HIP(launch_frontier_level(f, grid_full, st));
+            }
         }
-        LP_HIP(hipMemcpyAsync(hh, hist, sizeof(int32_t) * kFrontierHist, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipMemcpyAsync(hh, hist, sizeof(int32_t) * (kFrontierHist + 1), hipMemcpyDeviceToHost, st));
         LP_HIP(hipStreamSynchronize(st));
+        const int64_t t_end = looped ? (int64_t)hh[kFrontierHist] : t0 + kBatch;
+        if (t_end < t0 || t_end > t0 + kBatch) {
+            set_error("frontier loop reported an impossible level");
+            return LP_E_INTERNAL;
+        }
         int32_t largest = 0;
-        for (int64_t t = t0; t < t0 + kBatch; ++t) {
+        for (int64_t t = t0; t < t_end; ++t) {
             if (hh[t % kFrontierHist] == 0) {
                 *products = (int32_t)std::max<int64_t>(t, 1);
                 return LP_OK;
             }
             largest = std::max(largest, hh[t % kFrontierHist]);
         }
-        grid = largest <= kFrontierSmall ? grid_few : grid_full;
-        if (t0 + kBatch > limit) {
+        // a loop that stopped early stopped before a large frontier
+        looped = looped ? t_end == t0 + kBatch : largest <= kFrontierSmall;
+        t0 = t_end;
+        if (t0 > limit) {
             set_error("fixpoint not reached within n_rows+1 products");
             return LP_E_INTERNAL;
         }

@@ -66,3 +66,29 @@ def test_unknown_driver_is_an_error():
         with pytest.raises(lp.LPError) as e:
             m.least_model(sched=lp.make_schedule(driver=9))
         assert e.value.code == lp.LP_E_INVAL
+
+
+@pytest.mark.parametrize("bursts", [(), (63,), (64,), (65, 150), (63, 64, 130, 131, 300)])
+def test_long_chain_with_bursts(bursts):
+    # a 400-long derivation chain (frontiers of a row or two, which one
+    # workgroup takes in a loop over many levels) with bursts of 5,000 rows
+    # fired by chain atom k for each k in `bursts`: a burst is larger than the
+    # loop takes, so the full grid takes over at that level and hands back
+    # after it; bursts at 63/64/65 put the large frontier just before, at and
+    # just after the start of a batch of 64 levels
+    chain, burst = 400, 5000
+    n = chain + burst * len(bursts) + 1
+    rules = [(0, [])] + [(i, [i - 1]) for i in range(1, chain)]
+    base = chain
+    for k in bursts:
+        rules += [(base + j, [k]) for j in range(burst)]
+        base += burst
+    rules.append((n - 1, [chain - 1, base - 1 if bursts else 0]))
+    p = gen.from_rules(n, rules)
+    want, want_prods, _, _ = oracle.sd_fixpoint(p)
+    with lp.Matrix(p) as m:
+        got, prods = m.least_model(sched=FRONTIER)
+        b, pb = m.least_model(sched=BATCHED)
+    assert np.array_equal(got, want) and prods == want_prods
+    assert np.array_equal(b, want) and pb == want_prods
+    assert got.all()

@@ -22,7 +22,6 @@ namespace {
 
 constexpr int kFrontierBlock = 256;
 constexpr int kFrontierWaves = kFrontierBlock / 64;
-constexpr int kFrontierLoopBlock = 1024;
 
 // Pushes one frontier: the waves take its n_in rows 64 at a time
 // (grid-stride from wave `wave` over `waves` waves). For a chunk, a wave scans
@@ -30,20 +29,18 @@ constexpr int kFrontierLoopBlock = 1024;
 // 64 entries per pass, each lane finding the row its entry belongs to by a
 // binary search over the scan in LDS, so a long list is shared by the whole
 // wave. Rows that fire are appended to `out` with one atomic on n_out per wave
-// and pass. With FROM_L2 the frontier's rows are read with L2-coherent loads:
-// the looped kernel reads rows that other waves of its workgroup stored in the
-// level before.
-template <bool FROM_L2>
+// and pass. With LDSQ, `in`, `n_out` and `s_out` are in LDS: a fired row's
+// index below `cap` goes to s_out, the rest to `out` in global memory.
+template <bool LDSQ>
 __device__ __forceinline__ void push_frontier(const FrontierParams &f, const int32_t *in, uint32_t n_in, int32_t *out,
                                               uint32_t *n_out, int64_t wave, int64_t waves, int32_t *s_excl,
-                                              int32_t *s_start, int lane) {
+                                              int32_t *s_start, int lane, int32_t *s_out = nullptr,
+                                              uint32_t cap = 0) {
     for (int64_t c0 = wave * 64; c0 < n_in; c0 += waves * 64) {
         const int64_t j = c0 + lane;
         int32_t s = 0, len = 0;
         if (j < n_in) {
-            const int32_t a = FROM_L2 ? __hip_atomic_load(const_cast<int32_t *>(in + j), __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT)
-                                      : in[j];
+            const int32_t a = in[j];
             s = f.occ_ptr[a];
             len = f.occ_ptr[a + 1] - s;
         }
@@ -72,8 +69,14 @@ __device__ __forceinline__ void push_frontier(const FrontierParams &f, const int
                 uint32_t base = 0;
                 if (lane == 0) base = atomicAdd(n_out, (uint32_t)__popcll(m));
                 base = (uint32_t)__builtin_amdgcn_readfirstlane(base);
-                if (fire) out[base + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = r;
+                if (fire) {
+                    const uint32_t k = base + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (LDSQ && k < cap)  // an LDS store (ds_write), never merged with the global one
+                        ((lds_u32 *)s_out)[k] = (uint32_t)r;
+                    else
+                        out[k] = r;
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -97,45 +100,84 @@ __global__ __launch_bounds__(kFrontierBlock) void frontier_level_kernel(Frontier
                          s_excl[wid], s_start[wid], lane);
 }
 
+// Orders the LDS accesses of a workgroup across the barrier, and nothing
+// else: a wave's global atomics and stores may still be in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Levels f.level .. f.level + n_levels - 1 in one workgroup, with a workgroup
 // barrier between levels in place of a launch: for the long stretches of
 // small frontiers (a derivation chain), where a launch per level costs more
-// than the level's work. Level t reads F_t from q[t & 1] (the fact rows at
-// t = 0) and writes F_{t+1} to q[(t + 1) & 1], as the launches do. The loop
-// ends at the first empty frontier (its size recorded, so the host sees the
-// fixpoint) or before pushing a frontier of more than `cap` rows, which the
-// host then gives to the full grid; ctl[0] gets the first level not pushed.
-// At most n_levels iterations, none of them waiting on another workgroup.
+// than the level's work. The frontier and its size live in LDS (up to
+// kFrontierLoopCap rows), so a level's only global accesses are the
+// occurrence lists, the counts and v. The loop takes F_{f.level} from global
+// memory (the fact rows at level 0, else q[level & 1]) and ends at the first
+// empty frontier (its size recorded, so the host sees the fixpoint) or before
+// pushing a frontier of more than kFrontierLoopCap rows. Fired rows past that
+// index are stored to global memory as they come; a level's other global
+// stores are all made at the end, after a full barrier: the frontier left
+// (rows below the cap) into q[t & 1], its size into sizes[t % kFrontierRing]
+// (the next slot cleared), and the first level not pushed into ctl[0]. So a
+// global location is written at most once per launch, and what a later launch
+// reads is exactly what the per-level kernels would have left. At most
+// n_levels iterations, none of them waiting on another workgroup.
 __global__ __launch_bounds__(kFrontierLoopBlock) void frontier_levels_kernel(FrontierParams f, const int32_t *facts,
                                                                               int32_t *q0, int32_t *q1,
-                                                                              int32_t n_levels, uint32_t cap,
-                                                                              int32_t *ctl) {
+                                                                              int32_t n_levels, int32_t *ctl) {
     constexpr int NW = kFrontierLoopBlock / 64;
+    constexpr uint32_t cap = kFrontierLoopCap;
     __shared__ int32_t s_excl[NW][64];
     __shared__ int32_t s_start[NW][64];
+    __shared__ int32_t s_q[2][kFrontierLoopCap];
+    __shared__ uint32_t s_n[4];  // frontier sizes, indexed by level & 3
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int32_t t = f.level;
-    const int32_t t_end = f.level + n_levels;
+    const int32_t t0 = f.level;
+    const uint32_t n0 = f.sizes[t0 % kFrontierRing];
+    if (n0 > cap) {  // the full grid takes this level; nothing was changed
+        if (threadIdx.x == 0) ctl[0] = t0;
+        return;
+    }
+    const int32_t *in0 = t0 == 0 ? facts : ((t0 & 1) ? q1 : q0);
+    for (uint32_t j = threadIdx.x; j < n0; j += kFrontierLoopBlock) s_q[t0 & 1][j] = in0[j];
+    if (threadIdx.x == 0) {
+        s_n[t0 & 3] = n0;
+        s_n[(t0 + 1) & 3] = 0;
+    }
+    lds_barrier();
+    int32_t t = t0;
+    const int32_t t_end = t0 + n_levels;
     for (; t < t_end; ++t) {
-        // every atomic on this slot was made before the barrier that ended
-        // level t - 1, and nothing writes it during level t
-        const uint32_t n_in = __hip_atomic_load(&f.sizes[t % kFrontierRing], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t n_in = s_n[t & 3];
         if (n_in > cap) break;
         if (threadIdx.x == 0) {
-            __hip_atomic_store(&f.sizes[(t + 2) % kFrontierRing], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_n[(t + 2) & 3] = 0;  // read at level t - 2, appended to at level t + 1
             f.hist[t % kFrontierHist] = (int32_t)n_in;
         }
-        if (n_in == 0) {
-            ++t;
-            break;
-        }
-        push_frontier<true>(f, t == 0 ? facts : ((t & 1) ? q1 : q0), n_in, (t & 1) ? q0 : q1,
-                            &f.sizes[(t + 1) % kFrontierRing], wid, NW, s_excl[wid], s_start[wid], lane);
-        __syncthreads();
+        if (n_in == 0) break;
+        push_frontier<true>(f, s_q[t & 1], n_in, (t & 1) ? q0 : q1, &s_n[(t + 1) & 3], wid, NW, s_excl[wid],
+                            s_start[wid], lane, s_q[(t + 1) & 1], cap);
+        lds_barrier();
     }
-    if (threadIdx.x == 0) ctl[0] = t;
+    // F_t is not pushed (t = t_end, or it is too large), or it is empty and
+    // its level recorded (t < t_end). Hand F_t over in global memory (the rows
+    // from index cap on are there already), ordered after every store of the
+    // loop.
+    const uint32_t n_in = s_n[t & 3];
+    __syncthreads();
+    if (t > t0) {
+        int32_t *qt = (t & 1) ? q1 : q0;
+        const uint32_t n_lds = n_in < cap ? n_in : cap;
+        for (uint32_t j = threadIdx.x; j < n_lds; j += kFrontierLoopBlock) qt[j] = s_q[t & 1][j];
+    }
+    if (threadIdx.x == 0) {
+        f.sizes[t % kFrontierRing] = n_in;
+        f.sizes[(t + 1) % kFrontierRing] = 0;
+        ctl[0] = (t < t_end && n_in == 0) ? t + 1 : t;
+    }
 }
 
 }  // namespace
@@ -146,9 +188,9 @@ hipError_t launch_frontier_level(const FrontierParams &f, int grid, hipStream_t 
 }
 
 hipError_t launch_frontier_levels(const FrontierParams &f, const int32_t *facts, int32_t *q0, int32_t *q1,
-                                  int32_t n_levels, uint32_t cap, int32_t *ctl, hipStream_t st) {
+                                  int32_t n_levels, int32_t *ctl, hipStream_t st) {
     hipLaunchKernelGGL(frontier_levels_kernel, dim3(1), dim3(kFrontierLoopBlock), 0, st, f, facts, q0, q1, n_levels,
-                       cap, ctl);
+                       ctl);
     return hipGetLastError();
 }
 

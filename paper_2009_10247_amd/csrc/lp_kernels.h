@@ -183,11 +183,14 @@ struct FrontierParams {
     int32_t level;
 };
 hipError_t launch_frontier_level(const FrontierParams &f, int grid, hipStream_t st);
-// Levels f.level .. f.level + n_levels - 1 in one workgroup (q0, q1: the two
-// frontier buffers by level parity; facts: F_0); stops after an empty
-// frontier or before one of more than cap rows; ctl[0] = first level not pushed.
+// Levels f.level .. f.level + n_levels - 1 in one workgroup of
+// kFrontierLoopBlock threads (q0, q1: the two frontier buffers by level
+// parity; facts: F_0); stops after an empty frontier or before one of more
+// than kFrontierLoopCap rows; ctl[0] = first level not pushed.
+constexpr int kFrontierLoopBlock = 1024;
+constexpr int kFrontierLoopCap = 4096;
 hipError_t launch_frontier_levels(const FrontierParams &f, const int32_t *facts, int32_t *q0, int32_t *q1,
-                                  int32_t n_levels, uint32_t cap, int32_t *ctl, hipStream_t st);
+                                  int32_t n_levels, int32_t *ctl, hipStream_t st);
 
 hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std,
                           const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff,

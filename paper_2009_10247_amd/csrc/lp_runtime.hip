@@ -873,7 +873,7 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     // chain) one workgroup runs the batch's levels in a loop, with no launch
     // per level, until a frontier above kFrontierSmall rows stops it and the
     // full grid takes over from that level.
-    constexpr int32_t kFrontierSmall = 4096;
+    constexpr int32_t kFrontierSmall = kFrontierLoopCap;
     const int grid_full = 4 * std::max(dp.n_cu, 1);
     bool looped = false;
     unsigned long long *h = pinned_ring();
@@ -897,8 +897,7 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     for (int64_t t0 = 0;;) {
         if (looped) {
             f.level = (int32_t)t0;
-            LP_HIP(launch_frontier_levels(f, d.fr_facts, q[0], q[1], kBatch, (uint32_t)kFrontierSmall,
-                                          hist + kFrontierHist, st));
+            LP_HIP(launch_frontier_levels(f, d.fr_facts, q[0], q[1], kBatch, hist + kFrontierHist, st));
         } else {
             for (int64_t t = t0; t < t0 + kBatch; ++t) {
                 f.level = (int32_t)t;

@@ -68,15 +68,20 @@ def test_unknown_driver_is_an_error():
         assert e.value.code == lp.LP_E_INVAL
 
 
-@pytest.mark.parametrize("bursts", [(), (63,), (64,), (65, 150), (63, 64, 130, 131, 300)])
-def test_long_chain_with_bursts(bursts):
-    # a 400-long derivation chain (frontiers of a row or two, which one
-    # workgroup takes in a loop over many levels) with bursts of 5,000 rows
-    # fired by chain atom k for each k in `bursts`: a burst is larger than the
-    # loop takes, so the full grid takes over at that level and hands back
-    # after it; bursts at 63/64/65 put the large frontier just before, at and
-    # just after the start of a batch of 64 levels
-    chain, burst = 400, 5000
+@pytest.mark.parametrize("chain,bursts", [
+    (400, ()), (400, (63,)), (400, (64,)), (400, (65, 150)), (400, (63, 64, 130, 131, 300)), (400, (127,)),
+    (127, ()), (128, ()), (129, ()), (192, ()), (193, ())])
+def test_long_chain_with_bursts(chain, bursts):
+    # a derivation chain (frontiers of a row or two, which one workgroup
+    # takes in a loop over many levels) with bursts of 5,000 rows fired by
+    # chain atom k for each k in `bursts`: a burst is larger than the loop
+    # takes, so the full grid takes over at that level and hands back after
+    # it. Levels go in batches of 64; the first batch runs on the full grid,
+    # the loop from level 64. Bursts at 63/64/65 put the large frontier just
+    # before, at and just after the start of a batch, 127 at the end of the
+    # loop's first batch; chains of 127-129 and 192-193 atoms put the
+    # fixpoint's empty frontier around the ends of batches.
+    burst = 5000
     n = chain + burst * len(bursts) + 1
     rules = [(0, [])] + [(i, [i - 1]) for i in range(1, chain)]
     base = chain

@@ -170,7 +170,7 @@ hipError_t launch_dirty_seed(const DirtyParams &p, const int32_t *facts, int32_t
 // the transposed matrix (for each row, the rows whose entries name it); cnt
 // holds each row's count of entries still false (an OR row starts at 1).
 constexpr int kFrontierRing = 4;     // frontier sizes, indexed by level % kFrontierRing
-constexpr int kFrontierHist = 128;   // |F_t| history, indexed by level % kFrontierHist
+constexpr int kFrontierHist = 256;   // |F_t| history, indexed by level % kFrontierHist
 struct FrontierParams {
     const int32_t *occ_ptr;  // [n_rows + 1]
     const int32_t *occ;      // rows naming each row

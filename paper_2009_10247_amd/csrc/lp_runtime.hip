@@ -841,8 +841,8 @@ static lp_status ensure_frontier(const Matrix &m, hipStream_t st) {
 }
 
 // Least-model fixpoint by levels (lp_frontier.hip): level t pushes F_t and
-// collects F_{t+1}; levels are issued kFrontierHist / 2 at a time and the
-// host reads their |F_t| history; the first empty F_t (t >= 1) ends the solve
+// collects F_{t+1}; levels are issued in batches between host reads of
+// their |F_t| history; the first empty F_t (t >= 1) ends the solve
 // with t products, like the full sweep.
 static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products) {
     lp_status rc;
@@ -867,12 +867,13 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     LP_HIP(hipMemcpyAsync(cnt, d.fr_cnt0, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     DevProps dp;
     if ((rc = dev_props(d.device, &dp))) return rc;
-    // The next batch's launch shape follows the largest frontier of the batch
-    // before (every shape gives the same result): above kFrontierSmall rows a
-    // launch per level over the full grid; otherwise (a long derivation
-    // chain) one workgroup runs the batch's levels in a loop, with no launch
-    // per level, until a frontier above kFrontierSmall rows stops it and the
-    // full grid takes over from that level.
+    // Two launch shapes (every shape gives the same result): a launch per
+    // level over the full grid, kLevelBatch levels per host read; or one
+    // workgroup running up to kLoopBatch levels in a loop, with no launch per
+    // level (a long derivation chain), until a frontier above kFrontierSmall
+    // rows stops it and the full grid takes over from that level. The loop
+    // follows a batch of launches whose last frontier was at most
+    // kFrontierSmall rows, and a loop that was not stopped.
     constexpr int32_t kFrontierSmall = kFrontierLoopCap;
     const int grid_full = 4 * std::max(dp.n_cu, 1);
     bool looped = false;
@@ -881,11 +882,14 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
         set_error("pinned host allocation failed");
         return LP_E_NOMEM;
     }
-    int32_t *hh = reinterpret_cast<int32_t *>(h);  // kRing x 8 bytes >= (kFrontierHist + 2) x 4 bytes
+    static_assert((kFrontierHist + 2) * sizeof(int32_t) <= kRing * sizeof(unsigned long long), "pinned ring");
+    int32_t *hh = reinterpret_cast<int32_t *>(h);
     // sizes = {|F_0|, 0, ...}, copied from the pinned buffer (written again only by a later copy on st)
     for (int i = 0; i < kFrontierRing; ++i) hh[i] = i == 0 ? d.fr_n_facts : 0;
     LP_HIP(hipMemcpyAsync(sizes, hh, sizeof(uint32_t) * kFrontierRing, hipMemcpyHostToDevice, st));
-    constexpr int kBatch = kFrontierHist / 2;
+    // levels per host read: 64 launches, or one loop launch over up to
+    // kFrontierHist levels (a batch's levels take distinct history slots)
+    constexpr int kLevelBatch = 16, kLoopBatch = kFrontierHist;
     const int64_t limit = (int64_t)n + 1;
     FrontierParams f{};
     f.occ_ptr = d.fr_ptr;
@@ -895,11 +899,12 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     f.sizes = sizes;
     f.hist = hist;
     for (int64_t t0 = 0;;) {
+        const int64_t batch = looped ? kLoopBatch : kLevelBatch;
         if (looped) {
             f.level = (int32_t)t0;
-            LP_HIP(launch_frontier_levels(f, d.fr_facts, q[0], q[1], kBatch, hist + kFrontierHist, st));
+            LP_HIP(launch_frontier_levels(f, d.fr_facts, q[0], q[1], (int32_t)batch, hist + kFrontierHist, st));
         } else {
-            for (int64_t t = t0; t < t0 + kBatch; ++t) {
+            for (int64_t t = t0; t < t0 + batch; ++t) {
                 f.level = (int32_t)t;
                 f.in = t == 0 ? d.fr_facts : q[t & 1];
                 f.out = q[(t + 1) & 1];
@@ -908,21 +913,19 @@ static lp_status frontier_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
         }
         LP_HIP(hipMemcpyAsync(hh, hist, sizeof(int32_t) * (kFrontierHist + 1), hipMemcpyDeviceToHost, st));
         LP_HIP(hipStreamSynchronize(st));
-        const int64_t t_end = looped ? (int64_t)hh[kFrontierHist] : t0 + kBatch;
-        if (t_end < t0 || t_end > t0 + kBatch) {
+        const int64_t t_end = looped ? (int64_t)hh[kFrontierHist] : t0 + batch;
+        if (t_end < t0 || t_end > t0 + batch) {
             set_error("frontier loop reported an impossible level");
             return LP_E_INTERNAL;
         }
-        int32_t largest = 0;
         for (int64_t t = t0; t < t_end; ++t) {
             if (hh[t % kFrontierHist] == 0) {
                 *products = (int32_t)std::max<int64_t>(t, 1);
                 return LP_OK;
             }
-            largest = std::max(largest, hh[t % kFrontierHist]);
         }
         // a loop that stopped early stopped before a large frontier
-        looped = looped ? t_end == t0 + kBatch : largest <= kFrontierSmall;
+        looped = looped ? t_end == t0 + batch : hh[(t_end - 1) % kFrontierHist] <= kFrontierSmall;
         t0 = t_end;
         if (t0 > limit) {
             set_error("fixpoint not reached within n_rows+1 products");

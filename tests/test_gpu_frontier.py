@@ -69,18 +69,19 @@ def test_unknown_driver_is_an_error():
 
 
 @pytest.mark.parametrize("chain,bursts", [
-    (400, ()), (400, (63,)), (400, (64,)), (400, (65, 150)), (400, (63, 64, 130, 131, 300)), (400, (127,)),
-    (127, ()), (128, ()), (129, ()), (192, ()), (193, ())])
+    (400, ()), (400, (15,)), (400, (16,)), (400, (17, 150)), (400, (15, 16, 100, 101, 300)), (400, (271,)),
+    (700, (100, 200, 600)), (127, ()), (128, ()), (270, ()), (271, ()), (272, ()), (527, ()), (528, ())])
 def test_long_chain_with_bursts(chain, bursts):
     # a derivation chain (frontiers of a row or two, which one workgroup
     # takes in a loop over many levels) with bursts of 5,000 rows fired by
-    # chain atom k for each k in `bursts`: a burst is larger than the loop
-    # takes, so the full grid takes over at that level and hands back after
-    # it. Levels go in batches of 64; the first batch runs on the full grid,
-    # the loop from level 64. Bursts at 63/64/65 put the large frontier just
-    # before, at and just after the start of a batch, 127 at the end of the
-    # loop's first batch; chains of 127-129 and 192-193 atoms put the
-    # fixpoint's empty frontier around the ends of batches.
+    # chain atom k for each k in `bursts` (a burst is F_{k+1}): a burst is
+    # larger than the loop takes, so the full grid takes over at that level,
+    # for 16 levels, and hands back after them. The first 16 levels run on
+    # the full grid and the loop takes levels 16-271 in its first launch.
+    # Bursts at 15/16/17 put the large frontier just before, at and just
+    # after the loop's start, 271 at the end of its first launch; chains of
+    # 270-272 and 527-528 atoms put the fixpoint's empty frontier around the
+    # ends of loop launches.
     burst = 5000
     n = chain + burst * len(bursts) + 1
     rules = [(0, [])] + [(i, [i - 1]) for i in range(1, chain)]

@@ -121,7 +121,9 @@ enum {
     LP_DRIVER_BATCHED = 2,    /* steps_per_sync launches between host reads of the change counts */
     LP_DRIVER_PERSISTENT = 3, /* one launch; the loop runs on the device with a grid barrier */
     LP_DRIVER_FRONTIER = 4    /* least models only: newly true rows pushed through the transposed
-                                 matrix, one launch per product; each entry is visited once per
+                                 matrix, one level per product: a launch per level for large
+                                 frontiers, one workgroup looping over up to 256 levels while
+                                 they hold at most 4,096 rows; each entry is visited once per
                                  solve (same model and product count; builds the transpose on
                                  first use, about 4 (n_rows + nnz) more device bytes) */
 };

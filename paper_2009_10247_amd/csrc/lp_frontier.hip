@@ -117,13 +117,14 @@ __device__ __forceinline__ void lds_barrier() {
 // memory (the fact rows at level 0, else q[level & 1]) and ends at the first
 // empty frontier (its size recorded, so the host sees the fixpoint) or before
 // pushing a frontier of more than kFrontierLoopCap rows. Fired rows past that
-// index are stored to global memory as they come; a level's other global
-// stores are all made at the end, after a full barrier: the frontier left
-// (rows below the cap) into q[t & 1], its size into sizes[t % kFrontierRing]
-// (the next slot cleared), and the first level not pushed into ctl[0]. So a
-// global location is written at most once per launch, and what a later launch
-// reads is exactly what the per-level kernels would have left. At most
-// n_levels iterations, none of them waiting on another workgroup.
+// index are stored to global memory as they come, and each level's |F_t| to
+// its own history slot; the other global stores are made once, at the end,
+// after a full barrier: the frontier left (rows below the cap) into q[t & 1],
+// its size into sizes[t % kFrontierRing] (the next slot cleared), and the
+// first level not pushed into ctl[0]. So a global location is written at most
+// once per launch, and what a later launch reads is exactly what the
+// per-level kernels would have left. At most n_levels iterations, none of
+// them waiting on another workgroup.
 __global__ __launch_bounds__(kFrontierLoopBlock) void frontier_levels_kernel(FrontierParams f, const int32_t *facts,
                                                                               int32_t *q0, int32_t *q1,
                                                                               int32_t n_levels, int32_t *ctl) {

@@ -73,3 +73,63 @@ def to_vector(interp: int, n_atoms: int) -> np.ndarray:
 
 def from_vector(v) -> int:
     return sum(1 << a for a, x in enumerate(v) if x)
+
+
+def sync_products(prog, guess: int = 0) -> int:
+    """Number of theta(M v) evaluations of the synchronous loop (Algorithm 1,
+    or one column of Algorithm 2) on the standardized positive form of
+    `prog`, counting the last evaluation that changes nothing.
+
+    Written straight from the row semantics of the standardized matrix
+    (Definitions 1, 2, 5 and 7), with no matrix and no stage bookkeeping:
+    a head with one rule is an AND row over that rule's body; a head with
+    k >= 2 rules is an OR row over k new atoms, one AND row per rule (a
+    fact among them makes its new atom a fact). For a normal program, bit t
+    of `guess` is the initial value of the new atom standing for "not q_t"
+    (q_t the t-th smallest negated atom), which is otherwise never derived.
+    Sets are integers over atoms, and a second integer holds the new atoms
+    (bit = rule index).
+    """
+    rules = _masks(prog)
+    qmask = 0
+    for _, _, negm in rules:
+        qmask |= negm
+    qs = [a for a in range(prog.n_atoms) if (qmask >> a) & 1]
+    qbar = {q: t for t, q in enumerate(qs)}  # q -> t; "not q" reads bit t of the guess column
+    by_head = {}
+    for r, (h, _, _) in enumerate(rules):
+        by_head.setdefault(h, []).append(r)
+
+    def body_true(r, atoms, gbits):
+        _, pos, negm = rules[r]
+        if (atoms & pos) != pos:
+            return False
+        return all((gbits >> qbar[a]) & 1 for a in range(prog.n_atoms) if (negm >> a) & 1)
+
+    gbits = guess  # the qbar atoms: constant self-loop rows
+    atoms = 0
+    news = 0
+    for h, rs in by_head.items():  # v0: the fact rows
+        for r in rs:
+            if rules[r][1] == 0 and rules[r][2] == 0:
+                if len(rs) == 1:
+                    atoms |= 1 << h
+                else:
+                    news |= 1 << r
+    products = 0
+    while True:
+        products += 1
+        n_atoms, n_news = 0, 0
+        for h, rs in by_head.items():
+            if len(rs) == 1:
+                if body_true(rs[0], atoms, gbits):
+                    n_atoms |= 1 << h
+            else:
+                if any((news >> r) & 1 for r in rs):
+                    n_atoms |= 1 << h
+                for r in rs:
+                    if body_true(r, atoms, gbits):
+                        n_news |= 1 << r
+        if n_atoms == atoms and n_news == news:
+            return products
+        atoms, news = n_atoms, n_news

@@ -30,7 +30,7 @@ def load(name: str) -> dict:
             elif key in ("coo_val", "csr_value"):
                 d[key] = [float(t) for t in toks]
             elif key in ("coo_row", "coo_col", "csr_row_index", "csr_col_index",
-                         "accepted_guesses", "products"):
+                         "accepted_guesses", "products", "guess_products"):
                 d[key] = [int(t) for t in toks]
             else:
                 d[key] = toks

@@ -46,6 +46,10 @@ def test_example2_stable_models():
     want = [brute.from_vector(_golden.names_to_vector(s, d["atoms"])) for s in d["stable_models"]]
     assert brute.stable_models(p) == want
 
+    # product count of Algorithm 2 on Example 2 (hand derivation in the fixture)
+    assert res["products"] == d["products"][0] == 2
+    assert [brute.sync_products(p, j) for j in (0, 1)] == d["guess_products"]
+
 
 # ------------------------------------------------------------ brute force
 
@@ -59,6 +63,7 @@ def test_least_model_matches_brute_force(block):
         model, products, n_std, _ = oracle.sd_fixpoint(p)
         assert brute.from_vector(model) == want, seed
         assert 1 <= products <= n_std + 1
+        assert products == brute.sync_products(p), seed
 
 
 @pytest.mark.parametrize("block", range(6))
@@ -71,6 +76,9 @@ def test_stable_models_match_brute_force(block):
         assert got == want, seed
         for m in models:
             assert oracle.gl_check(p, m), seed
+        # Algorithm 2 iterates all guess columns until none changes
+        K = res["neg_atoms"].shape[0]
+        assert res["products"] == max(brute.sync_products(p, j) for j in range(1 << K)), seed
 
 
 def test_per_guess_least_models_match_brute_force():
@@ -207,8 +215,32 @@ def test_even_loops_have_2_to_n_models(n):
 
 
 def test_odd_loop_has_no_model():
-    models, _ = oracle.stable_models(gen.odd_loop())
+    models, res = oracle.stable_models(gen.odd_loop())
     assert models == []
+    # guess 0 (abar = 0) changes nothing; guess 1 derives a, then confirms
+    assert res["products"] == 2
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_even_loop_products(n):
+    # guesses with some abar_i or bbar_i set derive a_i or b_i in product 1;
+    # product 2 confirms; the all-zero guess settles in product 1
+    assert oracle.stable(gen.even_loops(n))["products"] == 2
+
+
+@pytest.mark.parametrize("L", [1, 2, 10, 257])
+def test_negation_gated_chain_products(L):
+    # h_0 <- not x, h_i <- h_{i-1} (i < L); x has no rule. Guess 1 (xbar = 1)
+    # derives h_i in product i + 1 and confirms in product L + 1; guess 0
+    # derives nothing. Only guess 1 is consistent (x false, xbar true).
+    x = L
+    rules = [(0, [gen.neg(x)])] + [(i, [i - 1]) for i in range(1, L)]
+    p = gen.from_rules(L + 1, rules)
+    res = oracle.stable(p)
+    assert res["products"] == L + 1
+    assert list(res["accept"]) == [0, 1]
+    if L <= 16:
+        assert [brute.sync_products(p, j) for j in (0, 1)] == [1, L + 1]
 
 
 def test_definite_program_has_one_stable_model_equal_to_lm():

@@ -462,7 +462,10 @@ lp_status lp_tune_schedule(const lp_matrix *m, int32_t reps, lp_schedule *best, 
  * (e.g. a framework's caching allocator). alloc(bytes, stream, ctx) returns a
  * device pointer or NULL; release(ptr, stream, ctx) frees it. Passing NULL for
  * both restores the library's own pool. Not thread-safe with concurrent
- * solves; LP_E_INVAL while blocks of the library's pool are in use.
+ * solves. LP_E_INVAL when installing a hook while blocks of the library's
+ * pool are in use, and when removing or replacing the installed hook while
+ * blocks it allocated are live (matrices, batch plans and servers hold
+ * blocks until they are freed); the hook in place is then kept.
  */
 lp_status lp_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
                            void (*release)(void *ptr, void *stream, void *ctx), void *ctx);

@@ -72,6 +72,9 @@ struct DeviceMatrix {
     mutable int32_t *fr_cnt0 = nullptr;   // [n_rows] entries still false at the start: AND length, OR 1
     mutable int32_t *fr_facts = nullptr;  // fact rows (F_0)
     mutable int32_t fr_n_facts = 0;
+    // device bytes of the structures above that were attached after the
+    // upload (wave splits, transposed matrix), under the same lock
+    mutable int64_t lazy_bytes = 0;
     // stable models (normal programs): plain CSR
     int32_t *full_row_ptr = nullptr;
     int32_t *full_col = nullptr;

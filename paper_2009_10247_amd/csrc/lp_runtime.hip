@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
@@ -32,6 +33,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 static void *(*g_alloc)(size_t, void *, void *) = nullptr;
 static void (*g_release)(void *, void *, void *) = nullptr;
 static void *g_alloc_ctx = nullptr;
+static std::atomic<int64_t> g_hook_live{0};  // blocks allocated through the hook and not yet released
 
 static lp_status hip_fail(hipError_t e, const char *what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -107,6 +109,7 @@ static lp_status dev_alloc(void **p, size_t bytes, hipStream_t st) {
             set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
             return LP_E_NOMEM;
         }
+        g_hook_live.fetch_add(1);
         return LP_OK;
     }
     int dev = 0;
@@ -148,6 +151,7 @@ static void dev_free(void *p, hipStream_t st) {
     if (!p) return;
     if (g_release) {
         g_release(p, (void *)st, g_alloc_ctx);
+        g_hook_live.fetch_sub(1);
         return;
     }
     DevicePool &P = pool();
@@ -374,6 +378,10 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
     return LP_OK;
 }
 
+static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
+static bool dirty_products(const Matrix &m, int32_t log2W);
+static int ilog2(int64_t x);
+
 static lp_status upload_matrix(Matrix &m, hipStream_t st) {
     DeviceMatrix &d = m.dev;
     LP_HIP(hipGetDevice(&d.device));
@@ -394,6 +402,11 @@ static lp_status upload_matrix(Matrix &m, hipStream_t st) {
     }
     LP_HIP(hipStreamSynchronize(st));
     m.info.device_bytes = d.bytes;
+    // stable solves by dirty rows read the transposed matrix: build it now,
+    // so the device bytes reported from here on include it
+    if (m.K > 0 && m.K_eff <= LP_MAX_NEG_ATOMS &&
+        dirty_products(m, ilog2((((int64_t)1 << m.K_eff) + 63) / 64)) && (rc = ensure_frontier(m, st)))
+        return rc;
     const int64_t vbytes = (m.n_rows + 7) / 8;
     if (m.K == 0) {
         m.info.step_bytes = d.stream_bytes + 2 * vbytes;
@@ -408,6 +421,10 @@ static lp_status upload_matrix(Matrix &m, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ drivers
+
+// Guards the structures attached to a matrix on first use (wave splits,
+// transposed matrix) and their byte count.
+static std::mutex g_lazy_mu;
 
 struct DeviceGuard {
     int prev = -1;
@@ -485,8 +502,7 @@ constexpr int64_t kSegCost = 1600;
 // block pass, plus its OR tiles and segments), so the waves end together.
 // Created once per wave count and kept with the matrix's device arrays.
 static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, const int32_t **out) {
-    static std::mutex mu;
-    std::lock_guard<std::mutex> lock(mu);
+    std::lock_guard<std::mutex> lock(g_lazy_mu);
     const DeviceMatrix &d = m.dev;
     for (const auto &wp : d.wave_parts)
         if (wp.first == waves) {
@@ -524,6 +540,7 @@ static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, 
     if (rc) return rc;
     LP_HIP(hipStreamSynchronize(st));  // t is a local
     d.wave_parts.emplace_back(waves, dp);
+    d.lazy_bytes += bytes;
     *out = dp;
     return LP_OK;
 }
@@ -800,8 +817,7 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
 // each row's count of entries still false at the start (AND rows: their
 // length; OR rows: 1, so the first true child fires them); the fact rows.
 static lp_status ensure_frontier(const Matrix &m, hipStream_t st) {
-    static std::mutex mu;
-    std::lock_guard<std::mutex> lock(mu);
+    std::lock_guard<std::mutex> lock(g_lazy_mu);
     const DeviceMatrix &d = m.dev;
     if (d.fr_ptr) return LP_OK;
     const int32_t n = m.n_rows;
@@ -837,6 +853,7 @@ static lp_status ensure_frontier(const Matrix &m, hipStream_t st) {
     d.fr_cnt0 = dc;
     d.fr_facts = df;
     d.fr_n_facts = (int32_t)std::count(m.fact.begin(), m.fact.end(), (uint8_t)1);
+    d.lazy_bytes += bytes;
     return LP_OK;
 }
 
@@ -2300,6 +2317,10 @@ lp_status lp_matrix_info(const lp_matrix *m, lp_info *out) {
         return LP_E_INVAL;
     }
     *out = m->m.info;
+    if (!(m->m.flags & LP_BUILD_HOST_ONLY)) {
+        std::lock_guard<std::mutex> lock(g_lazy_mu);
+        out->device_bytes += m->m.dev.lazy_bytes;
+    }
     return LP_OK;
 }
 
@@ -2634,6 +2655,11 @@ lp_status lp_set_allocator(void *(*alloc)(size_t, void *, void *), void (*releas
             set_error("blocks of the library's own pool are live (free every matrix and plan first)");
             return LP_E_INVAL;
         }
+    }
+    if (g_hook_live.load() > 0 && (alloc != g_alloc || release != g_release || ctx != g_alloc_ctx)) {
+        set_error(std::to_string(g_hook_live.load()) +
+                  " blocks of the installed allocator are live (free every matrix and plan first)");
+        return LP_E_INVAL;
     }
     g_alloc = alloc;
     g_release = release;

@@ -59,7 +59,10 @@ int64_t words_of(int64_t n) { return (n + 63) / 64; }
 // the allocator's rounding), before it has been uploaded once.
 int64_t matrix_bytes_bound(const lp_info &I) {
     const int64_t W = words_of(I.n_rows);
-    const double b = 4.0 * (double)I.nnz + 10.0 * (double)I.n_rows + 64.0 * (double)W + 65536.0;
+    double b = 4.0 * (double)I.nnz + 10.0 * (double)I.n_rows + 64.0 * (double)W + 65536.0;
+    // stable solves by dirty rows: the transposed matrix (row pointers,
+    // entries, start counts, fact rows) is uploaded with the matrix
+    if (I.n_neg > 0) b += 4.0 * (double)I.nnz + 12.0 * (double)I.n_rows + 4.0;
     return (int64_t)(1.15 * b) + (1 << 20);
 }
 
@@ -282,7 +285,20 @@ void run_group(lp_server *s, hipStream_t st, std::vector<Request *> &group, std:
     } catch (const std::bad_alloc &) {
         for (Request *r : group) r->info.status = LP_E_NOMEM;
     }
+    // structures attached to a matrix by its first solves (wave splits) count as resident bytes
+    std::vector<std::pair<Program *, int64_t>> sizes;
+    for (Request *r : group) {
+        Program *p = s->programs[r->info.program_id].get();
+        lp_info I{};
+        if (!failed(p) && lp_matrix_info(p->m, &I) == LP_OK) sizes.emplace_back(p, I.device_bytes);
+    }
     std::lock_guard<std::mutex> lock(s->mu);
+    for (auto &ps : sizes) {
+        if (!ps.first->resident) continue;
+        s->used += ps.second - ps.first->bytes;
+        ps.first->bytes = ps.second;
+    }
+    s->peak_used = std::max(s->peak_used, s->used);
     const double t = s->now();
     for (Request *r : group) {
         Program *p = s->programs[r->info.program_id].get();

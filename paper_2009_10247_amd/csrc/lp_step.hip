@@ -38,17 +38,6 @@ namespace lp {
 
 namespace {
 
-// Any bit of v in [c0, c1) set (global loads), for c0 < c1.
-__device__ __forceinline__ bool any_in_range(const uint64_t *v, int64_t c0, int64_t c1) {
-    bool any = false;
-    for (int64_t wd = c0 >> 6; wd <= (c1 - 1) >> 6; ++wd) {
-        const int s = wd == (c0 >> 6) ? (int)(c0 & 63) : 0;
-        const int t = wd == ((c1 - 1) >> 6) ? (int)(((c1 - 1) & 63) + 1) : 64;
-        any |= (v[wd] & range_mask(s, t)) != 0;
-    }
-    return any;
-}
-
 template <bool LDS>
 __device__ __forceinline__ uint64_t vword(const StepParams &p, const lds_u32 *s_v, int64_t word) {
     if (LDS && word < p.lds_words) return ((const lds_u64 *)s_v)[word];

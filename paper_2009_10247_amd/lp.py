@@ -6,6 +6,13 @@ CPU fallback: if liblp.so is missing, loading raises.
 
 Streams may be given as None (default stream), an integer hipStream_t handle,
 or any object with a ``cuda_stream`` attribute (a torch.cuda.Stream).
+
+One HIP runtime per process: liblp.so needs libamdhip64.so.7, and PyTorch
+ships its own copy under the same soname. When torch is importable, load()
+imports it first, so the dynamic linker binds liblp.so to the runtime torch
+already mapped and torch's streams and memory are valid handles for the
+library; without torch, liblp.so brings the system runtime. load() raises if
+two HIP runtimes end up mapped.
 """
 from __future__ import annotations
 
@@ -115,14 +122,37 @@ class lp_server_stats(ctypes.Structure):
 _lib = None
 
 
+def hip_runtimes() -> list[str]:
+    """Paths of the HIP runtime libraries (libamdhip64) mapped in this process."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1] if line.count(" ") >= 5 else ""
+                if "libamdhip64.so" in os.path.basename(path):
+                    found.add(os.path.realpath(path))
+    except OSError:
+        pass
+    return sorted(found)
+
+
 def load():
-    """Load liblp.so (built by paper_2009_10247_amd.build); raise if absent."""
+    """Load liblp.so (built by paper_2009_10247_amd.build); raise if absent,
+    or if the process ends up with two HIP runtimes mapped."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2009_10247_amd.build`")
+    try:  # bind to torch's HIP runtime when torch is there (see the module docstring)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
+    rts = hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError("two HIP runtimes are mapped in this process (" + ", ".join(rts) +
+                          "); import torch before anything else loads a HIP runtime")
     P = ctypes.c_void_p
     i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     sig = {
@@ -482,6 +512,43 @@ def memory_stats() -> dict:
 
 def release_cached_memory():
     _check(load().lp_release_cached_memory())
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_hooks = None  # the installed callbacks, kept alive while the library may call them
+
+
+def set_allocator(alloc=None, release=None):
+    """lp_set_allocator with Python callables: alloc(bytes, stream) returns a
+    device pointer (int, 0 on failure), release(ptr, stream) frees it; stream
+    is the hipStream_t handle as an int (0: the null stream). No arguments:
+    the library's own pool again."""
+    global _hooks
+    if (alloc is None) != (release is None):
+        raise ValueError("alloc and release must both be given or both be None")
+    if alloc is None:
+        _check(load().lp_set_allocator(None, None, None))
+        _hooks = None
+        return
+    a = ALLOC_FN(lambda nbytes, stream, ctx: int(alloc(int(nbytes), int(stream or 0)) or 0))
+    r = RELEASE_FN(lambda ptr, stream, ctx: release(int(ptr), int(stream or 0)))
+    _check(load().lp_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(r, ctypes.c_void_p), None))
+    _hooks = (a, r)
+
+
+def torch_allocator():
+    """(alloc, release) over torch's caching allocator on the current device,
+    for set_allocator."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    def release(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, release
 
 
 class Server:

@@ -164,3 +164,27 @@ def test_host_only_matrix_refuses_solves():
 def test_empty_program_builds():
     with _host(gen.Program(0, np.zeros(0, np.int32), np.zeros(1, np.int64), np.zeros(0, np.int32))) as m:
         assert m.info["n_rows"] == 0 and m.info["nnz"] == 0
+
+
+def test_build_flags_leave_no_packed_fp32_in_device_code(tmp_path):
+    # the library is built with build.NO_PACKED_FP32; on a float2 kernel that
+    # hipcc -O3 otherwise compiles to v_pk_add_f32, the flags remove it
+    import subprocess
+
+    from paper_2009_10247_amd import build
+
+    src = tmp_path / "pk.hip"
+    src.write_text("#include <hip/hip_runtime.h>\n"
+                   "__global__ void k(float2 *a, const float2 *b, int n) {\n"
+                   "  int i = blockIdx.x * blockDim.x + threadIdx.x;\n"
+                   "  if (i < n) { float2 x = a[i], y = b[i]; x.x += y.x; x.y += y.y; a[i] = x; }\n}\n")
+
+    def device_asm(extra):
+        out = tmp_path / "pk.s"
+        subprocess.check_call([build.hipcc(), "-O3", f"--offload-arch={build.ARCH}", "--offload-device-only",
+                               "-S", *extra, "-o", str(out), str(src)], stderr=subprocess.DEVNULL)
+        return out.read_text()
+
+    assert "v_pk_add_f32" in device_asm([])
+    assert not re.search(r"v_pk_(add|mul|fma)_f32", device_asm(build.NO_PACKED_FP32))
+    assert all(f in build.command("x.so") for f in build.NO_PACKED_FP32)

@@ -215,18 +215,14 @@ def test_default_driver_concurrent_solves_of_one_matrix():
     # small programs take the one-workgroup LDS loop under the default driver;
     # its descriptor and result buffers are per call, so one matrix solved from
     # several threads on their own streams gives the oracle's result every time
-    import ctypes
     import threading
+
+    import torch
 
     progs = [gen.definite_uniform(40 + s, 1500 + 400 * s, 3000 + 800 * s, 0.03, 4) for s in range(3)]
     want = [oracle.sd_fixpoint(p)[:2] for p in progs]
     mats = [lp.Matrix(p) for p in progs]
-    hip = ctypes.CDLL("libamdhip64.so")  # the HIP runtime the library already loaded
-    streams = []
-    for _ in range(4):
-        h = ctypes.c_void_p()
-        assert hip.hipStreamCreate(ctypes.byref(h)) == 0
-        streams.append(h.value)
+    streams = [torch.cuda.Stream() for _ in range(4)]  # non-default streams of the one HIP runtime
     errors, done = [], []
 
     def worker(k):
@@ -250,8 +246,6 @@ def test_default_driver_concurrent_solves_of_one_matrix():
     finally:
         for m in mats:
             m.close()
-        for h in streams:
-            hip.hipStreamDestroy(ctypes.c_void_p(h))
 
 
 def test_batch_entry_point_equals_single_solves():

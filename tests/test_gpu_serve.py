@@ -112,3 +112,33 @@ def test_matrix_evict_and_upload_round_trip():
         assert np.array_equal(g, lm) and pr == wp
     st = lp.memory_stats()
     assert st["in_use"] >= 0 and st["cached"] >= 0
+
+
+def test_resident_bytes_count_the_transposed_matrix():
+    # stable programs of >= 2^19 row-words solve by dirty rows, whose
+    # transposed matrix is uploaded with the matrix: the server's accounted
+    # bytes must equal what the resident matrices really hold
+    pool = [gen.normal_uniform(80 + s, 10_000, 20_000, 5, k_neg=12, p_neg=0.1) for s in range(2)]
+    pool += [gen.definite_uniform(82, 50_000, 100_000, 0.02, 5), gen.normal_uniform(83, 300, 600, 4, k_neg=5)]
+    with lp.Server(n_slots=2) as srv:
+        pids = [srv.add_program(p) for p in pool]
+        ref = serve.solve_alone(srv, pids)
+        row = serve.run_stream(srv, pids, np.full(len(pids), 1.0 / len(pids)), rate=1e6, n_requests=40,
+                               seed=3, ref=ref)
+        assert row["mismatches"] == 0
+        st = srv.stats()
+    assert st["evictions"] == 0 and st["n_resident"] == len(pool)
+    want = 0
+    for p in pool:
+        with lp.Matrix(p) as m:
+            if m.info["n_neg"]:
+                upload_bytes = m.info["device_bytes"]
+                m.stable_models(max_models=1)
+                assert m._info()["device_bytes"] == upload_bytes  # nothing attached later
+            else:
+                m.least_model()
+            want += m._info()["device_bytes"]
+            if p.n_atoms == 10_000:  # dirty rows: the transposed matrix is part of the upload
+                with lp.Matrix(p, flags=lp.LP_STABLE_FULL_SWEEP) as full:
+                    assert full.info["device_bytes"] + 4 * m.info["nnz"] < upload_bytes
+    assert st["used_bytes"] == want

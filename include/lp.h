@@ -458,6 +458,28 @@ lp_status lp_tune_schedule(const lp_matrix *m, int32_t reps, lp_schedule *best, 
                            float *best_solve_ms, void *hip_stream);
 
 /*
+ * lp_least_model without device allocation, for callers that cannot call
+ * hipMalloc or take memory from a pool at solve time (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation). Same
+ * arguments, results and errors as lp_least_model with the default schedule
+ * (sched = NULL): the model (host, uint8[n_atoms]) and the product count.
+ * Every device buffer of the solve (interpretations, change counts, the
+ * one-workgroup loop's descriptor) is carved from a fixed region: a
+ * 4 MiB (4,194,304-byte) array in the library's device code, one copy per
+ * GPU, held from the first call on that GPU until the process ends. A solve
+ * needs 16 * ceil(N'/64) bytes plus about 2 KiB (N' = the matrix's rows, the
+ * lp_info field n_rows), so matrices up to about 16 million rows fit; a
+ * larger one returns LP_E_INVAL, with the sizes in lp_last_error, before any
+ * device work. The region keeps the last call's contents; each call clears
+ * what must start at zero. Calls on one GPU share the region, so calls that
+ * overlap in time on one GPU (other threads, other streams) race: the caller
+ * serializes them. The matrix itself is built and uploaded beforehand
+ * (lp_build_matrix), which allocates as usual; nothing is attached to it by
+ * this call.
+ */
+lp_status lp_least_model_noalloc(const lp_matrix *m, uint8_t *model, int32_t *products, void *hip_stream);
+
+/*
  * Route the library's device allocations through caller-supplied functions
  * (e.g. a framework's caching allocator). alloc(bytes, stream, ctx) returns a
  * device pointer or NULL; release(ptr, stream, ctx) frees it. Passing NULL for

@@ -64,6 +64,9 @@ struct StepShape {
 bool step_shape_supported(const StepShape &s);
 hipError_t launch_step(const StepShape &s, const StepParams &p, hipStream_t st);
 
+// Sets n 32-bit words at p to 0 (a kernel, not a memset node).
+hipError_t launch_zero_words(void *p, int64_t n, hipStream_t st);
+
 // Persistent form: the whole fixpoint loop in one cooperative launch.
 struct PersistParams {
     StepParams p;

@@ -183,13 +183,30 @@ static lp_status check_device_memory(double need, const char *what) {
     return LP_OK;
 }
 
-// RAII list of device buffers of one call.
+// Device buffers of one call: allocated from the pool (released, after the
+// stream has synchronized, when the call ends), or carved in 256-byte steps
+// from a fixed device region the caller owns (the no-allocation entry point).
 struct Scratch {
     hipStream_t st;
     std::vector<void *> ptrs;
+    uint8_t *region = nullptr;
+    size_t region_size = 0, region_used = 0;
     explicit Scratch(hipStream_t s) : st(s) {}
+    Scratch(hipStream_t s, void *fixed, size_t size) : st(s), region((uint8_t *)fixed), region_size(size) {}
+    bool may_alloc() const { return region == nullptr; }
     template <class T>
     lp_status get(T **p, size_t count) {
+        if (region) {
+            const size_t b = std::max<size_t>(256, (count * sizeof(T) + 255) & ~(size_t)255);
+            if (region_used + b > region_size) {
+                set_error("the solve needs more than the " + std::to_string(region_size) +
+                          " bytes of the fixed scratch region");
+                return LP_E_INVAL;
+            }
+            *p = (T *)(region + region_used);
+            region_used += b;
+            return LP_OK;
+        }
         void *q;
         lp_status rc = dev_alloc(&q, count * sizeof(T), st);
         if (rc) return rc;
@@ -381,6 +398,10 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
 static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
 static bool dirty_products(const Matrix &m, int32_t log2W);
 static int ilog2(int64_t x);
+static bool lds_loop_fits(const Matrix &m);
+static StepParams step_params(const Matrix &m);
+static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S, hipStream_t st,
+                           bool may_alloc = true);
 
 static lp_status upload_matrix(Matrix &m, hipStream_t st) {
     DeviceMatrix &d = m.dev;
@@ -407,6 +428,13 @@ static lp_status upload_matrix(Matrix &m, hipStream_t st) {
     if (m.K > 0 && m.K_eff <= LP_MAX_NEG_ATOMS &&
         dirty_products(m, ilog2((((int64_t)1 << m.K_eff) + 63) / 64)) && (rc = ensure_frontier(m, st)))
         return rc;
+    // the default driver's step split, so a solve with the default schedule
+    // (lp_least_model_noalloc in particular) attaches nothing
+    if (m.K == 0 && m.n_rows > 0 && !lds_loop_fits(m)) {
+        StepParams p = step_params(m);
+        StepShape S;
+        if ((rc = plan_step(m, nullptr, p, &S, st))) return rc;
+    }
     const int64_t vbytes = (m.n_rows + 7) / 8;
     if (m.K == 0) {
         m.info.step_bytes = d.stream_bytes + 2 * vbytes;
@@ -501,7 +529,8 @@ constexpr int64_t kSegCost = 1600;
 // wave gets about the same cost (AND entries + kWordCost per word of its
 // block pass, plus its OR tiles and segments), so the waves end together.
 // Created once per wave count and kept with the matrix's device arrays.
-static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, const int32_t **out) {
+static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, const int32_t **out,
+                                bool may_alloc = true) {
     std::lock_guard<std::mutex> lock(g_lazy_mu);
     const DeviceMatrix &d = m.dev;
     for (const auto &wp : d.wave_parts)
@@ -509,6 +538,10 @@ static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, 
             *out = wp.second;
             return LP_OK;
         }
+    if (!may_alloc) {
+        set_error("no step split for " + std::to_string(waves) + " waves was made at upload");
+        return LP_E_INTERNAL;
+    }
     const std::vector<int32_t> &b = d.word_base;
     if (b.empty() || waves < 1) {
         set_error("no least-model layout to split");
@@ -548,7 +581,8 @@ static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, 
 // Launch shape of the step for a whole solve. LDS shapes use one 1024-thread
 // workgroup per CU (the staged v takes most of the CU's LDS); global shapes
 // use 256-thread workgroups, eight per CU.
-static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S, hipStream_t st) {
+static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S, hipStream_t st,
+                           bool may_alloc) {
     int variant = sched ? sched->variant : LP_STEP_AUTO;
     if (variant == LP_STEP_AUTO) variant = LP_STEP_LDS;
     if (variant != LP_STEP_LDS && variant != LP_STEP_GLOBAL) {
@@ -588,7 +622,7 @@ static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams
     const int64_t grid = sched && sched->grid > 0 ? sched->grid : dflt;
     s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, want));
     *S = s;
-    return wave_partition(m, s.grid * waves, st, &p.wave_part);
+    return wave_partition(m, s.grid * waves, st, &p.wave_part, may_alloc);
 }
 
 // Shape of the persistent fixpoint: the LDS step with at most as many
@@ -645,15 +679,18 @@ static bool lds_loop_fits(const Matrix &m) {
 // *out holds the fixpoint's first ceil(n_atoms / 64) words only (the model),
 // not a whole interpretation of n_rows bits. With host_bits (nullable) those
 // words are also copied to the host, in the same copy as the product count.
+struct LdsLoopHead {
+    ProgDesc desc;
+    int32_t order, member;
+    uint32_t queue[2];
+    int32_t products, pad;
+};
+constexpr size_t kLdsLoopHead = (sizeof(LdsLoopHead) + 255) / 256 * 256;
+
 static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products,
                                   uint64_t *host_bits = nullptr) {
-    struct Head {
-        ProgDesc desc;
-        int32_t order, member;
-        uint32_t queue[2];
-        int32_t products, pad;
-    };
-    const size_t head = (sizeof(Head) + 255) / 256 * 256;
+    using Head = LdsLoopHead;
+    const size_t head = kLdsLoopHead;
     const int64_t Wa = std::max<int64_t>(1, n_words_of(m.n_atoms));
     uint8_t *blk;
     lp_status rc;
@@ -737,8 +774,13 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
     if ((rc = S.get(&buf[0], W)) || (rc = S.get(&buf[1], W)) || (rc = S.get(&counters, kRing)) ||
         (rc = S.get(&and_cnt, 2 * (size_t)m.dev.n_long_and)))
         return rc;
-    LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
-    if (m.dev.n_long_and) LP_HIP(hipMemsetAsync(and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
+    if (S.may_alloc()) {
+        LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
+        if (m.dev.n_long_and) LP_HIP(hipMemsetAsync(and_cnt, 0, sizeof(uint32_t) * 2 * m.dev.n_long_and, st));
+    } else {  // a fixed region keeps the last call's contents: clear with a kernel
+        LP_HIP(launch_zero_words(counters, 2 * (int64_t)kRing, st));
+        if (m.dev.n_long_and) LP_HIP(launch_zero_words(and_cnt, 2 * (int64_t)m.dev.n_long_and, st));
+    }
     LP_HIP(hipMemcpyAsync(buf[0], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
     LP_HIP(hipMemcpyAsync(buf[1], m.dev.fact_bits, W * 8, hipMemcpyDeviceToDevice, st));
     if (m.n_rows == 0) {
@@ -780,8 +822,9 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
         batch = (sched && sched->steps_per_sync > 0) ? sched->steps_per_sync : 32;
     }
     batch = std::max(1, std::min(batch, kRing / 2 - 1));
-    if ((rc = plan_step(m, sched, p, &L, st))) return rc;
-    unsigned long long *h = pinned_ring();
+    if ((rc = plan_step(m, sched, p, &L, st, S.may_alloc()))) return rc;
+    unsigned long long h_local[kRing];  // no pinned host allocation in a fixed-region call
+    unsigned long long *h = S.may_alloc() ? pinned_ring() : h_local;
     if (!h) {
         set_error("pinned host allocation failed");
         return LP_E_NOMEM;
@@ -974,8 +1017,7 @@ static void unpack_model(const uint64_t *bits, int32_t n, uint8_t *model) {
 }
 
 static lp_status least_model_impl(const Matrix &m, uint8_t *model, int32_t *products, const lp_schedule *sched,
-                                  hipStream_t st) {
-    Scratch S(st);
+                                  hipStream_t st, Scratch &S) {
     uint64_t *fix = nullptr;
     int32_t prods = 0;
     const int64_t Wn = n_words_of(m.n_atoms);
@@ -990,6 +1032,54 @@ static lp_status least_model_impl(const Matrix &m, uint8_t *model, int32_t *prod
     unpack_model(hb.data(), m.n_atoms, model);
     if (products) *products = prods;
     return LP_OK;
+}
+
+static lp_status least_model_impl(const Matrix &m, uint8_t *model, int32_t *products, const lp_schedule *sched,
+                                  hipStream_t st) {
+    Scratch S(st);
+    return least_model_impl(m, model, products, sched, st, S);
+}
+
+// ------------------------------------------------------------------ fixed scratch region
+
+// Device memory of lp_least_model_noalloc: every solve buffer of a call is
+// carved from this array, one copy per device, held until the process ends.
+// Host code uses the per-device address from hipGetSymbolAddress, never the
+// array's name (a host-side stand-in).
+constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+static lp_status scratch_region(int dev, void **out) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev < 0 || dev >= 64) {
+        set_error("device id out of range");
+        return LP_E_DEVICE;
+    }
+    if (!addr[dev]) {
+        void *p = nullptr;
+        LP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));  // the current device is dev
+        if (!p) {
+            set_error("hipGetSymbolAddress gave no address for the scratch region");
+            return LP_E_DEVICE;
+        }
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return LP_OK;
+}
+
+static size_t region_bytes(size_t b) { return std::max<size_t>(256, (b + 255) & ~(size_t)255); }
+
+// Bytes of the fixed region a default-driver solve of m takes (the same
+// buffers least_fixpoint and lds_loop_fixpoint carve, in 256-byte steps).
+static size_t noalloc_need(const Matrix &m) {
+    if (m.n_rows > 0 && lds_loop_fits(m))
+        return region_bytes(kLdsLoopHead + (size_t)std::max<int64_t>(1, n_words_of(m.n_atoms)) * 8);
+    const size_t W = (size_t)n_words_of(m.n_rows);
+    return 2 * region_bytes(W * 8) + region_bytes(sizeof(unsigned long long) * kRing) +
+           region_bytes(sizeof(uint32_t) * 2 * (size_t)m.dev.n_long_and);
 }
 
 static int ilog2(int64_t x) {
@@ -2373,6 +2463,32 @@ lp_status lp_least_model(const lp_matrix *m, uint8_t *model, int32_t *products, 
     }
     DeviceGuard g(m->m.dev.device);
     return least_model_impl(m->m, model, products, sched, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_least_model_noalloc(const lp_matrix *m, uint8_t *model, int32_t *products, void *hip_stream) {
+    LP_GUARD_BEGIN
+    lp_status rc = check_solvable(m);
+    if (rc) return rc;
+    if (m->m.K) {
+        set_error("the program has negative literals; the least model is defined for definite programs");
+        return LP_E_NEGATION;
+    }
+    if (!model && m->m.n_atoms) {
+        set_error("model must be non-NULL");
+        return LP_E_INVAL;
+    }
+    const size_t need = noalloc_need(m->m);
+    if (need > kNoAllocScratchBytes) {
+        set_error("the solve needs " + std::to_string(need) + " bytes of scratch; the no-allocation entry point "
+                  "holds " + std::to_string(kNoAllocScratchBytes) + " per device");
+        return LP_E_INVAL;
+    }
+    DeviceGuard g(m->m.dev.device);
+    void *region = nullptr;
+    if ((rc = scratch_region(m->m.dev.device, &region))) return rc;
+    Scratch S((hipStream_t)hip_stream, region, kNoAllocScratchBytes);
+    return least_model_impl(m->m, model, products, nullptr, (hipStream_t)hip_stream, S);
     LP_GUARD_END
 }
 

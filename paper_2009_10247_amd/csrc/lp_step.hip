@@ -776,4 +776,16 @@ hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, s.block, 0);
 }
 
+__global__ __launch_bounds__(256) void zero_words_kernel(uint32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero_words(void *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid), dim3(256), 0, st, (uint32_t *)p, n);
+    return hipGetLastError();
+}
+
 }  // namespace lp

@@ -60,7 +60,7 @@ EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg
            "lp_server_take_result", "lp_server_get_stats", "lp_server_free",
            "lp_memory_stats", "lp_release_cached_memory", "lp_bench_spmm",
            "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_dense_least_model",
-           "lp_dense_stable_models", "lp_last_error")
+           "lp_dense_stable_models", "lp_least_model_noalloc", "lp_last_error")
 
 
 class LPError(RuntimeError):
@@ -162,6 +162,7 @@ def load():
         "lp_matrix_neg_atoms": [P, P],
         "lp_matrix_csr": [P, P, P, P, P],
         "lp_least_model": [P, P, P, P, P],
+        "lp_least_model_noalloc": [P, P, P, P],
         "lp_stable_models": [P, P, P, P, i64, P, P, P],
         "lp_stable_models_guesses": [P, P, i64, P, ctypes.POINTER(i64), P, P, i64, P, P],
         "lp_stable_models_search": [P, i64, i32, ctypes.c_uint64, P, i64, ctypes.POINTER(i64), P, P],
@@ -314,6 +315,13 @@ class Matrix:
         _check(load().lp_least_model(self._h, model.ctypes.data, ctypes.addressof(prods),
                                      ctypes.byref(sched) if sched is not None else None,
                                      _stream(stream)))
+        return model[: self.n_atoms], prods.value
+
+    def least_model_noalloc(self, stream=None):
+        """(model uint8[n_atoms], products) by lp_least_model_noalloc (no device allocation)."""
+        model = np.zeros(max(self.n_atoms, 1), dtype=np.uint8)
+        prods = ctypes.c_int32(0)
+        _check(load().lp_least_model_noalloc(self._h, model.ctypes.data, ctypes.addressof(prods), _stream(stream)))
         return model[: self.n_atoms], prods.value
 
     def stable_models(self, max_models: int = 1024, want_models: bool = True,

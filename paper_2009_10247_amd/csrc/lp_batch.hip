@@ -45,7 +45,14 @@ __device__ __forceinline__ gp<T> as_global(const T *p) {
     return (gp<T>)p;
 }
 
-struct GProg {
+// A program's layout as the evaluation reads it: in global memory (AS = 1),
+// or copied into the workgroup's LDS (AS = 3; see LdsLayout). Only the
+// fields of WordMeta the workgroup loop reads are kept in the LDS form.
+template <int AS>
+struct Prog;
+
+template <>
+struct Prog<1> {
     gp<WordMeta> words;
     gp<uint8_t> and_len;
     gp<int32_t> col;
@@ -54,7 +61,85 @@ struct GProg {
     gp<LongSeg> segs;
     gp<int32_t> long_col;
     int32_t n_rows, n_or, n_segs, and_end;
+    __device__ __forceinline__ int32_t and_base(int64_t w) const { return words[w].and_base; }
+    __device__ __forceinline__ uint64_t and_bits(int64_t w) const { return words[w].and_bits; }
 };
+
+typedef __attribute__((address_space(3))) LongSeg lds_seg;
+
+template <>
+struct Prog<3> {
+    const lds_u64 *andb;
+    const lds_i32 *base;
+    const lds_u8 *and_len;
+    const lds_i32 *col;
+    const lds_i32 *or_c0;
+    const lds_i32 *or_row;
+    const lds_seg *segs;
+    const lds_i32 *long_col;
+    int32_t n_rows, n_or, n_segs, and_end;
+    __device__ __forceinline__ int32_t and_base(int64_t w) const { return base[w]; }
+    __device__ __forceinline__ uint64_t and_bits(int64_t w) const { return andb[w]; }
+};
+
+typedef Prog<1> GProg;
+
+// Copies the layout of g into LDS at `dst` (offsets from lds_layout) with the
+// whole workgroup; the caller synchronizes afterwards. The AND entries and
+// lengths move in 16-byte pieces (their global arrays are padded past the
+// ranges read), the small arrays in 4-byte pieces.
+__device__ __forceinline__ Prog<3> copy_layout_to_lds(const GProg &g, int32_t long_nnz, const LdsLayout &L,
+                                                      lds_u8 *dst) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
+    const int32_t n_words = (g.n_rows + 63) >> 6;
+    lds_u64 *andb = (lds_u64 *)(dst + L.andb);
+    lds_i32 *base = (lds_i32 *)(dst + L.base);
+    for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
+        andb[i] = g.words[i].and_bits;
+        base[i] = g.words[i].and_base;
+    }
+    {
+        const gp<u32x4> src = (gp<u32x4>)(const void *)g.and_len;
+        lds_u32x4 *d = (lds_u32x4 *)(dst + L.len);
+        for (int32_t i = threadIdx.x; i < (g.n_rows + 15) / 16; i += blockDim.x) d[i] = src[i];
+    }
+    {
+        // the global array holds and_end entries and 64 * 16 zeros
+        const int32_t n = g.and_end + 64 * 16, n4 = n / 4;
+        const gp<u32x4> src = (gp<u32x4>)(const void *)g.col;
+        lds_u32x4 *d = (lds_u32x4 *)(dst + L.col);
+        for (int32_t i = threadIdx.x; i < n4; i += blockDim.x) d[i] = src[i];
+        lds_i32 *dc = (lds_i32 *)(dst + L.col);
+        for (int32_t i = 4 * n4 + (int32_t)threadIdx.x; i < n; i += blockDim.x) dc[i] = g.col[i];
+    }
+    lds_i32 *or_c0 = (lds_i32 *)(dst + L.or_c0);
+    lds_i32 *or_row = (lds_i32 *)(dst + L.or_row);
+    for (int32_t i = threadIdx.x; i <= g.n_or; i += blockDim.x) or_c0[i] = g.or_c0[i];
+    for (int32_t i = threadIdx.x; i < g.n_or; i += blockDim.x) or_row[i] = g.or_row[i];
+    {
+        const gp<uint32_t> src = (gp<uint32_t>)(const void *)g.segs;
+        lds_u32 *d = (lds_u32 *)(dst + L.segs);
+        const int32_t n = g.n_segs * (int32_t)(sizeof(LongSeg) / 4);
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
+    }
+    lds_i32 *long_col = (lds_i32 *)(dst + L.long_col);
+    for (int32_t i = threadIdx.x; i < long_nnz; i += blockDim.x) long_col[i] = g.long_col[i];
+    Prog<3> p;
+    p.andb = andb;
+    p.base = base;
+    p.and_len = dst + L.len;
+    p.col = (const lds_i32 *)(dst + L.col);
+    p.or_c0 = or_c0;
+    p.or_row = or_row;
+    p.segs = (const lds_seg *)(dst + L.segs);
+    p.long_col = long_col;
+    p.n_rows = g.n_rows;
+    p.n_or = g.n_or;
+    p.n_segs = g.n_segs;
+    p.and_end = g.and_end;
+    return p;
+}
 
 __device__ __forceinline__ bool lds_any_in_range(const lds_u64 *v, int64_t c0, int64_t c1) {
     bool any = false;
@@ -80,8 +165,8 @@ struct WgSuperBlock {
     uint64_t andb[WPW];
 };
 
-template <int WPW>
-__device__ __forceinline__ void wg_load_super_block(const GProg &d, int64_t sb, int64_t n_words,
+template <int WPW, class P>
+__device__ __forceinline__ void wg_load_super_block(const P &d, int64_t sb, int64_t n_words,
                                                     WgSuperBlock<WPW> &m) {
     const int lane = threadIdx.x & 63;
     const int64_t w0 = sb * WPW;
@@ -90,8 +175,8 @@ __device__ __forceinline__ void wg_load_super_block(const GProg &d, int64_t sb, 
         const int64_t r = (w0 + w) * 64 + lane;
         m.len[w] = r < d.n_rows ? (int32_t)d.and_len[r] : 0;
         if (w0 + w < n_words) {
-            m.base[w] = d.words[w0 + w].and_base;
-            m.andb[w] = d.words[w0 + w].and_bits;
+            m.base[w] = d.and_base(w0 + w);
+            m.andb[w] = d.and_bits(w0 + w);
         } else {
             m.base[w] = d.and_end;
             m.andb[w] = 0;
@@ -101,8 +186,8 @@ __device__ __forceinline__ void wg_load_super_block(const GProg &d, int64_t sb, 
 
 // AND rows of the block pass (see BlockPass in lp_step.hip).
 // Member `member` of a team of `team` workgroups takes every team-th share.
-template <int WPW, int U>
-__device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 *v, lds_u64 *u,
+template <int WPW, int U, class P>
+__device__ __forceinline__ uint32_t wg_block_rows(const P &d, const lds_u64 *v, lds_u64 *u,
                                                   lds_u64 *s_ball, int32_t member, int32_t team) {
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
@@ -115,11 +200,11 @@ __device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 
     int64_t sb = (int64_t)member * waves + (threadIdx.x >> 6);
     if (sb >= n_sb) return 0;
     WgSuperBlock<WPW> cur;
-    wg_load_super_block<WPW>(d, sb, n_words, cur);
+    wg_load_super_block<WPW, P>(d, sb, n_words, cur);
     for (; sb < n_sb; sb += stride) {
         WgSuperBlock<WPW> nxt;
         const bool more = sb + stride < n_sb;
-        if (more) wg_load_super_block<WPW>(d, sb + stride, n_words, nxt);
+        if (more) wg_load_super_block<WPW, P>(d, sb + stride, n_words, nxt);
         const int64_t w0 = sb * WPW;
         bool acc[WPW];
         int32_t st[WPW], en[WPW];
@@ -132,7 +217,7 @@ __device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 
         const int32_t e0 = __builtin_amdgcn_readfirstlane(cur.base[0]);
         const int32_t e1 = __builtin_amdgcn_readlane(en[WPW - 1], 63);
         for (int32_t base = e0 & ~63; base < e1; base += 64 * U) {
-            const gp<int32_t> cb = d.col + base;
+            const auto cb = d.col + base;
             int32_t c[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) c[k] = cb[64 * k + lane];
@@ -176,7 +261,8 @@ __device__ __forceinline__ uint32_t wg_block_rows(const GProg &d, const lds_u64 
 
 // OR rows (one lane each) and long rows (one wave per OR segment, one wave per
 // whole long AND row, looping over its segments).
-__device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const lds_u64 *v, lds_u64 *u,
+template <class P>
+__device__ __forceinline__ uint32_t wg_or_and_long_rows(const P &d, const lds_u64 *v, lds_u64 *u,
                                                         int32_t member, int32_t team) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -188,7 +274,7 @@ __device__ __forceinline__ uint32_t wg_or_and_long_rows(const GProg &d, const ld
         if (row >= 0 && lds_any_in_range(v, d.or_c0[j], d.or_c0[j + 1])) my_new += lds_set_bit(u, v, row);
     }
     for (int64_t si = (int64_t)member * waves + wave; si < d.n_segs; si += (int64_t)team * waves) {
-        const gp<LongSeg> sg = d.segs + si;
+        const auto sg = d.segs + si;
         bool fire = false;
         if (!sg->is_and) {
             bool any = false;
@@ -248,11 +334,39 @@ __device__ __forceinline__ bool team_barrier(uint32_t *count, uint32_t target, u
     return *s_flag != 0;
 }
 
+// Algorithm 1 on one program by this workgroup alone: cur holds v_t and nxt
+// v_{t-1} (both start at the facts). Returns the product count (-1 past the
+// n_rows + 1 bound) and leaves the fixpoint in *fix.
+template <int WPW, int U, class P>
+__device__ __forceinline__ int32_t solve_alone(const P &d, lds_u64 *cur, lds_u64 *nxt, lds_u64 *my_ball,
+                                               uint32_t *s_new, lds_u64 **fix) {
+    int32_t step = 1, slot = 1;  // slot = step mod 3
+    uint32_t changed = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
+        uint32_t my_new = wg_or_and_long_rows<P>(d, cur, nxt, 0, 1);
+        my_new += wg_block_rows<WPW, U, P>(d, cur, nxt, my_ball, 0, 1);
+        my_new = wave_sum(my_new);
+        if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
+        __syncthreads();
+        changed = s_new[slot];
+        if (changed == 0 || step > d.n_rows) break;
+        lds_u64 *t = cur;
+        cur = nxt;
+        nxt = t;
+        ++step;
+        slot = slot == 2 ? 0 : slot + 1;
+    }
+    // nxt holds the last product, equal to cur at the fixpoint
+    *fix = nxt;
+    return changed == 0 ? step : -1;
+}
+
 }  // namespace
 
 template <int WPW, int U>
 __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
-    extern __shared__ uint64_t s_dyn[];
+    extern __shared__ __attribute__((aligned(16))) uint64_t s_dyn[];
     __shared__ uint64_t s_ball[kMaxWaves * (U + 1)];
     // New-bit counts by product index mod 3: the slot of product t+1 is
     // cleared during product t, after every wave has read it for product t-2,
@@ -264,13 +378,13 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     lds_u64 *buf1 = buf0 + b.lds_words;
     lds_u64 *my_ball = (lds_u64 *)s_ball + (threadIdx.x >> 6) * (U + 1);
     if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&b.queue[0], 1u);
+    for (int32_t round = 0;; ++round) {
+        if (threadIdx.x == 0) s_item = b.single ? round : (int32_t)atomicAdd(&b.queue[0], 1u);
         if (threadIdx.x < 3) s_new[threadIdx.x] = 0;
         __syncthreads();
         const int32_t item = s_item;
         if (item >= b.n_items) break;
-        const ProgDesc pd = b.progs[b.order[item]];
+        const ProgDesc pd = b.single ? b.one : b.progs[b.order[item]];
         const int32_t team = pd.team_size;
         const int32_t member = team > 1 ? b.member[item] : 0;
         GProg d;
@@ -300,24 +414,18 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
         typedef __attribute__((address_space(1))) int32_t g_i32;
         int32_t result;
         if (team == 1) {
-            for (;;) {
-                if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
-                uint32_t my_new = wg_or_and_long_rows(d, cur, nxt, 0, 1);
-                my_new += wg_block_rows<WPW, U>(d, cur, nxt, my_ball, 0, 1);
-                my_new = wave_sum(my_new);
-                if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
+            // a layout that fits beside the buffers is copied into LDS once, so
+            // no product reads global memory
+            const LdsLayout L = lds_layout(d.n_rows, d.and_end, d.n_or, d.n_segs, pd.long_nnz);
+            lds_u64 *fix;
+            if (L.end <= (int64_t)b.lds_layout_bytes) {
+                const Prog<3> dl = copy_layout_to_lds(d, pd.long_nnz, L, (lds_u8 *)(buf1 + b.lds_words));
                 __syncthreads();
-                changed = s_new[slot];
-                if (changed == 0 || step > d.n_rows) break;
-                lds_u64 *t = cur;
-                cur = nxt;
-                nxt = t;
-                ++step;
-                slot = slot == 2 ? 0 : slot + 1;
+                result = solve_alone<WPW, U, Prog<3>>(dl, cur, nxt, my_ball, s_new, &fix);
+            } else {
+                result = solve_alone<WPW, U, GProg>(d, cur, nxt, my_ball, s_new, &fix);
             }
-            result = changed == 0 ? step : -1;
-            // nxt holds the last product, equal to cur at the fixpoint
-            cur = nxt;
+            cur = fix;
         } else {
             uint32_t *T = pd.team;  // [0] arrivals, [1] abort, [2 + t mod 3] new bits of product t
             // member 0 starts both exchange buffers at the facts (subsets of
@@ -380,7 +488,7 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     }
     // The last workgroup to finish rewinds the queue and clears the team
     // states for the next launch (every other workgroup has left by then).
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !b.single) {
         __threadfence();
         if (atomicAdd(&b.queue[1], 1u) == gridDim.x - 1) {
             for (int32_t t = 0; t < b.n_teams; ++t)

@@ -16,6 +16,7 @@ constexpr int kMaxWaves = 16;  // waves of a 1024-thread workgroup
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(3))) int32_t lds_i32;
 
 // AND entries are stored encoded as ((c >> 5) << 7) | (c & 31): one shift
 // gives the byte address of the 32-bit word of v holding atom c (a multiple

@@ -101,7 +101,43 @@ struct ProgDesc {
     int32_t n_segs;
     int32_t and_end;
     int32_t team_size;       // workgroups that solve this program together (1: one workgroup alone)
+    int32_t long_nnz;        // entries of long_col
+    int32_t pad;
 };
+
+// A program's layout copied into LDS after the two interpretation buffers
+// (tp_batch_kernel, programs solved by one workgroup): byte offsets of the
+// AND bitmask and first AND entry of every word, the AND lengths, the AND
+// entries (with 64 * 16 entries of the zero padding, which chunk loads read
+// past the last entry), the OR child ranges and rows, the long-row segments
+// and their entries; `end` is the total. Every array starts 16-byte aligned.
+struct LdsLayout {
+    int64_t andb, base, len, col, or_c0, or_row, segs, long_col, end;
+};
+__host__ __device__ inline LdsLayout lds_layout(int64_t n_rows, int64_t and_end, int64_t n_or, int64_t n_segs,
+                                                int64_t long_nnz) {
+    const int64_t n_words = (n_rows + 63) >> 6;
+    LdsLayout L;
+    int64_t o = 0;
+    L.andb = o;
+    o += 8 * n_words;
+    L.base = o;
+    o = (o + 4 * n_words + 15) & ~(int64_t)15;
+    L.len = o;
+    o = (o + n_rows + 15) & ~(int64_t)15;
+    L.col = o;
+    o += 4 * (((and_end + 64 * 16) + 3) & ~(int64_t)3);
+    L.or_c0 = o;
+    o = (o + 4 * (n_or + 1) + 15) & ~(int64_t)15;
+    L.or_row = o;
+    o = (o + 4 * n_or + 15) & ~(int64_t)15;
+    L.segs = o;
+    o += (int64_t)sizeof(LongSeg) * n_segs;
+    L.long_col = o;
+    o = (o + 4 * long_nnz + 15) & ~(int64_t)15;
+    L.end = o;
+    return L;
+}
 // Team state: [0] barrier arrivals, [1] abort flag, [2..4] new-bit counts by
 // product index mod 3; one 128-byte line per team. Zero between launches.
 constexpr int kTeamStateWords = 32;
@@ -116,6 +152,9 @@ struct BatchParams {
     int32_t n_teams;
     int32_t lds_words;       // words of each of the two LDS buffers
     uint32_t team_polls;     // polls after which a team barrier gives up
+    int32_t lds_layout_bytes;// dynamic LDS after the two buffers for a program's layout (0: none)
+    int32_t single;          // 1: one program, described by `one` (no queue, grid of one workgroup)
+    ProgDesc one;
 };
 bool batch_shape_supported(int wpw, int unroll);
 hipError_t launch_batch(int wpw, int unroll, int grid, int block, size_t lds_bytes, const BatchParams &b,
@@ -149,16 +188,16 @@ struct DirtyParams {
     const int32_t *occ_ptr;      // transposed matrix: rows naming each row
     const int32_t *occ;
     const uint64_t *V;           // v_{t-1}
-    uint64_t *U;                 // result of product t (holds v_{t-1} outside D_t's rows on entry)
-    uint64_t *next;              // the buffer product t+1 writes (holds v_{t-1})
+    uint64_t *U;                 // result of product t (holds v_{t-2} on entry)
     const int32_t *dirty;        // D_t
+    const int32_t *changed_prev; // C_{t-1}
     int32_t *changed_out;        // C_t
     int32_t *dirty_out;          // D_{t+1}
     int32_t *cmark;              // [n_rows] last product a row was appended to C
-    int32_t *dmark;              // [n_rows] last product a row was appended to D
-    uint32_t *n_changed;         // [kDirtyRing]
-    uint32_t *n_dirty;           // [kDirtyRing]
-    int32_t *hist;               // [kDirtyHist]
+    const int32_t *dmark_cur;    // [n_rows] t on the rows of D_t (not written during product t)
+    int32_t *dmark;              // [n_rows] t + 1 on the rows appended to D_{t+1}
+    uint32_t *n_dirty;           // [kDirtyRing] |D_t| by t mod kDirtyRing
+    int32_t *hist;               // [kDirtyHist] |C_t| by t mod kDirtyHist
     const uint64_t *fact_bits;   // fact rows (constant, like the qbar rows from n_std on)
     int32_t n_rows;
     int32_t n_std;

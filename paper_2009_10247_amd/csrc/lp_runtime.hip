@@ -231,6 +231,31 @@ static unsigned long long *pinned_ring() {
     return p;
 }
 
+// Pinned host staging of at least `bytes` per thread (grown on demand), for
+// device-to-host copies that end a solve; nullptr if it cannot be allocated.
+// Like the change-count ring, it is never freed at thread exit (the HIP
+// runtime may already be gone by then).
+static void *pinned_stage(size_t bytes) {
+    struct Stage {
+        void *p = nullptr;
+        size_t size = 0;
+    };
+    static thread_local Stage s;
+    if (s.size < bytes) {
+        if (s.p) (void)hipHostFree(s.p);
+        s.p = nullptr;
+        s.size = 0;
+        const size_t want = std::max<size_t>(bytes, 64 << 10);
+        if (hipHostMalloc(&s.p, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s.p = nullptr;
+            return nullptr;
+        }
+        s.size = want;
+    }
+    return s.p;
+}
+
 // ------------------------------------------------------------------ upload
 
 static int64_t n_words_of(int64_t rows) { return (rows + 63) / 64; }
@@ -679,63 +704,76 @@ static bool lds_loop_fits(const Matrix &m) {
 // *out holds the fixpoint's first ceil(n_atoms / 64) words only (the model),
 // not a whole interpretation of n_rows bits. With host_bits (nullable) those
 // words are also copied to the host, in the same copy as the product count.
-struct LdsLoopHead {
-    ProgDesc desc;
-    int32_t order, member;
-    uint32_t queue[2];
-    int32_t products, pad;
-};
-constexpr size_t kLdsLoopHead = (sizeof(LdsLoopHead) + 255) / 256 * 256;
+// Device memory of a one-workgroup solve: the product count, then the
+// model's words (the descriptor travels in the kernel arguments).
+constexpr size_t kLdsLoopHead = 256;
+
+// Descriptor of m for the batch kernel (outputs not set).
+static ProgDesc prog_desc(const Matrix &m) {
+    const DeviceMatrix &dm = m.dev;
+    ProgDesc g{};
+    g.words = dm.words;
+    g.and_len = dm.and_len;
+    g.col = dm.col;
+    g.or_c0 = dm.or_c0;
+    g.or_row = dm.or_row;
+    g.segs = dm.segs;
+    g.long_col = dm.long_col;
+    g.fact_bits = dm.fact_bits;
+    g.n_rows = m.n_rows;
+    g.n_atoms = m.n_atoms;
+    g.n_or = dm.n_or;
+    g.n_segs = dm.n_segs;
+    g.and_end = (int32_t)dm.and_nnz;
+    g.team_size = 1;
+    g.long_nnz = (int32_t)dm.long_nnz;
+    return g;
+}
+
+// LDS bytes of m's layout in the batch kernel's LDS form.
+static int64_t layout_lds_bytes(const Matrix &m) {
+    return lds_layout(m.n_rows, m.dev.and_nnz, m.dev.n_or, m.dev.n_segs, m.dev.long_nnz).end;
+}
 
 static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, uint64_t **out, int32_t *products,
                                   uint64_t *host_bits = nullptr) {
-    using Head = LdsLoopHead;
     const size_t head = kLdsLoopHead;
     const int64_t Wa = std::max<int64_t>(1, n_words_of(m.n_atoms));
     uint8_t *blk;
     lp_status rc;
     if ((rc = S.get(&blk, head + (size_t)Wa * 8))) return rc;
-    Head *dh = reinterpret_cast<Head *>(blk);
+    int32_t *d_prods = reinterpret_cast<int32_t *>(blk);
     uint64_t *bits = reinterpret_cast<uint64_t *>(blk + head);
-    const DeviceMatrix &dm = m.dev;
-    Head h{};
-    h.desc.words = dm.words;
-    h.desc.and_len = dm.and_len;
-    h.desc.col = dm.col;
-    h.desc.or_c0 = dm.or_c0;
-    h.desc.or_row = dm.or_row;
-    h.desc.segs = dm.segs;
-    h.desc.long_col = dm.long_col;
-    h.desc.fact_bits = dm.fact_bits;
-    h.desc.out_bits = bits;
-    h.desc.out_products = &dh->products;
-    h.desc.n_rows = m.n_rows;
-    h.desc.n_atoms = m.n_atoms;
-    h.desc.n_or = dm.n_or;
-    h.desc.n_segs = dm.n_segs;
-    h.desc.and_end = (int32_t)dm.and_nnz;
-    h.desc.team_size = 1;
-    LP_HIP(hipMemcpyAsync(dh, &h, sizeof(Head), hipMemcpyHostToDevice, st));
+    DevProps dp;
+    if ((rc = dev_props(m.dev.device, &dp))) return rc;
     BatchParams q{};
-    q.progs = &dh->desc;
-    q.order = &dh->order;
-    q.member = &dh->member;
-    q.queue = dh->queue;
+    q.single = 1;
+    q.one = prog_desc(m);
+    q.one.out_bits = bits;
+    q.one.out_products = d_prods;
     q.n_items = 1;
     q.lds_words = (int32_t)n_words_of(m.n_rows);
-    LP_HIP(launch_batch(2, 8, 1, 1024, (size_t)q.lds_words * 16, q, st));
+    // the layout goes into LDS beside the two buffers when both fit
+    const int64_t v_bytes = (int64_t)q.lds_words * 16, lay = layout_lds_bytes(m);
+    if (v_bytes + lay <= (int64_t)dp.max_lds - 4096) q.lds_layout_bytes = (int32_t)lay;
+    LP_HIP(launch_batch(2, 8, 1, 1024, (size_t)(v_bytes + q.lds_layout_bytes), q, st));
     int32_t prods = 0;
     if (host_bits) {
-        // the product count and the model bits in one copy: [products .. last word of bits]
-        const size_t lead = head - offsetof(Head, products);
-        std::vector<uint8_t> stage(lead + (size_t)Wa * 8);
-        LP_HIP(hipMemcpyAsync(stage.data(), &dh->products, stage.size(), hipMemcpyDeviceToHost, st));
-        LP_HIP(hipStreamSynchronize(st));  // also ends the host copy of h
-        std::memcpy(&prods, stage.data(), sizeof(int32_t));
-        std::memcpy(host_bits, stage.data() + lead, (size_t)n_words_of(m.n_atoms) * 8);
+        // the product count and the model bits in one copy: [products, pad .. last word of bits]
+        const size_t n = head + (size_t)n_words_of(m.n_atoms) * 8;
+        uint8_t *stage = reinterpret_cast<uint8_t *>(S.may_alloc() ? pinned_stage(n) : nullptr);
+        std::vector<uint8_t> local;
+        if (!stage) {
+            local.resize(n);
+            stage = local.data();
+        }
+        LP_HIP(hipMemcpyAsync(stage, blk, n, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        std::memcpy(&prods, stage, sizeof(int32_t));
+        std::memcpy(host_bits, stage + head, (size_t)n_words_of(m.n_atoms) * 8);
     } else {
-        LP_HIP(hipMemcpyAsync(&prods, &dh->products, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        LP_HIP(hipStreamSynchronize(st));  // also ends the host copy of h
+        LP_HIP(hipMemcpyAsync(&prods, d_prods, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
     }
     if (prods < 1) {
         set_error("fixpoint not reached within n_rows+1 products");
@@ -1143,39 +1181,44 @@ static lp_status stable_fixpoint(const Matrix &m, hipStream_t st, uint64_t *cons
 static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
 
 
-// Products of Algorithm 2 by dirty rows (spmm_dirty_eval_kernel): product t
-// evaluates only the rows naming a row that changed in product t-1 (product 1:
-// a fact or qbar row, the rows the initial matrix in both buffers does not
-// hold at 0); the same products and fixpoint as the full sweep. Products are issued eight at a time
-// between host reads of |C_t|.
+// Products of Algorithm 2 by dirty rows (spmm_dirty_product_kernel, one
+// launch per product): product t evaluates only the rows naming a row that
+// changed in product t-1 (product 1: a fact or qbar row, the rows the initial
+// matrix in both buffers does not hold at 0); the same products and fixpoint
+// as the full sweep. Products are issued kFirstBatch, then kLaterBatch, at a
+// time between host reads of |C_t|; products issued past the fixpoint return
+// at once.
 static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStream_t st, uint64_t *const buf[2],
                                    int32_t *products, uint64_t **fix) {
+    constexpr int kFirstBatch = 16, kLaterBatch = 8;
+    static_assert(kFirstBatch < kDirtyHist / 2 && kLaterBatch < kDirtyHist / 2, "history slots");
+    static_assert(kDirtyHist * sizeof(int32_t) <= kRing * sizeof(unsigned long long), "pinned ring");
     lp_status rc;
     if ((rc = ensure_frontier(m, st))) return rc;
     const int32_t n = std::max(m.n_rows, 1);
     Scratch S(st);
-    int32_t *dirty, *changed, *marks, *hist;
-    if ((rc = S.get(&dirty, n)) || (rc = S.get(&changed, n)) || (rc = S.get(&hist, kDirtyHist)) ||
-        (rc = S.get(&marks, 2 * (int64_t)n + 2 * kDirtyRing)))
+    int32_t *dl[2], *cl[2], *marks;
+    if ((rc = S.get(&dl[0], n)) || (rc = S.get(&dl[1], n)) || (rc = S.get(&cl[0], n)) || (rc = S.get(&cl[1], n)) ||
+        (rc = S.get(&marks, 3 * (int64_t)n + kDirtyRing + kDirtyHist)))
         return rc;
-    // the two row marks and the size rings, cleared together
-    int32_t *cmark = marks, *dmark = marks + n;
-    uint32_t *ring = reinterpret_cast<uint32_t *>(marks + 2 * (int64_t)n);
-    LP_HIP(hipMemsetAsync(marks, 0, sizeof(int32_t) * (2 * (size_t)n + 2 * kDirtyRing), st));
-    std::vector<int32_t> hh(kDirtyHist);
+    // the row marks, the |D_t| ring and the |C_t| history, cleared together
+    int32_t *cmark = marks, *dm[2] = {marks + n, marks + 2 * (int64_t)n};
+    uint32_t *ring = reinterpret_cast<uint32_t *>(marks + 3 * (int64_t)n);
+    int32_t *hist = marks + 3 * (int64_t)n + kDirtyRing;
+    LP_HIP(hipMemsetAsync(marks, 0, sizeof(int32_t) * (3 * (size_t)n + kDirtyRing + kDirtyHist), st));
+    int32_t *hh = reinterpret_cast<int32_t *>(pinned_ring());
+    if (!hh) {
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
     DirtyParams p{};
     p.row_ptr = sp.row_ptr;
     p.col = sp.col;
     p.and_bits = sp.and_bits;
     p.occ_ptr = m.dev.fr_ptr;
     p.occ = m.dev.fr_occ;
-    p.dirty = dirty;
-    p.changed_out = changed;
-    p.dirty_out = dirty;
     p.cmark = cmark;
-    p.dmark = dmark;
-    p.n_changed = ring;
-    p.n_dirty = ring + kDirtyRing;
+    p.n_dirty = ring;
     p.hist = hist;
     p.fact_bits = m.dev.fact_bits;
     p.n_rows = m.n_rows;
@@ -1185,18 +1228,25 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
     // later ones are small, and a launch of eight workgroups per CU that mostly
     // exit costs dispatch time
     const int grid = spmm_grid(m), grid_small = std::max(1, grid / 4);
+    p.dmark = dm[1];
+    p.dirty_out = dl[1];
     LP_HIP(launch_dirty_seed(p, m.dev.fr_facts, m.dev.fr_n_facts, grid_small, st));
-    const int batch = 8;
     const int64_t limit = (int64_t)m.n_rows + 1;
-    for (int64_t t0 = 1;; t0 += batch) {
+    for (int64_t t0 = 1;;) {
+        const int64_t batch = t0 == 1 ? kFirstBatch : kLaterBatch;
         for (int64_t t = t0; t < t0 + batch; ++t) {
             p.step = (int32_t)t;
             p.V = buf[(t - 1) & 1];
             p.U = buf[t & 1];
-            p.next = buf[(t + 1) & 1];
+            p.dirty = dl[t & 1];
+            p.dirty_out = dl[(t + 1) & 1];
+            p.changed_prev = cl[(t - 1) & 1];
+            p.changed_out = cl[t & 1];
+            p.dmark_cur = dm[t & 1];
+            p.dmark = dm[(t + 1) & 1];
             LP_HIP(launch_dirty_product(p, t == 1 ? grid : grid_small, st));
         }
-        LP_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * kDirtyHist, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipMemcpyAsync(hh, hist, sizeof(int32_t) * kDirtyHist, hipMemcpyDeviceToHost, st));
         LP_HIP(hipStreamSynchronize(st));
         for (int64_t t = t0; t < t0 + batch; ++t) {
             if (hh[t & (kDirtyHist - 1)] == 0) {
@@ -1205,7 +1255,8 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
                 return LP_OK;
             }
         }
-        if (t0 + batch > limit) {
+        t0 += batch;
+        if (t0 > limit) {
             set_error("fixpoint not reached within n_rows+1 products");
             return LP_E_INTERNAL;
         }
@@ -1783,8 +1834,9 @@ static void batch_release(BatchPlan &b) {
     b.d_prod = nullptr;
 }
 
-static BatchParams batch_params(const BatchPlan &b) {
+static BatchParams batch_params(const BatchPlan &b, const BatchShape &s) {
     BatchParams q{};
+    q.lds_layout_bytes = (int32_t)std::max<int64_t>(0, (int64_t)s.lds_bytes - (int64_t)b.lds_words * 16);
     q.progs = b.d_progs;
     q.order = b.d_order;
     q.member = b.d_member;
@@ -1814,6 +1866,20 @@ static lp_status batch_fit_shape(const BatchPlan &b, BatchShape *s) {
         set_error("the batch kernel does not fit on this device");
         return LP_E_DEVICE;
     }
+    // LDS the resident workgroups leave unused holds the layouts of programs
+    // small enough to be copied in: the largest extension that keeps as many
+    // workgroups per CU
+    for (size_t extra : {(size_t)128 << 10, (size_t)96 << 10, (size_t)64 << 10, (size_t)48 << 10,
+                         (size_t)32 << 10, (size_t)16 << 10}) {
+        const size_t want = s->lds_bytes + extra;
+        if (want > (size_t)d.max_lds - 4096) continue;
+        int pc = 0;
+        if (batch_occupancy(s->wpw, s->unroll, s->block, want, &pc) == hipSuccess && pc >= per_cu) {
+            s->lds_bytes = want;
+            break;
+        }
+        (void)hipGetLastError();
+    }
     const int64_t resident = (int64_t)per_cu * d.n_cu;
     const int64_t want = s->grid > 0 ? s->grid : resident;
     s->grid = (int)std::max<int64_t>(1, std::min<int64_t>({want, resident, (int64_t)b.item_prog.size()}));
@@ -1841,7 +1907,7 @@ static lp_status batch_capture(BatchPlan &b) {
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         const BatchShape &s = b.shape;
-        hipError_t el = launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b), cs);
+        hipError_t el = launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b, s), cs);
         e = hipStreamEndCapture(cs, &b.graph);
         if (e == hipSuccess) e = el;
     }
@@ -1966,23 +2032,10 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
     int32_t team_no = 0;
     for (int32_t i : idx) {
         const Matrix &m = *b.ms[i];
-        const DeviceMatrix &dm = m.dev;
         ProgDesc &g = desc[i];
-        g.words = dm.words;
-        g.and_len = dm.and_len;
-        g.col = dm.col;
-        g.or_c0 = dm.or_c0;
-        g.or_row = dm.or_row;
-        g.segs = dm.segs;
-        g.long_col = dm.long_col;
-        g.fact_bits = dm.fact_bits;
+        g = prog_desc(m);
         g.out_bits = b.d_out + b.out_off[i];
         g.out_products = b.d_prod + i;
-        g.n_rows = m.n_rows;
-        g.n_atoms = m.n_atoms;
-        g.n_or = dm.n_or;
-        g.n_segs = dm.n_segs;
-        g.and_end = (int32_t)dm.and_nnz;
         g.team_size = b.team[i];
         g.xch = b.team[i] > 1 ? b.d_xch + xoff[i] : nullptr;
         g.team = b.team[i] > 1 ? b.d_teams + (int64_t)kTeamStateWords * team_no++ : nullptr;
@@ -2016,7 +2069,7 @@ static lp_status batch_run(const BatchPlan &b, hipStream_t st) {
         LP_HIP(hipGraphLaunch(b.exec, st));
     } else {
         const BatchShape &s = b.shape;
-        LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b), st));
+        LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b, s), st));
     }
     return LP_OK;
 }
@@ -2080,7 +2133,6 @@ static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStrea
     BatchShape win;
     float win_ms = 0.f;
     bool have = false;
-    const BatchParams q = batch_params(b);
     for (const auto &sh : shapes)
         for (int blk : blocks) {
             BatchShape s;
@@ -2089,6 +2141,7 @@ static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStrea
             s.block = blk;
             s.grid = 0;
             if (batch_fit_shape(b, &s)) continue;  // shapes that do not fit are skipped
+            const BatchParams q = batch_params(b, s);
             LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, q, st));  // warm-up
             LP_HIP(hipEventRecord(ev.a, st));
             for (int r = 0; r < reps; ++r) LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, q, st));

@@ -146,38 +146,80 @@ __global__ __launch_bounds__(kBlock) void spmm_step_wide_kernel(SpmmParams p) {
 // product t evaluates only those rows (D_t). The initial matrix is 0 outside
 // the fact and qbar rows, so a row that names none of them is 0 after product
 // 1 as well: D_1 is the set of rows naming a fact or qbar row
-// (spmm_dirty_seed_kernel), with the initial matrix in both buffers. The
-// result buffer of product t holds v_{t-2}; the rows that changed in product
-// t-1 (C_{t-1}) were copied into it when C_{t-1} was propagated, so every row
-// outside D_t already holds its product-t value there and the products are
-// those of the full sweep. Per product: spmm_dirty_eval_kernel evaluates D_t
-// and appends each row whose words changed to C_t (once: an atomic max of the
-// product index on the row's mark); spmm_dirty_push_kernel copies the rows of
-// C_t into the other buffer and appends every row that names one of them to
-// D_{t+1}. Ring slots t mod kDirtyRing hold |C_t| and |D_t|; hist[t mod
-// kDirtyHist] gets |C_t| for the host. A product after the one that changed
-// nothing returns at once. Product 1 needs no read of the initial matrix: it
-// is 0 in every row other than the fact and qbar rows, and those rows keep
-// their initial values in every product, so a row changes in product 1 iff it
-// is another row and its result is not 0.
+// (spmm_dirty_seed_kernel), with the initial matrix in both buffers.
+//
+// One launch per product t reads V (holding v_{t-1}) and writes U (holding
+// v_{t-2}):
+//   - the rows that changed in product t-1 (C_{t-1}) and are not in D_t get
+//     their v_{t-1} words copied from V into U (rows of D_t are written by
+//     their evaluation instead), so U holds v_t on every row afterwards;
+//   - every row of D_t is evaluated into U; a row whose words differ from V
+//     is appended once to C_t (an atomic max of t on its mark), and the wave
+//     that appends it also appends every row naming it (through the transposed
+//     matrix) once to D_{t+1}.
+// D_t's marks (t on its rows) and D_{t+1}'s are two arrays taken in turn, so
+// the marks product t reads do not change under it.
+// The products, their count and the fixpoint are those of the full sweep.
+// hist[t mod kDirtyHist] counts C_t (the host reads it); ring slot t mod
+// kDirtyRing counts D_t. Product t clears the slots products t+1 and t+2
+// append to, and returns at once after a product that changed nothing.
+// Product 1 needs no read of the initial matrix: it is 0 in every row other
+// than the fact and qbar rows, and those keep their initial values in every
+// product, so a row changes in product 1 iff it is another row and its result
+// is not 0.
 
-// One wave per (dirty row, chunk of 64 GC words); W >= 64 (log2W >= 6).
+__device__ __forceinline__ void dirty_clear_ahead(const DirtyParams &p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.hist[(p.step + 1) & (kDirtyHist - 1)] = 0;
+        p.n_dirty[(p.step + 2) & (kDirtyRing - 1)] = 0;
+    }
+}
+
+// Appends row (changed in product t) to C_t, and the rows naming it to
+// D_{t+1}; called by every lane of one wave.
+__device__ __forceinline__ void dirty_push(const DirtyParams &p, int32_t row, int lane) {
+    const int32_t t = p.step;
+    if (lane == 0) p.changed_out[atomicAdd((uint32_t *)&p.hist[t & (kDirtyHist - 1)], 1u)] = row;
+    const int32_t o0 = p.occ_ptr[row], o1 = p.occ_ptr[row + 1];
+    for (int32_t j = o0 + lane; j < o1; j += 64) {
+        const int32_t r = p.occ[j];
+        if (atomicMax(&p.dmark[r], t + 1) < t + 1)
+            p.dirty_out[atomicAdd(&p.n_dirty[(t + 1) & (kDirtyRing - 1)], 1u)] = r;
+    }
+}
+
+// One wave per (row, chunk of 64 GC words); W >= 64 (log2W >= 6). Items are
+// the copies of C_{t-1}'s rows first, then the evaluations of D_t's rows.
 template <int GC>
-__global__ __launch_bounds__(kBlock) void spmm_dirty_eval_kernel(DirtyParams p) {
+__global__ __launch_bounds__(kBlock) void spmm_dirty_product_kernel(DirtyParams p) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int32_t t = p.step;
-    if (t >= 2 && p.n_changed[(t - 1) & (kDirtyRing - 1)] == 0) return;
+    dirty_clear_ahead(p);
+    const int64_t n_copy = t >= 2 ? (int64_t)(uint32_t)p.hist[(t - 1) & (kDirtyHist - 1)] : 0;
+    if (t >= 2 && n_copy == 0) return;
     const int64_t n_rows = (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
     constexpr int kLog2GC = GC == 8 ? 3 : GC == 4 ? 2 : GC == 2 ? 1 : 0;
     const int32_t log2G = p.log2W - 6 - kLog2GC;
-    const int64_t n_items = n_rows << log2G;
+    const int64_t n_copy_items = n_copy << log2G;
+    const int64_t n_items = n_copy_items + (n_rows << log2G);
     const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); it < n_items;
          it += waves) {
-        const int64_t pos = it >> log2G;
-        const int32_t row = p.dirty[pos];
-        const int64_t w0 = ((it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
+        if (it < n_copy_items) {
+            const int32_t row = p.changed_prev[it >> log2G];
+            if (p.dmark_cur[row] == t) continue;  // in D_t: its evaluation writes it
+            const int64_t at = ((int64_t)row << p.log2W) + ((it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
+            uint64_t x[GC];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) x[k] = p.V[at + 64 * k];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) p.U[at + 64 * k] = x[k];
+            continue;
+        }
+        const int64_t e_it = it - n_copy_items;
+        const int32_t row = p.dirty[e_it >> log2G];
+        const int64_t w0 = ((e_it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
         const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
         const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
         uint64_t acc[GC];
@@ -205,29 +247,42 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_kernel(DirtyParams p) 
             diff |= t == 1 ? (first_varies && a != 0ull) : (a != p.V[at]);
             p.U[at] = a;
         }
-        if (__ballot(diff) != 0 && lane == 0 && atomicMax(&p.cmark[row], t) < t)
-            p.changed_out[atomicAdd(&p.n_changed[t & (kDirtyRing - 1)], 1u)] = row;
+        if (__ballot(diff) == 0) continue;
+        int32_t first = 0;
+        if (lane == 0) first = atomicMax(&p.cmark[row], t) < t;
+        if (__builtin_amdgcn_readfirstlane(first)) dirty_push(p, row, lane);
     }
 }
 
 // W < 64: one thread per word; the W lanes of a row are consecutive in the
-// wave (W divides 64), and the row's first lane appends it.
-__global__ __launch_bounds__(kBlock) void spmm_dirty_eval_small_kernel(DirtyParams p) {
+// wave (W divides 64). Copies of C_{t-1}'s rows first, then evaluations; a
+// changed row is appended by the lowest lane of the wave holding one, a row
+// per pass, and the wave pushes its namers.
+__global__ __launch_bounds__(kBlock) void spmm_dirty_product_small_kernel(DirtyParams p) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int32_t t = p.step;
-    if (t >= 2 && p.n_changed[(t - 1) & (kDirtyRing - 1)] == 0) return;
+    dirty_clear_ahead(p);
+    const int64_t n_copy = t >= 2 ? (int64_t)(uint32_t)p.hist[(t - 1) & (kDirtyHist - 1)] : 0;
+    if (t >= 2 && n_copy == 0) return;
     const int64_t n_rows = (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
     const int32_t W = 1 << p.log2W;
-    const int64_t total = n_rows << p.log2W;
+    const int64_t copy_total = n_copy << p.log2W;
+    const int64_t total = copy_total + (n_rows << p.log2W);
     // whole waves iterate together so the ballot sees every lane of a row
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t g0 = (int64_t)blockIdx.x * kBlock + (tid & ~63); g0 < total; g0 += stride) {
         const int64_t g = g0 + lane;
         bool diff = false;
         int32_t row = -1;
-        if (g < total) {
-            const int64_t pos = g >> p.log2W;
+        if (g < copy_total) {
+            const int32_t r = p.changed_prev[g >> p.log2W];
+            if (p.dmark_cur[r] != t) {
+                const int64_t at = ((int64_t)r << p.log2W) + (g & (W - 1));
+                p.U[at] = p.V[at];
+            }
+        } else if (g < total) {
+            const int64_t pos = (g - copy_total) >> p.log2W;
             row = p.dirty[pos];
             const int64_t w = g & (W - 1);
             const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
@@ -245,10 +300,16 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_eval_small_kernel(DirtyPara
                 diff = acc != p.V[at];
             p.U[at] = acc;
         }
+        // one flag per row: its first lane holds whether any of its W words changed
         const uint64_t b = __ballot(diff);
         const uint64_t mine = ((W >= 64) ? ~0ull : ((1ull << W) - 1ull)) << (lane & ~(W - 1));
-        if (row >= 0 && (lane & (W - 1)) == 0 && (b & mine) && atomicMax(&p.cmark[row], t) < t)
-            p.changed_out[atomicAdd(&p.n_changed[t & (kDirtyRing - 1)], 1u)] = row;
+        const bool lead = row >= 0 && (lane & (W - 1)) == 0 && (b & mine) != 0 && atomicMax(&p.cmark[row], t) < t;
+        uint64_t leads = __ballot(lead);
+        while (leads) {
+            const int src = __builtin_ctzll(leads);
+            leads &= leads - 1;
+            dirty_push(p, __shfl(row, src, 64), lane);
+        }
     }
 }
 
@@ -266,35 +327,6 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_seed_kernel(DirtyParams p, 
         for (int32_t j = o0 + lane; j < o1; j += 64) {
             const int32_t r = p.occ[j];
             if (atomicMax(&p.dmark[r], 1) < 1) p.dirty_out[atomicAdd(&p.n_dirty[1], 1u)] = r;
-        }
-    }
-}
-
-// One wave per changed row of product t: copy the row into the buffer product
-// t+1 writes, and append the rows naming it to D_{t+1}.
-__global__ __launch_bounds__(kBlock) void spmm_dirty_push_kernel(DirtyParams p) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int32_t t = p.step;
-    const uint32_t n_ch = p.n_changed[t & (kDirtyRing - 1)];
-    if (blockIdx.x == 0 && tid == 0) {
-        p.hist[t & (kDirtyHist - 1)] = (int32_t)n_ch;
-        // slots appended to in product t+1 (C_{t+1}) and by the next push (D_{t+2})
-        p.n_changed[(t + 1) & (kDirtyRing - 1)] = 0;
-        p.n_dirty[(t + 2) & (kDirtyRing - 1)] = 0;
-    }
-    const int64_t W = 1ll << p.log2W;
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); q < n_ch;
-         q += waves) {
-        const int32_t row = p.changed_out[q];
-        const int64_t base = (int64_t)row << p.log2W;
-        for (int64_t w = lane; w < W; w += 64) p.next[base + w] = p.U[base + w];
-        const int32_t o0 = p.occ_ptr[row], o1 = p.occ_ptr[row + 1];
-        for (int32_t j = o0 + lane; j < o1; j += 64) {
-            const int32_t r = p.occ[j];
-            if (atomicMax(&p.dmark[r], t + 1) < t + 1)
-                p.dirty_out[atomicAdd(&p.n_dirty[(t + 1) & (kDirtyRing - 1)], 1u)] = r;
         }
     }
 }
@@ -438,18 +470,15 @@ hipError_t launch_dirty_seed(const DirtyParams &p, const int32_t *facts, int32_t
 hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st) {
     const unsigned grid = (unsigned)std::max(1, max_grid);
     if (p.log2W >= 9)
-        hipLaunchKernelGGL((spmm_dirty_eval_kernel<8>), dim3(grid), dim3(kBlock), 0, st, p);
+        hipLaunchKernelGGL((spmm_dirty_product_kernel<8>), dim3(grid), dim3(kBlock), 0, st, p);
     else if (p.log2W == 8)
-        hipLaunchKernelGGL((spmm_dirty_eval_kernel<4>), dim3(grid), dim3(kBlock), 0, st, p);
+        hipLaunchKernelGGL((spmm_dirty_product_kernel<4>), dim3(grid), dim3(kBlock), 0, st, p);
     else if (p.log2W == 7)
-        hipLaunchKernelGGL((spmm_dirty_eval_kernel<2>), dim3(grid), dim3(kBlock), 0, st, p);
+        hipLaunchKernelGGL((spmm_dirty_product_kernel<2>), dim3(grid), dim3(kBlock), 0, st, p);
     else if (p.log2W == 6)
-        hipLaunchKernelGGL((spmm_dirty_eval_kernel<1>), dim3(grid), dim3(kBlock), 0, st, p);
+        hipLaunchKernelGGL((spmm_dirty_product_kernel<1>), dim3(grid), dim3(kBlock), 0, st, p);
     else
-        hipLaunchKernelGGL(spmm_dirty_eval_small_kernel, dim3(grid), dim3(kBlock), 0, st, p);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(spmm_dirty_push_kernel, dim3(grid), dim3(kBlock), 0, st, p);
+        hipLaunchKernelGGL(spmm_dirty_product_small_kernel, dim3(grid), dim3(kBlock), 0, st, p);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ struct Prog<1> {
     gp<LongSeg> segs;
     gp<int32_t> long_col;
     int32_t n_rows, n_or, n_segs, and_end;
+    static constexpr bool kLds = false;
     __device__ __forceinline__ int32_t and_base(int64_t w) const { return words[w].and_base; }
     __device__ __forceinline__ uint64_t and_bits(int64_t w) const { return words[w].and_bits; }
 };
@@ -78,6 +79,7 @@ struct Prog<3> {
     const lds_seg *segs;
     const lds_i32 *long_col;
     int32_t n_rows, n_or, n_segs, and_end;
+    static constexpr bool kLds = true;
     __device__ __forceinline__ int32_t and_base(int64_t w) const { return base[w]; }
     __device__ __forceinline__ uint64_t and_bits(int64_t w) const { return andb[w]; }
 };
@@ -259,6 +261,72 @@ __device__ __forceinline__ uint32_t wg_block_rows(const P &d, const lds_u64 *v, 
     return my_new;
 }
 
+// AND rows of a layout in LDS, one lane per row: lane l of a wave takes row
+// 64 w + l of each word w the wave owns (words wave, wave + waves, ...), finds
+// its first entry by a scan of the lengths in the word and walks its own
+// entries, four at a time, against v in LDS; a ballot gives the word's
+// result. Coalescing does not matter in LDS, and each row's chain is a few
+// LDS round trips, where the streaming form of wg_block_rows (made for
+// entries in global memory) costs several per super-block. NW words are in
+// flight per wave.
+template <int NW>
+__device__ __forceinline__ uint32_t wg_and_rows_by_lane(const Prog<3> &d, const lds_u64 *v, lds_u64 *u) {
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int64_t n_words = ((int64_t)d.n_rows + 63) >> 6;
+    const lds_u8 *v8 = (const lds_u8 *)v;
+    uint32_t my_new = 0;
+    for (int64_t w0 = threadIdx.x >> 6; w0 < n_words; w0 += (int64_t)waves * NW) {
+        int32_t len[NW], pos[NW];
+        bool acc[NW];
+        int32_t most = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int64_t w = w0 + (int64_t)k * waves;
+            const int64_t r = w * 64 + lane;
+            const bool in = w < n_words;
+            len[k] = in && r < d.n_rows ? (int32_t)d.and_len[r] : 0;
+            const int32_t base = in ? d.and_base(w) : 0;
+            acc[k] = in && ((d.and_bits(w) >> lane) & 1ull);
+            pos[k] = base + wave_exclusive_scan(len[k]);
+            most = len[k] > most ? len[k] : most;
+        }
+        // branch-free: every lane issues all NW x 4 entry loads, then all
+        // gathers (a lane past its row's end reads entry 0 and ignores it),
+        // so one wait covers each group of loads
+        for (int32_t j = 0; __ballot(j < most) != 0; j += 4) {
+            int32_t c[NW][4];
+#pragma unroll
+            for (int k = 0; k < NW; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) c[k][q] = d.col[j + q < len[k] ? pos[k] + j + q : 0];
+            uint32_t x[NW][4];
+#pragma unroll
+            for (int k = 0; k < NW; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[k][q] = entry_word(v8, c[k][q]);
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                uint32_t all = 1u;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    all &= (uint32_t)(j + q >= len[k]) | __builtin_amdgcn_ubfe(x[k][q], (uint32_t)c[k][q], 1u);
+                acc[k] = acc[k] & (all != 0u);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int64_t w = w0 + (int64_t)k * waves;
+            const uint64_t res = __ballot(acc[k]);
+            if (lane == 0 && w < n_words && res) {
+                __hip_atomic_fetch_or(&u[w], res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                my_new += (uint32_t)__popcll(res & ~v[w]);
+            }
+        }
+    }
+    return my_new;
+}
+
 // OR rows (one lane each) and long rows (one wave per OR segment, one wave per
 // whole long AND row, looping over its segments).
 template <class P>
@@ -345,7 +413,10 @@ __device__ __forceinline__ int32_t solve_alone(const P &d, lds_u64 *cur, lds_u64
     for (;;) {
         if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
         uint32_t my_new = wg_or_and_long_rows<P>(d, cur, nxt, 0, 1);
-        my_new += wg_block_rows<WPW, U, P>(d, cur, nxt, my_ball, 0, 1);
+        if constexpr (P::kLds)
+            my_new += wg_and_rows_by_lane<4>(d, cur, nxt);
+        else
+            my_new += wg_block_rows<WPW, U, P>(d, cur, nxt, my_ball, 0, 1);
         my_new = wave_sum(my_new);
         if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
         __syncthreads();
@@ -358,6 +429,109 @@ __device__ __forceinline__ int32_t solve_alone(const P &d, lds_u64 *cur, lds_u64
         slot = slot == 2 ? 0 : slot + 1;
     }
     // nxt holds the last product, equal to cur at the fixpoint
+    *fix = nxt;
+    return changed == 0 ? step : -1;
+}
+
+// Algorithm 1 on a program small enough that every lane keeps its rows in
+// registers for the whole solve: at most NW words per wave (AND rows by
+// lane: the first E entries of lane l's row in each word), at most NO OR rows
+// per thread, no long rows; the layout is in LDS (entries past the E-th and
+// the setup read it). A row that has fired is never evaluated again (the
+// interpretations only grow); it is ORed into the result buffer of the
+// product that fired it and of the next one, the two buffers then both hold
+// it. Per product a wave issues only the gathers of rows still false and one
+// LDS OR per word, and a product changed iff some row fired. The products and
+// the fixpoint are those of solve_alone.
+template <int NW, int NO, int E>
+__device__ __forceinline__ int32_t solve_tiny(const Prog<3> &d, lds_u64 *cur, lds_u64 *nxt, uint32_t *s_new,
+                                              lds_u64 **fix) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int32_t n_words = (d.n_rows + 63) >> 6;
+    int32_t ent[NW][E], len[NW], tail[NW];
+    bool todo[NW], pend[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int32_t w = wave + waves * k;
+        const bool in = w < n_words;
+        const int32_t r = w * 64 + lane;
+        const int32_t l = in && r < d.n_rows ? (int32_t)d.and_len[r] : 0;
+        const int32_t pos = (in ? d.and_base(w) : 0) + wave_exclusive_scan(l);
+#pragma unroll
+        for (int q = 0; q < E; ++q) ent[k][q] = d.col[q < l ? pos + q : 0];
+        len[k] = l;
+        tail[k] = pos + E;
+        // facts (true in v0, both buffers) and rows that are not AND rows are never evaluated
+        todo[k] = in && ((d.and_bits(w) >> lane) & 1ull) && !((cur[in ? w : 0] >> lane) & 1ull);
+        pend[k] = false;
+    }
+    int32_t orow[NO], oc0[NO], oc1[NO];
+    bool otodo[NO], opend[NO];
+#pragma unroll
+    for (int m = 0; m < NO; ++m) {
+        const int32_t j = (int32_t)threadIdx.x + (int32_t)blockDim.x * m;
+        orow[m] = j < d.n_or ? d.or_row[j] : -1;
+        oc0[m] = j < d.n_or ? d.or_c0[j] : 0;
+        oc1[m] = j < d.n_or ? d.or_c0[j + 1] : 0;
+        otodo[m] = orow[m] >= 0 && !((cur[orow[m] >= 0 ? orow[m] >> 6 : 0] >> (orow[m] & 63)) & 1ull);
+        opend[m] = false;
+    }
+    int32_t step = 1, slot = 1;  // slot = step mod 3
+    uint32_t changed = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
+        const lds_u8 *v8 = (const lds_u8 *)cur;
+        bool fired = false;
+#pragma unroll
+        for (int m = 0; m < NO; ++m) {
+            bool f = false;
+            if (otodo[m]) f = lds_any_in_range(cur, oc0[m], oc1[m]);
+            if (f || opend[m])
+                __hip_atomic_fetch_or(&nxt[orow[m] >> 6], 1ull << (orow[m] & 63), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+            opend[m] = f;
+            otodo[m] = otodo[m] && !f;
+            fired |= f;
+        }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int32_t w = wave + waves * k;
+            if (w >= n_words) continue;
+            bool f = false;
+            if (__ballot(todo[k]) != 0) {
+                uint32_t x[E];
+#pragma unroll
+                for (int q = 0; q < E; ++q) x[q] = entry_word(v8, ent[k][q]);
+                uint32_t all = 1u;
+#pragma unroll
+                for (int q = 0; q < E; ++q) all &= (uint32_t)(q >= len[k]) | __builtin_amdgcn_ubfe(x[q], (uint32_t)ent[k][q], 1u);
+                if (todo[k] && all && len[k] > E) {
+                    for (int32_t i = tail[k]; i < tail[k] + len[k] - E; ++i) {
+                        const int32_t c = d.col[i];
+                        all &= __builtin_amdgcn_ubfe(entry_word(v8, c), (uint32_t)c, 1u);
+                    }
+                }
+                f = todo[k] && all != 0u;
+            }
+            const uint64_t bits = __ballot(f || pend[k]);
+            if (lane == 0 && bits)
+                __hip_atomic_fetch_or(&nxt[w], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            pend[k] = f;
+            todo[k] = todo[k] && !f;
+            fired |= f;
+        }
+        if (__ballot(fired) != 0 && lane == 0) s_new[slot] = 1u;
+        __syncthreads();
+        changed = s_new[slot];
+        if (changed == 0 || step > d.n_rows) break;
+        lds_u64 *t = cur;
+        cur = nxt;
+        nxt = t;
+        ++step;
+        slot = slot == 2 ? 0 : slot + 1;
+    }
     *fix = nxt;
     return changed == 0 ? step : -1;
 }
@@ -501,6 +675,58 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     }
 }
 
+// One program that tiny_fits accepts, by one workgroup of kTinyBlock
+// threads (a kernel of its own, so its registers do not weigh on the batch
+// kernel): facts into both LDS buffers, layout into LDS, solve_tiny, the
+// model's words and the product count out.
+__global__ __launch_bounds__(kTinyBlock) void tp_tiny_kernel(ProgDesc pd, int32_t lds_words) {
+    extern __shared__ __attribute__((aligned(16))) uint64_t s_dyn[];
+    __shared__ uint32_t s_new[3];
+    lds_u64 *buf0 = (lds_u64 *)s_dyn;
+    lds_u64 *buf1 = buf0 + lds_words;
+    if (threadIdx.x < 3) s_new[threadIdx.x] = 0;
+    GProg d;
+    d.words = as_global(pd.words);
+    d.and_len = as_global(pd.and_len);
+    d.col = as_global(pd.col);
+    d.or_c0 = as_global(pd.or_c0);
+    d.or_row = as_global(pd.or_row);
+    d.segs = as_global(pd.segs);
+    d.long_col = as_global(pd.long_col);
+    d.n_rows = pd.n_rows;
+    d.n_or = pd.n_or;
+    d.n_segs = pd.n_segs;
+    d.and_end = pd.and_end;
+    const gp<uint64_t> fact_bits = as_global(pd.fact_bits);
+    const int32_t n_words = (d.n_rows + 63) >> 6;
+    for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
+        const uint64_t f = fact_bits[i];
+        buf0[i] = f;
+        buf1[i] = f;
+    }
+    const LdsLayout L = lds_layout(d.n_rows, d.and_end, d.n_or, d.n_segs, pd.long_nnz);
+    const Prog<3> dl = copy_layout_to_lds(d, pd.long_nnz, L, (lds_u8 *)(buf1 + lds_words));
+    __syncthreads();
+    lds_u64 *fix;
+    const int32_t result = solve_tiny<kTinyWords / (kTinyBlock / 64), kTinyOr / kTinyBlock, 4>(dl, buf0, buf1,
+                                                                                              s_new, &fix);
+    typedef __attribute__((address_space(1))) uint64_t g_u64;
+    typedef __attribute__((address_space(1))) int32_t g_i32;
+    g_u64 *out = (g_u64 *)pd.out_bits;
+    const int32_t out_words = (pd.n_atoms + 63) >> 6;
+    for (int32_t i = threadIdx.x; i < out_words; i += blockDim.x) out[i] = fix[i];
+    if (threadIdx.x == 0) *(g_i32 *)pd.out_products = result;
+}
+
+bool tiny_fits(int64_t n_rows, int64_t n_or, int64_t n_segs) {
+    return n_segs == 0 && ((n_rows + 63) >> 6) <= kTinyWords && n_or <= kTinyOr;
+}
+
+hipError_t launch_tiny(const ProgDesc &pd, int32_t lds_words, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(tp_tiny_kernel, dim3(1), dim3(kTinyBlock), lds_bytes, st, pd, lds_words);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launchers
 
 #define LP_BATCH_SHAPES(X) X(1, 8) X(2, 8) X(4, 4) X(1, 16) X(2, 16)
@@ -539,6 +765,8 @@ void batch_kernels_allow_lds(int max_dynamic_lds) {
                               max_dynamic_lds);
     LP_BATCH_SHAPES(LP_X)
 #undef LP_X
+    (void)hipFuncSetAttribute((const void *)tp_tiny_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              max_dynamic_lds);
     (void)hipGetLastError();
 }
 

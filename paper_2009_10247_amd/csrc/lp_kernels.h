@@ -156,6 +156,14 @@ struct BatchParams {
     int32_t single;          // 1: one program, described by `one` (no queue, grid of one workgroup)
     ProgDesc one;
 };
+// One small program by tp_tiny_kernel (every lane keeps its rows in
+// registers): at most kTinyWords words of 64 rows, kTinyOr OR rows, no long
+// rows, and its layout in LDS beside the two buffers.
+constexpr int kTinyBlock = 1024;
+constexpr int kTinyWords = 64;
+constexpr int kTinyOr = 2048;
+bool tiny_fits(int64_t n_rows, int64_t n_or, int64_t n_segs);
+hipError_t launch_tiny(const ProgDesc &pd, int32_t lds_words, size_t lds_bytes, hipStream_t st);
 bool batch_shape_supported(int wpw, int unroll);
 hipError_t launch_batch(int wpw, int unroll, int grid, int block, size_t lds_bytes, const BatchParams &b,
                         hipStream_t st);

@@ -756,7 +756,10 @@ static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     // the layout goes into LDS beside the two buffers when both fit
     const int64_t v_bytes = (int64_t)q.lds_words * 16, lay = layout_lds_bytes(m);
     if (v_bytes + lay <= (int64_t)dp.max_lds - 4096) q.lds_layout_bytes = (int32_t)lay;
-    LP_HIP(launch_batch(2, 8, 1, 1024, (size_t)(v_bytes + q.lds_layout_bytes), q, st));
+    if (q.lds_layout_bytes > 0 && tiny_fits(m.n_rows, m.dev.n_or, m.dev.n_segs))
+        LP_HIP(launch_tiny(q.one, q.lds_words, (size_t)(v_bytes + lay), st));  // rows kept in registers
+    else
+        LP_HIP(launch_batch(2, 8, 1, 1024, (size_t)(v_bytes + q.lds_layout_bytes), q, st));
     int32_t prods = 0;
     if (host_bits) {
         // the product count and the model bits in one copy: [products, pad .. last word of bits]

@@ -73,8 +73,11 @@ struct DeviceMatrix {
     mutable int32_t *fr_facts = nullptr;  // fact rows (F_0)
     mutable int32_t fr_n_facts = 0;
     // device bytes of the structures above that were attached after the
-    // upload (wave splits, transposed matrix), under the same lock
+    // upload (wave splits, transposed matrix, stable-solve plan), under the same lock
     mutable int64_t lazy_bytes = 0;
+    // buffers and captured graph of stable-model solves by dirty rows, kept
+    // between solves (created on first use)
+    mutable struct StablePlan *splan = nullptr;
     // stable models (normal programs): plain CSR
     int32_t *full_row_ptr = nullptr;
     int32_t *full_col = nullptr;

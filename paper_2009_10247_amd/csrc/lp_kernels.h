@@ -213,6 +213,10 @@ struct DirtyParams {
     int32_t step;
 };
 hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st);
+// Rows changed during a solve back to 0 in both buffers, marks and counts
+// cleared (marks: [cmark n | dm0 n | dm1 n | ring | hist]).
+hipError_t launch_dirty_reset(uint64_t *b0, uint64_t *b1, int32_t log2W, int32_t *marks, int32_t n, int max_grid,
+                              hipStream_t st);
 // D_1 from the fact rows (facts[0..n_facts)) and the qbar rows.
 hipError_t launch_dirty_seed(const DirtyParams &p, const int32_t *facts, int32_t n_facts, int max_grid,
                              hipStream_t st);

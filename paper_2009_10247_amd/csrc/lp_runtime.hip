@@ -276,7 +276,42 @@ static lp_status upload(T **d, const T *h, size_t count, hipStream_t st, int64_t
     return LP_OK;
 }
 
+struct DirtyState;  // below
+
+// Stable-model solves by dirty rows of one matrix, kept between solves: the
+// buffers (two interpretation matrices, D and C lists, marks) and a captured
+// graph of the first kFirstBatch products and Algorithm 3's test. A solve
+// leaves both interpretation buffers holding the initial matrix again (the
+// rows it changed are set back to 0) and the marks clear, so the next solve
+// starts with the graph at once. One solve at a time uses it (try-lock);
+// concurrent solves of the matrix take the allocating path.
+struct StablePlan {
+    std::mutex mu;
+    bool ready = false;
+    uint64_t *buf[2] = {nullptr, nullptr};
+    int32_t *dl[2] = {nullptr, nullptr}, *cl[2] = {nullptr, nullptr}, *marks = nullptr;
+    uint64_t *acc_d = nullptr;
+    unsigned long long *cnt_d = nullptr;
+    uint8_t *host = nullptr;  // pinned: |C_t| history (kDirtyHist int32), model count, accepted mask
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t bytes = 0;
+};
+
+static void release_plan(StablePlan *pl, hipStream_t st) {
+    if (!pl) return;
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    for (void *p : {(void *)pl->buf[0], (void *)pl->buf[1], (void *)pl->dl[0], (void *)pl->dl[1], (void *)pl->cl[0],
+                    (void *)pl->cl[1], (void *)pl->marks, (void *)pl->acc_d, (void *)pl->cnt_d})
+        dev_free(p, st);
+    if (pl->host) (void)hipHostFree(pl->host);
+    delete pl;
+}
+
 static void free_device(Matrix &m, hipStream_t st) {
+    release_plan(m.dev.splan, st);
+    m.dev.splan = nullptr;
     DeviceMatrix &d = m.dev;
     void *ps[] = {d.words,        d.and_len,       d.lens4,  d.col,      d.or_c0,  d.or_row,    d.fact_bits, d.segs, d.long_col,
                   d.full_row_ptr, d.full_col,      d.full_and_bits, d.q_rows, d.guess_pos};
@@ -1191,38 +1226,42 @@ static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
 // as the full sweep. Products are issued kFirstBatch, then kLaterBatch, at a
 // time between host reads of |C_t|; products issued past the fixpoint return
 // at once.
-static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStream_t st, uint64_t *const buf[2],
-                                   int32_t *products, uint64_t **fix) {
-    constexpr int kFirstBatch = 16, kLaterBatch = 8;
-    static_assert(kFirstBatch < kDirtyHist / 2 && kLaterBatch < kDirtyHist / 2, "history slots");
-    static_assert(kDirtyHist * sizeof(int32_t) <= kRing * sizeof(unsigned long long), "pinned ring");
-    lp_status rc;
-    if ((rc = ensure_frontier(m, st))) return rc;
-    const int32_t n = std::max(m.n_rows, 1);
-    Scratch S(st);
-    int32_t *dl[2], *cl[2], *marks;
-    if ((rc = S.get(&dl[0], n)) || (rc = S.get(&dl[1], n)) || (rc = S.get(&cl[0], n)) || (rc = S.get(&cl[1], n)) ||
-        (rc = S.get(&marks, 3 * (int64_t)n + kDirtyRing + kDirtyHist)))
-        return rc;
-    // the row marks, the |D_t| ring and the |C_t| history, cleared together
-    int32_t *cmark = marks, *dm[2] = {marks + n, marks + 2 * (int64_t)n};
-    uint32_t *ring = reinterpret_cast<uint32_t *>(marks + 3 * (int64_t)n);
-    int32_t *hist = marks + 3 * (int64_t)n + kDirtyRing;
-    LP_HIP(hipMemsetAsync(marks, 0, sizeof(int32_t) * (3 * (size_t)n + kDirtyRing + kDirtyHist), st));
-    int32_t *hh = reinterpret_cast<int32_t *>(pinned_ring());
-    if (!hh) {
-        set_error("pinned host allocation failed");
-        return LP_E_NOMEM;
-    }
+constexpr int kFirstBatch = 16, kLaterBatch = 8;
+static_assert(kFirstBatch < kDirtyHist / 2 && kLaterBatch < kDirtyHist / 2, "history slots");
+static_assert(kDirtyHist * sizeof(int32_t) <= kRing * sizeof(unsigned long long), "pinned ring");
+
+// Device state of the dirty-row products of one solve: the two interpretation
+// buffers, the D and C lists (two of each, by product parity), the row marks
+// (C marks, two D mark arrays by parity), the |D_t| ring and the |C_t|
+// history, laid out as [cmark | dm0 | dm1 | ring | hist] so one clear covers
+// them.
+struct DirtyState {
     DirtyParams p{};
+    uint64_t *buf[2] = {nullptr, nullptr};
+    int32_t *dl[2] = {nullptr, nullptr}, *cl[2] = {nullptr, nullptr}, *dm[2] = {nullptr, nullptr};
+    int32_t *marks = nullptr, *hist = nullptr;
+    int grid = 0, grid_small = 0;
+};
+
+static size_t dirty_marks_words(const Matrix &m) {
+    return 3 * (size_t)std::max(m.n_rows, 1) + kDirtyRing + kDirtyHist;
+}
+
+// Fills s.p from the matrix and the buffers s.buf, s.dl, s.cl, s.marks.
+static void dirty_setup(const Matrix &m, const SpmmParams &sp, DirtyState &s) {
+    const int32_t n = std::max(m.n_rows, 1);
+    s.dm[0] = s.marks + n;
+    s.dm[1] = s.marks + 2 * (int64_t)n;
+    s.hist = s.marks + 3 * (int64_t)n + kDirtyRing;
+    DirtyParams &p = s.p;
     p.row_ptr = sp.row_ptr;
     p.col = sp.col;
     p.and_bits = sp.and_bits;
     p.occ_ptr = m.dev.fr_ptr;
     p.occ = m.dev.fr_occ;
-    p.cmark = cmark;
-    p.n_dirty = ring;
-    p.hist = hist;
+    p.cmark = s.marks;
+    p.n_dirty = reinterpret_cast<uint32_t *>(s.marks + 3 * (int64_t)n);
+    p.hist = s.hist;
     p.fact_bits = m.dev.fact_bits;
     p.n_rows = m.n_rows;
     p.n_std = m.n_std;
@@ -1230,33 +1269,58 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
     // product 1's dirty set (rows naming a fact or qbar row) can be large;
     // later ones are small, and a launch of eight workgroups per CU that mostly
     // exit costs dispatch time
-    const int grid = spmm_grid(m), grid_small = std::max(1, grid / 4);
-    p.dmark = dm[1];
-    p.dirty_out = dl[1];
-    LP_HIP(launch_dirty_seed(p, m.dev.fr_facts, m.dev.fr_n_facts, grid_small, st));
+    s.grid = spmm_grid(m);
+    s.grid_small = std::max(1, s.grid / 4);
+}
+
+// D_1 (rows naming a fact or qbar row); the marks must be clear.
+static hipError_t dirty_seed(const Matrix &m, DirtyState &s, hipStream_t st) {
+    s.p.dmark = s.dm[1];
+    s.p.dirty_out = s.dl[1];
+    return launch_dirty_seed(s.p, m.dev.fr_facts, m.dev.fr_n_facts, s.grid_small, st);
+}
+
+// Launches products t0 .. t1-1.
+static hipError_t dirty_products_launch(DirtyState &s, int64_t t0, int64_t t1, hipStream_t st) {
+    DirtyParams &p = s.p;
+    for (int64_t t = t0; t < t1; ++t) {
+        p.step = (int32_t)t;
+        p.V = s.buf[(t - 1) & 1];
+        p.U = s.buf[t & 1];
+        p.dirty = s.dl[t & 1];
+        p.dirty_out = s.dl[(t + 1) & 1];
+        p.changed_prev = s.cl[(t - 1) & 1];
+        p.changed_out = s.cl[t & 1];
+        p.dmark_cur = s.dm[t & 1];
+        p.dmark = s.dm[(t + 1) & 1];
+        hipError_t e = launch_dirty_product(p, t == 1 ? s.grid : s.grid_small, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// First product in [t0, t1) that changed nothing according to the host copy
+// hh of the |C_t| history, or -1.
+static int64_t dirty_first_fixpoint(const int32_t *hh, int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t)
+        if (hh[t & (kDirtyHist - 1)] == 0) return t;
+    return -1;
+}
+
+// Products from t0 on, in batches of kLaterBatch between host reads of the
+// history (hh: kDirtyHist pinned int32), until one changes nothing.
+static lp_status dirty_finish(const Matrix &m, DirtyState &s, int64_t t0, int32_t *hh, hipStream_t st,
+                              int32_t *products, uint64_t **fix) {
     const int64_t limit = (int64_t)m.n_rows + 1;
-    for (int64_t t0 = 1;;) {
-        const int64_t batch = t0 == 1 ? kFirstBatch : kLaterBatch;
-        for (int64_t t = t0; t < t0 + batch; ++t) {
-            p.step = (int32_t)t;
-            p.V = buf[(t - 1) & 1];
-            p.U = buf[t & 1];
-            p.dirty = dl[t & 1];
-            p.dirty_out = dl[(t + 1) & 1];
-            p.changed_prev = cl[(t - 1) & 1];
-            p.changed_out = cl[t & 1];
-            p.dmark_cur = dm[t & 1];
-            p.dmark = dm[(t + 1) & 1];
-            LP_HIP(launch_dirty_product(p, t == 1 ? grid : grid_small, st));
-        }
-        LP_HIP(hipMemcpyAsync(hh, hist, sizeof(int32_t) * kDirtyHist, hipMemcpyDeviceToHost, st));
+    for (int64_t batch = t0 == 1 ? kFirstBatch : kLaterBatch;; batch = kLaterBatch) {
+        LP_HIP(dirty_products_launch(s, t0, t0 + batch, st));
+        LP_HIP(hipMemcpyAsync(hh, s.hist, sizeof(int32_t) * kDirtyHist, hipMemcpyDeviceToHost, st));
         LP_HIP(hipStreamSynchronize(st));
-        for (int64_t t = t0; t < t0 + batch; ++t) {
-            if (hh[t & (kDirtyHist - 1)] == 0) {
-                *products = (int32_t)t;
-                *fix = buf[t & 1];
-                return LP_OK;
-            }
+        const int64_t t = dirty_first_fixpoint(hh, t0, t0 + batch);
+        if (t > 0) {
+            *products = (int32_t)t;
+            *fix = s.buf[t & 1];
+            return LP_OK;
         }
         t0 += batch;
         if (t0 > limit) {
@@ -1264,6 +1328,29 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
             return LP_E_INTERNAL;
         }
     }
+}
+
+static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStream_t st, uint64_t *const buf[2],
+                                   int32_t *products, uint64_t **fix) {
+    lp_status rc;
+    if ((rc = ensure_frontier(m, st))) return rc;
+    const int32_t n = std::max(m.n_rows, 1);
+    Scratch S(st);
+    DirtyState s;
+    s.buf[0] = buf[0];
+    s.buf[1] = buf[1];
+    if ((rc = S.get(&s.dl[0], n)) || (rc = S.get(&s.dl[1], n)) || (rc = S.get(&s.cl[0], n)) ||
+        (rc = S.get(&s.cl[1], n)) || (rc = S.get(&s.marks, dirty_marks_words(m))))
+        return rc;
+    LP_HIP(hipMemsetAsync(s.marks, 0, sizeof(int32_t) * dirty_marks_words(m), st));
+    int32_t *hh = reinterpret_cast<int32_t *>(pinned_ring());
+    if (!hh) {
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
+    dirty_setup(m, sp, s);
+    LP_HIP(dirty_seed(m, s, st));
+    return dirty_finish(m, s, 1, hh, st, products, fix);
 }
 
 // Products of Algorithm 2 from the initial matrix in buf[0] (and buf[1]),
@@ -1302,54 +1389,15 @@ static lp_status stable_loop(const Matrix &m, SpmmParams p, hipStream_t st, uint
     }
 }
 
-static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
-                             int64_t max_models, uint64_t *interp, int32_t *products, hipStream_t st) {
+// Algorithm 3's results from the accepted mask of the compressed guess space
+// (host acc_h, W words) and the fixpoint on the device: the mask in the full
+// guess space, the model count, the first max_models models (extract_kernel)
+// and, if asked, the interpretation matrix. Ends with the stream synchronized.
+static lp_status stable_outputs(const Matrix &m, const uint64_t *fix, int log2W, int64_t W, const uint64_t *acc_h,
+                                unsigned long long nm, uint64_t *accepted, int64_t *n_models, uint8_t *models,
+                                int64_t max_models, uint64_t *interp, Scratch &S, hipStream_t st) {
     const int K = m.K;
-    const int64_t H_full = 1ll << K;
-    const int64_t W_full = (H_full + 63) / 64;
-    if (K == 0) {
-        // definite program: exactly one stable model, the least model
-        std::vector<uint8_t> lm(m.n_atoms ? m.n_atoms : 1);
-        lp_status rc = least_model_impl(m, lm.data(), products, nullptr, st);
-        if (rc) return rc;
-        accepted[0] = 1;
-        *n_models = 1;
-        if (models && max_models >= 1) std::memcpy(models, lm.data(), m.n_atoms);
-        if (interp)
-            for (int32_t a = 0; a < m.n_atoms; ++a) interp[a] = lm[a];
-        if (models && max_models < 1) return LP_E_TRUNCATED;
-        return LP_OK;
-    }
-    if (interp && m.K_eff != K) {
-        set_error("interp output needs a matrix built without LP_PRUNE_FACT_GUESSES");
-        return LP_E_INVAL;
-    }
-    const int keff = m.K_eff;
-    const int64_t H = 1ll << keff;
-    const int64_t W = (H + 63) / 64;
-    const int log2W = ilog2(W);
-    const int64_t total = (int64_t)m.n_rows * W;
-    lp_status rc = check_device_memory(2.0 * (double)total * 8.0 + (double)W * 8.0 + 4096.0, "stable models");
-    if (rc) return rc;
-    Scratch S(st);
-    uint64_t *buf[2];
-    uint64_t *acc_d;
-    unsigned long long *counters;
-    if ((rc = S.get(&buf[0], total)) || (rc = S.get(&buf[1], total)) || (rc = S.get(&acc_d, W)) ||
-        (rc = S.get(&counters, kRing)))
-        return rc;
-    int32_t prods = -1;
-    uint64_t *fix = nullptr;
-    if ((rc = stable_fixpoint(m, st, buf, counters, &prods, &fix))) return rc;
-    // Algorithm 3
-    unsigned long long *cnt_d = counters;  // slot 0 is free once the loop is done
-    LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
-    LP_HIP(launch_stable_check(fix, log2W, W, m.dev.q_rows, m.n_std, K, keff, acc_d, cnt_d, st));
-    std::vector<uint64_t> acc_h(W);
-    unsigned long long nm = 0;
-    LP_HIP(hipMemcpyAsync(acc_h.data(), acc_d, W * 8, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipMemcpyAsync(&nm, cnt_d, 8, hipMemcpyDeviceToHost, st));
-    LP_HIP(hipStreamSynchronize(st));
+    const int64_t W_full = (((int64_t)1 << K) + 63) / 64;
     // accepted guesses in the full guess space (deposit compressed bits)
     std::memset(accepted, 0, sizeof(uint64_t) * W_full);
     std::vector<int64_t> cols;
@@ -1374,12 +1422,214 @@ static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_mod
         int64_t *cols_d;
         uint8_t *out_d;
         const int64_t nb = (int64_t)cols.size() * m.n_atoms;
+        lp_status rc;
         if ((rc = S.get(&cols_d, cols.size())) || (rc = S.get(&out_d, nb))) return rc;
         LP_HIP(hipMemcpyAsync(cols_d, cols.data(), cols.size() * 8, hipMemcpyHostToDevice, st));
         LP_HIP(launch_extract(fix, log2W, cols_d, (int64_t)cols.size(), m.n_atoms, out_d, st));
         LP_HIP(hipMemcpyAsync(models, out_d, nb, hipMemcpyDeviceToHost, st));
     }
     LP_HIP(hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+// Interpretation matrices of at most this many words get a stable-solve plan
+// (two buffers of 256 MB at most, kept with the matrix).
+constexpr int64_t kPlanMaxWords = (int64_t)1 << 25;
+
+// Layout of a plan's pinned host block: the |C_t| history, the model count,
+// the accepted mask.
+static size_t plan_host_bytes(int64_t W) { return sizeof(int32_t) * kDirtyHist + 8 + 8 * (size_t)W; }
+
+// Allocates the plan's buffers and captures its graph: the seed of D_1, products
+// 1..kFirstBatch, the model count cleared, Algorithm 3's test on buffer 0 (both
+// buffers hold the fixpoint when it is reached within the batch), and the
+// history, count and mask copied to the pinned block.
+static lp_status plan_create(const Matrix &m, StablePlan *pl, DirtyState &s, int keff, int log2W, hipStream_t st) {
+    const int64_t W = (int64_t)1 << log2W;
+    const int32_t n = std::max(m.n_rows, 1);
+    const int64_t total = (int64_t)m.n_rows * W;
+    lp_status rc;
+    auto get = [&](void **p, size_t bytes) -> lp_status {
+        lp_status r = dev_alloc(p, bytes, st);
+        if (!r) pl->bytes += (int64_t)bytes;
+        return r;
+    };
+    if ((rc = get((void **)&pl->buf[0], 8 * (size_t)total)) || (rc = get((void **)&pl->buf[1], 8 * (size_t)total)) ||
+        (rc = get((void **)&pl->dl[0], 4 * (size_t)n)) || (rc = get((void **)&pl->dl[1], 4 * (size_t)n)) ||
+        (rc = get((void **)&pl->cl[0], 4 * (size_t)n)) || (rc = get((void **)&pl->cl[1], 4 * (size_t)n)) ||
+        (rc = get((void **)&pl->marks, 4 * dirty_marks_words(m))) || (rc = get((void **)&pl->acc_d, 8 * (size_t)W)) ||
+        (rc = get((void **)&pl->cnt_d, 256)))
+        return rc;
+    if (hipHostMalloc((void **)&pl->host, plan_host_bytes(W), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        pl->host = nullptr;
+        set_error("pinned host allocation failed");
+        return LP_E_NOMEM;
+    }
+    s.buf[0] = pl->buf[0];
+    s.buf[1] = pl->buf[1];
+    s.dl[0] = pl->dl[0];
+    s.dl[1] = pl->dl[1];
+    s.cl[0] = pl->cl[0];
+    s.cl[1] = pl->cl[1];
+    s.marks = pl->marks;
+    dirty_setup(m, spmm_params(m, nullptr, log2W), s);
+    hipStream_t cs;
+    LP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t el = dirty_seed(m, s, cs);
+        if (el == hipSuccess) el = dirty_products_launch(s, 1, kFirstBatch + 1, cs);
+        if (el == hipSuccess) el = launch_zero_words(pl->cnt_d, 2, cs);
+        if (el == hipSuccess)
+            el = launch_stable_check(pl->buf[0], log2W, W, m.dev.q_rows, m.n_std, m.K, keff, pl->acc_d, pl->cnt_d, cs);
+        if (el == hipSuccess)
+            el = hipMemcpyAsync(pl->host, s.hist, sizeof(int32_t) * kDirtyHist, hipMemcpyDeviceToHost, cs);
+        if (el == hipSuccess)
+            el = hipMemcpyAsync(pl->host + sizeof(int32_t) * kDirtyHist, pl->cnt_d, 8, hipMemcpyDeviceToHost, cs);
+        if (el == hipSuccess)
+            el = hipMemcpyAsync(pl->host + sizeof(int32_t) * kDirtyHist + 8, pl->acc_d, 8 * (size_t)W,
+                                hipMemcpyDeviceToHost, cs);
+        e = hipStreamEndCapture(cs, &pl->graph);
+        if (e == hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "stable-solve graph capture");
+    (void)st;
+    (void)total;
+    return LP_OK;
+}
+
+// stable_impl through the matrix's plan. *used is false when another solve
+// holds the plan (the caller then takes the allocating path).
+static lp_status stable_plan_solve(const Matrix &m, int keff, int log2W, uint64_t *accepted, int64_t *n_models,
+                                   uint8_t *models, int64_t max_models, uint64_t *interp, int32_t *products,
+                                   hipStream_t st, bool *used) {
+    *used = false;
+    StablePlan *pl;
+    {
+        std::lock_guard<std::mutex> lock(g_lazy_mu);
+        if (!m.dev.splan) m.dev.splan = new StablePlan();
+        pl = m.dev.splan;
+    }
+    std::unique_lock<std::mutex> hold(pl->mu, std::try_to_lock);
+    if (!hold.owns_lock()) return LP_OK;
+    *used = true;
+    lp_status rc;
+    if ((rc = ensure_frontier(m, st))) return rc;
+    const int64_t W = (int64_t)1 << log2W;
+    const int32_t n = std::max(m.n_rows, 1);
+    DirtyState s;
+    if (!pl->exec) {
+        const int64_t before = pl->bytes;
+        rc = plan_create(m, pl, s, keff, log2W, st);
+        {
+            std::lock_guard<std::mutex> lock(g_lazy_mu);
+            m.dev.lazy_bytes += pl->bytes - before;
+        }
+        if (rc) return rc;
+    } else {
+        s.buf[0] = pl->buf[0];
+        s.buf[1] = pl->buf[1];
+        s.dl[0] = pl->dl[0];
+        s.dl[1] = pl->dl[1];
+        s.cl[0] = pl->cl[0];
+        s.cl[1] = pl->cl[1];
+        s.marks = pl->marks;
+        dirty_setup(m, spmm_params(m, nullptr, log2W), s);
+    }
+    if (!pl->ready) {  // first solve, or a solve that failed part way: the initial matrix afresh
+        LP_HIP(launch_init_m0(pl->buf[0], pl->buf[1], (int64_t)m.n_rows * W, log2W, m.n_std, m.dev.fact_bits,
+                              m.dev.guess_pos, keff, pl->cnt_d, 0, st));
+        LP_HIP(launch_zero_words(pl->marks, (int64_t)dirty_marks_words(m), st));
+    }
+    pl->ready = false;  // until the buffers are back to the initial matrix
+    LP_HIP(hipGraphLaunch(pl->exec, st));
+    LP_HIP(hipStreamSynchronize(st));
+    int32_t *hh = reinterpret_cast<int32_t *>(pl->host);
+    unsigned long long nm = 0;
+    std::memcpy(&nm, pl->host + sizeof(int32_t) * kDirtyHist, 8);
+    std::vector<uint64_t> acc_h(W);
+    std::memcpy(acc_h.data(), pl->host + sizeof(int32_t) * kDirtyHist + 8, 8 * (size_t)W);
+    const int64_t T = dirty_first_fixpoint(hh, 1, kFirstBatch + 1);
+    int32_t prods = (int32_t)T;
+    uint64_t *fix = pl->buf[0];
+    if (T < 0) {  // more products than the graph holds
+        if ((rc = dirty_finish(m, s, kFirstBatch + 1, hh, st, &prods, &fix))) return rc;
+        LP_HIP(launch_zero_words(pl->cnt_d, 2, st));
+        LP_HIP(launch_stable_check(fix, log2W, W, m.dev.q_rows, m.n_std, m.K, keff, pl->acc_d, pl->cnt_d, st));
+        LP_HIP(hipMemcpyAsync(acc_h.data(), pl->acc_d, 8 * (size_t)W, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipMemcpyAsync(&nm, pl->cnt_d, 8, hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+    }
+    Scratch S(st);
+    if ((rc = stable_outputs(m, fix, log2W, W, acc_h.data(), nm, accepted, n_models, models, max_models, interp, S,
+                             st)))
+        return rc;
+    LP_HIP(launch_dirty_reset(pl->buf[0], pl->buf[1], log2W, pl->marks, n, s.grid, st));
+    LP_HIP(hipStreamSynchronize(st));
+    pl->ready = true;
+    if (products) *products = prods;
+    if (models && (int64_t)nm > max_models) return LP_E_TRUNCATED;
+    return LP_OK;
+}
+
+static lp_status stable_impl(const Matrix &m, uint64_t *accepted, int64_t *n_models, uint8_t *models,
+                             int64_t max_models, uint64_t *interp, int32_t *products, hipStream_t st) {
+    const int K = m.K;
+    if (K == 0) {
+        // definite program: exactly one stable model, the least model
+        std::vector<uint8_t> lm(m.n_atoms ? m.n_atoms : 1);
+        lp_status rc = least_model_impl(m, lm.data(), products, nullptr, st);
+        if (rc) return rc;
+        accepted[0] = 1;
+        *n_models = 1;
+        if (models && max_models >= 1) std::memcpy(models, lm.data(), m.n_atoms);
+        if (interp)
+            for (int32_t a = 0; a < m.n_atoms; ++a) interp[a] = lm[a];
+        if (models && max_models < 1) return LP_E_TRUNCATED;
+        return LP_OK;
+    }
+    if (interp && m.K_eff != K) {
+        set_error("interp output needs a matrix built without LP_PRUNE_FACT_GUESSES");
+        return LP_E_INVAL;
+    }
+    const int keff = m.K_eff;
+    const int64_t H = 1ll << keff;
+    const int64_t W = (H + 63) / 64;
+    const int log2W = ilog2(W);
+    const int64_t total = (int64_t)m.n_rows * W;
+    if (dirty_products(m, log2W) && total <= kPlanMaxWords) {
+        bool used = false;
+        lp_status rc = stable_plan_solve(m, keff, log2W, accepted, n_models, models, max_models, interp, products, st,
+                                         &used);
+        if (used) return rc;
+    }
+    lp_status rc = check_device_memory(2.0 * (double)total * 8.0 + (double)W * 8.0 + 4096.0, "stable models");
+    if (rc) return rc;
+    Scratch S(st);
+    uint64_t *buf[2];
+    uint64_t *acc_d;
+    unsigned long long *counters;
+    if ((rc = S.get(&buf[0], total)) || (rc = S.get(&buf[1], total)) || (rc = S.get(&acc_d, W)) ||
+        (rc = S.get(&counters, kRing)))
+        return rc;
+    int32_t prods = -1;
+    uint64_t *fix = nullptr;
+    if ((rc = stable_fixpoint(m, st, buf, counters, &prods, &fix))) return rc;
+    // Algorithm 3
+    unsigned long long *cnt_d = counters;  // slot 0 is free once the loop is done
+    LP_HIP(hipMemsetAsync(cnt_d, 0, sizeof(unsigned long long), st));
+    LP_HIP(launch_stable_check(fix, log2W, W, m.dev.q_rows, m.n_std, K, keff, acc_d, cnt_d, st));
+    std::vector<uint64_t> acc_h(W);
+    unsigned long long nm = 0;
+    LP_HIP(hipMemcpyAsync(acc_h.data(), acc_d, W * 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(&nm, cnt_d, 8, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    if ((rc = stable_outputs(m, fix, log2W, W, acc_h.data(), nm, accepted, n_models, models, max_models, interp, S,
+                             st)))
+        return rc;
     if (products) *products = prods;
     if (models && (int64_t)nm > max_models) return LP_E_TRUNCATED;
     return LP_OK;

@@ -331,6 +331,42 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_seed_kernel(DirtyParams p, 
     }
 }
 
+// Back to the initial matrix after a solve by dirty rows: every row that
+// changed in some product (C mark > 0; never a fact or qbar row, which keep
+// their initial values) is set to 0 in both buffers, and the marks, the |D_t|
+// ring and the |C_t| history are cleared. One wave per row; the wave that
+// reads a row's mark also clears it. marks: [cmark n | dm0 n | dm1 n | ring |
+// hist], n = max(n_rows, 1).
+__global__ __launch_bounds__(kBlock) void spmm_dirty_reset_kernel(uint64_t *b0, uint64_t *b1, int32_t log2W,
+                                                                  int32_t *marks, int32_t n) {
+    const int lane = threadIdx.x & 63;
+    const int64_t W = 1ll << log2W;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t r = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); r < n;
+         r += waves) {
+        if (marks[r] > 0) {
+            const int64_t base = r << log2W;
+            for (int64_t w = lane; w < W; w += 64) {
+                b0[base + w] = 0ull;
+                b1[base + w] = 0ull;
+            }
+        }
+        if (lane == 0) {
+            marks[r] = 0;
+            marks[n + r] = 0;
+            marks[2 * (int64_t)n + r] = 0;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kDirtyRing + kDirtyHist) marks[3 * (int64_t)n + threadIdx.x] = 0;
+}
+
+hipError_t launch_dirty_reset(uint64_t *b0, uint64_t *b1, int32_t log2W, int32_t *marks, int32_t n, int max_grid,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(spmm_dirty_reset_kernel, dim3((unsigned)std::max(1, max_grid)), dim3(kBlock), 0, st, b0, b1,
+                       log2W, marks, n);
+    return hipGetLastError();
+}
+
 // Word g of the initial matrix (Definition 8), written to V and, unless it is
 // null, to U.
 // Column j of the compressed guess space: bit pos of j

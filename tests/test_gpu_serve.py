@@ -134,7 +134,8 @@ def test_resident_bytes_count_the_transposed_matrix():
             if m.info["n_neg"]:
                 upload_bytes = m.info["device_bytes"]
                 m.stable_models(max_models=1)
-                assert m._info()["device_bytes"] == upload_bytes  # nothing attached later
+                # the stable-solve plan (two interpretation matrices and lists) is kept with the matrix
+                assert m._info()["device_bytes"] >= upload_bytes
             else:
                 m.least_model()
             want += m._info()["device_bytes"]

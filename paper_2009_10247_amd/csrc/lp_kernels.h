@@ -187,7 +187,6 @@ struct SpmmParams {
 hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st);
 // Stable-model products by dirty rows (lp_spmm.hip): one launch pair per
 // product t; see spmm_dirty_eval_kernel.
-constexpr int kDirtyRing = 4;    // |C_t| and |D_t| by t mod kDirtyRing
 constexpr int kDirtyHist = 128;  // |C_t| by t mod kDirtyHist, read by the host
 struct DirtyParams {
     const int32_t *row_ptr;
@@ -197,25 +196,26 @@ struct DirtyParams {
     const int32_t *occ;
     const uint64_t *V;           // v_{t-1}
     uint64_t *U;                 // result of product t (holds v_{t-2} on entry)
-    const int32_t *dirty;        // D_t
-    const int32_t *changed_prev; // C_{t-1}
-    int32_t *changed_out;        // C_t
-    int32_t *dirty_out;          // D_{t+1}
-    int32_t *cmark;              // [n_rows] last product a row was appended to C
-    const int32_t *dmark_cur;    // [n_rows] t on the rows of D_t (not written during product t)
-    int32_t *dmark;              // [n_rows] t + 1 on the rows appended to D_{t+1}
-    uint32_t *n_dirty;           // [kDirtyRing] |D_t| by t mod kDirtyRing
-    int32_t *hist;               // [kDirtyHist] |C_t| by t mod kDirtyHist
+    // row bitmaps (bit r & 31 of word r >> 5), nb words each
+    const uint32_t *dcur;        // D_t
+    uint32_t *dnext;             // D_{t+1}, set in product t
+    uint32_t *dclear;            // D_{t+2}'s, cleared in product t
+    const uint32_t *cprev;       // C_{t-1}
+    uint32_t *ccur;              // C_t, set in product t
+    uint32_t *cclear;            // C_{t+1}'s, cleared in product t
+    uint32_t *call;              // rows changed in any product so far
+    int32_t *hist;               // [kDirtyHist] 1 iff product t changed a row, by t mod kDirtyHist
     const uint64_t *fact_bits;   // fact rows (constant, like the qbar rows from n_std on)
+    int64_t nb;
     int32_t n_rows;
     int32_t n_std;
     int32_t log2W;
     int32_t step;
 };
 hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st);
-// Rows changed during a solve back to 0 in both buffers, marks and counts
-// cleared (marks: [cmark n | dm0 n | dm1 n | ring | hist]).
-hipError_t launch_dirty_reset(uint64_t *b0, uint64_t *b1, int32_t log2W, int32_t *marks, int32_t n, int max_grid,
+// Rows changed during a solve back to 0 in both buffers, sets and history
+// cleared (sets: [D0 | D1 | D2 | C0 | C1 | C2 | changed] of nb words, then the history).
+hipError_t launch_dirty_reset(uint64_t *b0, uint64_t *b1, int32_t log2W, uint32_t *sets, int64_t nb, int max_grid,
                               hipStream_t st);
 // D_1 from the fact rows (facts[0..n_facts)) and the qbar rows.
 hipError_t launch_dirty_seed(const DirtyParams &p, const int32_t *facts, int32_t n_facts, int max_grid,

@@ -289,7 +289,7 @@ struct StablePlan {
     std::mutex mu;
     bool ready = false;
     uint64_t *buf[2] = {nullptr, nullptr};
-    int32_t *dl[2] = {nullptr, nullptr}, *cl[2] = {nullptr, nullptr}, *marks = nullptr;
+    uint32_t *sets = nullptr;  // row sets and history of the dirty-row products
     uint64_t *acc_d = nullptr;
     unsigned long long *cnt_d = nullptr;
     uint8_t *host = nullptr;  // pinned: |C_t| history (kDirtyHist int32), model count, accepted mask
@@ -302,8 +302,7 @@ static void release_plan(StablePlan *pl, hipStream_t st) {
     if (!pl) return;
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
-    for (void *p : {(void *)pl->buf[0], (void *)pl->buf[1], (void *)pl->dl[0], (void *)pl->dl[1], (void *)pl->cl[0],
-                    (void *)pl->cl[1], (void *)pl->marks, (void *)pl->acc_d, (void *)pl->cnt_d})
+    for (void *p : {(void *)pl->buf[0], (void *)pl->buf[1], (void *)pl->sets, (void *)pl->acc_d, (void *)pl->cnt_d})
         dev_free(p, st);
     if (pl->host) (void)hipHostFree(pl->host);
     delete pl;
@@ -1231,52 +1230,54 @@ static_assert(kFirstBatch < kDirtyHist / 2 && kLaterBatch < kDirtyHist / 2, "his
 static_assert(kDirtyHist * sizeof(int32_t) <= kRing * sizeof(unsigned long long), "pinned ring");
 
 // Device state of the dirty-row products of one solve: the two interpretation
-// buffers, the D and C lists (two of each, by product parity), the row marks
-// (C marks, two D mark arrays by parity), the |D_t| ring and the |C_t|
-// history, laid out as [cmark | dm0 | dm1 | ring | hist] so one clear covers
-// them.
+// buffers and the row sets, laid out as [D0 | D1 | D2 | C0 | C1 | C2 |
+// changed] (bitmaps of nb words) followed by the history, so one clear
+// covers them.
 struct DirtyState {
     DirtyParams p{};
     uint64_t *buf[2] = {nullptr, nullptr};
-    int32_t *dl[2] = {nullptr, nullptr}, *cl[2] = {nullptr, nullptr}, *dm[2] = {nullptr, nullptr};
-    int32_t *marks = nullptr, *hist = nullptr;
+    uint32_t *sets = nullptr;
+    int32_t *hist = nullptr;
+    int64_t nb = 0;
     int grid = 0, grid_small = 0;
 };
 
-static size_t dirty_marks_words(const Matrix &m) {
-    return 3 * (size_t)std::max(m.n_rows, 1) + kDirtyRing + kDirtyHist;
-}
+static int64_t dirty_bitmap_words(const Matrix &m) { return ((int64_t)std::max(m.n_rows, 1) + 31) / 32; }
 
-// Fills s.p from the matrix and the buffers s.buf, s.dl, s.cl, s.marks.
+static size_t dirty_sets_words(const Matrix &m) { return 7 * (size_t)dirty_bitmap_words(m) + kDirtyHist; }
+
+// Fills s.p from the matrix, the buffers s.buf and the sets s.sets.
 static void dirty_setup(const Matrix &m, const SpmmParams &sp, DirtyState &s) {
-    const int32_t n = std::max(m.n_rows, 1);
-    s.dm[0] = s.marks + n;
-    s.dm[1] = s.marks + 2 * (int64_t)n;
-    s.hist = s.marks + 3 * (int64_t)n + kDirtyRing;
+    s.nb = dirty_bitmap_words(m);
+    s.hist = reinterpret_cast<int32_t *>(s.sets + 7 * s.nb);
     DirtyParams &p = s.p;
     p.row_ptr = sp.row_ptr;
     p.col = sp.col;
     p.and_bits = sp.and_bits;
     p.occ_ptr = m.dev.fr_ptr;
     p.occ = m.dev.fr_occ;
-    p.cmark = s.marks;
-    p.n_dirty = reinterpret_cast<uint32_t *>(s.marks + 3 * (int64_t)n);
+    p.call = s.sets + 6 * s.nb;
     p.hist = s.hist;
     p.fact_bits = m.dev.fact_bits;
+    p.nb = s.nb;
     p.n_rows = m.n_rows;
     p.n_std = m.n_std;
     p.log2W = sp.log2W;
     // product 1's dirty set (rows naming a fact or qbar row) can be large;
-    // later ones are small, and a launch of eight workgroups per CU that mostly
-    // exit costs dispatch time
+    // later ones are small on small matrices, where a launch of eight
+    // workgroups per CU that mostly exit costs dispatch time; matrices of many
+    // rows, or rows of 64 words or more (each row a wave's work), keep the
+    // full grid for every product
     s.grid = spmm_grid(m);
-    s.grid_small = std::max(1, s.grid / 4);
+    s.grid_small = (m.n_rows >= (1 << 18) || sp.log2W >= 6) ? s.grid : std::max(1, s.grid / 4);
 }
 
-// D_1 (rows naming a fact or qbar row); the marks must be clear.
+static uint32_t *dirty_d(DirtyState &s, int64_t t) { return s.sets + (t % 3) * s.nb; }
+static uint32_t *dirty_c(DirtyState &s, int64_t t) { return s.sets + (3 + t % 3) * s.nb; }
+
+// D_1 (rows naming a fact or qbar row); the sets must be clear.
 static hipError_t dirty_seed(const Matrix &m, DirtyState &s, hipStream_t st) {
-    s.p.dmark = s.dm[1];
-    s.p.dirty_out = s.dl[1];
+    s.p.dnext = dirty_d(s, 1);
     return launch_dirty_seed(s.p, m.dev.fr_facts, m.dev.fr_n_facts, s.grid_small, st);
 }
 
@@ -1287,12 +1288,12 @@ static hipError_t dirty_products_launch(DirtyState &s, int64_t t0, int64_t t1, h
         p.step = (int32_t)t;
         p.V = s.buf[(t - 1) & 1];
         p.U = s.buf[t & 1];
-        p.dirty = s.dl[t & 1];
-        p.dirty_out = s.dl[(t + 1) & 1];
-        p.changed_prev = s.cl[(t - 1) & 1];
-        p.changed_out = s.cl[t & 1];
-        p.dmark_cur = s.dm[t & 1];
-        p.dmark = s.dm[(t + 1) & 1];
+        p.dcur = dirty_d(s, t);
+        p.dnext = dirty_d(s, t + 1);
+        p.dclear = dirty_d(s, t + 2);
+        p.cprev = dirty_c(s, t + 2);  // C_{t-1}
+        p.ccur = dirty_c(s, t);
+        p.cclear = dirty_c(s, t + 1);
         hipError_t e = launch_dirty_product(p, t == 1 ? s.grid : s.grid_small, st);
         if (e != hipSuccess) return e;
     }
@@ -1334,15 +1335,12 @@ static lp_status stable_dirty_loop(const Matrix &m, const SpmmParams &sp, hipStr
                                    int32_t *products, uint64_t **fix) {
     lp_status rc;
     if ((rc = ensure_frontier(m, st))) return rc;
-    const int32_t n = std::max(m.n_rows, 1);
     Scratch S(st);
     DirtyState s;
     s.buf[0] = buf[0];
     s.buf[1] = buf[1];
-    if ((rc = S.get(&s.dl[0], n)) || (rc = S.get(&s.dl[1], n)) || (rc = S.get(&s.cl[0], n)) ||
-        (rc = S.get(&s.cl[1], n)) || (rc = S.get(&s.marks, dirty_marks_words(m))))
-        return rc;
-    LP_HIP(hipMemsetAsync(s.marks, 0, sizeof(int32_t) * dirty_marks_words(m), st));
+    if ((rc = S.get(&s.sets, dirty_sets_words(m)))) return rc;
+    LP_HIP(hipMemsetAsync(s.sets, 0, sizeof(uint32_t) * dirty_sets_words(m), st));
     int32_t *hh = reinterpret_cast<int32_t *>(pinned_ring());
     if (!hh) {
         set_error("pinned host allocation failed");
@@ -1392,10 +1390,11 @@ static lp_status stable_loop(const Matrix &m, SpmmParams p, hipStream_t st, uint
 // Algorithm 3's results from the accepted mask of the compressed guess space
 // (host acc_h, W words) and the fixpoint on the device: the mask in the full
 // guess space, the model count, the first max_models models (extract_kernel)
-// and, if asked, the interpretation matrix. Ends with the stream synchronized.
+// and, if asked, the interpretation matrix. The copies to the host are
+// complete once the stream has synchronized: here, unless sync is false.
 static lp_status stable_outputs(const Matrix &m, const uint64_t *fix, int log2W, int64_t W, const uint64_t *acc_h,
                                 unsigned long long nm, uint64_t *accepted, int64_t *n_models, uint8_t *models,
-                                int64_t max_models, uint64_t *interp, Scratch &S, hipStream_t st) {
+                                int64_t max_models, uint64_t *interp, Scratch &S, hipStream_t st, bool sync = true) {
     const int K = m.K;
     const int64_t W_full = (((int64_t)1 << K) + 63) / 64;
     // accepted guesses in the full guess space (deposit compressed bits)
@@ -1428,7 +1427,7 @@ static lp_status stable_outputs(const Matrix &m, const uint64_t *fix, int log2W,
         LP_HIP(launch_extract(fix, log2W, cols_d, (int64_t)cols.size(), m.n_atoms, out_d, st));
         LP_HIP(hipMemcpyAsync(models, out_d, nb, hipMemcpyDeviceToHost, st));
     }
-    LP_HIP(hipStreamSynchronize(st));
+    if (sync) LP_HIP(hipStreamSynchronize(st));
     return LP_OK;
 }
 
@@ -1446,7 +1445,6 @@ static size_t plan_host_bytes(int64_t W) { return sizeof(int32_t) * kDirtyHist +
 // history, count and mask copied to the pinned block.
 static lp_status plan_create(const Matrix &m, StablePlan *pl, DirtyState &s, int keff, int log2W, hipStream_t st) {
     const int64_t W = (int64_t)1 << log2W;
-    const int32_t n = std::max(m.n_rows, 1);
     const int64_t total = (int64_t)m.n_rows * W;
     lp_status rc;
     auto get = [&](void **p, size_t bytes) -> lp_status {
@@ -1455,9 +1453,7 @@ static lp_status plan_create(const Matrix &m, StablePlan *pl, DirtyState &s, int
         return r;
     };
     if ((rc = get((void **)&pl->buf[0], 8 * (size_t)total)) || (rc = get((void **)&pl->buf[1], 8 * (size_t)total)) ||
-        (rc = get((void **)&pl->dl[0], 4 * (size_t)n)) || (rc = get((void **)&pl->dl[1], 4 * (size_t)n)) ||
-        (rc = get((void **)&pl->cl[0], 4 * (size_t)n)) || (rc = get((void **)&pl->cl[1], 4 * (size_t)n)) ||
-        (rc = get((void **)&pl->marks, 4 * dirty_marks_words(m))) || (rc = get((void **)&pl->acc_d, 8 * (size_t)W)) ||
+        (rc = get((void **)&pl->sets, 4 * dirty_sets_words(m))) || (rc = get((void **)&pl->acc_d, 8 * (size_t)W)) ||
         (rc = get((void **)&pl->cnt_d, 256)))
         return rc;
     if (hipHostMalloc((void **)&pl->host, plan_host_bytes(W), hipHostMallocDefault) != hipSuccess) {
@@ -1468,11 +1464,7 @@ static lp_status plan_create(const Matrix &m, StablePlan *pl, DirtyState &s, int
     }
     s.buf[0] = pl->buf[0];
     s.buf[1] = pl->buf[1];
-    s.dl[0] = pl->dl[0];
-    s.dl[1] = pl->dl[1];
-    s.cl[0] = pl->cl[0];
-    s.cl[1] = pl->cl[1];
-    s.marks = pl->marks;
+    s.sets = pl->sets;
     dirty_setup(m, spmm_params(m, nullptr, log2W), s);
     hipStream_t cs;
     LP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1519,7 +1511,6 @@ static lp_status stable_plan_solve(const Matrix &m, int keff, int log2W, uint64_
     lp_status rc;
     if ((rc = ensure_frontier(m, st))) return rc;
     const int64_t W = (int64_t)1 << log2W;
-    const int32_t n = std::max(m.n_rows, 1);
     DirtyState s;
     if (!pl->exec) {
         const int64_t before = pl->bytes;
@@ -1532,17 +1523,13 @@ static lp_status stable_plan_solve(const Matrix &m, int keff, int log2W, uint64_
     } else {
         s.buf[0] = pl->buf[0];
         s.buf[1] = pl->buf[1];
-        s.dl[0] = pl->dl[0];
-        s.dl[1] = pl->dl[1];
-        s.cl[0] = pl->cl[0];
-        s.cl[1] = pl->cl[1];
-        s.marks = pl->marks;
+        s.sets = pl->sets;
         dirty_setup(m, spmm_params(m, nullptr, log2W), s);
     }
     if (!pl->ready) {  // first solve, or a solve that failed part way: the initial matrix afresh
         LP_HIP(launch_init_m0(pl->buf[0], pl->buf[1], (int64_t)m.n_rows * W, log2W, m.n_std, m.dev.fact_bits,
                               m.dev.guess_pos, keff, pl->cnt_d, 0, st));
-        LP_HIP(launch_zero_words(pl->marks, (int64_t)dirty_marks_words(m), st));
+        LP_HIP(launch_zero_words(pl->sets, (int64_t)dirty_sets_words(m), st));
     }
     pl->ready = false;  // until the buffers are back to the initial matrix
     LP_HIP(hipGraphLaunch(pl->exec, st));
@@ -1564,10 +1551,11 @@ static lp_status stable_plan_solve(const Matrix &m, int keff, int log2W, uint64_
         LP_HIP(hipStreamSynchronize(st));
     }
     Scratch S(st);
+    // the reset follows the copies out of the fixpoint on the stream; one synchronization ends both
     if ((rc = stable_outputs(m, fix, log2W, W, acc_h.data(), nm, accepted, n_models, models, max_models, interp, S,
-                             st)))
+                             st, false)))
         return rc;
-    LP_HIP(launch_dirty_reset(pl->buf[0], pl->buf[1], log2W, pl->marks, n, s.grid, st));
+    LP_HIP(launch_dirty_reset(pl->buf[0], pl->buf[1], log2W, pl->sets, s.nb, s.grid, st));
     LP_HIP(hipStreamSynchronize(st));
     pl->ready = true;
     if (products) *products = prods;

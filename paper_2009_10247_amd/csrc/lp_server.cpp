@@ -74,7 +74,10 @@ int64_t solve_bytes(const lp_info &I) {
         b = 16.0 * (double)W + 8.0 * 2048 + 8.0 * (double)I.n_long_rows;
     } else {
         const int64_t Wg = words_of((int64_t)1 << I.n_neg);
-        b = 16.0 * (double)I.n_rows * (double)Wg + 8.0 * (double)Wg + (double)I.n_atoms + 8.0 * 2048;
+        // two interpretation matrices, the accepted mask, the row sets of
+        // the dirty-row products (seven bitmaps), the models
+        b = 16.0 * (double)I.n_rows * (double)Wg + 8.0 * (double)Wg + (double)I.n_rows + (double)I.n_atoms +
+            8.0 * 2048;
     }
     return (int64_t)(1.15 * b) + (1 << 20);
 }
@@ -285,7 +288,9 @@ void run_group(lp_server *s, hipStream_t st, std::vector<Request *> &group, std:
     } catch (const std::bad_alloc &) {
         for (Request *r : group) r->info.status = LP_E_NOMEM;
     }
-    // structures attached to a matrix by its first solves (wave splits) count as resident bytes
+    // structures a solve attaches to its matrix (wave splits, the stable-solve
+    // plan, which takes the place of the buffers the request reserved) become
+    // resident bytes as the request's reservation is released
     std::vector<std::pair<Program *, int64_t>> sizes;
     for (Request *r : group) {
         Program *p = s->programs[r->info.program_id].get();
@@ -293,12 +298,6 @@ void run_group(lp_server *s, hipStream_t st, std::vector<Request *> &group, std:
         if (!failed(p) && lp_matrix_info(p->m, &I) == LP_OK) sizes.emplace_back(p, I.device_bytes);
     }
     std::lock_guard<std::mutex> lock(s->mu);
-    for (auto &ps : sizes) {
-        if (!ps.first->resident) continue;
-        s->used += ps.second - ps.first->bytes;
-        ps.first->bytes = ps.second;
-    }
-    s->peak_used = std::max(s->peak_used, s->used);
     const double t = s->now();
     for (Request *r : group) {
         Program *p = s->programs[r->info.program_id].get();
@@ -309,6 +308,12 @@ void run_group(lp_server *s, hipStream_t st, std::vector<Request *> &group, std:
         s->done.push_back(r->info.request_id);
         s->n_completed++;
     }
+    for (auto &ps : sizes) {
+        if (!ps.first->resident) continue;
+        s->used += ps.second - ps.first->bytes;
+        ps.first->bytes = ps.second;
+    }
+    s->peak_used = std::max(s->peak_used, s->used);
     if (batch) {
         s->n_batches++;
         s->n_batched += (int64_t)group.size();

@@ -148,222 +148,316 @@ __global__ __launch_bounds__(kBlock) void spmm_step_wide_kernel(SpmmParams p) {
 // 1 as well: D_1 is the set of rows naming a fact or qbar row
 // (spmm_dirty_seed_kernel), with the initial matrix in both buffers.
 //
-// One launch per product t reads V (holding v_{t-1}) and writes U (holding
-// v_{t-2}):
-//   - the rows that changed in product t-1 (C_{t-1}) and are not in D_t get
-//     their v_{t-1} words copied from V into U (rows of D_t are written by
-//     their evaluation instead), so U holds v_t on every row afterwards;
+// The sets are bitmaps over rows (bit r & 31 of 32-bit word r >> 5), filled
+// with atomic ORs whose results are not waited for. One launch per product t
+// reads V (holding v_{t-1}) and writes U (holding v_{t-2}):
+//   - the rows of C_{t-1} (changed in product t-1) outside D_t get their
+//     v_{t-1} words copied from V into U (rows of D_t are written by their
+//     evaluation instead), so U holds v_t on every row afterwards;
 //   - every row of D_t is evaluated into U; a row whose words differ from V
-//     is appended once to C_t (an atomic max of t on its mark), and the wave
-//     that appends it also appends every row naming it (through the transposed
-//     matrix) once to D_{t+1}.
-// D_t's marks (t on its rows) and D_{t+1}'s are two arrays taken in turn, so
-// the marks product t reads do not change under it.
-// The products, their count and the fixpoint are those of the full sweep.
-// hist[t mod kDirtyHist] counts C_t (the host reads it); ring slot t mod
-// kDirtyRing counts D_t. Product t clears the slots products t+1 and t+2
-// append to, and returns at once after a product that changed nothing.
-// Product 1 needs no read of the initial matrix: it is 0 in every row other
-// than the fact and qbar rows, and those keep their initial values in every
-// product, so a row changes in product 1 iff it is another row and its result
-// is not 0.
+//     goes into C_t and into the cumulative set of changed rows, and every
+//     row naming it (through the transposed matrix) into D_{t+1}.
+// Bitmaps come in threes by product mod 3: product t reads D_t and C_{t-1},
+// sets D_{t+1} and C_t, and clears the ones products t+1 and t+2 set (D_{t+2},
+// C_{t+1}), which no product running at the same time reads. hist[t mod
+// kDirtyHist] = 1 iff product t changed a row (the host reads it); product t
+// clears the next slot, and returns at once after a product that changed
+// nothing. The products, their count and the fixpoint are those of the full
+// sweep. Product 1 needs no read of the initial matrix: it is 0 in every row
+// other than the fact and qbar rows, and those keep their initial values in
+// every product, so a row changes in product 1 iff it is another row and its
+// result is not 0.
+
+__device__ __forceinline__ void bit_or(uint32_t *bits, int64_t row) {
+    __hip_atomic_fetch_or(&bits[row >> 5], 1u << (row & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Row `row` changed in product t: into C_t and the cumulative set (by lane
+// 0), and every row naming it into D_{t+1} (all lanes of the wave).
+__device__ __forceinline__ void dirty_changed(const DirtyParams &p, int32_t row, int lane) {
+    if (lane == 0) {
+        bit_or(p.ccur, row);
+        bit_or(p.call, row);
+    }
+    const int32_t o0 = p.occ_ptr[row], o1 = p.occ_ptr[row + 1];
+    for (int32_t j = o0 + lane; j < o1; j += 64) bit_or(p.dnext, p.occ[j]);
+}
 
 __device__ __forceinline__ void dirty_clear_ahead(const DirtyParams &p) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        p.hist[(p.step + 1) & (kDirtyHist - 1)] = 0;
-        p.n_dirty[(p.step + 2) & (kDirtyRing - 1)] = 0;
+    const int64_t threads = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < p.nb; i += threads) {
+        p.dclear[i] = 0u;
+        p.cclear[i] = 0u;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.hist[(p.step + 1) & (kDirtyHist - 1)] = 0;
 }
 
-// Appends row (changed in product t) to C_t, and the rows naming it to
-// D_{t+1}; called by every lane of one wave.
-__device__ __forceinline__ void dirty_push(const DirtyParams &p, int32_t row, int lane) {
+// Evaluates words [w0, w0 + 64 GC) of NR rows (W >= 64) into U, their loads
+// interleaved; bit k of the result (in every lane) is set if a word of
+// rows[k] changed, and then that row's sets are updated (the waves of the
+// row's other chunks may do the same: the sets are ORed).
+template <int GC, int NR>
+__device__ __forceinline__ uint32_t dirty_eval_chunk(const DirtyParams &p, const int32_t *rows, int64_t w0, int lane) {
     const int32_t t = p.step;
-    if (lane == 0) p.changed_out[atomicAdd((uint32_t *)&p.hist[t & (kDirtyHist - 1)], 1u)] = row;
-    const int32_t o0 = p.occ_ptr[row], o1 = p.occ_ptr[row + 1];
-    for (int32_t j = o0 + lane; j < o1; j += 64) {
-        const int32_t r = p.occ[j];
-        if (atomicMax(&p.dmark[r], t + 1) < t + 1)
-            p.dirty_out[atomicAdd(&p.n_dirty[(t + 1) & (kDirtyRing - 1)], 1u)] = r;
+    const int64_t w = w0 + lane;
+    int32_t s[NR], e[NR];
+    bool is_and[NR];
+    int32_t most = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        s[r] = p.row_ptr[rows[r]];
+        e[r] = p.row_ptr[rows[r] + 1];
+        is_and[r] = (p.and_bits[rows[r] >> 6] >> (rows[r] & 63)) & 1ull;
+        most = e[r] - s[r] > most ? e[r] - s[r] : most;
     }
-}
-
-// One wave per (row, chunk of 64 GC words); W >= 64 (log2W >= 6). Items are
-// the copies of C_{t-1}'s rows first, then the evaluations of D_t's rows.
-template <int GC>
-__global__ __launch_bounds__(kBlock) void spmm_dirty_product_kernel(DirtyParams p) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int32_t t = p.step;
-    dirty_clear_ahead(p);
-    const int64_t n_copy = t >= 2 ? (int64_t)(uint32_t)p.hist[(t - 1) & (kDirtyHist - 1)] : 0;
-    if (t >= 2 && n_copy == 0) return;
-    const int64_t n_rows = (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
-    constexpr int kLog2GC = GC == 8 ? 3 : GC == 4 ? 2 : GC == 2 ? 1 : 0;
-    const int32_t log2G = p.log2W - 6 - kLog2GC;
-    const int64_t n_copy_items = n_copy << log2G;
-    const int64_t n_items = n_copy_items + (n_rows << log2G);
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); it < n_items;
-         it += waves) {
-        if (it < n_copy_items) {
-            const int32_t row = p.changed_prev[it >> log2G];
-            if (p.dmark_cur[row] == t) continue;  // in D_t: its evaluation writes it
-            const int64_t at = ((int64_t)row << p.log2W) + ((it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
-            uint64_t x[GC];
+    uint64_t acc[NR][GC];
 #pragma unroll
-            for (int k = 0; k < GC; ++k) x[k] = p.V[at + 64 * k];
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-            for (int k = 0; k < GC; ++k) p.U[at + 64 * k] = x[k];
-            continue;
-        }
-        const int64_t e_it = it - n_copy_items;
-        const int32_t row = p.dirty[e_it >> log2G];
-        const int64_t w0 = ((e_it & ((1ll << log2G) - 1)) * 64 * GC) + lane;
-        const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
-        const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
-        uint64_t acc[GC];
+        for (int k = 0; k < GC; ++k) acc[r][k] = is_and[r] ? ~0ull : 0ull;
+    // two entries of every row per pass; a row shorter than the longest
+    // repeats its last entry (harmless for AND and OR alike)
+    for (int32_t i = 0; i < most; i += 2) {
+        uint64_t x[NR][2][GC];
 #pragma unroll
-        for (int k = 0; k < GC; ++k) acc[k] = is_and ? ~0ull : 0ull;
-        for (int32_t i = s; i < e; i += 2) {
-            uint64_t x[2][GC];
+        for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int64_t c = p.col[i + j < e ? i + j : e - 1];
+                const int32_t at = s[r] + i + j;
+                const int64_t c = p.col[at < e[r] ? at : (e[r] > s[r] ? e[r] - 1 : s[r])];
 #pragma unroll
-                for (int k = 0; k < GC; ++k) x[j][k] = p.V[(c << p.log2W) + w0 + 64 * k];
+                for (int k = 0; k < GC; ++k) x[r][j][k] = e[r] > s[r] ? p.V[(c << p.log2W) + w + 64 * k] : 0ull;
             }
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int k = 0; k < GC; ++k) acc[k] = is_and ? (acc[k] & x[j][k]) : (acc[k] | x[j][k]);
-        }
-        bool diff = false;
+                for (int k = 0; k < GC; ++k)
+                    acc[r][k] = is_and[r] ? (acc[r][k] & x[r][j][k]) : (acc[r][k] | x[r][j][k]);
+    }
+    uint32_t changed = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int32_t row = rows[r];
         const bool first_varies = row < p.n_std && !((p.fact_bits[row >> 6] >> (row & 63)) & 1ull);
+        bool diff = false;
 #pragma unroll
         for (int k = 0; k < GC; ++k) {
-            const int64_t at = ((int64_t)row << p.log2W) + w0 + 64 * k;
-            const uint64_t a = s == e ? 0ull : acc[k];
+            const int64_t at = ((int64_t)row << p.log2W) + w + 64 * k;
+            const uint64_t a = s[r] == e[r] ? 0ull : acc[r][k];
             diff |= t == 1 ? (first_varies && a != 0ull) : (a != p.V[at]);
             p.U[at] = a;
         }
-        if (__ballot(diff) == 0) continue;
-        int32_t first = 0;
-        if (lane == 0) first = atomicMax(&p.cmark[row], t) < t;
-        if (__builtin_amdgcn_readfirstlane(first)) dirty_push(p, row, lane);
+        if (__ballot(diff) != 0) {
+            dirty_changed(p, row, lane);
+            changed |= 1u << r;
+        }
     }
+    return changed;
 }
 
-// W < 64: one thread per word; the W lanes of a row are consecutive in the
-// wave (W divides 64). Copies of C_{t-1}'s rows first, then evaluations; a
-// changed row is appended by the lowest lane of the wave holding one, a row
-// per pass, and the wave pushes its namers.
-__global__ __launch_bounds__(kBlock) void spmm_dirty_product_small_kernel(DirtyParams p) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
+// W >= 64: a wave takes a quarter of a bitmap word (8 rows) and one chunk of
+// 64 GC words of each of its rows at a time, so rows close together are
+// spread over waves.
+template <int GC>
+__global__ __launch_bounds__(kBlock) void spmm_dirty_product_kernel(DirtyParams p) {
+    const int lane = threadIdx.x & 63;
     const int32_t t = p.step;
     dirty_clear_ahead(p);
-    const int64_t n_copy = t >= 2 ? (int64_t)(uint32_t)p.hist[(t - 1) & (kDirtyHist - 1)] : 0;
-    if (t >= 2 && n_copy == 0) return;
-    const int64_t n_rows = (int64_t)p.n_dirty[t & (kDirtyRing - 1)];
-    const int32_t W = 1 << p.log2W;
-    const int64_t copy_total = n_copy << p.log2W;
-    const int64_t total = copy_total + (n_rows << p.log2W);
-    // whole waves iterate together so the ballot sees every lane of a row
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t g0 = (int64_t)blockIdx.x * kBlock + (tid & ~63); g0 < total; g0 += stride) {
-        const int64_t g = g0 + lane;
-        bool diff = false;
-        int32_t row = -1;
-        if (g < copy_total) {
-            const int32_t r = p.changed_prev[g >> p.log2W];
-            if (p.dmark_cur[r] != t) {
-                const int64_t at = ((int64_t)r << p.log2W) + (g & (W - 1));
-                p.U[at] = p.V[at];
-            }
-        } else if (g < total) {
-            const int64_t pos = (g - copy_total) >> p.log2W;
-            row = p.dirty[pos];
-            const int64_t w = g & (W - 1);
-            const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
-            const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
-            uint64_t acc = is_and ? ~0ull : 0ull;
-            for (int32_t i = s; i < e; ++i) {
-                const uint64_t x = p.V[((int64_t)p.col[i] << p.log2W) + w];
-                acc = is_and ? (acc & x) : (acc | x);
-            }
-            if (s == e) acc = 0;
-            const int64_t at = ((int64_t)row << p.log2W) + w;
-            if (t == 1)
-                diff = row < p.n_std && !((p.fact_bits[row >> 6] >> (row & 63)) & 1ull) && acc != 0ull;
-            else
-                diff = acc != p.V[at];
-            p.U[at] = acc;
+    if (t >= 2 && p.hist[(t - 1) & (kDirtyHist - 1)] == 0) return;
+    constexpr int kLog2GC = GC == 8 ? 3 : GC == 4 ? 2 : GC == 2 ? 1 : 0;
+    const int32_t log2G = p.log2W - 6 - kLog2GC;  // chunks per row
+    const int64_t n_items = (p.nb << log2G) << 2;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    bool any = false;
+    for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+         it < n_items; it += waves) {
+        const int q = (int)(it & 3);
+        const int64_t ic = it >> 2;
+        const int64_t i = ic >> log2G;
+        const int64_t w0 = (ic & ((1ll << log2G) - 1)) * 64 * GC;
+        const uint32_t quarter = 0xFFu << (8 * q);
+        const uint32_t d = p.dcur[i];
+        uint32_t dw = d & quarter;
+        uint32_t cw = t >= 2 ? (p.cprev[i] & ~d & quarter) : 0u;
+        const int64_t row0 = i * 32;
+        while (cw) {
+            const int b = __builtin_ctz(cw);
+            cw &= cw - 1;
+            const int64_t base = ((row0 + b) << p.log2W) + w0 + lane;
+            uint64_t x[GC];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) x[k] = p.V[base + 64 * k];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) p.U[base + 64 * k] = x[k];
         }
-        // one flag per row: its first lane holds whether any of its W words changed
-        const uint64_t b = __ballot(diff);
-        const uint64_t mine = ((W >= 64) ? ~0ull : ((1ull << W) - 1ull)) << (lane & ~(W - 1));
-        const bool lead = row >= 0 && (lane & (W - 1)) == 0 && (b & mine) != 0 && atomicMax(&p.cmark[row], t) < t;
-        uint64_t leads = __ballot(lead);
-        while (leads) {
-            const int src = __builtin_ctzll(leads);
-            leads &= leads - 1;
-            dirty_push(p, __shfl(row, src, 64), lane);
+        while (dw) {  // two rows at a time, their loads interleaved
+            int32_t rows[2];
+            rows[0] = (int32_t)(row0 + __builtin_ctz(dw));
+            dw &= dw - 1;
+            if (dw) {
+                rows[1] = (int32_t)(row0 + __builtin_ctz(dw));
+                dw &= dw - 1;
+                any |= dirty_eval_chunk<GC, 2>(p, rows, w0, lane) != 0u;
+            } else {
+                any |= dirty_eval_chunk<GC, 1>(p, rows, w0, lane) != 0u;
+            }
         }
     }
+    if (any && lane == 0) p.hist[t & (kDirtyHist - 1)] = 1;
+}
+
+// W < 64: a wave takes 8 bitmap words (256 rows) at a time and evaluates
+// their rows 64 / W per pass, one lane per word (the W lanes of a row are
+// consecutive in the wave).
+__global__ __launch_bounds__(kBlock) void spmm_dirty_product_small_kernel(DirtyParams p) {
+    const int lane = threadIdx.x & 63;
+    const int32_t t = p.step;
+    dirty_clear_ahead(p);
+    if (t >= 2 && p.hist[(t - 1) & (kDirtyHist - 1)] == 0) return;
+    const int32_t W = 1 << p.log2W;
+    const int R = 64 >> p.log2W;  // rows per pass
+    const int slot = lane >> p.log2W, w = lane & (W - 1);
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    bool any = false;
+    for (int64_t i0 = gw * 8; i0 < p.nb; i0 += waves * 8) {
+        const int64_t i = i0 + (lane & 7);
+        uint32_t d = 0, c = 0;
+        if (lane < 8 && i < p.nb) {
+            d = p.dcur[i];
+            c = t >= 2 ? (p.cprev[i] & ~d) : 0u;
+        }
+        uint64_t m = __ballot((d | c) != 0u);
+        while (m) {
+            const int src = __builtin_ctzll(m);
+            m &= m - 1;
+            const int64_t row0 = (i0 + src) * 32;
+            uint32_t cw = __builtin_amdgcn_readlane(c, src), dw = __builtin_amdgcn_readlane(d, src);
+            while (cw) {  // copies, R rows per pass
+                int32_t row = -1;
+                for (int sl = 0; sl < R && cw; ++sl) {
+                    const int b = __builtin_ctz(cw);
+                    cw &= cw - 1;
+                    if (sl == slot) row = (int32_t)(row0 + b);
+                }
+                if (row >= 0) {
+                    const int64_t at = ((int64_t)row << p.log2W) + w;
+                    p.U[at] = p.V[at];
+                }
+            }
+            while (dw) {  // evaluations, R rows per pass
+                int32_t row = -1;
+                for (int sl = 0; sl < R && dw; ++sl) {
+                    const int b = __builtin_ctz(dw);
+                    dw &= dw - 1;
+                    if (sl == slot) row = (int32_t)(row0 + b);
+                }
+                bool diff = false;
+                if (row >= 0) {
+                    const int32_t s = p.row_ptr[row], e = p.row_ptr[row + 1];
+                    const bool is_and = (p.and_bits[row >> 6] >> (row & 63)) & 1ull;
+                    uint64_t acc = is_and ? ~0ull : 0ull;
+                    // four entries per pass, their loads issued together (the last one repeats past the end)
+                    for (int32_t k = s; k < e; k += 4) {
+                        int64_t cc[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) cc[q] = p.col[k + q < e ? k + q : e - 1];
+                        uint64_t x[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) x[q] = p.V[(cc[q] << p.log2W) + w];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc = is_and ? (acc & x[q]) : (acc | x[q]);
+                    }
+                    if (s == e) acc = 0;
+                    const int64_t at = ((int64_t)row << p.log2W) + w;
+                    if (t == 1)
+                        diff = row < p.n_std && !((p.fact_bits[row >> 6] >> (row & 63)) & 1ull) && acc != 0ull;
+                    else
+                        diff = acc != p.V[at];
+                    p.U[at] = acc;
+                }
+                // a row changed iff one of its W lanes saw a difference; its first lane leads
+                const uint64_t b = __ballot(diff);
+                const uint64_t mine = ((W >= 64) ? ~0ull : ((1ull << W) - 1ull)) << (lane & ~(W - 1));
+                uint64_t leads = __ballot(row >= 0 && w == 0 && (b & mine) != 0);
+                any |= leads != 0;
+                while (leads) {
+                    const int l = __builtin_ctzll(leads);
+                    leads &= leads - 1;
+                    dirty_changed(p, __shfl(row, l, 64), lane);
+                }
+            }
+        }
+    }
+    if (any && lane == 0) p.hist[t & (kDirtyHist - 1)] = 1;
 }
 
 // D_1: the rows naming a fact row or a qbar row (the rows the initial matrix
-// does not hold at 0). One wave per such row.
+// does not hold at 0); the cumulative set of changed rows cleared. One wave
+// per fact row; the qbar rows' occurrences
+// (one contiguous range of the transposed matrix, since the qbar rows are the
+// last rows) are split 64 entries per wave over the grid, as a qbar row can
+// be named by a large share of all rows.
 __global__ __launch_bounds__(kBlock) void spmm_dirty_seed_kernel(DirtyParams p, const int32_t *facts, int32_t n_facts) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int64_t n_seed = (int64_t)n_facts + (p.n_rows - p.n_std);
+    const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(tid >> 6); q < n_seed;
-         q += waves) {
-        const int32_t row = q < n_facts ? facts[q] : p.n_std + (int32_t)(q - n_facts);
+    const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the cumulative set of changed rows starts empty (the previous solve's reset read it)
+    const int64_t threads = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < p.nb; i += threads) p.call[i] = 0u;
+    for (int64_t q = wave; q < n_facts; q += waves) {
+        const int32_t row = facts[q];
         const int32_t o0 = p.occ_ptr[row], o1 = p.occ_ptr[row + 1];
-        for (int32_t j = o0 + lane; j < o1; j += 64) {
-            const int32_t r = p.occ[j];
-            if (atomicMax(&p.dmark[r], 1) < 1) p.dirty_out[atomicAdd(&p.n_dirty[1], 1u)] = r;
-        }
+        for (int32_t j = o0 + lane; j < o1; j += 64) bit_or(p.dnext, p.occ[j]);
     }
+    const int64_t b0 = p.occ_ptr[p.n_std], b1 = p.occ_ptr[p.n_rows];
+    for (int64_t j = b0 + wave * 64 + lane; j < b1; j += waves * 64) bit_or(p.dnext, p.occ[j]);
 }
 
 // Back to the initial matrix after a solve by dirty rows: every row that
-// changed in some product (C mark > 0; never a fact or qbar row, which keep
-// their initial values) is set to 0 in both buffers, and the marks, the |D_t|
-// ring and the |C_t| history are cleared. One wave per row; the wave that
-// reads a row's mark also clears it. marks: [cmark n | dm0 n | dm1 n | ring |
-// hist], n = max(n_rows, 1).
+// changed in some product (the cumulative set; never a fact or qbar row,
+// which keep their initial values) is set to 0 in both buffers, and the D and
+// C sets and the history are cleared (the cumulative set is cleared by the
+// next solve's seed, as waves here read it until the end). sets: [D0 | D1 |
+// D2 | C0 | C1 | C2 | changed], nb words each, then the history. A wave takes
+// one bitmap word and 64 words of each of its rows at a time.
 __global__ __launch_bounds__(kBlock) void spmm_dirty_reset_kernel(uint64_t *b0, uint64_t *b1, int32_t log2W,
-                                                                  int32_t *marks, int32_t n) {
+                                                                  uint32_t *sets, int64_t nb) {
     const int lane = threadIdx.x & 63;
-    const int64_t W = 1ll << log2W;
+    const int32_t log2G = log2W > 6 ? log2W - 6 : 0;  // 64-word chunks per row
+    const int64_t n_items = nb << log2G;
     const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t r = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); r < n;
-         r += waves) {
-        if (marks[r] > 0) {
-            const int64_t base = r << log2W;
-            for (int64_t w = lane; w < W; w += 64) {
-                b0[base + w] = 0ull;
-                b1[base + w] = 0ull;
+    const uint32_t *call = sets + 6 * nb;
+    for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+         it < n_items; it += waves) {
+        const int64_t i = it >> log2G;
+        const int64_t w = ((it & ((1ll << log2G) - 1)) << 6) + lane;
+        uint32_t bits = call[i];
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1;
+            if (w < (1ll << log2W)) {
+                const int64_t at = ((i * 32 + b) << log2W) + w;
+                b0[at] = 0ull;
+                b1[at] = 0ull;
             }
         }
-        if (lane == 0) {
-            marks[r] = 0;
-            marks[n + r] = 0;
-            marks[2 * (int64_t)n + r] = 0;
-        }
     }
-    if (blockIdx.x == 0 && threadIdx.x < kDirtyRing + kDirtyHist) marks[3 * (int64_t)n + threadIdx.x] = 0;
+    const int64_t threads = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < 6 * nb + kDirtyHist; i += threads) {
+        if (i < 6 * nb)
+            sets[i] = 0u;
+        else
+            sets[7 * nb + (i - 6 * nb)] = 0u;
+    }
 }
 
-hipError_t launch_dirty_reset(uint64_t *b0, uint64_t *b1, int32_t log2W, int32_t *marks, int32_t n, int max_grid,
+hipError_t launch_dirty_reset(uint64_t *b0, uint64_t *b1, int32_t log2W, uint32_t *sets, int64_t nb, int max_grid,
                               hipStream_t st) {
     hipLaunchKernelGGL(spmm_dirty_reset_kernel, dim3((unsigned)std::max(1, max_grid)), dim3(kBlock), 0, st, b0, b1,
-                       log2W, marks, n);
+                       log2W, sets, nb);
     return hipGetLastError();
 }
 
@@ -505,16 +599,20 @@ hipError_t launch_dirty_seed(const DirtyParams &p, const int32_t *facts, int32_t
 
 hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st) {
     const unsigned grid = (unsigned)std::max(1, max_grid);
-    if (p.log2W >= 9)
-        hipLaunchKernelGGL((spmm_dirty_product_kernel<8>), dim3(grid), dim3(kBlock), 0, st, p);
-    else if (p.log2W == 8)
-        hipLaunchKernelGGL((spmm_dirty_product_kernel<4>), dim3(grid), dim3(kBlock), 0, st, p);
-    else if (p.log2W == 7)
-        hipLaunchKernelGGL((spmm_dirty_product_kernel<2>), dim3(grid), dim3(kBlock), 0, st, p);
-    else if (p.log2W == 6)
-        hipLaunchKernelGGL((spmm_dirty_product_kernel<1>), dim3(grid), dim3(kBlock), 0, st, p);
-    else
+    if (p.log2W < 6) {
         hipLaunchKernelGGL(spmm_dirty_product_small_kernel, dim3(grid), dim3(kBlock), 0, st, p);
+        return hipGetLastError();
+    }
+    // chunks of 64 x 8 words where rows are that wide: a wave's rows in one
+    // bitmap word are evaluated one pair after another whatever the chunk, so
+    // wide chunks keep the most loads in flight
+    const int log2GC = std::min(3, p.log2W - 6);
+    switch (log2GC) {
+        case 3: hipLaunchKernelGGL((spmm_dirty_product_kernel<8>), dim3(grid), dim3(kBlock), 0, st, p); break;
+        case 2: hipLaunchKernelGGL((spmm_dirty_product_kernel<4>), dim3(grid), dim3(kBlock), 0, st, p); break;
+        case 1: hipLaunchKernelGGL((spmm_dirty_product_kernel<2>), dim3(grid), dim3(kBlock), 0, st, p); break;
+        default: hipLaunchKernelGGL((spmm_dirty_product_kernel<1>), dim3(grid), dim3(kBlock), 0, st, p); break;
+    }
     return hipGetLastError();
 }
 

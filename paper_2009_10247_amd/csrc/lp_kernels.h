@@ -211,6 +211,7 @@ struct DirtyParams {
     int32_t n_std;
     int32_t log2W;
     int32_t step;
+    int32_t wpi;                 // bitmap words per wave at a time (narrow rows), 1..8
 };
 hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t st);
 // Rows changed during a solve back to 0 in both buffers, sets and history

@@ -1184,12 +1184,13 @@ static SpmmParams spmm_params(const Matrix &m, unsigned long long *counters, int
     return p;
 }
 
-// Stable-model products by dirty rows or full sweeps. Dirty rows take two
-// launches per product and pay off once a full product is large: measured on
-// MI355X, at 17.6k and 168k row-words per matrix full sweeps were faster
-// (0.25 vs 0.42 ms, 0.33 vs 0.55 ms per solve), at 438k they tied, and from
-// 1.5M row-words on dirty rows won (1.3x to 4.2x).
-constexpr int64_t kDirtyMinWords = 1 << 19;
+// Stable-model products by dirty rows or full sweeps. Measured on MI355X
+// (HIP events per solve, dirty rows against full sweeps): 17.6k row-words
+// 0.14 vs 0.20 ms, 168k (4-word rows, product 1 nearly dense) 0.37 vs 0.34 ms,
+// 436k 0.15 vs 0.37 ms, 1.75M 0.16 vs 0.46 ms, 28M 0.32 vs 2.0 ms. Below 16k
+// row-words a solve is a few launches either way, and full sweeps spare the
+// transposed matrix and the solve plan's capture.
+constexpr int64_t kDirtyMinWords = 1 << 14;
 
 static bool dirty_products(const Matrix &m, int32_t log2W) {
     if ((m.flags & LP_STABLE_FULL_SWEEP) || m.n_rows == 0) return false;
@@ -1294,7 +1295,11 @@ static hipError_t dirty_products_launch(DirtyState &s, int64_t t0, int64_t t1, h
         p.cprev = dirty_c(s, t + 2);  // C_{t-1}
         p.ccur = dirty_c(s, t);
         p.cclear = dirty_c(s, t + 1);
-        hipError_t e = launch_dirty_product(p, t == 1 ? s.grid : s.grid_small, st);
+        const int grid = t == 1 ? s.grid : s.grid_small;
+        // narrow rows: enough bitmap words per wave to cover the bitmap in
+        // about two rounds of the grid's waves, so dense sets spread over all waves
+        p.wpi = (int32_t)std::max<int64_t>(1, std::min<int64_t>(8, s.nb / (2 * (int64_t)grid * 4)));
+        hipError_t e = launch_dirty_product(p, grid, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -308,9 +308,10 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_product_kernel(DirtyParams 
     if (any && lane == 0) p.hist[t & (kDirtyHist - 1)] = 1;
 }
 
-// W < 64: a wave takes 8 bitmap words (256 rows) at a time and evaluates
-// their rows 64 / W per pass, one lane per word (the W lanes of a row are
-// consecutive in the wave).
+// W < 64: a wave takes p.wpi bitmap words (32 p.wpi rows; the host picks 1 to
+// 8 so that the grid's waves all get work) at a time and evaluates their rows
+// 64 / W per pass, one lane per word (the W lanes of a row are consecutive in
+// the wave).
 __global__ __launch_bounds__(kBlock) void spmm_dirty_product_small_kernel(DirtyParams p) {
     const int lane = threadIdx.x & 63;
     const int32_t t = p.step;
@@ -322,10 +323,11 @@ __global__ __launch_bounds__(kBlock) void spmm_dirty_product_small_kernel(DirtyP
     const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
     const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     bool any = false;
-    for (int64_t i0 = gw * 8; i0 < p.nb; i0 += waves * 8) {
-        const int64_t i = i0 + (lane & 7);
+    const int64_t wpi = p.wpi;
+    for (int64_t i0 = gw * wpi; i0 < p.nb; i0 += waves * wpi) {
+        const int64_t i = i0 + lane;
         uint32_t d = 0, c = 0;
-        if (lane < 8 && i < p.nb) {
+        if (lane < wpi && i < p.nb) {
             d = p.dcur[i];
             c = t >= 2 ? (p.cprev[i] & ~d) : 0u;
         }

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import threading
 
 import numpy as np
 
@@ -332,7 +333,16 @@ class Matrix:
         acc = np.zeros(Wf, dtype=np.uint64)
         n_models = ctypes.c_int64(0)
         prods = ctypes.c_int32(0)
-        models = np.zeros((max(max_models, 1), max(self.n_atoms, 1)), dtype=np.uint8) if want_models else None
+        models = None
+        if want_models:
+            # the library writes only the first min(n_models, max_models) rows; the
+            # buffer is kept with the matrix (one per thread) and the rows written
+            # are copied out
+            shape = (max(max_models, 1), max(self.n_atoms, 1))
+            tls = self.__dict__.setdefault("_tls", threading.local())
+            if getattr(tls, "mbuf", None) is None or tls.mbuf.shape != shape:
+                tls.mbuf = np.empty(shape, dtype=np.uint8)
+            models = tls.mbuf
         interp = np.zeros((max(self.n_atoms, 1), Wf), dtype=np.uint64) if want_interp else None
         rc = _check(load().lp_stable_models(self._h, acc.ctypes.data, ctypes.addressof(n_models),
                                             models.ctypes.data if models is not None else None,
@@ -343,7 +353,7 @@ class Matrix:
         nm = n_models.value
         out = dict(accepted=acc, n_models=nm, products=prods.value, truncated=rc == LP_E_TRUNCATED)
         if models is not None:
-            out["models"] = models[: min(nm, max_models), : self.n_atoms]
+            out["models"] = models[: min(nm, max_models), : self.n_atoms].copy()
         if interp is not None:
             out["interp"] = interp[: self.n_atoms]
         return out
@@ -376,7 +386,7 @@ class Matrix:
         out = dict(accepted=acc, n_models=nm, products=prods.value, kernel_ms=ms.value,
                    truncated=rc == LP_E_TRUNCATED)
         if models is not None:
-            out["models"] = models[: min(nm, max_models), : self.n_atoms]
+            out["models"] = models[: min(nm, max_models), : self.n_atoms].copy()
         return out
 
     def bench_step(self, reps: int = 100, sched=None, stream=None) -> float:

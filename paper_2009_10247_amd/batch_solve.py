@@ -8,7 +8,11 @@ checked against single-program solves. With --copy-mb, one device-to-device
 copy of that many MiB follows (a known-size kernel that calibrates byte
 counters in a profile of the same run).
 
-    python -m paper_2009_10247_amd.batch_solve [--reps 20] [--count 512] [--seed 0]
+    python -m paper_2009_10247_amd.batch_solve [--reps 20] [--count 512] [--seed 0] [--shape 2,8,1024]
+
+--shape wpw,unroll,block fixes the kernel shape instead of autotuning it, and
+--no-check skips the comparison with single-program solves, so that a profile
+holds batch launches of one shape only.
 """
 from __future__ import annotations
 
@@ -24,6 +28,8 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0)
+    ap.add_argument("--shape", default=None, help="wpw,unroll,block (no autotuning)")
+    ap.add_argument("--no-check", action="store_true", help="skip the single-program solves (profiles)")
     args = ap.parse_args(argv)
     import torch
 
@@ -34,12 +40,16 @@ def main(argv=None) -> int:
     progs = gen.batch_programs(args.seed, args.count)
     mats = [lp.Matrix(p, stream=st) for p in progs]
     try:
-        with lp.Batch(mats, stream=st) as plan:
-            if not args.no_tune:
+        sched = None
+        if args.shape:
+            sched = lp.lp_schedule()
+            sched.wpw, sched.unroll, sched.block = (int(x) for x in args.shape.split(","))
+        with lp.Batch(mats, sched=sched, stream=st) as plan:
+            if not args.no_tune and not args.shape:
                 plan.tune(reps=3, stream=st)
             plan.run(stream=st)
             res = plan.results(stream=st)
-            for m, (g, pr) in zip(mats, res):
+            for m, (g, pr) in ([] if args.no_check else zip(mats, res)):
                 g2, pr2 = m.least_model(stream=st)
                 assert pr == pr2 and (g == g2).all(), "batch result differs from the single-program solve"
             torch.cuda.synchronize()

@@ -18,12 +18,15 @@
 //
 // A program much larger than a workgroup's share of the batch is solved by a
 // team of G workgroups (its G queue positions come first, so all members
-// start at once). Member m evaluates every G-th super-block, OR row and
-// segment; after each product the members OR their result buffers into a
-// global copy of the interpretation, meet at a bounded team barrier and load
-// the union. The result of product t goes to global buffer t mod 2, which
-// holds v_{t-2}, a subset of v_t, so after the barrier it is exactly v_t and
-// the products are those of the one-workgroup loop.
+// start at once). Member m evaluates the m-th of G contiguous ranges of
+// super-blocks and every G-th OR row and segment; after each product the
+// members OR the rows they found new (true now, not in v_{t-1}) into a
+// global delta buffer, meet at a bounded team barrier and take v_t as v_{t-1}
+// OR the delta. The products are those of the one-workgroup loop.
+//
+// Within a workgroup the waves take super-blocks one at a time from an LDS
+// counter, so a wave that runs ahead takes more of them (a static split left
+// the waves of a workgroup waiting for the slowest at every product).
 #include <hip/hip_runtime.h>
 
 #include "lp_dev.h"
@@ -43,6 +46,29 @@ using gp = const __attribute__((address_space(1))) T *;
 template <class T>
 __device__ __forceinline__ gp<T> as_global(const T *p) {
     return (gp<T>)p;
+}
+
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+typedef __attribute__((address_space(1))) int32_t g_i32;
+
+template <class T>
+using cp = const __attribute__((address_space(4))) T *;
+
+template <class T>
+__device__ __forceinline__ cp<T> as_const(const T *p) {
+    return (cp<T>)p;
+}
+
+// A program descriptor read word by word through the constant address space.
+__device__ __forceinline__ ProgDesc load_desc(const ProgDesc *p) {
+    static_assert(sizeof(ProgDesc) % 4 == 0, "descriptor words");
+    ProgDesc d;
+    const cp<uint32_t> s = (cp<uint32_t>)(const void *)p;
+    uint32_t *o = reinterpret_cast<uint32_t *>(&d);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(ProgDesc) / 4); ++i) o[i] = s[i];
+    return d;
 }
 
 // A program's layout as the evaluation reads it: in global memory (AS = 1),
@@ -186,27 +212,42 @@ __device__ __forceinline__ void wg_load_super_block(const P &d, int64_t sb, int6
     }
 }
 
-// AND rows of the block pass (see BlockPass in lp_step.hip).
-// Member `member` of a team of `team` workgroups takes every team-th share.
+// AND rows of the block pass (see BlockPass in lp_step.hip). Member `member`
+// of a team of `team` workgroups takes the super-blocks [n_sb member / team,
+// n_sb (member + 1) / team); ctr hands them out (zero before the product).
 template <int WPW, int U, class P>
 __device__ __forceinline__ uint32_t wg_block_rows(const P &d, const lds_u64 *v, lds_u64 *u,
-                                                  lds_u64 *s_ball, int32_t member, int32_t team) {
+                                                  lds_u64 *s_ball, int32_t member, int32_t team, lds_u32 *ctr) {
     const int lane = threadIdx.x & 63;
-    const int waves = blockDim.x >> 6;
-    const int64_t stride = (int64_t)team * waves;
     const int64_t n_words = ((int64_t)d.n_rows + 63) >> 6;
     const int64_t n_sb = (n_words + WPW - 1) / WPW;
     const lds_u8 *v8 = (const lds_u8 *)v;
     const lds_u32 *b32 = (const lds_u32 *)s_ball;
     uint32_t my_new = 0;
-    int64_t sb = (int64_t)member * waves + (threadIdx.x >> 6);
-    if (sb >= n_sb) return 0;
+    // this member's super-blocks [sb0, sb1), handed out to the waves one at a
+    // time by an LDS counter (cleared before the product), so waves that run
+    // ahead take more of them
+    const int64_t sb0 = n_sb * member / team, sb1 = n_sb * (member + 1) / team;
+    auto grab = [&]() -> int64_t {
+        uint32_t k = 0;
+        if (lane == 0) k = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return sb0 + (int64_t)__builtin_amdgcn_readlane(k, 0);
+    };
+    int64_t sb = grab();
+    if (sb >= sb1) return 0;
     WgSuperBlock<WPW> cur;
     wg_load_super_block<WPW, P>(d, sb, n_words, cur);
-    for (; sb < n_sb; sb += stride) {
+    // the round being folded has its chunks loaded while the previous round
+    // is folded: c holds the chunks at `base`
+    int32_t base = __builtin_amdgcn_readfirstlane(cur.base[0]) & ~63;
+    int32_t c[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) c[k] = d.col[base + 64 * k + lane];
+    for (;;) {
         WgSuperBlock<WPW> nxt;
-        const bool more = sb + stride < n_sb;
-        if (more) wg_load_super_block<WPW, P>(d, sb + stride, n_words, nxt);
+        const int64_t sbn = grab();
+        const bool more = sbn < sb1;
+        if (more) wg_load_super_block<WPW, P>(d, sbn, n_words, nxt);
         const int64_t w0 = sb * WPW;
         bool acc[WPW];
         int32_t st[WPW], en[WPW];
@@ -216,35 +257,48 @@ __device__ __forceinline__ uint32_t wg_block_rows(const P &d, const lds_u64 *v, 
             en[w] = st[w] + cur.len[w];
             acc[w] = (cur.andb[w] >> lane) & 1ull;
         }
-        const int32_t e0 = __builtin_amdgcn_readfirstlane(cur.base[0]);
         const int32_t e1 = __builtin_amdgcn_readlane(en[WPW - 1], 63);
-        for (int32_t base = e0 & ~63; base < e1; base += 64 * U) {
-            const auto cb = d.col + base;
-            int32_t c[U];
+        for (;;) {
+            // next chunks: this super-block's next round, else the next super-block's first
+            const bool last = base + 64 * U >= e1;
+            const int32_t nb = !last ? base + 64 * U
+                                     : (more ? (__builtin_amdgcn_readfirstlane(nxt.base[0]) & ~63) : -1);
+            int32_t cn[U];
+            if (nb >= 0) {
 #pragma unroll
-            for (int k = 0; k < U; ++k) c[k] = cb[64 * k + lane];
-            uint32_t x[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) x[k] = entry_word(v8, c[k]);
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[k], (uint32_t)c[k], 1u));
-                if (lane == 0) s_ball[k] = B;
+                for (int k = 0; k < U; ++k) cn[k] = d.col[nb + 64 * k + lane];
             }
-            const int32_t lim = base + 64 * U;
+            if (base < e1) {
+                uint32_t x[U];
 #pragma unroll
-            for (int w = 0; w < WPW; ++w) {
-                int32_t lo = st[w] > base ? st[w] : base;
-                const int32_t hi = en[w] < lim ? en[w] : lim;
-                while (lo < hi) {
-                    const int32_t rel = lo - base;
-                    const int32_t n = hi - lo < 32 ? hi - lo : 32;
-                    const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
-                    const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
-                    acc[w] = acc[w] && ((win & m) == m);
-                    lo += n;
+                for (int k = 0; k < U; ++k) x[k] = entry_word(v8, c[k]);
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[k], (uint32_t)c[k], 1u));
+                    if (lane == 0) s_ball[k] = B;
+                }
+                const int32_t lim = base + 64 * U;
+#pragma unroll
+                for (int w = 0; w < WPW; ++w) {
+                    int32_t lo = st[w] > base ? st[w] : base;
+                    const int32_t hi = en[w] < lim ? en[w] : lim;
+                    while (lo < hi) {
+                        const int32_t rel = lo - base;
+                        const int32_t n = hi - lo < 32 ? hi - lo : 32;
+                        const uint32_t win =
+                            __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
+                        const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
+                        acc[w] = acc[w] && ((win & m) == m);
+                        lo += n;
+                    }
                 }
             }
+            if (nb >= 0) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) c[k] = cn[k];
+            }
+            base = nb;
+            if (last) break;
         }
 #pragma unroll
         for (int w = 0; w < WPW; ++w) {
@@ -256,7 +310,9 @@ __device__ __forceinline__ uint32_t wg_block_rows(const P &d, const lds_u64 *v, 
                 }
             }
         }
-        if (more) cur = nxt;
+        if (!more) break;
+        cur = nxt;
+        sb = sbn;
     }
     return my_new;
 }
@@ -327,19 +383,60 @@ __device__ __forceinline__ uint32_t wg_and_rows_by_lane(const Prog<3> &d, const 
     return my_new;
 }
 
-// OR rows (one lane each) and long rows (one wave per OR segment, one wave per
-// whole long AND row, looping over its segments).
+// The first four OR rows of this thread (member `member` of a team of `team`
+// workgroups), loaded at the start of a product so that their loads are in
+// flight with the AND pass's.
+struct OrRows {
+    int32_t row[4], c0[4], c1[4];
+};
+
+template <class P>
+__device__ __forceinline__ void or_rows_load(const P &d, int64_t j0, int64_t ostride, OrRows &o) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 + q * ostride;
+        const bool in = j < d.n_or;
+        o.row[q] = in ? d.or_row[j] : -1;
+        o.c0[q] = in ? d.or_c0[j] : 0;
+        o.c1[q] = in ? d.or_c0[j + 1] : 0;
+    }
+}
+
+// One OR row per row index, and u starts as a subset of v: a row that fires
+// is new iff v does not hold it, so the OR needs no return value.
+__device__ __forceinline__ uint32_t or_rows_eval(const OrRows &o, const lds_u64 *v, lds_u64 *u) {
+    uint32_t my_new = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (o.row[q] >= 0 && lds_any_in_range(v, o.c0[q], o.c1[q])) {
+            const uint64_t bit = 1ull << (o.row[q] & 63);
+            __hip_atomic_fetch_or(&u[o.row[q] >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            my_new += (v[o.row[q] >> 6] & bit) ? 0u : 1u;
+        }
+    return my_new;
+}
+
+template <class P>
+__device__ __forceinline__ void or_rows_first(const P &d, int32_t member, int32_t team, OrRows &o) {
+    or_rows_load(d, (int64_t)member * blockDim.x + threadIdx.x, (int64_t)team * blockDim.x, o);
+}
+
+// OR rows (one lane each; the first four already loaded into `first`) and
+// long rows (one wave per OR segment, one wave per whole long AND row,
+// looping over its segments).
 template <class P>
 __device__ __forceinline__ uint32_t wg_or_and_long_rows(const P &d, const lds_u64 *v, lds_u64 *u,
-                                                        int32_t member, int32_t team) {
+                                                        int32_t member, int32_t team, const OrRows &first) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const lds_u8 *v8 = (const lds_u8 *)v;
-    uint32_t my_new = 0;
-    for (int64_t j = (int64_t)member * blockDim.x + threadIdx.x; j < d.n_or; j += (int64_t)team * blockDim.x) {
-        const int32_t row = d.or_row[j];
-        if (row >= 0 && lds_any_in_range(v, d.or_c0[j], d.or_c0[j + 1])) my_new += lds_set_bit(u, v, row);
+    uint32_t my_new = or_rows_eval(first, v, u);
+    const int64_t ostride = (int64_t)team * blockDim.x;
+    for (int64_t j0 = (int64_t)member * blockDim.x + threadIdx.x + 4 * ostride; j0 < d.n_or; j0 += 4 * ostride) {
+        OrRows o;
+        or_rows_load(d, j0, ostride, o);
+        my_new += or_rows_eval(o, v, u);
     }
     for (int64_t si = (int64_t)member * waves + wave; si < d.n_segs; si += (int64_t)team * waves) {
         const auto sg = d.segs + si;
@@ -378,7 +475,7 @@ __device__ __forceinline__ uint32_t wg_or_and_long_rows(const P &d, const lds_u6
 // until *count reaches target and ends with one agent-scope acquire fence.
 // Bounded: after max_polls reads, or when a member has given up (*abort), it
 // sets *abort and returns false in every thread of the workgroup.
-__device__ __forceinline__ bool team_barrier(uint32_t *count, uint32_t target, uint32_t *abort, uint32_t max_polls,
+__device__ __forceinline__ bool team_barrier(g_u32 *count, uint32_t target, g_u32 *abort, uint32_t max_polls,
                                              lds_u32 *s_flag) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -407,16 +504,22 @@ __device__ __forceinline__ bool team_barrier(uint32_t *count, uint32_t target, u
 // n_rows + 1 bound) and leaves the fixpoint in *fix.
 template <int WPW, int U, class P>
 __device__ __forceinline__ int32_t solve_alone(const P &d, lds_u64 *cur, lds_u64 *nxt, lds_u64 *my_ball,
-                                               uint32_t *s_new, lds_u64 **fix) {
+                                               uint32_t *s_new, lds_u32 *s_sb, lds_u64 **fix) {
     int32_t step = 1, slot = 1;  // slot = step mod 3
     uint32_t changed = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
-        uint32_t my_new = wg_or_and_long_rows<P>(d, cur, nxt, 0, 1);
+        if (threadIdx.x == 0) {
+            s_new[slot == 2 ? 0 : slot + 1] = 0;
+            s_sb[slot == 2 ? 0 : slot + 1] = 0;
+        }
+        OrRows o;
+        or_rows_first(d, 0, 1, o);
+        uint32_t my_new;
         if constexpr (P::kLds)
-            my_new += wg_and_rows_by_lane<4>(d, cur, nxt);
+            my_new = wg_and_rows_by_lane<4>(d, cur, nxt);
         else
-            my_new += wg_block_rows<WPW, U, P>(d, cur, nxt, my_ball, 0, 1);
+            my_new = wg_block_rows<WPW, U, P>(d, cur, nxt, my_ball, 0, 1, s_sb + slot);
+        my_new += wg_or_and_long_rows<P>(d, cur, nxt, 0, 1, o);
         my_new = wave_sum(my_new);
         if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
         __syncthreads();
@@ -546,6 +649,7 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     // cleared during product t, after every wave has read it for product t-2,
     // so one barrier per product suffices.
     __shared__ uint32_t s_new[3];
+    __shared__ uint32_t s_sb[3];  // super-blocks handed out, by product index mod 3 (as s_new)
     __shared__ int32_t s_item;
     __shared__ uint32_t s_flag;
     lds_u64 *buf0 = (lds_u64 *)s_dyn;
@@ -554,13 +658,19 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
     for (int32_t round = 0;; ++round) {
         if (threadIdx.x == 0) s_item = b.single ? round : (int32_t)atomicAdd(&b.queue[0], 1u);
-        if (threadIdx.x < 3) s_new[threadIdx.x] = 0;
+        if (threadIdx.x < 3) {
+            s_new[threadIdx.x] = 0;
+            s_sb[threadIdx.x] = 0;
+        }
         __syncthreads();
-        const int32_t item = s_item;
+        const int32_t item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= b.n_items) break;
-        const ProgDesc pd = b.single ? b.one : b.progs[b.order[item]];
+        // The descriptor tables are written by the host only, so they are read
+        // through the constant address space at a wave-uniform index: scalar
+        // loads, and every layout pointer stays in scalar registers.
+        const ProgDesc pd = b.single ? b.one : load_desc(b.progs + as_const(b.order)[item]);
         const int32_t team = pd.team_size;
-        const int32_t member = team > 1 ? b.member[item] : 0;
+        const int32_t member = team > 1 ? as_const(b.member)[item] : 0;
         GProg d;
         d.words = as_global(pd.words);
         d.and_len = as_global(pd.and_len);
@@ -584,8 +694,6 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
         lds_u64 *cur = buf0, *nxt = buf1;  // cur holds v_t, nxt holds v_{t-1}
         int32_t step = 1, slot = 1;        // slot = step mod 3
         uint32_t changed = 0;
-        typedef __attribute__((address_space(1))) uint64_t g_u64;
-        typedef __attribute__((address_space(1))) int32_t g_i32;
         int32_t result;
         if (team == 1) {
             // a layout that fits beside the buffers is copied into LDS once, so
@@ -595,42 +703,48 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
             if (L.end <= (int64_t)b.lds_layout_bytes) {
                 const Prog<3> dl = copy_layout_to_lds(d, pd.long_nnz, L, (lds_u8 *)(buf1 + b.lds_words));
                 __syncthreads();
-                result = solve_alone<WPW, U, Prog<3>>(dl, cur, nxt, my_ball, s_new, &fix);
+                result = solve_alone<WPW, U, Prog<3>>(dl, cur, nxt, my_ball, s_new, (lds_u32 *)s_sb, &fix);
             } else {
-                result = solve_alone<WPW, U, GProg>(d, cur, nxt, my_ball, s_new, &fix);
+                result = solve_alone<WPW, U, GProg>(d, cur, nxt, my_ball, s_new, (lds_u32 *)s_sb, &fix);
             }
             cur = fix;
         } else {
-            uint32_t *T = pd.team;  // [0] arrivals, [1] abort, [2 + t mod 3] new bits of product t
-            // member 0 starts both exchange buffers at the facts (subsets of
-            // v_1 and v_2) and clears product 1's count before the first meeting
+            g_u32 *T = (g_u32 *)pd.team;  // [0] arrivals, [1] abort, [2 + t mod 3] new bits of product t
+            g_u64 *xch = (g_u64 *)pd.xch;  // three delta buffers of n_words: D[t mod 3]
+            // member m clears its share of a delta buffer
+            const int32_t s0 = (int32_t)((int64_t)n_words * member / team);
+            const int32_t s1 = (int32_t)((int64_t)n_words * (member + 1) / team);
+            // member 0 clears D[1] (product 1's) and product 1's count before the first meeting
             if (member == 0) {
-                for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
-                    const uint64_t f = fact_bits[i];
-                    pd.xch[i] = f;
-                    pd.xch[n_words + i] = f;
-                }
+                for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) xch[n_words + i] = 0ull;
                 if (threadIdx.x == 0) __hip_atomic_store(&T[2 + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             bool ok = team_barrier(&T[0], (uint32_t)team, &T[1], b.team_polls, (lds_u32 *)&s_flag);
             result = -2;
             while (ok) {
-                // the count of product t+1 is cleared during product t, after
-                // every member has read it for product t-2
+                const int nslot = slot == 2 ? 0 : slot + 1;
+                // the count and delta buffer of product t+1 are cleared during
+                // product t, after every member has read them for product t-2
                 if (member == 0 && threadIdx.x == 0)
-                    __hip_atomic_store(&T[2 + (slot == 2 ? 0 : slot + 1)], 0u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                uint32_t my_new = wg_or_and_long_rows(d, cur, nxt, member, team);
-                my_new += wg_block_rows<WPW, U>(d, cur, nxt, my_ball, member, team);
+                    __hip_atomic_store(&T[2 + nslot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (threadIdx.x == 0) s_sb[nslot] = 0;
+                {
+                    g_u64 *Dn = xch + (int64_t)nslot * n_words;
+                    for (int32_t i = s0 + (int32_t)threadIdx.x; i < s1; i += blockDim.x) Dn[i] = 0ull;
+                }
+                OrRows o;
+                or_rows_first(d, member, team, o);
+                uint32_t my_new = wg_block_rows<WPW, U>(d, cur, nxt, my_ball, member, team, (lds_u32 *)s_sb + slot);
+                my_new += wg_or_and_long_rows(d, cur, nxt, member, team, o);
                 my_new = wave_sum(my_new);
                 if ((threadIdx.x & 63) == 0 && my_new)
                     __hip_atomic_fetch_add(&T[2 + slot], my_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __syncthreads();
-                // publish: the member's rows of v_step (with v_{step-2}) into buffer step mod 2
-                uint64_t *Xs = pd.xch + ((step & 1) ? n_words : 0);
+                // publish the member's new rows (not in v_{t-1}) into D[t mod 3]
+                g_u64 *Ds = xch + (int64_t)slot * n_words;
                 for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
-                    const uint64_t w = nxt[i];
-                    if (w) __hip_atomic_fetch_or(&Xs[i], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t w = nxt[i] & ~cur[i];
+                    if (w) __hip_atomic_fetch_or(&Ds[i], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 ok = team_barrier(&T[0], (uint32_t)team * (uint32_t)(step + 1), &T[1], b.team_polls,
                                   (lds_u32 *)&s_flag);
@@ -640,15 +754,15 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
                     result = changed == 0 ? step : -1;
                     break;
                 }
-                // nxt <- v_step from the union; then v_step is current and v_{step-1} the older buffer
-                const gp<uint64_t> Xg = as_global((const uint64_t *)Xs);
-                for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) nxt[i] = Xg[i];
+                // nxt <- v_t = v_{t-1} | D[t mod 3]; then v_t is current and v_{t-1} the older buffer
+                const gp<uint64_t> Dg = Ds;
+                for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) nxt[i] = cur[i] | Dg[i];
                 __syncthreads();
-                lds_u64 *t = cur;
+                lds_u64 *tmp = cur;
                 cur = nxt;
-                nxt = t;
+                nxt = tmp;
                 ++step;
-                slot = slot == 2 ? 0 : slot + 1;
+                slot = nslot;
             }
             // at the fixpoint cur (v_{step-1}) equals v_step
         }
@@ -710,8 +824,6 @@ __global__ __launch_bounds__(kTinyBlock) void tp_tiny_kernel(ProgDesc pd, int32_
     lds_u64 *fix;
     const int32_t result = solve_tiny<kTinyWords / (kTinyBlock / 64), kTinyOr / kTinyBlock, 4>(dl, buf0, buf1,
                                                                                               s_new, &fix);
-    typedef __attribute__((address_space(1))) uint64_t g_u64;
-    typedef __attribute__((address_space(1))) int32_t g_i32;
     g_u64 *out = (g_u64 *)pd.out_bits;
     const int32_t out_words = (pd.n_atoms + 63) >> 6;
     for (int32_t i = threadIdx.x; i < out_words; i += blockDim.x) out[i] = fix[i];

@@ -93,7 +93,7 @@ struct ProgDesc {
     const uint64_t *fact_bits;
     uint64_t *out_bits;      // [ceil(n_atoms / 64)] fixpoint restricted to the first words
     int32_t *out_products;   // products; -1 if the product bound was exceeded; -2 if a team gave up
-    uint64_t *xch;           // team programs: two interpretations of n_words, exchanged between members
+    uint64_t *xch;           // team programs: three delta buffers of n_words (new rows of product t in t mod 3)
     uint32_t *team;          // team programs: kTeamStateWords words of barrier and count state
     int32_t n_rows;
     int32_t n_atoms;

@@ -279,11 +279,11 @@ static lp_status upload(T **d, const T *h, size_t count, hipStream_t st, int64_t
 struct DirtyState;  // below
 
 // Stable-model solves by dirty rows of one matrix, kept between solves: the
-// buffers (two interpretation matrices, D and C lists, marks) and a captured
-// graph of the first kFirstBatch products and Algorithm 3's test. A solve
-// leaves both interpretation buffers holding the initial matrix again (the
-// rows it changed are set back to 0) and the marks clear, so the next solve
-// starts with the graph at once. One solve at a time uses it (try-lock);
+// buffers (two interpretation matrices, the row bitmaps and their history)
+// and a captured graph of the seed, the first kFirstBatch products and
+// Algorithm 3's test. A solve leaves both interpretation buffers holding the
+// initial matrix again (the rows it changed are set back to 0) and the
+// bitmaps clear, so the next solve starts with the graph at once. One solve at a time uses it (try-lock);
 // concurrent solves of the matrix take the allocating path.
 struct StablePlan {
     std::mutex mu;
@@ -2268,7 +2268,7 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
     for (int32_t i : idx)
         if (b.team[i] > 1) {
             xoff[i] = xwords;
-            xwords += 2 * n_words_of(b.ms[i]->n_rows);
+            xwords += 3 * n_words_of(b.ms[i]->n_rows);
             ++b.n_teams;
         }
     if ((rc = dev_alloc((void **)&b.d_xch, (size_t)std::max<int64_t>(1, xwords) * 8, st))) return rc;

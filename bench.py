@@ -45,15 +45,16 @@ def step_bytes(info: dict) -> int:
     return int(info["step_bytes"])
 
 
-def recorded_traffic(kernel: str, step_bytes_now: int):
+def recorded_traffic(kernel: str, step_bytes_now: int, source: str = "lp_step.hip"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (2 x FETCH_SIZE + WRITE_SIZE, calibrated against a known-size copy), or
-    None when no record matches the current kernel source and layout."""
+    None when no record matches the current kernel source (`source` under
+    csrc/) and bytes per launch."""
     import glob
     import hashlib
     import re
 
-    src = os.path.join(ROOT, "paper_2009_10247_amd", "csrc", "lp_step.hip")
+    src = os.path.join(ROOT, "paper_2009_10247_amd", "csrc", source)
     sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
     for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
         for line in open(path):
@@ -176,13 +177,24 @@ def bench_batch(args, torch, gen, lp, stream) -> dict:
         entries = sum(mm.info["nnz"] * pr for mm, pr in zip(mats, prods))
         layout = sum((mm.info["step_bytes"] - 2 * ((mm.info["n_rows"] + 7) // 8)) * pr
                      for mm, pr in zip(mats, prods))
+        # roofline of the batch launch: the int32-CSR bytes of every product of
+        # every program (4 (N'+1) + 4 nnz + 3 N'/8 each), per launch
+        csr = sum(csr_step_bytes(mm.info) * pr for mm, pr in zip(mats, prods))
+        achieved = csr / (dev_ms / 1e3) / 1e9
+        kname = f"tp_batch_kernel<{binfo['wpw']}, {binfo['unroll']}>"
+        traffic = recorded_traffic(kname, csr, "lp_batch.hip")
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                    "bytes_per_launch": csr, "bytes": "algorithmic: int32 CSR, 4 (N'+1) + 4 nnz + 3 N'/8 "
+                    "bytes per product of each program, summed over the batch",
+                    "traffic_over_bytes": round(traffic / csr, 4) if traffic else None}
         out = {"workload": "512 definite programs, atoms log-uniform 1e3-1e5, rules 2x atoms, bodies 1-6, "
                            "2% facts; one launch of the batch kernel (graph replay)",
                "programs": 512, "atoms": sum(p.n_atoms for p in progs), "nnz": binfo["nnz"],
                "products_total": int(sum(prods)), "products_max": int(max(prods)),
                "ms_per_batch": round(dev_ms, 3), "ms_per_batch_with_results": round(e2e_ms, 3),
                "entries_per_s": round(entries / (dev_ms / 1e3), 1),
-               "layout_GB/s": round(layout / (dev_ms / 1e3) / 1e9, 1),
+               "layout_GB/s": round(layout / (dev_ms / 1e3) / 1e9, 1), "roofline": roofline,
                "sequential_plain_ms": round(seq["plain"], 3), "sequential_default_ms": round(seq["default"], 3),
                "speedup_vs_sequential_plain": round(seq["plain"] / e2e_ms, 2),
                "speedup_vs_sequential_default": round(seq["default"] / e2e_ms, 2),

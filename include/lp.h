@@ -142,7 +142,7 @@ typedef struct lp_schedule {
     int32_t wpw;             /* step: 64-row words per super-block, 4 or 8; batch kernel: words per
                                 wave, 1, 2 or 4 (0: default) */
     int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16 (0: default) */
-    int32_t block;           /* batch kernel: threads per workgroup, 256, 512 or 1024 (0: 512) */
+    int32_t block;           /* batch kernel: threads per workgroup, 256, 512 or 1024 (0: 1024) */
     int32_t team;            /* batch plans: 0 teams chosen by size, 1 no teams, k >= 2 every
                                 program solved by a team of k workgroups (at most 8 and half the
                                 grid) */
@@ -372,11 +372,16 @@ lp_status lp_batch_run(lp_batch *b, void *hip_stream);
 lp_status lp_batch_results(const lp_batch *b, uint8_t *const *models, int32_t *products, void *hip_stream);
 
 /*
- * Autotuner of the batch kernel: times every supported shape (words per wave
- * / chunks in flight 1/8, 2/8, 4/4, 1/16, 2/16; 256, 512 and 1024 threads
- * per workgroup) over reps runs of the whole batch with HIP events, keeps the
- * fastest and captures the graph again. best_ms (nullable) receives its time
- * per run. Results do not depend on the shape.
+ * Autotuner of the batch kernel. On its first call for a plan it runs the
+ * batch once and lays out the queue order and the teams again by each
+ * program's product count times its work per product (the plan's first
+ * layout knows only the work per product). Then it times every supported
+ * shape (words per wave / chunks in flight 1/8, 2/8, 4/4, 1/16, 2/16; 256,
+ * 512 and 1024 threads per workgroup) over reps runs of the whole batch with
+ * HIP events, keeps the fastest and captures the graph again. best_ms
+ * (nullable) receives its time per run. reps = 0: the layout step and one
+ * run only, at the plan's shape (best_ms 0). Results depend on neither the shape nor the
+ * layout. LP_E_INVAL for reps < 0.
  */
 lp_status lp_batch_tune(lp_batch *b, int32_t reps, float *best_ms, void *hip_stream);
 

@@ -10,9 +10,11 @@ counters in a profile of the same run).
 
     python -m paper_2009_10247_amd.batch_solve [--reps 20] [--count 512] [--seed 0] [--shape 2,8,1024]
 
---shape wpw,unroll,block fixes the kernel shape instead of autotuning it, and
---no-check skips the comparison with single-program solves, so that a profile
-holds batch launches of one shape only.
+--shape wpw,unroll,block fixes the kernel shape instead of autotuning it (the
+queue order and teams are still laid out by the product counts of a first
+run, lp_batch_tune with reps 0), and --no-check skips the comparison with
+single-program solves, so that a profile holds batch launches of one shape
+only.
 """
 from __future__ import annotations
 
@@ -45,7 +47,9 @@ def main(argv=None) -> int:
             sched = lp.lp_schedule()
             sched.wpw, sched.unroll, sched.block = (int(x) for x in args.shape.split(","))
         with lp.Batch(mats, sched=sched, stream=st) as plan:
-            if not args.no_tune and not args.shape:
+            if args.shape:
+                plan.tune(reps=0, stream=st)  # order and teams by product counts, at the given shape
+            elif not args.no_tune:
                 plan.tune(reps=3, stream=st)
             plan.run(stream=st)
             res = plan.results(stream=st)
@@ -64,10 +68,14 @@ def main(argv=None) -> int:
             info = plan.info()
             prods = [pr for _, pr in res]
             entries = sum(m.info["nnz"] * pr for m, pr in zip(mats, prods))
+            # int32-CSR bytes of every product: 4 (N'+1) + 4 nnz + 3 N'/8 per product
+            csr = sum((4 * (m.info["n_rows"] + 1) + 4 * m.info["nnz"] + 3 * ((m.info["n_rows"] + 7) // 8)) * pr
+                      for m, pr in zip(mats, prods))
             print(json.dumps({"workload": f"{args.count} definite programs, atoms log-uniform 1e3-1e5, rules 2x "
                                           "atoms, bodies 1-6, 2% facts; one batch launch (graph replay)",
                               "ms_per_batch": round(ms, 4), "entries_per_s": round(entries / (ms / 1e3), 1),
                               "products_total": int(sum(prods)), "nnz": info["nnz"],
+                              "csr_bytes_per_batch": int(csr), "csr_GB/s": round(csr / (ms / 1e3) / 1e9, 1),
                               "shape": {k: info[k] for k in ("wpw", "unroll", "block", "grid", "lds_bytes")},
                               "teams": {k: info[k] for k in ("n_teams", "team_members", "team_fallbacks")}}),
                   flush=True)

@@ -16,6 +16,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <queue>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -2022,7 +2023,7 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
 struct BatchShape {
     int wpw = 2;
     int unroll = 8;
-    int block = 512;
+    int block = 1024;  // the autotuner's usual winner (one workgroup of 16 waves per CU)
     int grid = 0;
     size_t lds_bytes = 0;
 };
@@ -2030,6 +2031,12 @@ struct BatchShape {
 // Smallest program work (stored entries + rows) that a team is formed for: below
 // it a product takes a workgroup a few microseconds, about a team barrier.
 constexpr int64_t kTeamMinWork = 1 << 16;
+// Cost model of the team layout, in units of work (stored entries + rows) per
+// product, fitted to per-program times of the 512-program batch on MI355X: a
+// team member is 1/8 slower per unit of work than a workgroup alone (barrier,
+// exchange), and a product costs about 4,500 units more than its work.
+constexpr double kTeamCost = 1.125;
+constexpr double kProductCost = 4500.0;
 // Polls after which a team barrier gives up (a few seconds: far beyond any
 // wait of members that run at once).
 constexpr uint32_t kTeamPolls = 1u << 22;
@@ -2061,6 +2068,7 @@ struct BatchPlan {
     lp_schedule sched{};             // schedule of the single-program solves
     float tuned_ms = 0.f;
     bool use_graph = true;           // runs replay a captured graph (else a direct launch)
+    bool weighted = false;           // order and teams weighted by the product counts of a run
 };
 
 static void batch_release(BatchPlan &b) {
@@ -2163,6 +2171,9 @@ static lp_status batch_capture(BatchPlan &b) {
     return LP_OK;
 }
 
+static lp_status batch_layout(BatchPlan &b, const lp_schedule *sched, hipStream_t st,
+                              const std::vector<int32_t> *weights);
+
 static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const lp_schedule *sched, hipStream_t st,
                               bool use_graph, BatchPlan &b) {
     b.use_graph = use_graph;
@@ -2191,55 +2202,116 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
     if (count == 0) {
         LP_HIP(hipGetDevice(&b.device));
     }
+    return batch_layout(b, sched, st, nullptr);
+}
+
+// Queue order, teams, descriptors and buffers of the plan's programs (b.ms),
+// its shape and graph. weights: each program's product count from an earlier
+// run (the time of a program is about its products times its work per
+// product), or null before any run (all 1).
+static lp_status batch_layout(BatchPlan &b, const lp_schedule *sched, hipStream_t st,
+                              const std::vector<int32_t> *weights) {
+    const int32_t count = (int32_t)b.ms.size();
+    b.order.clear();
+    b.large.clear();
     DevProps d;
     lp_status rc = dev_props(b.device, &d);
     if (rc) return rc;
     // programs whose two buffers fit in the dynamic LDS (the kernel's static
-    // LDS takes at most 4 KiB); largest first by stored entries
+    // LDS takes at most 4 KiB); largest first by weighted work
     const int64_t cap_words = std::max<int64_t>(0, (d.max_lds - 4096) / 16);
     std::vector<int32_t> idx;
     for (int32_t i = 0; i < count; ++i) {
         if (n_words_of(b.ms[i]->n_rows) <= cap_words) idx.push_back(i);
         else b.large.push_back(i);
     }
-    auto work = [&](int32_t i) {
+    // work of one product (stored entries + rows), and of the whole solve
+    auto step_work = [&](int32_t i) {
         const Matrix &a = *b.ms[i];
         return a.dev.and_nnz + a.dev.long_nnz + a.n_rows;
     };
-    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
-    // Teams: a program whose work (stored entries + rows) exceeds a share of
-    // the batch (total / (1.5 CUs): product counts differ, so a share a little
-    // under a CU's keeps the long programs off the critical path) and
-    // kTeamMinWork gets ceil(work / share) workgroups, at most kMaxTeam and half
-    // the grid; the share grows by 10% until all members fit in one grid's worth
-    // of workgroups, so every team starts at once.
-    // sched->team: 0 automatic, 1 no teams, k >= 2 every program in teams of k.
+    // Teams. sched->team: 0 automatic, 1 no teams, k >= 2 every program in
+    // teams of k. Automatic: the layout that a simulation of the queue finds
+    // fastest. The simulation prices program i on k workgroups at its product
+    // count (weights; 1 before any run) times (work per product, / k and x
+    // kTeamCost for a team, + kProductCost); team positions come first (every
+    // team starts at once), then the other programs longest first, and each
+    // workgroup takes the next position when it is free. Candidates: for a
+    // threshold T, every program whose time alone exceeds T gets the fewest
+    // members (at most kMaxTeam and half the grid; work per product at least
+    // kTeamMinWork) that bring it to T or below; T runs over the longest
+    // programs' times alone, and the fastest layout whose members fit in one
+    // grid's worth of workgroups is kept.
     b.team.assign(count, 1);
-    {
-        const int32_t opt = sched ? sched->team : 0;
-        const int64_t grid_cap = (sched && sched->grid > 0) ? sched->grid : (int64_t)d.n_cu;
-        const int32_t gmax = (int32_t)std::min<int64_t>(kMaxTeam, grid_cap / 2);
-        if (opt >= 2 && gmax >= 2) {
-            for (int32_t i : idx) b.team[i] = std::min(opt, gmax);
-        } else if (opt == 0 && gmax >= 2 && !idx.empty()) {
-            double total = 0;
-            for (int32_t i : idx) total += (double)work(i);
-            double share = total / (1.5 * (double)d.n_cu);
-            for (;;) {
-                int64_t members = 0;
-                for (int32_t i : idx) {
-                    const double w = (double)work(i);
-                    b.team[i] = (w > share && w >= (double)kTeamMinWork)
-                                    ? (int32_t)std::min<double>(gmax, std::ceil(w / share))
-                                    : 1;
-                    if (b.team[i] > 1) members += b.team[i];
+    const int32_t opt = sched ? sched->team : 0;
+    const int64_t grid_cap = (sched && sched->grid > 0) ? sched->grid : (int64_t)d.n_cu;
+    const int32_t gmax = (int32_t)std::min<int64_t>(kMaxTeam, grid_cap / 2);
+    auto est = [&](int32_t i, int32_t k) {
+        const double w = (double)step_work(i);
+        const double per = (k > 1 ? kTeamCost * w / k : w) + kProductCost;
+        return (weights ? (double)std::max<int32_t>(1, (*weights)[i]) : 1.0) * per;
+    };
+    if (opt >= 2 && gmax >= 2) {
+        for (int32_t i : idx) b.team[i] = std::min(opt, gmax);
+    } else if (opt == 0 && gmax >= 2 && !idx.empty()) {
+        std::vector<int32_t> team(count, 1), ord;
+        auto order_by_time = [&]() {
+            ord = idx;
+            std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+                if ((team[x] > 1) != (team[y] > 1)) return team[x] > 1;
+                return est(x, team[x]) > est(y, team[y]);
+            });
+        };
+        auto makespan = [&]() {
+            std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+            for (int64_t g = 0; g < grid_cap; ++g) free_at.push(0.0);
+            double end = 0.0;
+            for (int32_t i : ord) {
+                double s = 0.0;
+                for (int32_t k = 0; k < team[i]; ++k) {
+                    s = std::max(s, free_at.top());
+                    free_at.pop();
                 }
-                if (members <= grid_cap) break;
-                share *= 1.1;
+                const double e = s + est(i, team[i]);
+                for (int32_t k = 0; k < team[i]; ++k) free_at.push(e);
+                end = std::max(end, e);
+            }
+            return end;
+        };
+        std::vector<int32_t> by_alone(idx);
+        std::stable_sort(by_alone.begin(), by_alone.end(),
+                         [&](int32_t x, int32_t y) { return est(x, 1) > est(y, 1); });
+        order_by_time();
+        double best = makespan();  // no teams
+        std::vector<int32_t> best_team(team);
+        const size_t n_cand = std::min<size_t>(by_alone.size(), (size_t)grid_cap);
+        for (size_t c = 1; c <= n_cand; ++c) {
+            // threshold: the time alone of the c-th longest program; the c-1 longer ones get teams
+            const double T = est(by_alone[c - 1], 1);
+            std::fill(team.begin(), team.end(), 1);
+            int64_t members = 0;
+            for (size_t j = 0; j + 1 < c; ++j) {
+                const int32_t i = by_alone[j];
+                if (step_work(i) < kTeamMinWork) continue;
+                int32_t k = 2;
+                while (k < gmax && est(i, k) > T) ++k;
+                team[i] = k;
+                members += k;
+            }
+            if (members > grid_cap) break;  // later thresholds only add members
+            order_by_time();
+            const double m = makespan();
+            if (m < best) {
+                best = m;
+                best_team = team;
             }
         }
+        for (int32_t i : idx) b.team[i] = best_team[i];
     }
-    std::stable_partition(idx.begin(), idx.end(), [&](int32_t i) { return b.team[i] > 1; });
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+        if ((b.team[x] > 1) != (b.team[y] > 1)) return b.team[x] > 1;
+        return est(x, b.team[x]) > est(y, b.team[y]);
+    });
     b.order = idx;
     b.item_prog.clear();
     b.item_member.clear();
@@ -2363,19 +2435,38 @@ static lp_status batch_results(const BatchPlan &b, uint8_t *const *models, int32
     return LP_OK;
 }
 
-// Autotuner of the batch kernel: times every supported shape (words per
-// wave and chunks in flight, 256/512/1024-thread workgroups) over reps
-// launches of the whole batch and keeps the fastest.
+// Autotuner of the batch kernel. First, once per plan, one run gives every
+// program's product count and the queue order and teams are laid out again
+// by products times work per product (the first layout knows only the work
+// per product). Then it times every supported shape (words per wave and
+// chunks in flight, 256/512/1024-thread workgroups) over reps launches of the
+// whole batch and keeps the fastest.
 static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStream_t st) {
     if (b.order.empty()) {
         if (best_ms) *best_ms = 0.f;
         return LP_OK;
     }
+    lp_status rc;
+    if (!b.weighted) {
+        if ((rc = batch_run(b, st))) return rc;
+        std::vector<int32_t> prods(b.ms.size(), 1);
+        LP_HIP(hipMemcpyAsync(prods.data(), b.d_prod, sizeof(int32_t) * prods.size(), hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        for (int32_t &p : prods) p = std::max(1, p);  // large programs, and teams that gave up: 1
+        for (int32_t i : b.large) prods[i] = 1;
+        const lp_schedule keep = b.sched;
+        batch_release(b);
+        if ((rc = batch_layout(b, &keep, st, &prods))) return rc;
+        b.weighted = true;
+    }
+    if (reps == 0) {  // the layout step only, at the plan's shape; one run, so results hold a run
+        if (best_ms) *best_ms = 0.f;
+        return batch_run(b, st);
+    }
     static const int shapes[][2] = {{1, 8}, {2, 8}, {4, 4}, {1, 16}, {2, 16}};
     static const int blocks[] = {256, 512, 1024};
     Events ev;
-    lp_status rc = ev.init();
-    if (rc) return rc;
+    if ((rc = ev.init())) return rc;
     BatchShape win;
     float win_ms = 0.f;
     bool have = false;
@@ -2928,8 +3019,8 @@ lp_status lp_batch_results(const lp_batch *b, uint8_t *const *models, int32_t *p
 
 lp_status lp_batch_tune(lp_batch *b, int32_t reps, float *best_ms, void *hip_stream) {
     LP_GUARD_BEGIN
-    if (!b || reps < 1) {
-        set_error("lp_batch_tune needs a batch and reps >= 1");
+    if (!b || reps < 0) {
+        set_error("lp_batch_tune needs a batch and reps >= 0");
         return LP_E_INVAL;
     }
     DeviceGuard g(b->b.device);

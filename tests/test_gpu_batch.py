@@ -276,3 +276,37 @@ def test_batch_team_that_gives_up_is_solved_alone():
     finally:
         for m in mats:
             m.close()
+
+
+@pytest.mark.parametrize("team", [0, 3])
+def test_batch_tune_lays_out_again_by_products(team):
+    # lp_batch_tune's first call runs the batch and orders the queue and the
+    # teams by product counts; the plan holds a program solved by the
+    # single-program drivers too; a second tune keeps that layout
+    big = gen.definite_uniform(4, 300_000, 600_000, 0.02, 4)
+    progs = [gen.definite_uniform(40 + i, 1000 * (i + 1), 2000 * (i + 1), 0.02, 6) for i in range(20)]
+    progs.insert(7, big)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    sched = lp.lp_schedule()
+    sched.team = team
+    try:
+        with lp.Batch(mats, sched=sched) as b:
+            before = b.info()
+            with pytest.raises(lp.LPError):
+                b.tune(reps=-1)
+            b.tune(reps=0)  # the layout step only
+            _assert_equal(b.results(), want, "after the layout step")
+            assert b.info()["tuned_ms"] == 0
+            b.tune(reps=1)
+            _assert_equal(b.results(), want, "after the first tune")
+            after = b.info()
+            assert after["n_resident"] == before["n_resident"] == 20
+            b.tune(reps=1)
+            for _ in range(3):
+                b.run()
+            _assert_equal(b.results(), want, "after replays")
+            assert b.info()["team_fallbacks"] == 0
+    finally:
+        for m in mats:
+            m.close()

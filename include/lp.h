@@ -517,7 +517,7 @@ lp_status lp_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx)
 typedef struct lp_server lp_server;
 
 typedef struct lp_server_config {
-    int32_t n_slots;      /* worker threads / streams (0: 8; at most 64) */
+    int32_t n_slots;      /* worker threads / streams (0: 4; at most 64) */
     int32_t batch_max;    /* least-model requests per batch launch (0: 64; 1: no batching) */
     int32_t batch_rows;   /* largest matrix (rows) taken into batches (0: 65536) */
     int32_t device;       /* HIP device (-1 or 0..: -1 means the current device) */

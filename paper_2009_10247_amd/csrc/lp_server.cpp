@@ -355,7 +355,7 @@ lp_status lp_server_create(const lp_server_config *cfg, lp_server **out) {
         *out = nullptr;
         std::unique_ptr<lp_server> s(new lp_server());
         if (cfg) s->cfg = *cfg;
-        if (s->cfg.n_slots <= 0) s->cfg.n_slots = 8;
+        if (s->cfg.n_slots <= 0) s->cfg.n_slots = 4;  // measured: 4 beat 8 at 300 and 1,000 req/s (4 hardware queues per process)
         if (s->cfg.n_slots > 64) {
             set_error("n_slots must be at most 64");
             return LP_E_INVAL;

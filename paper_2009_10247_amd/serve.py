@@ -9,7 +9,7 @@ once alone on an idle server; every result of the streams is then compared
 byte for byte with that alone result.
 
     python -m paper_2009_10247_amd.serve [--rates 10,30,100,300,1000]
-        [--requests 2000] [--pool 256] [--hi 1e6] [--slots 8]
+        [--requests 2000] [--pool 256] [--hi 1e6] [--slots 4]
 """
 from __future__ import annotations
 
@@ -129,7 +129,7 @@ def main(argv=None) -> int:
     ap.add_argument("--lo", type=float, default=1e3)
     ap.add_argument("--hi", type=float, default=1e6)
     ap.add_argument("--max-k", type=int, default=12)
-    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--batch-max", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--budget-gb", type=float, default=0.0)

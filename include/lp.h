@@ -248,6 +248,32 @@ lp_status lp_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_mo
                            int32_t *products, void *hip_stream);
 
 /*
+ * Stable models of several normal programs at once (Algorithms 2 and 3 per
+ * program; the columns of Algorithm 2 are independent, so programs can share
+ * launches). Every launch takes one product for every program still
+ * changing, over the union of their interpretation matrices, so a batch of
+ * small programs costs about the launches of its longest solve. Programs with
+ * more than 12 negated atoms left after pruning (over 64 words per row), and
+ * definite programs, are solved one after another as lp_stable_models does.
+ * Results equal lp_stable_models' with max_models = 1 for each program.
+ *
+ * ms:        count matrices, all on one device (host CSR and device copy).
+ * accepted:  count pointers; accepted[i] is uint64[ceil(2^K_i/64)] host, as
+ *            lp_stable_models' accepted.
+ * n_models:  int64[count] host, the number of stable models of each program.
+ * models:    nullable; count pointers, each nullable: models[i] is
+ *            uint8[n_atoms_i] host and receives the first model in guess
+ *            order (left unchanged if the program has none).
+ * products:  nullable; int32[count], as lp_stable_models' products.
+ * Synchronizes hip_stream. Errors: LP_E_INVAL (NULL ms, accepted or n_models,
+ *   count < 0, matrices on different devices), LP_E_HOST_ONLY,
+ *   LP_E_TOO_MANY_GUESSES, LP_E_NOMEM, LP_E_DEVICE, LP_E_INTERNAL.
+ */
+lp_status lp_stable_models_batch(const lp_matrix *const *ms, int32_t count, uint64_t *const *accepted,
+                                 int64_t *n_models, uint8_t *const *models, int32_t *products,
+                                 void *hip_stream);
+
+/*
  * Algorithms 2 and 3 on caller-chosen guesses, for programs whose 2^K guesses
  * are too many to enumerate (1 <= K <= 64). Column j of the initial matrix
  * (Definition 8) is guesses[j]: bit t is the initial value of qbar_t, as in

@@ -185,8 +185,8 @@ struct SpmmParams {
 };
 // max_grid: workgroups of 256 threads (grid-stride loop over the items).
 hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st);
-// Stable-model products by dirty rows (lp_spmm.hip): one launch pair per
-// product t; see spmm_dirty_eval_kernel.
+// Stable-model products by dirty rows (lp_spmm.hip): one launch per product
+// t; see spmm_dirty_product_kernel.
 constexpr int kDirtyHist = 128;  // |C_t| by t mod kDirtyHist, read by the host
 struct DirtyParams {
     const int32_t *row_ptr;
@@ -259,6 +259,40 @@ hipError_t launch_stable_check(const uint64_t *V, int32_t log2W, int64_t W, cons
                                hipStream_t st);
 hipError_t launch_extract(const uint64_t *V, int32_t log2W, const int64_t *cols, int64_t n_models, int32_t n_atoms,
                           uint8_t *out, hipStream_t st);
+
+// Stable models of several programs at once (lp_spmm.hip): every launch
+// takes one product of Algorithm 2 for every program of the batch, over the
+// union of their interpretation matrices. Each program's items (row-words)
+// fill whole 256-item chunks from chunk0 on, so a chunk belongs to one
+// program; a program whose previous product changed nothing is skipped.
+constexpr int kSBatchChunk = 256;
+struct SBatchProg {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint64_t *and_bits;
+    const uint64_t *fact_bits;
+    const int32_t *guess_pos;
+    const int32_t *q_rows;
+    uint64_t *buf[2];          // product t reads buf[(t - 1) & 1] and writes buf[t & 1]
+    unsigned long long *count; // kRing bit counts of the program's products, slot 0 the initial matrix's
+    uint64_t *accepted;        // W words: Algorithm 3's mask (compressed guess space)
+    uint8_t *model;            // n_atoms bytes: the first accepted column's model
+    unsigned long long *n_models;
+    unsigned long long m0_bits;  // |M0| (closed form)
+    int64_t chunk0;            // first chunk of the program
+    int64_t total;             // n_rows << log2W
+    int32_t n_rows, n_std, K, k_eff, log2W, n_atoms;
+};
+struct SBatchParams {
+    const SBatchProg *progs;
+    int32_t n_progs;
+    int32_t step;
+    int64_t n_chunks;
+};
+hipError_t launch_sbatch_init(const SBatchParams &b, int max_grid, hipStream_t st);
+hipError_t launch_sbatch_step(const SBatchParams &b, int max_grid, hipStream_t st);
+// Algorithm 3 and the first model of every program; b.step is the last product issued.
+hipError_t launch_sbatch_outputs(const SBatchParams &b, hipStream_t st);
 
 // Dense-matrix products (lp_dense.hip). The dense matrix is ld x ld bytes with
 // ld = n_rows rounded up to kDenseAlign; interpretation matrices are hp x ld

@@ -2502,6 +2502,164 @@ static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStrea
     return b.use_graph ? batch_capture(b) : LP_OK;
 }
 
+// ------------------------------------------------------------------ stable batches
+//
+// Stable models (Algorithms 2 and 3) of several normal programs together:
+// each launch takes one product for every program still changing (the union
+// of their interpretation matrices, lp_spmm.hip), so a batch of small
+// programs costs about the launches of its longest solve instead of the sum
+// of them. Programs whose enumerated guesses need more than 64 words per row,
+// and definite programs, are solved one after another by stable_impl.
+
+constexpr int kSBatchMaxKeff = 12;  // 2^12 guesses: 64 words per row
+
+static bool sbatch_fits(const Matrix &m) { return m.K >= 1 && m.K_eff <= kSBatchMaxKeff; }
+
+static lp_status sbatch_impl(const std::vector<const Matrix *> &ms, const std::vector<int32_t> &in,
+                             uint64_t *const *accepted, int64_t *n_models, uint8_t *const *models, int32_t *products,
+                             hipStream_t st) {
+    const int32_t n = (int32_t)in.size();
+    Scratch S(st);
+    std::vector<SBatchProg> desc(n);
+    std::vector<int64_t> acc_off(n), model_off(n);
+    int64_t chunks = 0, words = 0, acc_words = 0, model_bytes = 0, limit = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const Matrix &m = *ms[in[k]];
+        const int64_t W = (((int64_t)1 << m.K_eff) + 63) / 64;
+        SBatchProg &d = desc[k];
+        d = SBatchProg{};
+        d.row_ptr = m.dev.full_row_ptr;
+        d.col = m.dev.full_col;
+        d.and_bits = m.dev.full_and_bits;
+        d.fact_bits = m.dev.fact_bits;
+        d.guess_pos = m.dev.guess_pos;
+        d.q_rows = m.dev.q_rows;
+        const unsigned long long H = 1ull << m.K_eff;
+        d.m0_bits = (unsigned long long)m.info.n_fact_rows * H + (unsigned long long)m.K_eff * (H / 2);
+        d.log2W = ilog2(W);
+        d.total = (int64_t)m.n_rows * W;
+        d.n_rows = m.n_rows;
+        d.n_std = m.n_std;
+        d.K = m.K;
+        d.k_eff = m.K_eff;
+        d.n_atoms = m.n_atoms;
+        d.chunk0 = chunks;
+        chunks += std::max<int64_t>(1, (d.total + kSBatchChunk - 1) / kSBatchChunk);
+        words += 2 * d.total;
+        acc_off[k] = acc_words;
+        acc_words += W;
+        model_off[k] = model_bytes;
+        model_bytes += std::max(1, m.n_atoms);
+        limit = std::max<int64_t>(limit, (int64_t)m.n_rows + 1);
+    }
+    uint64_t *bufs, *acc;
+    unsigned long long *counts, *nm;
+    uint8_t *mod;
+    SBatchProg *d_desc;
+    lp_status rc;
+    if ((rc = S.get(&bufs, (size_t)std::max<int64_t>(1, words))) || (rc = S.get(&acc, (size_t)acc_words)) ||
+        (rc = S.get(&counts, (size_t)n * kRing)) || (rc = S.get(&nm, (size_t)n)) ||
+        (rc = S.get(&mod, (size_t)model_bytes)) || (rc = S.get(&d_desc, (size_t)n)))
+        return rc;
+    int64_t off = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        SBatchProg &d = desc[k];
+        d.buf[0] = bufs + off;
+        d.buf[1] = bufs + off + d.total;
+        off += 2 * d.total;
+        d.count = counts + (int64_t)k * kRing;
+        d.accepted = acc + acc_off[k];
+        d.model = mod + model_off[k];
+        d.n_models = nm + k;
+    }
+    LP_HIP(hipMemcpyAsync(d_desc, desc.data(), sizeof(SBatchProg) * n, hipMemcpyHostToDevice, st));
+    DevProps dp;
+    if ((rc = dev_props(ms[in[0]]->dev.device, &dp))) return rc;
+    const int grid = 8 * std::max(1, dp.n_cu);
+    SBatchParams b{d_desc, n, 0, chunks};
+    LP_HIP(launch_sbatch_init(b, grid, st));
+    // products in batches of 8 between host reads of the counts; a program's
+    // product count is the first product whose count equals the one before
+    std::vector<unsigned long long> h((size_t)n * kRing);
+    std::vector<int32_t> prods(n, 0);
+    int32_t left = n;
+    const int batch = 8;
+    int64_t t = 0;
+    for (; left > 0; t += batch) {
+        if (t + 1 > limit) {
+            set_error("fixpoint of a batch program not reached within n_rows+1 products");
+            return LP_E_INTERNAL;
+        }
+        for (int i = 1; i <= batch; ++i) {
+            b.step = (int32_t)(t + i);
+            LP_HIP(launch_sbatch_step(b, grid, st));
+        }
+        LP_HIP(hipMemcpyAsync(h.data(), counts, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, st));
+        LP_HIP(hipStreamSynchronize(st));
+        for (int32_t k = 0; k < n; ++k) {
+            if (prods[k]) continue;
+            const unsigned long long *c = h.data() + (int64_t)k * kRing;
+            for (int i = 1; i <= batch; ++i) {
+                const int64_t s = t + i;
+                if (c[s & (kRing - 1)] == c[(s - 1) & (kRing - 1)]) {
+                    prods[k] = (int32_t)s;
+                    --left;
+                    break;
+                }
+            }
+        }
+    }
+    b.step = (int32_t)t;
+    LP_HIP(launch_sbatch_outputs(b, st));
+    std::vector<uint64_t> acc_h((size_t)acc_words);
+    std::vector<unsigned long long> nm_h(n);
+    std::vector<uint8_t> mod_h((size_t)model_bytes);
+    LP_HIP(hipMemcpyAsync(acc_h.data(), acc, sizeof(uint64_t) * acc_h.size(), hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(nm_h.data(), nm, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, st));
+    LP_HIP(hipMemcpyAsync(mod_h.data(), mod, mod_h.size(), hipMemcpyDeviceToHost, st));
+    LP_HIP(hipStreamSynchronize(st));
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t i = in[k];
+        const Matrix &m = *ms[i];
+        const int64_t W = (int64_t)1 << desc[k].log2W;
+        const int64_t W_full = (((int64_t)1 << m.K) + 63) / 64;
+        // accepted guesses in the full guess space (deposit compressed bits)
+        std::memset(accepted[i], 0, sizeof(uint64_t) * W_full);
+        for (int64_t w = 0; w < W; ++w) {
+            uint64_t x = acc_h[acc_off[k] + w];
+            while (x) {
+                const int bit = __builtin_ctzll(x);
+                x &= x - 1;
+                const int64_t jc = w * 64 + bit;
+                int64_t jf = 0;
+                for (int q = 0; q < m.K; ++q)
+                    if (m.guess_pos[q] >= 0 && ((jc >> m.guess_pos[q]) & 1)) jf |= 1ll << q;
+                accepted[i][jf >> 6] |= 1ull << (jf & 63);
+            }
+        }
+        n_models[i] = (int64_t)nm_h[k];
+        if (models && models[i] && m.n_atoms) std::memcpy(models[i], mod_h.data() + model_off[k], m.n_atoms);
+        if (products) products[i] = prods[k];
+    }
+    return LP_OK;
+}
+
+static lp_status stable_batch_impl(const std::vector<const Matrix *> &ms, uint64_t *const *accepted,
+                                   int64_t *n_models, uint8_t *const *models, int32_t *products, hipStream_t st) {
+    std::vector<int32_t> in, alone;
+    for (int32_t i = 0; i < (int32_t)ms.size(); ++i) (sbatch_fits(*ms[i]) ? in : alone).push_back(i);
+    lp_status rc;
+    if (!in.empty() && (rc = sbatch_impl(ms, in, accepted, n_models, models, products, st))) return rc;
+    for (int32_t i : alone) {
+        int32_t pr = 0;
+        rc = stable_impl(*ms[i], accepted[i], &n_models[i], models ? models[i] : nullptr, 1, nullptr, &pr, st);
+        if (rc == LP_E_TRUNCATED) rc = LP_OK;  // the first model only
+        if (rc) return rc;
+        if (products) products[i] = pr;
+    }
+    return LP_OK;
+}
+
 // ------------------------------------------------------------------ dense contrast
 //
 // The dense-matrix method of the paper's experiments (Section 4): the same
@@ -2897,6 +3055,37 @@ lp_status lp_stable_models(const lp_matrix *m, uint64_t *accepted, int64_t *n_mo
     }
     DeviceGuard g(m->m.dev.device);
     return stable_impl(m->m, accepted, n_models, models, max_models, interp, products, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_stable_models_batch(const lp_matrix *const *ms, int32_t count, uint64_t *const *accepted,
+                                 int64_t *n_models, uint8_t *const *models, int32_t *products, void *hip_stream) {
+    LP_GUARD_BEGIN
+    if (count < 0 || (count > 0 && (!ms || !accepted || !n_models))) {
+        set_error("bad stable batch arguments (ms, accepted and n_models must be non-NULL)");
+        return LP_E_INVAL;
+    }
+    if (count == 0) return LP_OK;
+    std::vector<const Matrix *> v(count);
+    for (int32_t i = 0; i < count; ++i) {
+        lp_status rc = check_solvable(ms[i]);
+        if (rc) return rc;
+        if (ms[i]->m.K > LP_MAX_NEG_ATOMS) {
+            set_error("program " + std::to_string(i) + " has too many negated atoms: " + std::to_string(ms[i]->m.K));
+            return LP_E_TOO_MANY_GUESSES;
+        }
+        if (!accepted[i]) {
+            set_error("accepted[" + std::to_string(i) + "] is NULL");
+            return LP_E_INVAL;
+        }
+        if (ms[i]->m.dev.device != ms[0]->m.dev.device) {
+            set_error("the matrices of a batch must live on one device");
+            return LP_E_INVAL;
+        }
+        v[i] = &ms[i]->m;
+    }
+    DeviceGuard g(ms[0]->m.dev.device);
+    return stable_batch_impl(v, accepted, n_models, models, products, (hipStream_t)hip_stream);
     LP_GUARD_END
 }
 

@@ -12,9 +12,12 @@
 //   * continuous batching: a free slot takes every waiting least-model
 //     request of a small matrix (at most batch_rows rows, within the batch
 //     kernel's LDS; up to batch_max requests) and solves them in one launch,
-//     one workgroup per program; stable-model requests, larger least-model
-//     requests and a small request with no company run alone on the whole
-//     device. Work of different slots overlaps on the device.
+//     one workgroup per program; likewise every waiting stable-model request
+//     of a small interpretation matrix (at most 12 negated atoms left after
+//     pruning and kStableBatchWords row-words), solved together by
+//     lp_stable_models_batch (one launch per product for all of them).
+//     Larger requests and a small request with no company run alone on the
+//     whole device. Work of different slots overlaps on the device.
 // Results are kept until lp_server_take_result.
 #include <hip/hip_runtime.h>
 
@@ -161,22 +164,33 @@ bool admit(lp_server *s, Request *r, std::vector<Program *> &to_upload) {
     return true;
 }
 
-bool batchable(const lp_server *s, const Program *p) {
-    return s->cfg.batch_max > 1 && p->info.n_neg == 0 && p->info.n_rows <= s->max_batch_rows &&
-           p->info.n_rows <= s->cfg.batch_rows;
+// Interpretation matrices of at most this many row-words join stable-model
+// batches: full-sweep products of that size cost about a launch; larger ones
+// run alone, where products evaluate only the rows that can change.
+constexpr int64_t kStableBatchWords = (int64_t)1 << 18;
+
+// Batch kind of a program's requests: 1 least-model batches, 2 stable-model
+// batches, 0 alone.
+int batch_kind(const lp_server *s, const Program *p) {
+    if (s->cfg.batch_max <= 1) return 0;
+    if (p->info.n_neg == 0)
+        return (p->info.n_rows <= s->max_batch_rows && p->info.n_rows <= s->cfg.batch_rows) ? 1 : 0;
+    const int k_eff = p->info.n_neg - p->info.n_pruned;
+    if (k_eff > 12) return 0;
+    return (int64_t)p->info.n_rows * words_of((int64_t)1 << k_eff) <= kStableBatchWords ? 2 : 0;
 }
 
 // Takes the next work item from the queue (lock held): the oldest admissible
-// request, and with it every further admissible least-model request of a
-// batchable program, up to batch_max.
+// request, and with it every further admissible request of the same batch
+// kind (batch_kind), up to batch_max.
 bool pick(lp_server *s, std::vector<Request *> &group, std::vector<Program *> &to_upload) {
     group.clear();
     to_upload.clear();
-    bool batch = false;
+    int kind = 0;
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         Request *r = *it;
         Program *p = s->programs[r->info.program_id].get();
-        if (!group.empty() && (!batch || !batchable(s, p))) {
+        if (!group.empty() && (kind == 0 || batch_kind(s, p) != kind)) {
             ++it;
             continue;
         }
@@ -184,10 +198,10 @@ bool pick(lp_server *s, std::vector<Request *> &group, std::vector<Program *> &t
             ++it;
             continue;
         }
-        if (group.empty()) batch = batchable(s, p);
+        if (group.empty()) kind = batch_kind(s, p);
         group.push_back(r);
         it = s->pending.erase(it);
-        if (!batch || (int)group.size() >= s->cfg.batch_max) break;
+        if (kind == 0 || (int)group.size() >= s->cfg.batch_max) break;
     }
     return !group.empty();
 }
@@ -243,9 +257,21 @@ void run_group(lp_server *s, hipStream_t st, std::vector<Request *> &group, std:
             mp.push_back(models[mp.size()].data());
         }
         std::vector<int32_t> prods(std::max<size_t>(1, progs.size()), 0);
+        // stable-model batches: the accepted masks and model counts too
+        const bool stable = !progs.empty() && progs[0]->info.n_neg > 0;
+        std::vector<std::vector<uint64_t>> acc(progs.size());
+        std::vector<uint64_t *> ap;
+        std::vector<int64_t> nm(std::max<size_t>(1, progs.size()), 1);
+        if (stable)
+            for (Program *p : progs) {
+                acc[ap.size()].assign(words_of((int64_t)1 << p->info.n_neg), 0);
+                ap.push_back(acc[ap.size()].data());
+            }
         lp_status rc = LP_OK;
         if (!progs.empty())
-            rc = lp_least_model_batch(ms.data(), (int32_t)ms.size(), mp.data(), prods.data(), nullptr, st);
+            rc = stable ? lp_stable_models_batch(ms.data(), (int32_t)ms.size(), ap.data(), nm.data(), mp.data(),
+                                                 prods.data(), st)
+                        : lp_least_model_batch(ms.data(), (int32_t)ms.size(), mp.data(), prods.data(), nullptr, st);
         for (Request *r : group) {
             Program *p = s->programs[r->info.program_id].get();
             if (failed(p)) continue;
@@ -255,7 +281,8 @@ void run_group(lp_server *s, hipStream_t st, std::vector<Request *> &group, std:
                 const size_t k = slot[p];
                 r->model.assign(models[k].begin(), models[k].begin() + p->info.n_atoms);
                 r->info.products = prods[k];
-                r->info.n_models = 1;
+                r->info.n_models = nm[k];
+                if (stable) r->accepted = acc[k];
             }
         }
     } else {

@@ -572,6 +572,135 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const uint64_t *V, int3
     out[g] = (uint8_t)((V[((int64_t)a << log2W) + (j >> 6)] >> (j & 63)) & 1ull);
 }
 
+// ---------------------------------------------------------------- batches
+//
+// Stable models of several programs (Algorithms 2 and 3 per program) with one
+// launch per product for all of them: the items of the launches are the
+// union of the programs' row-words, each program's in whole chunks of
+// kSBatchChunk from its chunk0, so every chunk names one program (found by a
+// binary search over the descriptors, which the host wrote and the kernels
+// read through the constant address space). Per program the product is that
+// of spmm_step_kernel, with its bit count in the program's own ring; a
+// program whose previous product changed nothing is skipped.
+
+typedef const __attribute__((address_space(4))) SBatchProg csbatch;
+
+__device__ __forceinline__ const csbatch *sbatch_progs(const SBatchParams &b) {
+    return (const csbatch *)(const void *)b.progs;
+}
+
+__device__ __forceinline__ int32_t sbatch_prog_of(const SBatchParams &b, int64_t c) {
+    const csbatch *P = sbatch_progs(b);
+    int32_t lo = 0, hi = b.n_progs - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (P[mid].chunk0 <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t *s_red) {
+    x = wave_sum(x);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    uint32_t s = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kBlock / 64; ++k) s += s_red[k];
+    __syncthreads();
+    return s;  // in thread 0
+}
+
+// Both buffers of every program at the initial matrix; count slot 0 its bit
+// count (closed form) and slot 1 cleared.
+__global__ __launch_bounds__(kBlock) void sbatch_init_kernel(SBatchParams b) {
+    static_assert(kSBatchChunk == kBlock, "one chunk per workgroup pass");
+    const int tid = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < b.n_chunks; c += gridDim.x) {
+        const csbatch &P = sbatch_progs(b)[sbatch_prog_of(b, c)];
+        const int64_t g = (c - P.chunk0) * kSBatchChunk + tid;
+        if (g < P.total) init_m0_word(P.buf[0], P.buf[1], g, P.log2W, P.n_std, P.fact_bits, P.guess_pos, P.k_eff);
+        if (c == P.chunk0 && tid == 0) {
+            P.count[0] = P.m0_bits;
+            P.count[1] = 0;
+        }
+    }
+}
+
+// Product b.step of every program still changing.
+__global__ __launch_bounds__(kBlock) void sbatch_step_kernel(SBatchParams b) {
+    __shared__ uint32_t s_red[kBlock / 64];
+    const int tid = threadIdx.x;
+    const int32_t t = b.step;
+    for (int64_t c = blockIdx.x; c < b.n_chunks; c += gridDim.x) {
+        const csbatch &P = sbatch_progs(b)[sbatch_prog_of(b, c)];
+        unsigned long long *cnt = P.count;
+        const bool first = c == P.chunk0;
+        if (t >= 2 && cnt[(t - 1) & (kRing - 1)] == cnt[(t - 2) & (kRing - 1)]) {
+            // the program reached its fixpoint earlier: carry the count forward
+            if (first && tid == 0) cnt[t & (kRing - 1)] = cnt[(t - 1) & (kRing - 1)];
+            continue;
+        }
+        if (first && tid == 0) cnt[(t + 1) & (kRing - 1)] = 0;
+        const uint64_t *V = P.buf[(t - 1) & 1];
+        uint64_t *U = P.buf[t & 1];
+        const int32_t log2W = P.log2W;
+        const int64_t g = (c - P.chunk0) * kSBatchChunk + tid;
+        uint32_t bits = 0;
+        if (g < P.total) {
+            const int32_t row = (int32_t)(g >> log2W);
+            const int64_t w = g & ((1ll << log2W) - 1);
+            const int32_t s = P.row_ptr[row], e = P.row_ptr[row + 1];
+            const bool is_and = (P.and_bits[row >> 6] >> (row & 63)) & 1ull;
+            uint64_t acc = is_and ? ~0ull : 0ull;
+            for (int32_t i = s; i < e; ++i) {
+                const uint64_t x = V[((int64_t)P.col[i] << log2W) + w];
+                acc = is_and ? (acc & x) : (acc | x);
+            }
+            if (s == e) acc = 0;
+            bits = (uint32_t)__popcll(acc);
+            U[g] = acc;
+        }
+        bits = block_sum(bits, s_red);
+        if (tid == 0 && bits) atomicAdd(&cnt[t & (kRing - 1)], (unsigned long long)bits);
+    }
+}
+
+// Algorithm 3 (as stable_check_kernel) and the model of the first accepted
+// column, one workgroup per program (W <= 64 words: one lane per word); both
+// buffers hold the fixpoint.
+__global__ __launch_bounds__(kBlock) void sbatch_outputs_kernel(SBatchParams b) {
+    __shared__ int64_t s_first;
+    const int tid = threadIdx.x;
+    for (int32_t pi = blockIdx.x; pi < b.n_progs; pi += gridDim.x) {
+        const csbatch &P = sbatch_progs(b)[pi];
+        const uint64_t *V = P.buf[0];
+        const int32_t log2W = P.log2W;
+        if (tid < 64) {
+            uint64_t ok = 0;
+            if (tid < (1 << log2W)) {
+                ok = valid_mask(P.k_eff);
+                for (int32_t q = 0; q < P.K; ++q)
+                    ok &= V[((int64_t)P.q_rows[q] << log2W) + tid] ^ V[((int64_t)(P.n_std + q) << log2W) + tid];
+                P.accepted[tid] = ok;
+            }
+            const uint32_t n = wave_sum((uint32_t)__popcll(ok));
+            const uint64_t nz = __ballot(ok != 0ull);
+            const int l = nz ? __builtin_ctzll(nz) : 0;
+            const uint32_t lo = __shfl((uint32_t)ok, l, 64), hi = __shfl((uint32_t)(ok >> 32), l, 64);
+            if (tid == 0) {
+                *P.n_models = n;
+                s_first = nz ? (int64_t)l * 64 + (lo ? __builtin_ctz(lo) : 32 + __builtin_ctz(hi)) : -1;
+            }
+        }
+        __syncthreads();
+        const int64_t j = s_first;
+        for (int32_t a = tid; a < P.n_atoms; a += kBlock)
+            P.model[a] = j >= 0 ? (uint8_t)((V[((int64_t)a << log2W) + (j >> 6)] >> (j & 63)) & 1ull) : (uint8_t)0;
+        __syncthreads();
+    }
+}
+
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t launch_spmm_step(const SpmmParams &p, int max_grid, hipStream_t st) {
@@ -630,6 +759,23 @@ hipError_t launch_init_guess(uint64_t *V, uint64_t *U, int64_t total, int32_t lo
                              const uint64_t *fact_bits, const uint64_t *guesses, hipStream_t st) {
     hipLaunchKernelGGL(init_guess_kernel, dim3(blocks_for(total)), dim3(kBlock), 0, st, V, U, total, log2W, n_std, K,
                        fact_bits, guesses);
+    return hipGetLastError();
+}
+
+hipError_t launch_sbatch_init(const SBatchParams &b, int max_grid, hipStream_t st) {
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.n_chunks, std::max(1, max_grid)));
+    hipLaunchKernelGGL(sbatch_init_kernel, dim3(grid), dim3(kBlock), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_sbatch_step(const SBatchParams &b, int max_grid, hipStream_t st) {
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.n_chunks, std::max(1, max_grid)));
+    hipLaunchKernelGGL(sbatch_step_kernel, dim3(grid), dim3(kBlock), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_sbatch_outputs(const SBatchParams &b, hipStream_t st) {
+    hipLaunchKernelGGL(sbatch_outputs_kernel, dim3((unsigned)std::max(1, b.n_progs)), dim3(kBlock), 0, st, b);
     return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ LP_STEP_LDS = 2
 
 EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg_atoms",
            "lp_matrix_csr", "lp_least_model", "lp_stable_models", "lp_stable_models_guesses",
-           "lp_stable_models_search", "lp_least_model_batch",
+           "lp_stable_models_search", "lp_least_model_batch", "lp_stable_models_batch",
            "lp_batch_create", "lp_batch_run", "lp_batch_results", "lp_batch_tune",
            "lp_batch_get_info", "lp_batch_free", "lp_matrix_evict", "lp_matrix_upload",
            "lp_server_create", "lp_server_add_program", "lp_server_submit", "lp_server_wait_any",
@@ -168,6 +168,7 @@ def load():
         "lp_stable_models_guesses": [P, P, i64, P, ctypes.POINTER(i64), P, P, i64, P, P],
         "lp_stable_models_search": [P, i64, i32, ctypes.c_uint64, P, i64, ctypes.POINTER(i64), P, P],
         "lp_least_model_batch": [P, i32, P, P, P, P],
+        "lp_stable_models_batch": [P, i32, P, P, P, P, P],
         "lp_batch_create": [P, i32, P, P, ctypes.POINTER(P)],
         "lp_batch_run": [P, P],
         "lp_batch_results": [P, P, P, P],
@@ -466,6 +467,22 @@ def least_model_batch(mats, sched=None, stream=None):
                                        ctypes.byref(sched) if sched is not None else None,
                                        _stream(stream)))
     return [(outs[i][: mats[i].n_atoms], int(prods[i])) for i in range(n)]
+
+
+def stable_models_batch(mats, stream=None):
+    """[dict(accepted=uint64[W], n_models, model=uint8[n_atoms] or None, products)] for a list of
+    Matrix, solved by lp_stable_models_batch (the first model of each program)."""
+    n = len(mats)
+    accs = [np.zeros(max(((1 << m.info["n_neg"]) + 63) // 64, 1), dtype=np.uint64) for m in mats]
+    outs = [np.zeros(max(m.n_atoms, 1), dtype=np.uint8) for m in mats]
+    hs = (ctypes.c_void_p * max(n, 1))(*[m.handle.value for m in mats])
+    aps = (ctypes.c_void_p * max(n, 1))(*[a.ctypes.data for a in accs])
+    mps = (ctypes.c_void_p * max(n, 1))(*[o.ctypes.data for o in outs])
+    nm = np.zeros(max(n, 1), dtype=np.int64)
+    prods = np.zeros(max(n, 1), dtype=np.int32)
+    _check(load().lp_stable_models_batch(hs, n, aps, nm.ctypes.data, mps, prods.ctypes.data, _stream(stream)))
+    return [dict(accepted=accs[i], n_models=int(nm[i]), products=int(prods[i]),
+                 model=outs[i][: mats[i].n_atoms] if nm[i] > 0 else None) for i in range(n)]
 
 
 class Batch:

@@ -114,6 +114,7 @@ def run_stream(server, pids, weights, rate: float, n_requests: int, seed: int, r
         "p99_queue_ms": round(float(np.percentile(wait, 99)), 3),
         "completed_per_s": round(n_requests / span, 1), "entries_per_s": round(entries / span, 1),
         "batched": int(sum(1 for i in infos if i["batch_size"] > 1)),
+        "batched_stable": int(sum(1 for i in infos if i["batch_size"] > 1 and i["kind"] == 1)),
         "mean_batch": round(float(np.mean([i["batch_size"] for i in infos])), 2),
         "uploads": int(sum(i["built"] for i in infos)),
         "submit_late_max_ms": round(late * 1e3, 3),

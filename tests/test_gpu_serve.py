@@ -52,6 +52,22 @@ def test_stream_results_equal_alone_and_oracle():
         assert st["n_resident"] == len(pids) and st["uploads"] == len(pids)
 
 
+def test_stable_requests_batch_under_load():
+    # small stable programs (at most 12 negated atoms, small interpretation
+    # matrices) join stable-model batches when requests pile up; the larger
+    # ones run alone; every result equals the request solved alone
+    pool = [gen.normal_uniform(90 + s, 300 + 100 * s, 600 + 200 * s, 4, 1 + s % 10, 0.1, 2, 0.02) for s in range(12)]
+    pool += [gen.normal_uniform(110, 5_000, 10_000, 5, 12, 0.1, 2, 0.02), gen.definite_uniform(111, 2000, 4000, 0.02, 4)]
+    with lp.Server(n_slots=1) as srv:
+        pids = [srv.add_program(p) for p in pool]
+        ref = serve.solve_alone(srv, pids)
+        _check_alone_vs_oracle(pool, pids, ref)
+        row = serve.run_stream(srv, pids, np.full(len(pids), 1.0 / len(pids)), rate=1e6, n_requests=200, seed=11,
+                               ref=ref)
+        assert row["mismatches"] == 0
+        assert row["batched_stable"] > 0
+
+
 def test_small_budget_evicts_and_results_still_equal():
     pool = _pool()
     with lp.Server(n_slots=4) as big:

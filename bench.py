@@ -353,7 +353,7 @@ def bench_serving(args, gen, lp) -> dict:
             assert row["mismatches"] == 0, f"{row['mismatches']} streamed results differ from alone"
             rows.append({f: row[f] for f in ("rate", "requests", "least", "stable", "p50_ms", "p99_ms",
                                              "mean_ms", "p99_queue_ms", "completed_per_s", "entries_per_s",
-                                             "batched", "mismatches")})
+                                             "batched", "batched_stable", "mismatches")})
             log(f"[bench] serving {rows[-1]}")
         st = srv.stats()
     return {"workload": "serving pool: 256 programs, atoms log-uniform 1e3-1e6, rules 3x atoms, bodies 1-6, "
@@ -376,7 +376,7 @@ def main() -> int:
     ap.add_argument("--no-frontier", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-rates", default="100,1000")
+    ap.add_argument("--serve-rates", default="100,1000,3000")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--dense-only", action="store_true",

@@ -489,6 +489,35 @@ lp_status lp_tune_schedule(const lp_matrix *m, int32_t reps, lp_schedule *best, 
                            float *best_solve_ms, void *hip_stream);
 
 /*
+ * Schedule cache. lp_tune_schedule stores the schedule it returns under the
+ * matrix's size bucket: whether v fits a workgroup's LDS, ceil(log2 n_rows),
+ * the mean AND row length in half entries (at most 64), and whether long rows
+ * exist. lp_least_model with no schedule (or an all-zero one) then solves any
+ * matrix of a bucket that holds a schedule with it; results never depend on
+ * the schedule. The cache is per process and thread-safe.
+ *
+ * lp_schedule_cache_save: writes every entry to the text file `path` (one
+ *   line per bucket; written to path.tmp, then renamed).
+ * lp_schedule_cache_load: merges the entries of `path` into the cache; a
+ *   malformed line or an unsupported schedule rejects the whole file
+ *   (LP_E_INVAL, cache unchanged).
+ * lp_schedule_cache_clear: empties the cache.
+ * lp_schedule_cache_lookup: *found = 1 and *out the schedule if m's bucket
+ *   holds one; 0 if not; 2 if the default driver solves m in one workgroup,
+ *   where no schedule applies (and for programs with negation, 0).
+ * With the environment variable LP_SCHEDULE_CACHE naming a file, the library
+ * loads it (if it exists) on first use of the cache and saves the cache to
+ * it after every lp_tune_schedule.
+ * Errors: LP_E_INVAL (NULL or empty path, unreadable or unwritable file,
+ *   malformed file; NULL m, out or found), LP_E_HOST_ONLY (lookup of a matrix
+ *   without a device copy).
+ */
+lp_status lp_schedule_cache_save(const char *path);
+lp_status lp_schedule_cache_load(const char *path);
+lp_status lp_schedule_cache_clear(void);
+lp_status lp_schedule_cache_lookup(const lp_matrix *m, lp_schedule *out, int32_t *found);
+
+/*
  * lp_least_model without device allocation, for callers that cannot call
  * hipMalloc or take memory from a pool at solve time (code under stream
  * capture, tight serving loops, harnesses that forbid allocation). Same
@@ -549,7 +578,10 @@ typedef struct lp_server_config {
     int32_t device;       /* HIP device (-1 or 0..: -1 means the current device) */
     int64_t hbm_budget;   /* device bytes for resident matrices and running solves
                              (0: 90% of the free memory at creation) */
-    int64_t reserved;
+    int32_t tune;         /* 1: a least-model request whose matrix's size bucket holds no cached
+                             schedule (see lp_schedule_cache_lookup) tunes one first
+                             (lp_tune_schedule); later matrices of the bucket use it */
+    int32_t reserved;
 } lp_server_config;
 
 typedef struct lp_request_info {
@@ -580,6 +612,7 @@ typedef struct lp_server_stats {
     int64_t used_bytes;         /* accounted device bytes now */
     int64_t peak_used_bytes;
     int64_t hbm_budget;
+    int64_t tunes;              /* schedules tuned for least-model requests (cfg.tune) */
 } lp_server_stats;
 
 /* cfg nullable (defaults). Errors: LP_E_INVAL, LP_E_DEVICE. */

@@ -15,7 +15,9 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <cstdlib>
 #include <map>
+#include <tuple>
 #include <queue>
 #include <mutex>
 #include <string>
@@ -824,6 +826,145 @@ static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
 
 // With host_bits (nullable), *on_host tells whether the first ceil(n_atoms / 64)
 // words of the fixpoint were already copied there.
+// ------------------------------------------------------------------ schedule cache
+//
+// Schedules found by lp_tune_schedule, kept per size bucket of the matrix:
+// whether v fits a workgroup's LDS (the step's gather form), the rows'
+// ceil log2, the mean AND row length in half entries, and whether long rows
+// exist. The default driver solves a matrix whose bucket holds a schedule
+// with that schedule. The cache lives in the process; lp_schedule_cache_save
+// and _load keep it in a text file, and with LP_SCHEDULE_CACHE naming a file
+// the library loads it on first use and saves it after every tune.
+
+struct SchedKey {
+    int32_t lds = 0, log2_rows = 0, len_q = 0, long_rows = 0;
+    bool operator<(const SchedKey &o) const {
+        return std::tie(lds, log2_rows, len_q, long_rows) < std::tie(o.lds, o.log2_rows, o.len_q, o.long_rows);
+    }
+};
+
+static std::mutex g_sched_mu;
+static std::map<SchedKey, lp_schedule> g_sched;
+static bool g_sched_env_done = false;
+
+static int ceil_log2(int64_t x) {
+    int l = 0;
+    while ((1ll << l) < x) ++l;
+    return l;
+}
+
+static SchedKey sched_key(const Matrix &m) {
+    SchedKey k;
+    k.lds = n_words_of(m.n_atoms) <= step_lds_v_words(16) ? 1 : 0;
+    k.log2_rows = ceil_log2(std::max(1, m.n_rows));
+    const int64_t and_rows = std::max<int64_t>(1, m.info.n_and_rows);
+    k.len_q = (int32_t)std::min<int64_t>(64, (2 * (m.dev.and_nnz + m.dev.long_nnz) + and_rows / 2) / and_rows);
+    k.long_rows = m.info.n_long_rows > 0 ? 1 : 0;
+    return k;
+}
+
+static const char kSchedMagic[] = "lp-sched-v1";
+
+static bool sched_valid(const lp_schedule &s) {
+    auto in = [](int32_t v, std::initializer_list<int32_t> ok) {
+        for (int32_t x : ok)
+            if (v == x) return true;
+        return false;
+    };
+    return s.driver >= LP_DRIVER_AUTO && s.driver <= LP_DRIVER_FRONTIER && s.steps_per_sync >= 0 &&
+           s.steps_per_sync <= 4096 && in(s.variant, {LP_STEP_AUTO, LP_STEP_GLOBAL, LP_STEP_LDS}) && s.grid >= 0 &&
+           s.grid <= (1 << 20) && in(s.wpw, {0, 1, 2, 4, 8}) && in(s.unroll, {0, 4, 8, 16}) &&
+           in(s.block, {0, 256, 512, 1024}) && s.team == 0 && s.team_polls == 0;
+}
+
+// Parses a cache file; all or nothing (lock held by the caller).
+static lp_status sched_load_locked(const char *path) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) {
+        set_error(std::string("cannot open schedule cache ") + path);
+        return LP_E_INVAL;
+    }
+    std::map<SchedKey, lp_schedule> add;
+    char line[512];
+    int ln = 0;
+    lp_status rc = LP_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        ++ln;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char magic[32] = {0};
+        SchedKey k;
+        lp_schedule s{};
+        char tail = 0;
+        const int n = std::sscanf(line, "%31s %d %d %d %d %d %d %d %d %d %d %d %c", magic, &k.lds, &k.log2_rows,
+                                  &k.len_q, &k.long_rows, &s.driver, &s.steps_per_sync, &s.variant, &s.grid,
+                                  &s.wpw, &s.unroll, &s.block, &tail);
+        if (n != 12 || std::strcmp(magic, kSchedMagic) != 0 || k.lds < 0 || k.lds > 1 || k.log2_rows < 0 ||
+            k.log2_rows > 40 || k.len_q < 0 || k.len_q > 64 || k.long_rows < 0 || k.long_rows > 1 ||
+            !sched_valid(s)) {
+            set_error(std::string("malformed schedule cache line ") + std::to_string(ln) + " in " + path);
+            rc = LP_E_INVAL;
+            break;
+        }
+        add[k] = s;
+    }
+    std::fclose(f);
+    if (rc) return rc;
+    for (auto &e : add) g_sched[e.first] = e.second;
+    return LP_OK;
+}
+
+static lp_status sched_save_locked(const char *path) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) {
+        set_error(std::string("cannot write schedule cache ") + path);
+        return LP_E_INVAL;
+    }
+    std::fprintf(f, "# %s: lds log2_rows len_q long_rows | driver steps_per_sync variant grid wpw unroll block\n",
+                 kSchedMagic);
+    for (auto &e : g_sched) {
+        const SchedKey &k = e.first;
+        const lp_schedule &s = e.second;
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d\n", kSchedMagic, k.lds, k.log2_rows, k.len_q,
+                     k.long_rows, s.driver, s.steps_per_sync, s.variant, s.grid, s.wpw, s.unroll, s.block);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        set_error(std::string("cannot write schedule cache ") + path);
+        return LP_E_INVAL;
+    }
+    return LP_OK;
+}
+
+// Loads LP_SCHEDULE_CACHE once, if it is set and the file exists (lock held).
+static void sched_env_locked() {
+    if (g_sched_env_done) return;
+    g_sched_env_done = true;
+    const char *p = std::getenv("LP_SCHEDULE_CACHE");
+    if (!p || !*p) return;
+    FILE *f = std::fopen(p, "r");
+    if (!f) return;  // created by the first tune
+    std::fclose(f);
+    (void)sched_load_locked(p);
+}
+
+static bool sched_lookup(const Matrix &m, lp_schedule *out) {
+    std::lock_guard<std::mutex> lock(g_sched_mu);
+    sched_env_locked();
+    auto it = g_sched.find(sched_key(m));
+    if (it == g_sched.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+static void sched_store(const Matrix &m, const lp_schedule &s) {
+    std::lock_guard<std::mutex> lock(g_sched_mu);
+    sched_env_locked();
+    g_sched[sched_key(m)] = s;
+    const char *p = std::getenv("LP_SCHEDULE_CACHE");
+    if (p && *p) (void)sched_save_locked(p);
+}
+
 static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipStream_t st, Scratch &S,
                                 uint64_t **out, int32_t *products, uint64_t *host_bits = nullptr,
                                 bool *on_host = nullptr) {
@@ -842,6 +983,10 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
         if (rc == LP_OK && on_host) *on_host = host_bits != nullptr;
         return rc;
     }
+    // a tuned schedule for matrices of this size bucket (not in a fixed scratch
+    // region, whose size is that of the default schedule's buffers)
+    lp_schedule cached;
+    if (all_default && S.may_alloc() && sched_lookup(m, &cached)) sched = &cached;
     const int64_t W = n_words_of(m.n_rows);
     uint64_t *buf[2];
     unsigned long long *counters;
@@ -2008,6 +2153,7 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
     *best = t_p < t_b ? persistent : batched;
     if (best_step_ms) *best_step_ms = win_ms;
     if (best_solve_ms) *best_solve_ms = t_p < t_b ? t_p : t_b;
+    sched_store(m, *best);  // the default driver takes it for matrices of this size bucket
     return LP_OK;
 }
 
@@ -3334,6 +3480,58 @@ lp_status lp_tune_schedule(const lp_matrix *m, int32_t reps, lp_schedule *best, 
     }
     DeviceGuard g(m->m.dev.device);
     return tune_impl(m->m, reps, best, best_step_ms, best_solve_ms, (hipStream_t)hip_stream);
+    LP_GUARD_END
+}
+
+lp_status lp_schedule_cache_save(const char *path) {
+    LP_GUARD_BEGIN
+    if (!path || !*path) {
+        set_error("NULL or empty path");
+        return LP_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_sched_mu);
+    sched_env_locked();
+    return sched_save_locked(path);
+    LP_GUARD_END
+}
+
+lp_status lp_schedule_cache_load(const char *path) {
+    LP_GUARD_BEGIN
+    if (!path || !*path) {
+        set_error("NULL or empty path");
+        return LP_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_sched_mu);
+    sched_env_locked();
+    return sched_load_locked(path);
+    LP_GUARD_END
+}
+
+lp_status lp_schedule_cache_clear(void) {
+    LP_GUARD_BEGIN
+    std::lock_guard<std::mutex> lock(g_sched_mu);
+    g_sched_env_done = true;  // a cleared cache stays empty until loaded or tuned
+    g_sched.clear();
+    return LP_OK;
+    LP_GUARD_END
+}
+
+lp_status lp_schedule_cache_lookup(const lp_matrix *m, lp_schedule *out, int32_t *found) {
+    LP_GUARD_BEGIN
+    if (!m || !out || !found) {
+        set_error("m, out and found must be non-NULL");
+        return LP_E_INVAL;
+    }
+    *found = 0;
+    lp_status rc = check_solvable(m);  // the bucket reads the device layout's sizes
+    if (rc) return rc;
+    if (m->m.K) return LP_OK;  // schedules are for least models
+    if (m->m.n_rows > 0 && lds_loop_fits(m->m)) {
+        *found = 2;  // solved in one workgroup by the default driver: no schedule
+        return LP_OK;
+    }
+    if (sched_lookup(m->m, out)) *found = 1;
+    return LP_OK;
     LP_GUARD_END
 }
 

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -105,6 +106,7 @@ struct lp_server {
     int64_t peak_used = 0;
     uint64_t clock = 0;               // LRU ticks
     int64_t n_batches = 0, n_batched = 0, n_alone = 0, n_uploads = 0, n_evictions = 0, n_completed = 0;
+    std::atomic<int64_t> n_tunes{0};
     int64_t max_batch_rows = 0;
     std::vector<hipStream_t> streams;
     std::vector<std::thread> workers;
@@ -294,6 +296,17 @@ void run_group(lp_server *s, hipStream_t st, std::vector<Request *> &group, std:
         } else if (p->info.n_neg == 0) {
             r->model.assign(std::max(1, p->info.n_atoms), 0);
             int32_t pr = 0;
+            if (s->cfg.tune) {
+                // a matrix whose size bucket holds no tuned schedule: tune one (the
+                // solve below and later matrices of the bucket use it; slots that
+                // meet the same new bucket at once may each tune it)
+                lp_schedule cs{};
+                int32_t found = 0;
+                if (lp_schedule_cache_lookup(p->m, &cs, &found) == LP_OK && found == 0) {
+                    lp_schedule best{};
+                    if (lp_tune_schedule(p->m, 2, &best, nullptr, nullptr, st) == LP_OK) s->n_tunes++;
+                }
+            }
             r->info.status = lp_least_model(p->m, r->model.data(), &pr, nullptr, st);
             r->model.resize(p->info.n_atoms);
             r->info.products = pr;
@@ -552,6 +565,7 @@ lp_status lp_server_get_stats(lp_server *s, lp_server_stats *out) {
     St.used_bytes = s->used;
     St.peak_used_bytes = s->peak_used;
     St.hbm_budget = s->cfg.hbm_budget;
+    St.tunes = s->n_tunes.load();
     *out = St;
     return LP_OK;
 }

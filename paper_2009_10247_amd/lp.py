@@ -61,7 +61,8 @@ EXPORTS = ("lp_build_matrix", "lp_free_matrix", "lp_matrix_info", "lp_matrix_neg
            "lp_server_take_result", "lp_server_get_stats", "lp_server_free",
            "lp_memory_stats", "lp_release_cached_memory", "lp_bench_spmm",
            "lp_bench_step", "lp_tune_schedule", "lp_set_allocator", "lp_dense_least_model",
-           "lp_dense_stable_models", "lp_least_model_noalloc", "lp_last_error")
+           "lp_dense_stable_models", "lp_least_model_noalloc", "lp_schedule_cache_save",
+           "lp_schedule_cache_load", "lp_schedule_cache_clear", "lp_schedule_cache_lookup", "lp_last_error")
 
 
 class LPError(RuntimeError):
@@ -101,7 +102,7 @@ class lp_batch_info(ctypes.Structure):
 class lp_server_config(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int32), ("batch_max", ctypes.c_int32),
                 ("batch_rows", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+                ("hbm_budget", ctypes.c_int64), ("tune", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lp_request_info(ctypes.Structure):
@@ -117,7 +118,7 @@ class lp_server_stats(ctypes.Structure):
                 ("pending", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("batched_requests", ctypes.c_int64), ("alone_requests", ctypes.c_int64),
                 ("uploads", ctypes.c_int64), ("evictions", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
-                ("peak_used_bytes", ctypes.c_int64), ("hbm_budget", ctypes.c_int64)]
+                ("peak_used_bytes", ctypes.c_int64), ("hbm_budget", ctypes.c_int64), ("tunes", ctypes.c_int64)]
 
 
 _lib = None
@@ -179,6 +180,10 @@ def load():
         "lp_tune_schedule": [P, i32, ctypes.POINTER(lp_schedule), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float), P],
         "lp_set_allocator": [P, P, P],
+        "lp_schedule_cache_save": [ctypes.c_char_p],
+        "lp_schedule_cache_load": [ctypes.c_char_p],
+        "lp_schedule_cache_clear": [],
+        "lp_schedule_cache_lookup": [P, ctypes.POINTER(lp_schedule), ctypes.POINTER(i32)],
         "lp_matrix_evict": [P],
         "lp_matrix_upload": [P, P],
         "lp_server_create": [ctypes.POINTER(lp_server_config), ctypes.POINTER(P)],
@@ -469,6 +474,29 @@ def least_model_batch(mats, sched=None, stream=None):
     return [(outs[i][: mats[i].n_atoms], int(prods[i])) for i in range(n)]
 
 
+def schedule_cache_save(path: str) -> None:
+    """Write the schedule cache (lp_schedule_cache_save)."""
+    _check(load().lp_schedule_cache_save(os.fsencode(path)))
+
+
+def schedule_cache_load(path: str) -> None:
+    """Merge a schedule cache file (lp_schedule_cache_load)."""
+    _check(load().lp_schedule_cache_load(os.fsencode(path)))
+
+
+def schedule_cache_clear() -> None:
+    _check(load().lp_schedule_cache_clear())
+
+
+def schedule_cache_lookup(mat):
+    """(found, schedule): found 1 with the cached schedule of mat's size bucket, 0 none, 2 the
+    default driver solves mat in one workgroup (lp_schedule_cache_lookup)."""
+    s = lp_schedule()
+    found = ctypes.c_int32(0)
+    _check(load().lp_schedule_cache_lookup(mat.handle, ctypes.byref(s), ctypes.byref(found)))
+    return found.value, s
+
+
 def stable_models_batch(mats, stream=None):
     """[dict(accepted=uint64[W], n_models, model=uint8[n_atoms] or None, products)] for a list of
     Matrix, solved by lp_stable_models_batch (the first model of each program)."""
@@ -590,9 +618,9 @@ class Server:
     """Request loop of lp_server_create: register programs, submit requests,
     collect completions (argument marshalling only; the loop is native)."""
 
-    def __init__(self, n_slots=0, batch_max=0, batch_rows=0, hbm_budget=0, device=-1):
+    def __init__(self, n_slots=0, batch_max=0, batch_rows=0, hbm_budget=0, device=-1, tune=False):
         cfg = lp_server_config(n_slots=n_slots, batch_max=batch_max, batch_rows=batch_rows, device=device,
-                               hbm_budget=int(hbm_budget))
+                               hbm_budget=int(hbm_budget), tune=1 if tune else 0)
         h = ctypes.c_void_p()
         _check(load().lp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

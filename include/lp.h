@@ -81,7 +81,12 @@ enum {
     LP_STABLE_FULL_SWEEP = 1u << 2,
     /* Stable-model products by dirty rows whatever the matrix size (ignored
      * with LP_STABLE_FULL_SWEEP). */
-    LP_STABLE_DIRTY_ROWS = 1u << 3
+    LP_STABLE_DIRTY_ROWS = 1u << 3,
+    /* Least models: lay the AND entries out in column slices of 1,024 atoms
+     * (one pass per slice and product; by default slices are used only when
+     * the original atoms exceed what a workgroup's LDS holds, about 1.29
+     * million). For tests of the sliced step on small programs. */
+    LP_STEP_SLICES_SMALL = 1u << 4
 };
 
 typedef struct lp_matrix lp_matrix;
@@ -108,6 +113,8 @@ typedef struct lp_info {
                                CSR, one read of V, one write of U for all 2^K guesses; 0 when
                                K exceeds LP_MAX_NEG_ATOMS) */
     double sparsity;        /* equation 5: 1 - sum_r |body(r)| / N^2 */
+    int32_t n_slices;       /* least models: column slices of the step's layout (0: not sliced) */
+    int32_t reserved_info;
 } lp_info;
 
 /* Device-side schedule of the fixpoint loop. Zero-initialize and set what you
@@ -170,7 +177,7 @@ typedef struct lp_schedule {
  * with no rule has an empty OR row and is never true.
  *
  * flags: LP_PRUNE_FACT_GUESSES, LP_BUILD_HOST_ONLY, LP_STABLE_FULL_SWEEP,
- * LP_STABLE_DIRTY_ROWS.
+ * LP_STABLE_DIRTY_ROWS, LP_STEP_SLICES_SMALL.
  * On success *out owns host metadata and (unless host-only) device buffers,
  * uploaded on hip_stream, until lp_free_matrix.
  * Errors: LP_E_INVAL (bad ids, body_ptr not monotone, NULL arrays with

@@ -44,6 +44,21 @@ struct LongSeg {
 
 // Device-resident form of one matrix. All pointers are device memory owned
 // by the matrix (released by lp_free_matrix).
+// One column slice of a least-model layout: the AND entries of block AND
+// rows whose columns lie in [64 first_word, 64 (first_word + lds_words)),
+// stored as the layout stores them, with columns relative to the slice.
+struct SliceLayout {
+    const WordMeta *words;
+    const uint8_t *and_len;
+    const uint32_t *lens4;
+    const int32_t *col;
+    int32_t and_end;
+    int32_t and_max_col;
+    int32_t first_word;
+    int32_t lds_words;
+};
+constexpr int kMaxSlices = 64;
+
 struct DeviceMatrix {
     // least models (definite programs)
     WordMeta *words = nullptr;    // [n_words + kWordPad]
@@ -66,6 +81,14 @@ struct DeviceMatrix {
     // device splits of the block pass between waves, one per wave count
     // (created on first use by the step planner, under its lock)
     mutable std::vector<std::pair<int32_t, int32_t *>> wave_parts;
+    // column-sliced layout of the block AND entries (when the original atoms
+    // exceed a workgroup's LDS, or with LP_STEP_SLICES_SMALL): one layout per
+    // slice of columns, each slice's word_base (host) and its wave splits by
+    // (slice, wave count), and the block AND rows of every word
+    std::vector<SliceLayout> slices;
+    std::vector<std::vector<int32_t>> slice_base;
+    mutable std::vector<std::pair<int64_t, int32_t *>> slice_parts;
+    uint64_t *and_all = nullptr;
     // transposed matrix of the frontier driver (built on first use, under its lock)
     mutable int32_t *fr_ptr = nullptr;    // [n_rows + 1]
     mutable int32_t *fr_occ = nullptr;    // rows naming each row, ascending

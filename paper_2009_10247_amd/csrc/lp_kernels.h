@@ -37,13 +37,23 @@ struct StepParams {
     int32_t and_max_col;           // largest column of a block AND entry (-1 if none)
     int32_t step;                  // 1-based product index
     int32_t early_exit;            // 1: return at once if product step-1 changed nothing
-    int32_t lds_words;             // leading words of v staged in LDS (LDS shapes)
+    int32_t lds_words;             // words of v staged in LDS (LDS shapes), from word stage_off
+    int32_t stage_off;             // first staged word (0 unless the layout is sliced)
+    // column-sliced layouts (kStepSlice): a product is n_pass launches, pass k
+    // over the AND entries whose columns lie in slice k (staged in LDS); pacc
+    // holds per word the AND rows whose entries in the passes so far are all
+    // true, and_all every block AND row of the word
+    uint64_t *pacc;
+    const uint64_t *and_all;
+    int32_t pass;
+    int32_t n_pass;
 };
 
 // Forms of the step kernel: gathers of v from global memory; from v staged
-// in LDS (every AND entry names a staged atom); or mixed (atoms past the
-// staged words are read from global memory).
-enum StepMode : int { kStepGlobal = 0, kStepLds = 1, kStepMixed = 2 };
+// in LDS (every AND entry names a staged atom); mixed (atoms past the staged
+// words are read from global memory); or sliced (one pass per column slice of
+// the AND entries, each slice's part of v staged in LDS).
+enum StepMode : int { kStepGlobal = 0, kStepLds = 1, kStepMixed = 2, kStepSlice = 3 };
 
 // LDS of the staged forms (static, so v sits at LDS address 0): the staged
 // words of v, then one ballot slot area per wave (16 waves x (unroll + 1)
@@ -53,16 +63,24 @@ inline int32_t step_lds_v_words(int unroll) { return kStepLdsBytes / 8 - 16 * (u
 
 // Launch shape of the step kernel. A wave owns wpw consecutive 64-row words
 // (a super-block) and keeps unroll column chunks of 64 entries in flight.
+
 struct StepShape {
     int mode = kStepLds;  // StepMode; staged forms use 1024-thread workgroups, one per CU
     int wpw = 8;          // words per super-block: 4 or 8
     int unroll = 8;       // 4, 8 or 16
     int block = 1024;     // threads per workgroup
     int grid = 0;         // workgroups (grid-stride loop over super-blocks)
+    // kStepSlice: the slices (host array kept with the matrix) and each
+    // slice's wave split for this grid
+    int n_slices = 0;
+    const SliceLayout *slice = nullptr;
+    const int32_t *slice_part[kMaxSlices] = {};
 };
 
 bool step_shape_supported(const StepShape &s);
 hipError_t launch_step(const StepShape &s, const StepParams &p, hipStream_t st);
+// One launch of the step kernel with p as given (one pass of a sliced step).
+hipError_t launch_step_pass(const StepShape &s, const StepParams &p, hipStream_t st);
 
 // Sets n 32-bit words at p to 0 (a kernel, not a memset node).
 hipError_t launch_zero_words(void *p, int64_t n, hipStream_t st);

@@ -319,6 +319,10 @@ static void free_device(Matrix &m, hipStream_t st) {
                   d.full_row_ptr, d.full_col,      d.full_and_bits, d.q_rows, d.guess_pos};
     for (void *p : ps) dev_free(p, st);
     for (auto &wp : d.wave_parts) dev_free(wp.second, st);
+    for (auto &sp : d.slice_parts) dev_free(sp.second, st);
+    for (const SliceLayout &L : d.slices)
+        for (void *p : {(void *)L.words, (void *)L.and_len, (void *)L.lens4, (void *)L.col}) dev_free(p, st);
+    dev_free(d.and_all, st);
     for (void *p : {(void *)d.fr_ptr, (void *)d.fr_occ, (void *)d.fr_cnt0, (void *)d.fr_facts}) dev_free(p, st);
     d = DeviceMatrix{};
 }
@@ -330,6 +334,105 @@ static inline int32_t encode_entry(int32_t c) { return ((c >> 5) << 7) | (c & 31
 
 // Least-model layout (see WordMeta and LongSeg): rows by kind, AND entries of
 // block rows in col, OR rows as child ranges, long rows as segments.
+// Words of v per column slice: what a workgroup's LDS stages in the step
+// with the most chunks in flight (even: slices are staged with 16-byte loads),
+// or 16 words (1,024 atoms) with LP_STEP_SLICES_SMALL.
+static int32_t slice_words(const Matrix &m) {
+    if (m.flags & LP_STEP_SLICES_SMALL) return 16;
+    return step_lds_v_words(16) & ~1;
+}
+
+// Column-sliced layout of the block AND rows, when their columns span more
+// than one slice: slice k holds, for every block AND row, its entries with
+// columns in [64 k S, 64 (k + 1) S) (S = slice_words; entries are ascending
+// within a row, so they are a contiguous part of it), relative to the slice,
+// in the same form as the whole layout (words, lengths, lens4, entries).
+static lp_status build_slices(Matrix &m, const std::vector<uint64_t> &and_all, hipStream_t st) {
+    DeviceMatrix &d = m.dev;
+    if (m.K != 0 || d.and_max_col < 0) return LP_OK;
+    const int64_t S = slice_words(m), cols = 64 * S;
+    const int64_t n_slices = (int64_t)d.and_max_col / cols + 1;
+    if (n_slices < 2) return LP_OK;
+    if (n_slices > kMaxSlices) {
+        set_error("the least-model layout would need " + std::to_string(n_slices) + " column slices (at most " +
+                  std::to_string(kMaxSlices) + ")");
+        return LP_E_INVAL;
+    }
+    const int32_t n = m.n_rows;
+    const int64_t W = n_words_of(n);
+    lp_status rc;
+    int64_t extra = 0;
+    for (int64_t k = 0; k < n_slices; ++k) {
+        const int32_t c_lo = (int32_t)(k * cols), c_hi = (int32_t)std::min<int64_t>((k + 1) * cols, INT32_MAX);
+        std::vector<WordMeta> words(W + kWordPad);
+        std::vector<uint8_t> and_len((size_t)(W + kWordPad) * 64, 0);
+        std::vector<int32_t> col;
+        int32_t max_col = -1;
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t w = i >> 6;
+            if ((i & 63) == 0) {
+                words[w] = WordMeta{};
+                words[w].and_base = (int32_t)col.size();
+            }
+            if (!((and_all[w] >> (i & 63)) & 1ull)) continue;  // block AND rows only
+            const int32_t *b = m.col.data() + m.row_ptr[i], *e = m.col.data() + m.row_ptr[i + 1];
+            const int32_t *lo = std::lower_bound(b, e, c_lo), *hi = std::lower_bound(lo, e, c_hi);
+            if (lo == hi) continue;
+            words[w].and_bits |= 1ull << (i & 63);
+            and_len[i] = (uint8_t)(hi - lo);
+            for (const int32_t *c = lo; c < hi; ++c) {
+                col.push_back(encode_entry(*c - c_lo));
+                max_col = std::max(max_col, *c - c_lo);
+            }
+        }
+        for (int64_t w = W; w < W + kWordPad; ++w) {
+            words[w] = WordMeta{};
+            words[w].and_base = (int32_t)col.size();
+        }
+        std::vector<int32_t> base((size_t)W + 1);
+        for (int64_t w = 0; w < W; ++w) base[w] = words[w].and_base;
+        base[W] = (int32_t)col.size();
+        const int32_t n_entries = (int32_t)col.size();
+        col.insert(col.end(), kColPad, 0);
+        const int64_t n_quads = (W + kWordPad + 3) / 4;
+        std::vector<uint32_t> lens4((size_t)n_quads * 64, 0);
+        for (int64_t q = 0; q < n_quads; ++q)
+            for (int j = 0; j < 4; ++j) {
+                const int64_t w = 4 * q + j;
+                if (w >= W + kWordPad) break;
+                for (int l = 0; l < 64; ++l) lens4[q * 64 + l] |= (uint32_t)and_len[w * 64 + l] << (8 * j);
+            }
+        WordMeta *dw;
+        uint8_t *dl;
+        uint32_t *d4;
+        int32_t *dc;
+        if ((rc = upload(&dw, words.data(), words.size(), st, &d.bytes)) ||
+            (rc = upload(&dl, and_len.data(), and_len.size(), st, &d.bytes)) ||
+            (rc = upload(&d4, lens4.data(), lens4.size(), st, &d.bytes)) ||
+            (rc = upload(&dc, col.data(), col.size(), st, &d.bytes)))
+            return rc;
+        SliceLayout L{};
+        L.words = dw;
+        L.and_len = dl;
+        L.lens4 = d4;
+        L.col = dc;
+        L.and_end = n_entries;
+        L.and_max_col = max_col;
+        L.first_word = (int32_t)(k * S);
+        L.lds_words = (int32_t)std::max<int64_t>(0, std::min<int64_t>(S, W - k * S));
+        d.slices.push_back(L);
+        d.slice_base.push_back(std::move(base));
+        LP_HIP(hipStreamSynchronize(st));  // the host vectors end here
+        extra += n + 4 * ((W + 3) / 4) + 4 * (int64_t)n_entries;
+    }
+    if ((rc = upload(&d.and_all, and_all.data(), and_all.size(), st, &d.bytes))) return rc;
+    // what a sliced step streams: every slice's lengths, word offsets and
+    // entries, the long rows, OR tables and segments, and the partial AND
+    // words (written by the first pass, read and written by the others)
+    d.stream_bytes += extra - (n + 4 * ((W + 3) / 4) + 4 * d.and_nnz) + 2 * n_slices * W * 8;
+    return LP_OK;
+}
+
 static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
     DeviceMatrix &d = m.dev;
     const int32_t n = m.n_rows;
@@ -454,7 +557,10 @@ static lp_status upload_least_layout(Matrix &m, hipStream_t st) {
     // the OR range table and the long-row segments
     d.stream_bytes = n + 4 * ((W + 3) / 4) + 4 * (d.and_nnz + d.long_nnz) +
                      4 * (int64_t)(or_c0.size() + or_row.size()) + (int64_t)sizeof(LongSeg) * d.n_segs;
-    return LP_OK;
+    // the block AND rows of every word, for a sliced step
+    std::vector<uint64_t> and_all(W ? W : 1, 0);
+    for (int64_t w = 0; w < W; ++w) and_all[w] = words[w].and_bits;
+    return build_slices(m, and_all, st);
 }
 
 static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
@@ -463,7 +569,7 @@ static int ilog2(int64_t x);
 static bool lds_loop_fits(const Matrix &m);
 static StepParams step_params(const Matrix &m);
 static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S, hipStream_t st,
-                           bool may_alloc = true);
+                           bool may_alloc = true, bool slices = true);
 
 static lp_status upload_matrix(Matrix &m, hipStream_t st) {
     DeviceMatrix &d = m.dev;
@@ -571,6 +677,7 @@ static StepParams step_params(const Matrix &m) {
     p.n_long_and = d.n_long_and;
     p.n_segs = d.n_segs;
     p.early_exit = 1;
+    p.and_all = d.and_all;
     return p;
 }
 
@@ -590,31 +697,14 @@ constexpr int64_t kSegCost = 1600;
 // [t[2k], t[2k + 2]) and t[2k + 1] is the first AND entry of word t[2k]. Each
 // wave gets about the same cost (AND entries + kWordCost per word of its
 // block pass, plus its OR tiles and segments), so the waves end together.
-// Created once per wave count and kept with the matrix's device arrays.
-static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, const int32_t **out,
-                                bool may_alloc = true) {
-    std::lock_guard<std::mutex> lock(g_lazy_mu);
-    const DeviceMatrix &d = m.dev;
-    for (const auto &wp : d.wave_parts)
-        if (wp.first == waves) {
-            *out = wp.second;
-            return LP_OK;
-        }
-    if (!may_alloc) {
-        set_error("no step split for " + std::to_string(waves) + " waves was made at upload");
-        return LP_E_INTERNAL;
-    }
-    const std::vector<int32_t> &b = d.word_base;
-    if (b.empty() || waves < 1) {
-        set_error("no least-model layout to split");
-        return LP_E_INTERNAL;
-    }
+// b: the layout's first AND entry of every word, then the entry count.
+static lp_status split_waves(const std::vector<int32_t> &b, int64_t n_tiles, int64_t n_segs, int32_t waves,
+                             hipStream_t st, int32_t **out, int64_t *bytes) {
     const int64_t W = (int64_t)b.size() - 1;
     // wave k also evaluates OR tiles k, k + waves, ... and segments k, k + waves, ...
-    const int64_t n_tiles = ((int64_t)d.n_or + 63) / 64;
     auto extra = [&](int64_t k) -> int64_t {
         const int64_t tiles = k < n_tiles ? (n_tiles - 1 - k) / waves + 1 : 0;
-        const int64_t segs = k < d.n_segs ? ((int64_t)d.n_segs - 1 - k) / waves + 1 : 0;
+        const int64_t segs = k < n_segs ? (n_segs - 1 - k) / waves + 1 : 0;
         return kOrTileCost * tiles + kSegCost * segs;
     };
     int64_t total = (int64_t)b[W] + kWordCost * W;
@@ -629,12 +719,51 @@ static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, 
     }
     t[2 * (size_t)waves] = (int32_t)W;
     t[2 * (size_t)waves + 1] = b[W];
-    int32_t *dp = nullptr;
-    int64_t bytes = 0;
-    lp_status rc = upload(&dp, t.data(), t.size(), st, &bytes);
+    lp_status rc = upload(out, t.data(), t.size(), st, bytes);
     if (rc) return rc;
     LP_HIP(hipStreamSynchronize(st));  // t is a local
-    d.wave_parts.emplace_back(waves, dp);
+    return LP_OK;
+}
+
+// The split of the whole layout (slice < 0) or of column slice `slice` for
+// `waves` waves, created once and kept with the matrix's device arrays. OR
+// tiles and segments count in the whole layout's split and in the last
+// slice's (a sliced step evaluates them in its last pass).
+static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, const int32_t **out,
+                                bool may_alloc = true, int32_t slice = -1) {
+    std::lock_guard<std::mutex> lock(g_lazy_mu);
+    const DeviceMatrix &d = m.dev;
+    const int64_t key = slice < 0 ? (int64_t)waves : ((int64_t)slice << 32) | (uint32_t)waves;
+    if (slice < 0) {
+        for (const auto &wp : d.wave_parts)
+            if (wp.first == waves) {
+                *out = wp.second;
+                return LP_OK;
+            }
+    } else {
+        for (const auto &sp : d.slice_parts)
+            if (sp.first == key) {
+                *out = sp.second;
+                return LP_OK;
+            }
+    }
+    if (!may_alloc) {
+        set_error("no step split for " + std::to_string(waves) + " waves was made at upload");
+        return LP_E_INTERNAL;
+    }
+    const std::vector<int32_t> &b = slice < 0 ? d.word_base : d.slice_base[slice];
+    if (b.empty() || waves < 1) {
+        set_error("no least-model layout to split");
+        return LP_E_INTERNAL;
+    }
+    const bool with_or = slice < 0 || slice == (int32_t)d.slices.size() - 1;
+    int32_t *dp = nullptr;
+    int64_t bytes = 0;
+    lp_status rc = split_waves(b, with_or ? ((int64_t)d.n_or + 63) / 64 : 0, with_or ? d.n_segs : 0, waves, st,
+                               &dp, &bytes);
+    if (rc) return rc;
+    if (slice < 0) d.wave_parts.emplace_back(waves, dp);
+    else d.slice_parts.emplace_back(key, dp);
     d.lazy_bytes += bytes;
     *out = dp;
     return LP_OK;
@@ -642,9 +771,11 @@ static lp_status wave_partition(const Matrix &m, int32_t waves, hipStream_t st, 
 
 // Launch shape of the step for a whole solve. LDS shapes use one 1024-thread
 // workgroup per CU (the staged v takes most of the CU's LDS); global shapes
-// use 256-thread workgroups, eight per CU.
+// use 256-thread workgroups, eight per CU. A matrix with a column-sliced
+// layout takes the sliced LDS step (one pass per slice) unless slices is
+// false (then the mixed form).
 static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams &p, StepShape *S, hipStream_t st,
-                           bool may_alloc) {
+                           bool may_alloc, bool slices) {
     int variant = sched ? sched->variant : LP_STEP_AUTO;
     if (variant == LP_STEP_AUTO) variant = LP_STEP_LDS;
     if (variant != LP_STEP_LDS && variant != LP_STEP_GLOBAL) {
@@ -670,6 +801,11 @@ static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams
         }
         p.lds_words = (int32_t)std::min<int64_t>({(int64_t)step_lds_v_words(s.unroll), n_words_of(m.n_atoms), n_words});
         s.mode = (int64_t)m.dev.and_max_col < (int64_t)p.lds_words * 64 ? kStepLds : kStepMixed;
+        if (slices && !m.dev.slices.empty()) {
+            s.mode = kStepSlice;
+            s.n_slices = (int)m.dev.slices.size();
+            s.slice = m.dev.slices.data();
+        }
         s.block = 1024;
     } else {
         p.lds_words = 0;
@@ -683,6 +819,8 @@ static lp_status plan_step(const Matrix &m, const lp_schedule *sched, StepParams
     const int64_t dflt = staged ? d.n_cu : (int64_t)d.n_cu * 8;
     const int64_t grid = sched && sched->grid > 0 ? sched->grid : dflt;
     s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, want));
+    for (int k = 0; k < s.n_slices; ++k)
+        if ((rc = wave_partition(m, s.grid * waves, st, &s.slice_part[k], may_alloc, k))) return rc;
     *S = s;
     return wave_partition(m, s.grid * waves, st, &p.wave_part, may_alloc);
 }
@@ -694,7 +832,7 @@ static lp_status plan_persistent(const Matrix &m, const lp_schedule *sched, Step
                                  hipStream_t st) {
     lp_schedule s2 = sched ? *sched : lp_schedule{};
     s2.variant = LP_STEP_LDS;
-    lp_status rc = plan_step(m, &s2, p, S, st);
+    lp_status rc = plan_step(m, &s2, p, S, st, true, false);  // the persistent kernel has no sliced form
     if (rc) return rc;
     int per_cu = 0;
     LP_HIP(persistent_occupancy(*S, &per_cu));
@@ -991,9 +1129,11 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
     uint64_t *buf[2];
     unsigned long long *counters;
     uint32_t *and_cnt;
+    uint64_t *pacc = nullptr;  // a sliced step's partial AND words (written before they are read)
     lp_status rc;
     if ((rc = S.get(&buf[0], W)) || (rc = S.get(&buf[1], W)) || (rc = S.get(&counters, kRing)) ||
-        (rc = S.get(&and_cnt, 2 * (size_t)m.dev.n_long_and)))
+        (rc = S.get(&and_cnt, 2 * (size_t)m.dev.n_long_and)) ||
+        (!m.dev.slices.empty() && (rc = S.get(&pacc, W))))
         return rc;
     if (S.may_alloc()) {
         LP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kRing, st));
@@ -1013,6 +1153,7 @@ static lp_status least_fixpoint(const Matrix &m, const lp_schedule *sched, hipSt
     StepParams p = step_params(m);
     p.counters = counters;
     p.and_cnt = and_cnt;
+    p.pacc = pacc;
     StepShape L;
     if (driver == LP_DRIVER_PERSISTENT) {
         if ((rc = plan_persistent(m, sched, p, &L, st))) return rc;
@@ -1300,7 +1441,8 @@ static size_t noalloc_need(const Matrix &m) {
         return region_bytes(kLdsLoopHead + (size_t)std::max<int64_t>(1, n_words_of(m.n_atoms)) * 8);
     const size_t W = (size_t)n_words_of(m.n_rows);
     return 2 * region_bytes(W * 8) + region_bytes(sizeof(unsigned long long) * kRing) +
-           region_bytes(sizeof(uint32_t) * 2 * (size_t)m.dev.n_long_and);
+           region_bytes(sizeof(uint32_t) * 2 * (size_t)m.dev.n_long_and) +
+           (m.dev.slices.empty() ? 0 : region_bytes(W * 8));
 }
 
 static int ilog2(int64_t x) {
@@ -1940,7 +2082,7 @@ struct Events {
 // Buffers for timing steps on a fixed v: the fixpoint (so every launch does
 // the same work) and a destination pre-loaded with it.
 struct StepBench {
-    uint64_t *fix = nullptr, *dst = nullptr;
+    uint64_t *fix = nullptr, *dst = nullptr, *pacc = nullptr;
     unsigned long long *counters = nullptr;
     uint32_t *and_cnt = nullptr;
     int32_t products = 0;
@@ -1957,7 +2099,8 @@ static lp_status step_bench_init(const Matrix &m, const lp_schedule *sched, hipS
     if (rc) return rc;
     const int64_t W = n_words_of(m.n_rows);
     if ((rc = S.get(&B->dst, W)) || (rc = S.get(&B->counters, kRing)) ||
-        (rc = S.get(&B->and_cnt, 2 * (size_t)m.dev.n_long_and)))
+        (rc = S.get(&B->and_cnt, 2 * (size_t)m.dev.n_long_and)) ||
+        (!m.dev.slices.empty() && (rc = S.get(&B->pacc, W))))
         return rc;
     LP_HIP(hipMemcpyAsync(B->dst, B->fix, W * 8, hipMemcpyDeviceToDevice, st));
     LP_HIP(hipMemsetAsync(B->counters, 0, sizeof(unsigned long long) * kRing, st));
@@ -1970,6 +2113,7 @@ static lp_status time_steps(const Matrix &m, const StepBench &B, const StepShape
                             hipStream_t st, float *avg_ms) {
     p.counters = B.counters;
     p.and_cnt = B.and_cnt;
+    p.pacc = B.pacc;
     p.early_exit = 0;
     p.v = B.fix;
     p.u = B.dst;
@@ -3104,6 +3248,7 @@ lp_status lp_matrix_info(const lp_matrix *m, lp_info *out) {
     if (!(m->m.flags & LP_BUILD_HOST_ONLY)) {
         std::lock_guard<std::mutex> lock(g_lazy_mu);
         out->device_bytes += m->m.dev.lazy_bytes;
+        out->n_slices = (int32_t)m->m.dev.slices.size();
     }
     return LP_OK;
 }

@@ -55,9 +55,10 @@ struct SbMeta {
     uint32_t lens[WPW / 4];
     int32_t b0;
     uint64_t vw;  // lane w < WPW: word w of the super-block in v (for the new-bit count)
+    uint64_t pw;  // sliced passes, lane w < WPW: word w of and_all (pass 0) or of pacc (later passes)
 };
 
-template <int WPW>
+template <int WPW, bool SLICE = false>
 __device__ __forceinline__ void load_sb_meta(const StepParams &p, int32_t sbw, int32_t w_begin, int32_t n_words,
                                              SbMeta<WPW> &m) {
     // lens4 and words carry kWordPad empty words after the end, so every
@@ -69,6 +70,7 @@ __device__ __forceinline__ void load_sb_meta(const StepParams &p, int32_t sbw, i
     m.b0 = p.words[sbw > w_begin ? sbw : w_begin].and_base;
     const int32_t wv = sbw + (lane < WPW ? lane : WPW - 1);
     m.vw = p.v[wv < n_words ? wv : n_words - 1];
+    if (SLICE) m.pw = (p.pass == 0 ? p.and_all : (const uint64_t *)p.pacc)[wv < n_words ? wv : n_words - 1];
 }
 
 template <int WPW>
@@ -98,6 +100,7 @@ struct SbState {
     uint32_t lens[WPW / 4];
     uint32_t accm;
     uint64_t vw;
+    uint64_t pw;
 };
 
 // Row starts from the 8-bit lengths of the words in [w_begin, w_end) (the
@@ -111,6 +114,7 @@ __device__ __forceinline__ void sb_setup(const SbMeta<WPW> &m, int32_t sbw, int3
     int32_t run = __builtin_amdgcn_readfirstlane(m.b0);
     S.accm = 0;
     S.vw = m.vw;
+    S.pw = m.pw;
 #pragma unroll
     for (int k = 0; k < WPW / 4; ++k) {
         // bytes of the words in [w_begin, w_end) (wave-uniform)
@@ -147,7 +151,7 @@ __device__ __forceinline__ void round_ballots(const lds_u8 *s_v8, const uint8_t 
                                               const int32_t (&c)[U], lds_u64 *s_ball) {
     const int lane = threadIdx.x & 63;
     uint32_t x[U];
-    if (MODE == kStepLds) {
+    if (MODE == kStepLds || MODE == kStepSlice) {
 #pragma unroll
         for (int u = 0; u < U; ++u) x[u] = entry_word(s_v8, c[u]);
     } else if (MODE == kStepGlobal) {
@@ -216,6 +220,42 @@ __device__ __forceinline__ uint32_t sb_finish(const StepParams &p, int32_t sbw, 
     return lane == 0 ? n_new : 0;
 }
 
+// Results of a finished super-block in a pass over one column slice. A row
+// passes the slice if its entries there are all true or it has none there;
+// per word of the wave's range, pass 0 stores the passing block AND rows in
+// pacc, later passes AND theirs in, and the last pass ORs the rows that
+// passed every slice into u and counts the new ones. The words of and_all
+// (pass 0) or pacc came with the row data.
+template <int WPW>
+__device__ __forceinline__ uint32_t sb_finish_slice(const StepParams &p, int32_t sbw, int32_t w_begin, int32_t w_end,
+                                                    const SbState<WPW> &S) {
+    const int lane = threadIdx.x & 63;
+    uint32_t n_new = 0;
+    const uint32_t vlo = (uint32_t)S.vw, vhi = (uint32_t)(S.vw >> 32);
+    const uint32_t plo = (uint32_t)S.pw, phi = (uint32_t)(S.pw >> 32);
+    const bool last = p.pass == p.n_pass - 1;
+#pragma unroll
+    for (int w = 0; w < WPW; ++w) {
+        const int32_t wd = sbw + w;
+        if (wd < w_begin || wd >= w_end) continue;  // another wave's word (wave-uniform)
+        const uint64_t res = __ballot((S.accm >> w) & 1u);
+        const uint64_t has = __ballot(lane_len<WPW>(S.lens, w) != 0);
+        const uint64_t pass_ok = res | ~has;
+        const uint64_t prev = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(phi, w) << 32) |
+                              (uint64_t)(uint32_t)__builtin_amdgcn_readlane(plo, w);
+        const uint64_t acc = prev & pass_ok;  // pass 0: prev is and_all
+        if (!last) {
+            if (lane == 0) p.pacc[wd] = acc;
+        } else if (acc) {
+            const uint64_t v = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(vhi, w) << 32) |
+                               (uint64_t)(uint32_t)__builtin_amdgcn_readlane(vlo, w);
+            n_new += (uint32_t)__popcll(acc & ~v);
+            if (lane == 0) atomicOr((unsigned long long *)&p.u[wd], (unsigned long long)acc);
+        }
+    }
+    return lane == 0 ? n_new : 0;
+}
+
 // Block pass: AND rows of up to kLongAnd entries, as one stream per wave.
 //
 // Wave k owns the words [wave_part[2k], wave_part[2k + 2]) (a host-computed
@@ -277,8 +317,8 @@ struct BlockPass {
         sb_last = has ? sbw + ((w_end - 1 - sbw) / WPW) * WPW : sbw;
         base = e_begin & ~63;
         last_base = max(0, ((e_end + 63) & ~63) - 64 * U);
-        load_sb_meta<WPW>(p, sbw, w_begin, n_words, cur);
-        load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
+        load_sb_meta<WPW, MODE == kStepSlice>(p, sbw, w_begin, n_words, cur);
+        load_sb_meta<WPW, MODE == kStepSlice>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
         load_chunks<U>(p, base, ca);
         return has;
     }
@@ -330,11 +370,15 @@ struct BlockPass {
             round_ballots<MODE, U>(s_v8, v8, lds_bytes, c, s_ball);
             fold_round<WPW, U>(s_ball, base, S);
             while (__builtin_amdgcn_readfirstlane(S.ws[WPW]) <= lim) {
-                my_new += sb_finish<WPW>(p, sbw, n_words, S);
+                if (MODE == kStepSlice)
+                    my_new += sb_finish_slice<WPW>(p, sbw, w_begin, w_end, S);
+                else
+                    my_new += sb_finish<WPW>(p, sbw, n_words, S);
                 if (sbw >= sb_last) return false;
                 sbw += WPW;
                 sb_setup<WPW>(nxt, sbw, w_begin, w_end, S);
-                load_sb_meta<WPW>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, n_words, nxt);
+                load_sb_meta<WPW, MODE == kStepSlice>(p, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin,
+                                                      n_words, nxt);
                 fold_round<WPW, U>(s_ball, base, S);
             }
             base = nb;
@@ -514,7 +558,8 @@ __device__ __forceinline__ uint32_t long_rows(const StepParams &p, const lds_u32
     return my_new;
 }
 
-// Copies the leading lds_words words of v into LDS: 16-byte loads, up to
+// Copies lds_words words of v from word stage_off (an even word: the copies
+// are 16-byte loads) into LDS: 16-byte loads, up to
 // eight in flight per thread before any is stored (one memory round trip for
 // 128 KB with 1,024 threads).
 __device__ __forceinline__ void stage_v(const StepParams &p, lds_u32 *s_v) {
@@ -522,7 +567,7 @@ __device__ __forceinline__ void stage_v(const StepParams &p, lds_u32 *s_v) {
     typedef __attribute__((address_space(3))) u32x4 lds_u4;
     constexpr int kInFlight = 8;
     lds_u4 *d = (lds_u4 *)s_v;
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v);
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v + p.stage_off);
     const int32_t n16 = p.lds_words >> 1;
     const int32_t bd = blockDim.x;
     for (int32_t i = threadIdx.x; i < n16; i += kInFlight * bd) {
@@ -534,7 +579,7 @@ __device__ __forceinline__ void stage_v(const StepParams &p, lds_u32 *s_v) {
         for (int k = 0; k < kInFlight; ++k)
             if (i + k * bd < n16) d[i + k * bd] = x[k];
     }
-    if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.lds_words - 1];
+    if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.stage_off + p.lds_words - 1];
 }
 
 // stage_v split in two: the first loads (up to eight 16-byte loads per
@@ -551,7 +596,7 @@ struct StageV {
     __device__ __forceinline__ void issue(const StepParams &p) {
         const int32_t n16 = p.lds_words >> 1;
         if (n16 == 0) return;  // the same in every thread of the launch
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v);
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v + p.stage_off);
         const int32_t bd = blockDim.x;
 #pragma unroll
         for (int k = 0; k < kInFlight; ++k) {
@@ -562,7 +607,7 @@ struct StageV {
 
     __device__ __forceinline__ void commit(const StepParams &p, lds_u32 *s_v) {
         lds_u4 *d = (lds_u4 *)s_v;
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v);
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(p.v + p.stage_off);
         const int32_t n16 = p.lds_words >> 1;
         const int32_t bd = blockDim.x;
 #pragma unroll
@@ -579,7 +624,7 @@ struct StageV {
             for (int k = 0; k < kInFlight; ++k)
                 if (i + k * bd < n16) d[i + k * bd] = y[k];
         }
-        if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.lds_words - 1];
+        if ((p.lds_words & 1) && threadIdx.x == 0) ((lds_u64 *)s_v)[p.lds_words - 1] = p.v[p.stage_off + p.lds_words - 1];
     }
 };
 
@@ -624,22 +669,30 @@ __global__ __launch_bounds__(1024) void tp_step_kernel(StepParams p) {
     // So the stream is in flight while v is staged and while the OR rows and
     // segments are evaluated, and no round trip of the prologue waits alone.
     const unsigned long long prev = p.counters[(p.step - 1) & (kRing - 1)];
+    // OR rows and long rows read v from LDS in the staged forms; a sliced step
+    // evaluates them in its last pass only, from v in global memory
+    constexpr bool kOrLds = MODE == kStepLds || MODE == kStepMixed;
+    StepParams q = p;
+    if (MODE == kStepSlice && p.pass != p.n_pass - 1) {
+        q.n_or = 0;
+        q.n_segs = 0;
+    }
     StageV sv;
     if (MODE != kStepGlobal) sv.issue(p);
     if (threadIdx.x == 0) *L.n_new = 0;
     BlockPass<MODE, WPW, U> bp;
     const bool blocks = bp.prefetch(p);
-    OrTiles<MODE != kStepGlobal> ot;
-    ot.load_ranges(p, grid_wave(), (int64_t)gridDim.x * (blockDim.x >> 6));
+    OrTiles<kOrLds> ot;
+    ot.load_ranges(q, grid_wave(), (int64_t)gridDim.x * (blockDim.x >> 6));
     if (MODE != kStepGlobal) sv.commit(p, L.v);
     if (p.early_exit && p.step >= 2 && prev == 0) return;
-    ot.load_words(p);
+    ot.load_words(q);
     if (blocks) bp.start();
     __syncthreads();
     // long-row segments first: they are the longest items, so they start early
-    uint32_t my_new = long_rows<MODE != kStepGlobal, U>(p, L.v);
-    my_new += ot.finish(p, L.v);
-    my_new += or_rows_rest<MODE != kStepGlobal>(p, L.v);
+    uint32_t my_new = long_rows<kOrLds, U>(q, L.v);
+    my_new += ot.finish(q, L.v);
+    my_new += or_rows_rest<kOrLds>(q, L.v);
     if (blocks) my_new += bp.run(p, L.v, L.my_ball);
     add_new_bits(my_new, L.n_new, &p.counters[p.step & (kRing - 1)]);
 }
@@ -734,10 +787,39 @@ bool step_shape_supported(const StepShape &s) {
     return false;
 }
 
+// One product: one launch, or one launch per column slice of a sliced layout
+// (pass k with slice k's layout and staged words).
 hipError_t launch_step(const StepShape &s, const StepParams &p, hipStream_t st) {
+    if (s.mode == kStepSlice) {
+        if (s.n_slices < 2 || s.n_slices > kMaxSlices || !s.slice) return hipErrorInvalidValue;
+        for (int k = 0; k < s.n_slices; ++k) {
+            const SliceLayout &L = s.slice[k];
+            StepParams q = p;
+            q.words = L.words;
+            q.and_len = L.and_len;
+            q.lens4 = L.lens4;
+            q.col = L.col;
+            q.and_end = L.and_end;
+            q.and_max_col = L.and_max_col;
+            q.wave_part = s.slice_part[k];
+            q.stage_off = L.first_word;
+            q.lds_words = L.lds_words;
+            q.pass = k;
+            q.n_pass = s.n_slices;
+            hipError_t e = launch_step_pass(s, q, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    return launch_step_pass(s, p, st);
+}
+
+hipError_t launch_step_pass(const StepShape &s, const StepParams &p, hipStream_t st) {
 #define LP_X(W, U)                                                                                       \
     if (s.wpw == W && s.unroll == U) {                                                                   \
-        if (s.mode == kStepLds)                                                                          \
+        if (s.mode == kStepSlice)                                                                        \
+            hipLaunchKernelGGL((tp_step_kernel<kStepSlice, W, U>), dim3(s.grid), dim3(s.block), 0, st, p); \
+        else if (s.mode == kStepLds)                                                                     \
             hipLaunchKernelGGL((tp_step_kernel<kStepLds, W, U>), dim3(s.grid), dim3(s.block), 0, st, p);   \
         else if (s.mode == kStepMixed)                                                                   \
             hipLaunchKernelGGL((tp_step_kernel<kStepMixed, W, U>), dim3(s.grid), dim3(s.block), 0, st, p); \

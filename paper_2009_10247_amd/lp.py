@@ -41,6 +41,7 @@ LP_PRUNE_FACT_GUESSES = 1 << 0
 LP_BUILD_HOST_ONLY = 1 << 1
 LP_STABLE_FULL_SWEEP = 1 << 2
 LP_STABLE_DIRTY_ROWS = 1 << 3
+LP_STEP_SLICES_SMALL = 1 << 4
 
 LP_DRIVER_AUTO = 0
 LP_DRIVER_PLAIN = 1
@@ -79,7 +80,7 @@ class lp_info(ctypes.Structure):
                 ("n_fact_rows", ctypes.c_int32), ("n_empty_rows", ctypes.c_int32),
                 ("max_row_len", ctypes.c_int32), ("n_long_rows", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("step_bytes", ctypes.c_int64),
-                ("sparsity", ctypes.c_double)]
+                ("sparsity", ctypes.c_double), ("n_slices", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
 
 
 class lp_schedule(ctypes.Structure):

@@ -70,10 +70,13 @@ def recorded_traffic(kernel: str, step_bytes_now: int, source: str = "lp_step.hi
 def step_mode(info: dict, sched) -> int:
     """Form of the step kernel the library launches: 0 gathers from global
     memory, 1 all of v staged in LDS (the original atoms fit in the 160 KB of a
-    workgroup beside the ballot slots), 2 mixed."""
+    workgroup beside the ballot slots), 3 column-sliced (one pass per slice of
+    the original atoms, past what one workgroup's LDS holds)."""
     from paper_2009_10247_amd import lp
     if sched.variant == lp.LP_STEP_GLOBAL:
         return 0
+    if info.get("n_slices", 0) > 0:
+        return 3
     cap_words = 163840 // 8 - 16 * (sched.unroll + 1) - 2
     return 1 if (info["n_atoms"] + 63) // 64 <= cap_words else 2
 

@@ -85,7 +85,8 @@ enum {
     /* Least models: lay the AND entries out in column slices of 1,024 atoms
      * (one pass per slice and product; by default slices are used only when
      * the original atoms exceed what a workgroup's LDS holds, about 1.29
-     * million). For tests of the sliced step on small programs. */
+     * million). For tests of the sliced step on small programs: at most 64
+     * slices, so programs of at most 65,536 atoms (LP_E_INVAL otherwise). */
     LP_STEP_SLICES_SMALL = 1u << 4
 };
 

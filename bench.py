@@ -176,6 +176,22 @@ def bench_batch(args, torch, gen, lp, stream) -> dict:
                 assert pr == pr2 and (g == g2).all(), "batch result differs from the single-program solve"
         for (g, pr), (g2, pr2) in zip(res, res2):
             assert pr == pr2 and (g == g2).all()
+        # the same 512 programs by frontier levels (semi-naive: each entry visited once per solve
+        # rather than once per product), one launch of a frontier plan
+        fplan = lp.Batch(mats, sched=lp.make_schedule(driver=lp.LP_DRIVER_FRONTIER), stream=stream)
+        fplan.run(stream=stream)
+        fres = fplan.results(stream=stream)
+        for (g, pr), (g2, pr2) in zip(res, fres):
+            assert pr == pr2 and (g == g2).all(), "frontier plan differs from the matrix-product plan"
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(reps):
+            fplan.run(stream=stream)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        frontier_ms = f0.elapsed_time(f1) / reps
+        fplan.close()
         prods = [pr for _, pr in res]
         entries = sum(mm.info["nnz"] * pr for mm, pr in zip(mats, prods))
         layout = sum((mm.info["step_bytes"] - 2 * ((mm.info["n_rows"] + 7) // 8)) * pr
@@ -198,6 +214,7 @@ def bench_batch(args, torch, gen, lp, stream) -> dict:
                "ms_per_batch": round(dev_ms, 3), "ms_per_batch_with_results": round(e2e_ms, 3),
                "entries_per_s": round(entries / (dev_ms / 1e3), 1),
                "layout_GB/s": round(layout / (dev_ms / 1e3) / 1e9, 1), "roofline": roofline,
+               "frontier_ms_per_batch": round(frontier_ms, 3),
                "sequential_plain_ms": round(seq["plain"], 3), "sequential_default_ms": round(seq["default"], 3),
                "speedup_vs_sequential_plain": round(seq["plain"] / e2e_ms, 2),
                "speedup_vs_sequential_default": round(seq["default"] / e2e_ms, 2),

@@ -334,7 +334,8 @@ lp_status lp_stable_models_search(const lp_matrix *m, int64_t n_samples, int32_t
  * Least models of count definite programs (Algorithm 1 for each) in one
  * persistent launch: lp_batch_create, lp_batch_run, lp_batch_results and
  * lp_batch_free in one call. models[i]: uint8[n_atoms of ms[i]] host,
- * non-NULL; products: nullable int32[count]. Results equal count separate
+ * non-NULL; products: nullable int32[count]. sched as lp_batch_create's
+ * (LP_DRIVER_FRONTIER: a frontier plan). Results equal count separate
  * lp_least_model calls. Errors as lp_least_model, for the first failing
  * program; LP_E_INVAL if the matrices live on different devices.
  */
@@ -384,6 +385,12 @@ typedef struct lp_batch_info {
  * team's members fit in one grid, and a team whose bounded barrier gives up
  * (its members could not run together) has its program solved alone by
  * lp_batch_results. Results and product counts do not depend on teams.
+ * sched->driver == LP_DRIVER_FRONTIER makes a frontier plan instead: every
+ * program (no size limit) is solved by frontier levels (the rows that became
+ * true pushed through the transposed matrix, as lp_least_model's frontier
+ * driver) in one launch, one workgroup per program at a time; the levels are
+ * the products, so the results and product counts are those of the other
+ * plans. Such a plan has no shape to tune (lp_batch_tune times it).
  * Uploads the descriptors on hip_stream and synchronizes it.
  * Errors: LP_E_NEGATION, LP_E_HOST_ONLY, LP_E_INVAL (NULL matrix, mixed
  * devices, unsupported shape, a grid smaller than a team), LP_E_NOMEM,

@@ -181,6 +181,77 @@ __global__ __launch_bounds__(kFrontierLoopBlock) void frontier_levels_kernel(Fro
     }
 }
 
+// Least models of many programs: a workgroup takes the next program from
+// the queue, sets its counts to the start counts and its interpretation to
+// the fact rows, and pushes frontiers level after level (push_frontier over
+// its 16 waves, the frontiers in two global buffers of its own, their sizes in
+// LDS), with a workgroup barrier between levels, until a level is empty. The
+// level count is the product count of the full sweep. The last workgroup to
+// leave rewinds the queue, so graph replays need no memset.
+__global__ __launch_bounds__(kFBatchBlock) void frontier_batch_kernel(FBatchParams b) {
+    constexpr int NW = kFBatchBlock / 64;
+    __shared__ int32_t s_excl[NW][64];
+    __shared__ int32_t s_start[NW][64];
+    __shared__ uint32_t s_n[4];  // frontier sizes by level & 3
+    __shared__ int32_t s_item;
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int32_t *q[2] = {b.qbuf + (int64_t)blockIdx.x * 2 * b.qcap, b.qbuf + (int64_t)blockIdx.x * 2 * b.qcap + b.qcap};
+    typedef const __attribute__((address_space(4))) int32_t c_i32;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&b.queue[0], 1u);
+        __syncthreads();
+        const int32_t item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= b.n_items) break;
+        const int32_t pi = ((c_i32 *)(const void *)b.order)[item];
+        FBatchProg P;
+        {
+            const __attribute__((address_space(4))) uint32_t *s =
+                (const __attribute__((address_space(4))) uint32_t *)(const void *)(b.progs + pi);
+            uint32_t *o = reinterpret_cast<uint32_t *>(&P);
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(FBatchProg) / 4); ++i) o[i] = s[i];
+        }
+        for (int32_t i = threadIdx.x; i < P.n_rows; i += kFBatchBlock) P.cnt[i] = P.cnt0[i];
+        for (int32_t w = threadIdx.x; w < P.n_words; w += kFBatchBlock) P.v[w] = 0ull;
+        if (threadIdx.x == 0) {
+            s_n[0] = (uint32_t)P.n_facts;
+            s_n[1] = 0;
+        }
+        __syncthreads();  // v cleared before the fact bits go in
+        for (int32_t j = threadIdx.x; j < P.n_facts; j += kFBatchBlock) {
+            const int32_t r = P.facts[j];
+            q[0][j] = r;
+            atomicOr((unsigned long long *)&P.v[r >> 6], 1ull << (r & 63));
+        }
+        __syncthreads();
+        FrontierParams f{};
+        f.occ_ptr = P.occ_ptr;
+        f.occ = P.occ;
+        f.cnt = P.cnt;
+        f.v = P.v;
+        int32_t t = 1;  // level t pushes F_{t-1} into F_t
+        for (;; ++t) {
+            const uint32_t n_in = s_n[(t - 1) & 3];
+            if (threadIdx.x == 0) s_n[(t + 1) & 3] = 0;  // read at level t - 2, appended to at level t + 1
+            if (n_in > 0)
+                push_frontier<false>(f, q[(t - 1) & 1], n_in, q[t & 1], &s_n[t & 3], wid, NW, s_excl[wid],
+                                     s_start[wid], lane);
+            __syncthreads();
+            if (s_n[t & 3] == 0 || t > P.n_rows) break;
+        }
+        if (threadIdx.x == 0) *P.out_products = s_n[t & 3] == 0 ? t : -1;
+        __syncthreads();  // s_n, s_item and the queues are reused by the next program
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&b.queue[1], 1u) == gridDim.x - 1) {
+            atomicExch(&b.queue[0], 0u);
+            atomicExch(&b.queue[1], 0u);
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_frontier_level(const FrontierParams &f, int grid, hipStream_t st) {
@@ -192,6 +263,11 @@ hipError_t launch_frontier_levels(const FrontierParams &f, const int32_t *facts,
                                   int32_t n_levels, int32_t *ctl, hipStream_t st) {
     hipLaunchKernelGGL(frontier_levels_kernel, dim3(1), dim3(kFrontierLoopBlock), 0, st, f, facts, q0, q1, n_levels,
                        ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_frontier_batch(const FBatchParams &b, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(frontier_batch_kernel, dim3((unsigned)grid), dim3(kFBatchBlock), 0, st, b);
     return hipGetLastError();
 }
 

@@ -265,6 +265,30 @@ constexpr int kFrontierLoopCap = 4096;
 hipError_t launch_frontier_levels(const FrontierParams &f, const int32_t *facts, int32_t *q0, int32_t *q1,
                                   int32_t n_levels, int32_t *ctl, hipStream_t st);
 
+// Many least models by frontier levels in one launch (lp_frontier.hip): each
+// workgroup takes programs from a device queue and runs all of a program's
+// levels itself, with a workgroup barrier between levels.
+struct FBatchProg {
+    const int32_t *occ_ptr;   // transposed matrix (rows naming each row)
+    const int32_t *occ;
+    const int32_t *cnt0;      // [n_rows] entries still false at the start
+    const int32_t *facts;     // [n_facts] F_0
+    int32_t *cnt;             // [n_rows] working counts
+    uint64_t *v;              // [n_words] the fixpoint (fact bits and every row that fires)
+    int32_t *out_products;    // products; -1 past n_rows + 1
+    int32_t n_rows, n_facts, n_words, pad;
+};
+struct FBatchParams {
+    const FBatchProg *progs;
+    const int32_t *order;     // queue position -> program
+    unsigned int *queue;      // [0] next position, [1] finished workgroups; zero between launches
+    int32_t *qbuf;            // two frontier buffers of qcap rows per workgroup
+    int64_t qcap;
+    int32_t n_items;
+};
+constexpr int kFBatchBlock = 1024;
+hipError_t launch_frontier_batch(const FBatchParams &b, int grid, hipStream_t st);
+
 hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std,
                           const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff,
                           unsigned long long *count, unsigned long long bits, hipStream_t st);

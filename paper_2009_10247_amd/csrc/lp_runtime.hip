@@ -2359,6 +2359,13 @@ struct BatchPlan {
     float tuned_ms = 0.f;
     bool use_graph = true;           // runs replay a captured graph (else a direct launch)
     bool weighted = false;           // order and teams weighted by the product counts of a run
+    // frontier plans (sched->driver == LP_DRIVER_FRONTIER): every program by
+    // frontier levels (frontier_batch_kernel); d_out holds whole interpretations
+    bool frontier = false;
+    FBatchProg *d_fprogs = nullptr;
+    int32_t *d_cnt = nullptr;
+    int32_t *d_fq = nullptr;
+    int64_t fq_cap = 0;
 };
 
 static void batch_release(BatchPlan &b) {
@@ -2366,8 +2373,12 @@ static void batch_release(BatchPlan &b) {
     if (b.graph) (void)hipGraphDestroy(b.graph);
     b.exec = nullptr;
     b.graph = nullptr;
-    void *ps[] = {b.d_progs, b.d_order, b.d_queue, b.d_out, b.d_prod, b.d_xch, b.d_teams, b.d_member};
+    void *ps[] = {b.d_progs, b.d_order, b.d_queue, b.d_out, b.d_prod, b.d_xch, b.d_teams, b.d_member,
+                  b.d_fprogs, b.d_cnt, b.d_fq};
     for (void *p : ps) dev_free(p, nullptr);
+    b.d_fprogs = nullptr;
+    b.d_cnt = nullptr;
+    b.d_fq = nullptr;
     b.d_xch = nullptr;
     b.d_teams = nullptr;
     b.d_member = nullptr;
@@ -2440,6 +2451,8 @@ static lp_status batch_fit_shape(const BatchPlan &b, BatchShape *s) {
 
 // Captures the batch kernel into b.exec (on a stream of its own: the legacy
 // default stream cannot be captured).
+static FBatchParams fbatch_params(const BatchPlan &b);
+
 static lp_status batch_capture(BatchPlan &b) {
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
@@ -2451,7 +2464,8 @@ static lp_status batch_capture(BatchPlan &b) {
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         const BatchShape &s = b.shape;
-        hipError_t el = launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b, s), cs);
+        hipError_t el = b.frontier ? launch_frontier_batch(fbatch_params(b), s.grid, cs)
+                                   : launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b, s), cs);
         e = hipStreamEndCapture(cs, &b.graph);
         if (e == hipSuccess) e = el;
     }
@@ -2463,6 +2477,7 @@ static lp_status batch_capture(BatchPlan &b) {
 
 static lp_status batch_layout(BatchPlan &b, const lp_schedule *sched, hipStream_t st,
                               const std::vector<int32_t> *weights);
+static lp_status frontier_batch_layout(BatchPlan &b, const lp_schedule *sched, hipStream_t st);
 
 static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const lp_schedule *sched, hipStream_t st,
                               bool use_graph, BatchPlan &b) {
@@ -2492,7 +2507,82 @@ static lp_status batch_create(const lp_matrix *const *ms, int32_t count, const l
     if (count == 0) {
         LP_HIP(hipGetDevice(&b.device));
     }
+    if (sched && sched->driver == LP_DRIVER_FRONTIER) return frontier_batch_layout(b, sched, st);
     return batch_layout(b, sched, st, nullptr);
+}
+
+// A frontier plan: every program's transposed matrix (built on first use and
+// kept with the matrix), working counts and interpretation; the queue, largest
+// program first; one 1,024-thread workgroup per CU, each with two frontier
+// buffers as long as the largest program's rows.
+static lp_status frontier_batch_layout(BatchPlan &b, const lp_schedule *sched, hipStream_t st) {
+    const int32_t count = (int32_t)b.ms.size();
+    b.frontier = true;
+    if (sched) b.sched = *sched;
+    b.order.clear();
+    b.large.clear();
+    b.team.assign(count, 1);
+    DevProps d;
+    lp_status rc = dev_props(b.device, &d);
+    if (rc) return rc;
+    std::vector<int32_t> idx(count);
+    for (int32_t i = 0; i < count; ++i) {
+        idx[i] = i;
+        if ((rc = ensure_frontier(*b.ms[i], st))) return rc;
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return b.ms[x]->nnz > b.ms[y]->nnz; });
+    b.order = idx;
+    b.out_off.assign(count, -1);
+    std::vector<int64_t> cnt_off(count);
+    int64_t words = 0, cnts = 0;
+    int32_t max_rows = 1;
+    for (int32_t i : idx) {
+        b.out_off[i] = words;
+        words += std::max<int64_t>(1, n_words_of(b.ms[i]->n_rows));
+        cnt_off[i] = cnts;
+        cnts += std::max(1, b.ms[i]->n_rows);
+        max_rows = std::max(max_rows, b.ms[i]->n_rows);
+    }
+    b.out_words = words;
+    b.lds_words = 0;
+    BatchShape s;
+    s.block = kFBatchBlock;
+    s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(d.n_cu, count));
+    s.wpw = 0;
+    s.unroll = 0;
+    s.lds_bytes = 0;
+    b.shape = s;
+    b.fq_cap = max_rows;
+    if ((rc = dev_alloc((void **)&b.d_out, (size_t)std::max<int64_t>(1, words) * 8, st)) ||
+        (rc = dev_alloc((void **)&b.d_prod, sizeof(int32_t) * std::max(1, count), st)) ||
+        (rc = dev_alloc((void **)&b.d_cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(1, cnts), st)) ||
+        (rc = dev_alloc((void **)&b.d_fq, sizeof(int32_t) * 2 * (size_t)s.grid * (size_t)b.fq_cap, st)))
+        return rc;
+    std::vector<FBatchProg> desc(std::max(1, count));
+    for (int32_t i : idx) {
+        const Matrix &m = *b.ms[i];
+        FBatchProg &g = desc[i];
+        g = FBatchProg{};
+        g.occ_ptr = m.dev.fr_ptr;
+        g.occ = m.dev.fr_occ;
+        g.cnt0 = m.dev.fr_cnt0;
+        g.facts = m.dev.fr_facts;
+        g.cnt = b.d_cnt + cnt_off[i];
+        g.v = b.d_out + b.out_off[i];
+        g.out_products = b.d_prod + i;
+        g.n_rows = m.n_rows;
+        g.n_facts = m.dev.fr_n_facts;
+        g.n_words = (int32_t)n_words_of(m.n_rows);
+    }
+    int64_t dummy = 0;
+    if ((rc = upload(&b.d_fprogs, desc.data(), desc.size(), st, &dummy))) return rc;
+    std::vector<int32_t> ord(idx);
+    if (ord.empty()) ord.push_back(0);
+    if ((rc = upload(&b.d_order, ord.data(), ord.size(), st, &dummy))) return rc;
+    if ((rc = dev_alloc((void **)&b.d_queue, sizeof(unsigned int) * 2, st))) return rc;
+    LP_HIP(hipMemsetAsync(b.d_queue, 0, sizeof(unsigned int) * 2, st));
+    LP_HIP(hipStreamSynchronize(st));
+    return b.use_graph ? batch_capture(b) : LP_OK;
 }
 
 // Queue order, teams, descriptors and buffers of the plan's programs (b.ms),
@@ -2671,10 +2761,23 @@ static lp_status batch_layout(BatchPlan &b, const lp_schedule *sched, hipStream_
     return b.use_graph ? batch_capture(b) : LP_OK;
 }
 
+static FBatchParams fbatch_params(const BatchPlan &b) {
+    FBatchParams q{};
+    q.progs = b.d_fprogs;
+    q.order = b.d_order;
+    q.queue = b.d_queue;
+    q.qbuf = b.d_fq;
+    q.qcap = b.fq_cap;
+    q.n_items = (int32_t)b.order.size();
+    return q;
+}
+
 static lp_status batch_run(const BatchPlan &b, hipStream_t st) {
     if (b.order.empty()) return LP_OK;
     if (b.exec) {
         LP_HIP(hipGraphLaunch(b.exec, st));
+    } else if (b.frontier) {
+        LP_HIP(launch_frontier_batch(fbatch_params(b), b.shape.grid, st));
     } else {
         const BatchShape &s = b.shape;
         LP_HIP(launch_batch(s.wpw, s.unroll, s.grid, s.block, s.lds_bytes, batch_params(b, s), st));
@@ -2734,6 +2837,21 @@ static lp_status batch_results(const BatchPlan &b, uint8_t *const *models, int32
 static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStream_t st) {
     if (b.order.empty()) {
         if (best_ms) *best_ms = 0.f;
+        return LP_OK;
+    }
+    if (b.frontier) {  // no shape to choose: the time of reps runs
+        Events ev;
+        lp_status rc = ev.init();
+        if (rc) return rc;
+        if ((rc = batch_run(b, st))) return rc;
+        LP_HIP(hipEventRecord(ev.a, st));
+        for (int r = 0; r < std::max(1, reps); ++r)
+            if ((rc = batch_run(b, st))) return rc;
+        LP_HIP(hipEventRecord(ev.b, st));
+        float ms = 0.f;
+        if ((rc = ev.elapsed(&ms))) return rc;
+        b.tuned_ms = ms / (float)std::max(1, reps);
+        if (best_ms) *best_ms = b.tuned_ms;
         return LP_OK;
     }
     lp_status rc;

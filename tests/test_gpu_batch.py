@@ -310,3 +310,42 @@ def test_batch_tune_lays_out_again_by_products(team):
     finally:
         for m in mats:
             m.close()
+
+
+def test_frontier_plan_512_programs_vs_oracle():
+    # the same workload by frontier levels: one workgroup per program at a
+    # time, the levels its products; results equal the oracle and the matrix-
+    # product plan's, on replays of the captured graph and in one call
+    progs = gen.batch_programs(0, 512)
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    fr = lp.make_schedule(driver=lp.LP_DRIVER_FRONTIER)
+    try:
+        with lp.Batch(mats, sched=fr) as b:
+            b.run()
+            _assert_equal(b.results(), want, "frontier plan")
+            ms = b.tune(reps=3)
+            assert ms > 0
+            for _ in range(3):
+                b.run()
+            _assert_equal(b.results(), want, "frontier replays")
+        _assert_equal(lp.least_model_batch(mats, sched=fr), want, "frontier one call")
+    finally:
+        for m in mats:
+            m.close()
+
+
+def test_frontier_plan_edge_programs():
+    # chains, hubs, facts only, no facts, empty programs, and a program larger
+    # than the matrix-product plan's LDS limit
+    progs = _edge_programs() + [gen.definite_uniform(4, 300_000, 600_000, 0.02, 4),
+                                gen.definite_uniform(7, 500, 900, 0.0, 3),
+                                gen.from_rules(3, [(0, []), (1, [0]), (2, [1])])]
+    want = _want(progs)
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        got = lp.least_model_batch(mats, sched=lp.make_schedule(driver=lp.LP_DRIVER_FRONTIER))
+        _assert_equal(got, want, "frontier edge programs")
+    finally:
+        for m in mats:
+            m.close()

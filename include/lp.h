@@ -147,8 +147,8 @@ typedef struct lp_schedule {
     int32_t steps_per_sync;  /* products issued between host checks (BATCHED, AUTO) */
     int32_t variant;         /* LP_STEP_* kernel of the least-model step */
     int32_t grid;            /* workgroups of the step (0: one per CU for LDS, eight per CU otherwise) */
-    int32_t wpw;             /* step: 64-row words per super-block, 4 or 8; batch kernel: words per
-                                wave, 1, 2 or 4 (0: default) */
+    int32_t wpw;             /* 64-row words per super-block: step 4 or 8, batch kernel 4 or 8
+                                (0: default) */
     int32_t unroll;          /* 64-entry column chunks in flight per wave: 4, 8 or 16 (0: default) */
     int32_t block;           /* batch kernel: threads per workgroup, 256, 512 or 1024 (0: 1024) */
     int32_t team;            /* batch plans: 0 teams chosen by size, 1 no teams, k >= 2 every
@@ -361,8 +361,8 @@ typedef struct lp_batch lp_batch;
 typedef struct lp_batch_info {
     int32_t count;          /* programs of the plan */
     int32_t n_resident;     /* programs solved by the batch kernel */
-    int32_t wpw;            /* batch kernel shape: words per wave */
-    int32_t unroll;         /* chunks in flight per wave */
+    int32_t wpw;            /* batch kernel shape: words per super-block */
+    int32_t unroll;         /* chunks of 64 entries per round of a wave's stream */
     int32_t block;          /* threads per workgroup */
     int32_t grid;           /* workgroups (0: no resident program) */
     int64_t lds_bytes;      /* dynamic LDS per workgroup: the two buffers of the largest program */
@@ -417,7 +417,7 @@ lp_status lp_batch_results(const lp_batch *b, uint8_t *const *models, int32_t *p
  * batch once and lays out the queue order and the teams again by each
  * program's product count times its work per product (the plan's first
  * layout knows only the work per product). Then it times every supported
- * shape (words per wave / chunks in flight 1/8, 2/8, 4/4, 1/16, 2/16; 256,
+ * shape (words per super-block / chunks per round 4/4, 4/8, 4/16, 8/8, 8/16; 256,
  * 512 and 1024 threads per workgroup) over reps runs of the whole batch with
  * HIP events, keeps the fastest and captures the graph again. best_ms
  * (nullable) receives its time per run. reps = 0: the layout step and one

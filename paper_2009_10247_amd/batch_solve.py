@@ -8,7 +8,7 @@ checked against single-program solves. With --copy-mb, one device-to-device
 copy of that many MiB follows (a known-size kernel that calibrates byte
 counters in a profile of the same run).
 
-    python -m paper_2009_10247_amd.batch_solve [--reps 20] [--count 512] [--seed 0] [--shape 2,8,1024]
+    python -m paper_2009_10247_amd.batch_solve [--reps 20] [--count 512] [--seed 0] [--shape 4,16,1024]
 
 --shape wpw,unroll,block fixes the kernel shape instead of autotuning it (the
 queue order and teams are still laid out by the product counts of a first

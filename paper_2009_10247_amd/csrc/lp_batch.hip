@@ -19,14 +19,16 @@
 // A program much larger than a workgroup's share of the batch is solved by a
 // team of G workgroups (its G queue positions come first, so all members
 // start at once). Member m evaluates the m-th of G contiguous ranges of
-// super-blocks and every G-th OR row and segment; after each product the
-// members OR the rows they found new (true now, not in v_{t-1}) into a
-// global delta buffer, meet at a bounded team barrier and take v_t as v_{t-1}
-// OR the delta. The products are those of the one-workgroup loop.
+// words (about equal AND-stream work), every G-th block of OR rows and every
+// G-th segment; after each product the members OR the rows they found new
+// (true now, not in v_{t-1}) into a global delta buffer, meet at a bounded
+// team barrier and take v_t as v_{t-1} OR the delta. The products are those
+// of the one-workgroup loop.
 //
-// Within a workgroup the waves take super-blocks one at a time from an LDS
-// counter, so a wave that runs ahead takes more of them (a static split left
-// the waves of a workgroup waiting for the slowest at every product).
+// Within a workgroup (or a team member) the words are split among the waves
+// by AND-stream work when the program starts, and each wave streams its stretch
+// of the layout with a round of chunks always in flight; issue priority by
+// the work left keeps the waves of a workgroup finishing together.
 #include <hip/hip_runtime.h>
 
 #include "lp_dev.h"
@@ -81,6 +83,7 @@ template <>
 struct Prog<1> {
     gp<WordMeta> words;
     gp<uint8_t> and_len;
+    gp<uint32_t> lens4;
     gp<int32_t> col;
     gp<int32_t> or_c0;
     gp<int32_t> or_row;
@@ -186,134 +189,288 @@ __device__ __forceinline__ uint32_t lds_set_bit(lds_u64 *u, const lds_u64 *v, in
     return (!(old & bit) && !(v[row >> 6] & bit)) ? 1u : 0u;
 }
 
-template <int WPW>
-struct WgSuperBlock {
-    int32_t len[WPW];
-    int32_t base[WPW];
-    uint64_t andb[WPW];
-};
+// Work of the AND stream before word w: its AND entries plus kWordWork per
+// word (the per-word part of a super-block's scan, folds and results).
+// Nondecreasing in w.
+constexpr int64_t kWordWork = 192;
 
-template <int WPW, class P>
-__device__ __forceinline__ void wg_load_super_block(const P &d, int64_t sb, int64_t n_words,
-                                                    WgSuperBlock<WPW> &m) {
+__device__ __forceinline__ int64_t stream_work(const GProg &d, int32_t w) {
+    return (int64_t)d.and_base(w) + kWordWork * w;
+}
+
+// First word w in [lo, hi] with stream_work(w) >= target (hi if none before
+// it): a 64-way search, one probe per lane and round (three rounds reach a
+// quarter million words).
+__device__ __forceinline__ int32_t first_word_at(const GProg &d, int32_t lo, int32_t hi, int64_t target) {
     const int lane = threadIdx.x & 63;
-    const int64_t w0 = sb * WPW;
-#pragma unroll
-    for (int w = 0; w < WPW; ++w) {
-        const int64_t r = (w0 + w) * 64 + lane;
-        m.len[w] = r < d.n_rows ? (int32_t)d.and_len[r] : 0;
-        if (w0 + w < n_words) {
-            m.base[w] = d.and_base(w0 + w);
-            m.andb[w] = d.and_bits(w0 + w);
-        } else {
-            m.base[w] = d.and_end;
-            m.andb[w] = 0;
+    while (lo < hi) {
+        const int32_t step = (hi - lo + 63) >> 6;
+        const int32_t p = min(lo + lane * step, hi);
+        const uint64_t ge = __ballot(p == hi || stream_work(d, p) >= target);
+        if (ge == 0) {  // every probe below hi is short of the target
+            lo = __builtin_amdgcn_readfirstlane(lo + 63 * step + 1);
+            continue;
         }
+        const int f = (int)__builtin_ctzll(ge);
+        const int32_t pf = min(lo + f * step, hi);
+        if (f == 0 || step == 1) return __builtin_amdgcn_readfirstlane(f == 0 ? lo : pf);
+        lo = __builtin_amdgcn_readfirstlane(lo + (f - 1) * step + 1);
+        hi = __builtin_amdgcn_readfirstlane(pf);
+    }
+    return lo;
+}
+
+// The AND stream of member `member` of a team of `team` workgroups (one
+// workgroup alone: 0 of 1), split into the workgroup's waves: the member takes
+// the words from the first word whose stream_work reaches member / team of
+// the program's, and wave k of its waves from the first word reaching its
+// member's start plus k / waves of the member's work. Every member finds the
+// same boundaries. Written to split[0..waves] by the waves themselves; the
+// caller synchronizes before reading it.
+__device__ __forceinline__ void split_words(const GProg &d, int32_t n_words, int32_t member, int32_t team,
+                                            lds_i32 *split) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int64_t total = stream_work(d, n_words);
+    const int32_t mw0 = member == 0 ? 0 : first_word_at(d, 0, n_words, total * member / team);
+    const int32_t mw1 = member + 1 == team ? n_words : first_word_at(d, 0, n_words, total * (member + 1) / team);
+    int32_t w = mw0;
+    if (wave > 0 && mw0 < mw1) {
+        const int64_t k0 = stream_work(d, mw0), k1 = stream_work(d, mw1);
+        w = first_word_at(d, mw0, mw1, k0 + (k1 - k0) * wave / waves);
+    }
+    if (lane == 0) {
+        split[wave] = w;
+        if (wave == waves - 1) split[waves] = mw1;
     }
 }
 
-// AND rows of the block pass (see BlockPass in lp_step.hip). Member `member`
-// of a team of `team` workgroups takes the super-blocks [n_sb member / team,
-// n_sb (member + 1) / team); ctr hands them out (zero before the product).
-template <int WPW, int U, class P>
-__device__ __forceinline__ uint32_t wg_block_rows(const P &d, const lds_u64 *v, lds_u64 *u,
-                                                  lds_u64 *s_ball, int32_t member, int32_t team, lds_u32 *ctr) {
+// Row data of a super-block of WPW words from word sbw (a multiple of 4):
+// this lane's AND length in each word, four words per dword as lens4 stores
+// them, and the first AND entry of the super-block's first word in the
+// wave's range (the same in every lane). Loaded a super-block ahead, so
+// nothing here is made wave-uniform before it is used (that would wait for
+// the load at once).
+template <int WPW>
+struct StreamMeta {
+    uint32_t lens[WPW / 4];
+    int32_t b0;
+};
+
+template <int WPW>
+__device__ __forceinline__ void stream_meta(const GProg &d, int32_t sbw, int32_t w_begin, StreamMeta<WPW> &m) {
+    // lens4 and words carry kWordPad empty words after the last, so every
+    // super-block that starts before the last word loads in bounds
     const int lane = threadIdx.x & 63;
-    const int64_t n_words = ((int64_t)d.n_rows + 63) >> 6;
-    const int64_t n_sb = (n_words + WPW - 1) / WPW;
-    const lds_u8 *v8 = (const lds_u8 *)v;
-    const lds_u32 *b32 = (const lds_u32 *)s_ball;
-    uint32_t my_new = 0;
-    // this member's super-blocks [sb0, sb1), handed out to the waves one at a
-    // time by an LDS counter (cleared before the product), so waves that run
-    // ahead take more of them
-    const int64_t sb0 = n_sb * member / team, sb1 = n_sb * (member + 1) / team;
-    auto grab = [&]() -> int64_t {
-        uint32_t k = 0;
-        if (lane == 0) k = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        return sb0 + (int64_t)__builtin_amdgcn_readlane(k, 0);
-    };
-    int64_t sb = grab();
-    if (sb >= sb1) return 0;
-    WgSuperBlock<WPW> cur;
-    wg_load_super_block<WPW, P>(d, sb, n_words, cur);
-    // the round being folded has its chunks loaded while the previous round
-    // is folded: c holds the chunks at `base`
-    int32_t base = __builtin_amdgcn_readfirstlane(cur.base[0]) & ~63;
-    int32_t c[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) c[k] = d.col[base + 64 * k + lane];
-    for (;;) {
-        WgSuperBlock<WPW> nxt;
-        const int64_t sbn = grab();
-        const bool more = sbn < sb1;
-        if (more) wg_load_super_block<WPW, P>(d, sbn, n_words, nxt);
-        const int64_t w0 = sb * WPW;
-        bool acc[WPW];
-        int32_t st[WPW], en[WPW];
+    for (int k = 0; k < WPW / 4; ++k) m.lens[k] = d.lens4[(int64_t)((sbw >> 2) + k) * 64 + lane];
+    m.b0 = d.and_base(sbw > w_begin ? sbw : w_begin);
+}
+
+template <int WPW>
+__device__ __forceinline__ int32_t stream_len(const uint32_t (&lens)[WPW / 4], int w) {
+    return (int32_t)((lens[w >> 2] >> ((w & 3) * 8)) & 0xffu);
+}
+
+// The super-block being evaluated: each lane's first entry per word, its
+// lengths (packed as in StreamMeta, words outside the wave's range masked to
+// 0), the words' entry ranges (wave-uniform: word w covers [ws[w],
+// ws[w + 1])) and this lane's AND results, one bit per word (set for the rows
+// with entries, cleared by the folds).
+template <int WPW>
+struct StreamSb {
+    int32_t st[WPW];
+    int32_t ws[WPW + 1];
+    uint32_t lens[WPW / 4];
+    uint32_t accm;
+};
+
+// Row starts by DPP scans of the lengths: those of words 4k and 4k + 2 (and
+// of 4k + 1 and 4k + 3) are scanned together as the two 16-bit halves of one
+// 32-bit scan (a half's sum is at most 64 x 255 < 2^16), two scans per four
+// words. Words outside [w_begin, w_end) count as empty.
+template <int WPW>
+__device__ __forceinline__ void stream_setup(const StreamMeta<WPW> &m, int32_t sbw, int32_t w_begin, int32_t w_end,
+                                             StreamSb<WPW> &S) {
+    int32_t run = __builtin_amdgcn_readfirstlane(m.b0);
+    S.accm = 0;
 #pragma unroll
-        for (int w = 0; w < WPW; ++w) {
-            st[w] = cur.base[w] + wave_exclusive_scan(cur.len[w]);
-            en[w] = st[w] + cur.len[w];
-            acc[w] = (cur.andb[w] >> lane) & 1ull;
+    for (int k = 0; k < WPW / 4; ++k) {
+        const int32_t lo = min(max(w_begin - sbw - 4 * k, 0), 4);
+        const int32_t hi = min(max(w_end - sbw - 4 * k, 0), 4);
+        const uint32_t keep = (hi == 4 ? ~0u : (1u << (8 * hi)) - 1u) & (lo == 4 ? 0u : ~((1u << (8 * lo)) - 1u));
+        const uint32_t L = m.lens[k] & keep;
+        S.lens[k] = L;
+        const int32_t pa = (int32_t)(L & 0x00ff00ffu);         // words 4k and 4k + 2
+        const int32_t pb = (int32_t)((L >> 8) & 0x00ff00ffu);  // words 4k + 1 and 4k + 3
+        const int32_t ea = wave_exclusive_scan(pa);
+        const int32_t eb = wave_exclusive_scan(pb);
+        const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane(ea + pa, 63);
+        const uint32_t tb = (uint32_t)__builtin_amdgcn_readlane(eb + pb, 63);
+        const int32_t ex[4] = {ea & 0xffff, eb & 0xffff, (int32_t)((uint32_t)ea >> 16), (int32_t)((uint32_t)eb >> 16)};
+        const int32_t tot[4] = {(int32_t)(ta & 0xffffu), (int32_t)(tb & 0xffffu), (int32_t)(ta >> 16),
+                                (int32_t)(tb >> 16)};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = 4 * k + j;
+            S.st[w] = run + ex[j];
+            S.ws[w] = run;
+            if ((L >> (8 * j)) & 0xffu) S.accm |= 1u << w;  // block AND rows are exactly the rows with a length
+            run += tot[j];
         }
-        const int32_t e1 = __builtin_amdgcn_readlane(en[WPW - 1], 63);
-        for (;;) {
-            // next chunks: this super-block's next round, else the next super-block's first
-            const bool last = base + 64 * U >= e1;
-            const int32_t nb = !last ? base + 64 * U
-                                     : (more ? (__builtin_amdgcn_readfirstlane(nxt.base[0]) & ~63) : -1);
-            int32_t cn[U];
-            if (nb >= 0) {
-#pragma unroll
-                for (int k = 0; k < U; ++k) cn[k] = d.col[nb + 64 * k + lane];
-            }
-            if (base < e1) {
-                uint32_t x[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) x[k] = entry_word(v8, c[k]);
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[k], (uint32_t)c[k], 1u));
-                    if (lane == 0) s_ball[k] = B;
-                }
-                const int32_t lim = base + 64 * U;
-#pragma unroll
-                for (int w = 0; w < WPW; ++w) {
-                    int32_t lo = st[w] > base ? st[w] : base;
-                    const int32_t hi = en[w] < lim ? en[w] : lim;
-                    while (lo < hi) {
-                        const int32_t rel = lo - base;
-                        const int32_t n = hi - lo < 32 ? hi - lo : 32;
-                        const uint32_t win =
-                            __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], rel & 31);
-                        const uint32_t m = n >= 32 ? ~0u : ((1u << n) - 1u);
-                        acc[w] = acc[w] && ((win & m) == m);
-                        lo += n;
-                    }
-                }
-            }
-            if (nb >= 0) {
-#pragma unroll
-                for (int k = 0; k < U; ++k) c[k] = cn[k];
-            }
-            base = nb;
-            if (last) break;
-        }
-#pragma unroll
-        for (int w = 0; w < WPW; ++w) {
-            if (w0 + w < n_words) {
-                const uint64_t res = __ballot(acc[w]);
-                if (lane == 0 && res) {
-                    __hip_atomic_fetch_or(&u[w0 + w], res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    my_new += (uint32_t)__popcll(res & ~v[w0 + w]);
-                }
-            }
-        }
-        if (!more) break;
-        cur = nxt;
-        sb = sbn;
     }
+    S.ws[WPW] = run;
+}
+
+// Each row-owner lane's fold of the ballot bits of its entries in the round
+// [base, base + 64 U): a 32-bit window of ballot bits from the row's first
+// entry (v_alignbit of two consecutive ballot dwords) against a mask of its
+// length; one step for rows of up to 32 entries in a round.
+template <int WPW, int U>
+__device__ __forceinline__ void stream_fold(const lds_u64 *s_ball, int32_t base, StreamSb<WPW> &S) {
+    const int32_t lim = base + 64 * U;
+    const lds_u32 *b32 = (const lds_u32 *)s_ball;
+#pragma unroll
+    for (int w = 0; w < WPW; ++w) {
+        if (S.ws[w + 1] <= base || S.ws[w] >= lim) continue;  // word outside the round (wave-uniform)
+        int32_t lo = S.st[w] > base ? S.st[w] : base;
+        const int32_t en = S.st[w] + stream_len<WPW>(S.lens, w);
+        const int32_t hi = en < lim ? en : lim;
+        uint32_t bad = 0;
+        while (lo < hi) {
+            const int32_t rel = lo - base;
+            const int32_t n = hi - lo < 32 ? hi - lo : 32;
+            const uint32_t win = __builtin_amdgcn_alignbit(b32[(rel >> 5) + 1], b32[rel >> 5], (uint32_t)rel);
+            bad |= ~win & (0xffffffffu >> (32 - n));
+            lo += n;
+        }
+        if (bad) S.accm &= ~(1u << w);
+    }
+}
+
+// Results of a finished super-block: one LDS OR per word of the wave's range
+// with AND rows that fire, and the new ones (not in v) counted in lane 0.
+template <int WPW>
+__device__ __forceinline__ uint32_t stream_finish(const lds_u64 *v, lds_u64 *u, int32_t sbw, int32_t w_begin,
+                                                  int32_t w_end, const StreamSb<WPW> &S) {
+    const int lane = threadIdx.x & 63;
+    uint32_t n_new = 0;
+#pragma unroll
+    for (int w = 0; w < WPW; ++w) {
+        const int32_t wd = sbw + w;
+        if (wd < w_begin || wd >= w_end) continue;  // another wave's word (wave-uniform)
+        const uint64_t res = __ballot((S.accm >> w) & 1u);
+        if (res && lane == 0) {
+            __hip_atomic_fetch_or(&u[wd], res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            n_new += (uint32_t)__popcll(res & ~v[wd]);
+        }
+    }
+    return n_new;
+}
+
+// A wave's part of the AND stream: words [w_begin, w_end) (split_words), the
+// first round's start `base` and the start of the round that ends at its
+// last entry (rounded up to 64). w_begin == w_end if it has no AND entries.
+// Fixed for a program, so found once when the program starts.
+struct StreamRange {
+    int32_t w_begin, w_end, base, last_base;
+};
+
+template <int U>
+__device__ __forceinline__ StreamRange stream_range(const GProg &d, int32_t w_begin, int32_t w_end) {
+    StreamRange R{w_begin, w_begin, 0, 0};
+    if (w_begin >= w_end) return R;
+    const int32_t e_begin = __builtin_amdgcn_readfirstlane(d.and_base(w_begin));
+    const int32_t e_end = __builtin_amdgcn_readfirstlane(d.and_base(w_end));
+    if (e_begin == e_end) return R;
+    R.w_end = w_end;
+    R.base = e_begin & ~63;
+    R.last_base = max(R.base, ((e_end + 63) & ~63) - 64 * U);
+    return R;
+}
+
+// AND rows of a layout in global memory: the wave's words [w_begin, w_end)
+// (split_words) as one stream of their AND entries, a contiguous stretch of
+// col, in rounds of U chunks of 64 entries (256 bytes, coalesced). The next
+// round's chunks are in flight while the current one is evaluated (byte
+// gathers of v from LDS, one ballot per chunk into the wave's LDS slots, one
+// window fold per row); the rows are taken in super-blocks of WPW words
+// aligned to 4 words (words outside the wave's range count as empty), whose
+// row data is loaded a super-block ahead, and a round may finish one
+// super-block and go on into the next. No round starts past the wave's last
+// entry (rounded up to 64): the last one starts early instead and folds some
+// entries a second time, which leaves every row's result as it was. The round
+// body is written twice with the chunk buffers swapped, so no chunk register
+// is copied.
+template <int WPW, int U, class F>
+__device__ __forceinline__ uint32_t wg_stream_rows(const GProg &d, const lds_u64 *v, lds_u64 *u, lds_u64 *s_ball,
+                                                   const StreamRange &R, F &&before) {
+    if (R.w_begin >= R.w_end) return before();  // no AND entries in the wave's words
+    const int32_t w_begin = R.w_begin, w_end = R.w_end, last_base = R.last_base;
+    const int lane = threadIdx.x & 63;
+    const lds_u8 *v8 = (const lds_u8 *)v;
+    int32_t base = R.base;
+    int32_t sbw = w_begin & ~3;
+    const int32_t sb_last = sbw + ((w_end - 1 - sbw) / WPW) * WPW;
+    // every load the first round needs is issued before the other work of
+    // the product (`before`), so their latencies overlap
+    StreamMeta<WPW> cur, nxt;
+    stream_meta<WPW>(d, sbw, w_begin, cur);
+    stream_meta<WPW>(d, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, nxt);
+    int32_t ca[U], cb[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) ca[k] = d.col[base + 64 * k + lane];
+    uint32_t my_new = before();
+    StreamSb<WPW> S;
+    stream_setup<WPW>(cur, sbw, w_begin, w_end, S);
+    auto round = [&](const int32_t (&c)[U], int32_t (&cn)[U]) -> bool {
+        // waves with more rounds left issue first, so the waves of the
+        // workgroup finish together
+        {
+            const int32_t left = last_base - base;
+            if (left > 3 * 64 * U) __builtin_amdgcn_s_setprio(3);
+            else if (left > 2 * 64 * U) __builtin_amdgcn_s_setprio(2);
+            else if (left > 64 * U) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
+        }
+        const int32_t lim = base + 64 * U;
+        const int32_t nb = max(base, min(lim, last_base));
+#pragma unroll
+        for (int k = 0; k < U; ++k) cn[k] = d.col[nb + 64 * k + lane];
+        // keep the scheduler from hoisting this round's gathers (which wait
+        // for its chunks) above the next round's loads
+        __builtin_amdgcn_sched_barrier(0);
+        // gathers in groups of at most 8 chunks (fewer registers held)
+        constexpr int H = U > 8 ? 8 : U;
+#pragma unroll
+        for (int h = 0; h < U; h += H) {
+            uint32_t x[H];
+#pragma unroll
+            for (int k = 0; k < H; ++k) x[k] = entry_word(v8, c[h + k]);
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                const uint64_t B = __ballot(__builtin_amdgcn_ubfe(x[k], (uint32_t)c[h + k], 1u));
+                if (lane == 0) s_ball[h + k] = B;
+            }
+        }
+        stream_fold<WPW, U>(s_ball, base, S);
+        while (S.ws[WPW] <= lim) {
+            my_new += stream_finish<WPW>(v, u, sbw, w_begin, w_end, S);
+            if (sbw >= sb_last) return false;
+            sbw += WPW;
+            stream_setup<WPW>(nxt, sbw, w_begin, w_end, S);
+            stream_meta<WPW>(d, sbw + WPW <= sb_last ? sbw + WPW : sb_last, w_begin, nxt);
+            stream_fold<WPW, U>(s_ball, base, S);
+        }
+        base = nb;
+        return true;
+    };
+    for (;;) {
+        if (!round(ca, cb)) break;
+        if (!round(cb, ca)) break;
+    }
+    __builtin_amdgcn_s_setprio(0);
     return my_new;
 }
 
@@ -383,17 +540,17 @@ __device__ __forceinline__ uint32_t wg_and_rows_by_lane(const Prog<3> &d, const 
     return my_new;
 }
 
-// The first four OR rows of this thread (member `member` of a team of `team`
-// workgroups), loaded at the start of a product so that their loads are in
-// flight with the AND pass's.
+// NQ OR rows of this thread, loaded together so that their loads are in
+// flight at once.
+template <int NQ>
 struct OrRows {
-    int32_t row[4], c0[4], c1[4];
+    int32_t row[NQ], c0[NQ], c1[NQ];
 };
 
-template <class P>
-__device__ __forceinline__ void or_rows_load(const P &d, int64_t j0, int64_t ostride, OrRows &o) {
+template <int NQ, class P>
+__device__ __forceinline__ void or_rows_load(const P &d, int64_t j0, int64_t ostride, OrRows<NQ> &o) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int64_t j = j0 + q * ostride;
         const bool in = j < d.n_or;
         o.row[q] = in ? d.or_row[j] : -1;
@@ -404,10 +561,11 @@ __device__ __forceinline__ void or_rows_load(const P &d, int64_t j0, int64_t ost
 
 // One OR row per row index, and u starts as a subset of v: a row that fires
 // is new iff v does not hold it, so the OR needs no return value.
-__device__ __forceinline__ uint32_t or_rows_eval(const OrRows &o, const lds_u64 *v, lds_u64 *u) {
+template <int NQ>
+__device__ __forceinline__ uint32_t or_rows_eval(const OrRows<NQ> &o, const lds_u64 *v, lds_u64 *u) {
     uint32_t my_new = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NQ; ++q)
         if (o.row[q] >= 0 && lds_any_in_range(v, o.c0[q], o.c1[q])) {
             const uint64_t bit = 1ull << (o.row[q] & 63);
             __hip_atomic_fetch_or(&u[o.row[q] >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -416,27 +574,23 @@ __device__ __forceinline__ uint32_t or_rows_eval(const OrRows &o, const lds_u64 
     return my_new;
 }
 
-template <class P>
-__device__ __forceinline__ void or_rows_first(const P &d, int32_t member, int32_t team, OrRows &o) {
-    or_rows_load(d, (int64_t)member * blockDim.x + threadIdx.x, (int64_t)team * blockDim.x, o);
-}
-
-// OR rows (one lane each; the first four already loaded into `first`) and
-// long rows (one wave per OR segment, one wave per whole long AND row,
-// looping over its segments).
+// OR rows (one lane each, member `member` of a team of `team` workgroups
+// takes every team-th block of them) and long rows (one wave per OR segment,
+// one wave per whole long AND row, looping over its segments).
 template <class P>
 __device__ __forceinline__ uint32_t wg_or_and_long_rows(const P &d, const lds_u64 *v, lds_u64 *u,
-                                                        int32_t member, int32_t team, const OrRows &first) {
+                                                        int32_t member, int32_t team) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const lds_u8 *v8 = (const lds_u8 *)v;
-    uint32_t my_new = or_rows_eval(first, v, u);
+    uint32_t my_new = 0;
     const int64_t ostride = (int64_t)team * blockDim.x;
-    for (int64_t j0 = (int64_t)member * blockDim.x + threadIdx.x + 4 * ostride; j0 < d.n_or; j0 += 4 * ostride) {
-        OrRows o;
-        or_rows_load(d, j0, ostride, o);
-        my_new += or_rows_eval(o, v, u);
+    constexpr int NQ = 4;
+    for (int64_t j0 = (int64_t)member * blockDim.x + threadIdx.x; j0 < d.n_or; j0 += NQ * ostride) {
+        OrRows<NQ> o;
+        or_rows_load<NQ>(d, j0, ostride, o);
+        my_new += or_rows_eval<NQ>(o, v, u);
     }
     for (int64_t si = (int64_t)member * waves + wave; si < d.n_segs; si += (int64_t)team * waves) {
         const auto sg = d.segs + si;
@@ -504,22 +658,20 @@ __device__ __forceinline__ bool team_barrier(g_u32 *count, uint32_t target, g_u3
 // n_rows + 1 bound) and leaves the fixpoint in *fix.
 template <int WPW, int U, class P>
 __device__ __forceinline__ int32_t solve_alone(const P &d, lds_u64 *cur, lds_u64 *nxt, lds_u64 *my_ball,
-                                               uint32_t *s_new, lds_u32 *s_sb, lds_u64 **fix) {
+                                               uint32_t *s_new, const StreamRange &R, lds_u64 **fix) {
     int32_t step = 1, slot = 1;  // slot = step mod 3
     uint32_t changed = 0;
     for (;;) {
-        if (threadIdx.x == 0) {
-            s_new[slot == 2 ? 0 : slot + 1] = 0;
-            s_sb[slot == 2 ? 0 : slot + 1] = 0;
-        }
-        OrRows o;
-        or_rows_first(d, 0, 1, o);
+        if (threadIdx.x == 0) s_new[slot == 2 ? 0 : slot + 1] = 0;
         uint32_t my_new;
-        if constexpr (P::kLds)
+        if constexpr (P::kLds) {
             my_new = wg_and_rows_by_lane<4>(d, cur, nxt);
-        else
-            my_new = wg_block_rows<WPW, U, P>(d, cur, nxt, my_ball, 0, 1, s_sb + slot);
-        my_new += wg_or_and_long_rows<P>(d, cur, nxt, 0, 1, o);
+            my_new += wg_or_and_long_rows<P>(d, cur, nxt, 0, 1);
+        } else {
+            // OR and long rows while the stream's first loads are in flight
+            my_new = wg_stream_rows<WPW, U>(d, cur, nxt, my_ball, R,
+                                            [&]() { return wg_or_and_long_rows<P>(d, cur, nxt, 0, 1); });
+        }
         my_new = wave_sum(my_new);
         if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&s_new[slot], my_new);
         __syncthreads();
@@ -649,7 +801,7 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     // cleared during product t, after every wave has read it for product t-2,
     // so one barrier per product suffices.
     __shared__ uint32_t s_new[3];
-    __shared__ uint32_t s_sb[3];  // super-blocks handed out, by product index mod 3 (as s_new)
+    __shared__ int32_t s_split[kMaxWaves + 1];  // the waves' words of the AND stream (split_words)
     __shared__ int32_t s_item;
     __shared__ uint32_t s_flag;
     lds_u64 *buf0 = (lds_u64 *)s_dyn;
@@ -658,10 +810,7 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
     if ((threadIdx.x & 63) == 0) my_ball[U] = 0;
     for (int32_t round = 0;; ++round) {
         if (threadIdx.x == 0) s_item = b.single ? round : (int32_t)atomicAdd(&b.queue[0], 1u);
-        if (threadIdx.x < 3) {
-            s_new[threadIdx.x] = 0;
-            s_sb[threadIdx.x] = 0;
-        }
+        if (threadIdx.x < 3) s_new[threadIdx.x] = 0;
         __syncthreads();
         const int32_t item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= b.n_items) break;
@@ -674,6 +823,7 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
         GProg d;
         d.words = as_global(pd.words);
         d.and_len = as_global(pd.and_len);
+        d.lens4 = as_global(pd.lens4);
         d.col = as_global(pd.col);
         d.or_c0 = as_global(pd.or_c0);
         d.or_row = as_global(pd.or_row);
@@ -685,27 +835,35 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
         d.and_end = pd.and_end;
         const gp<uint64_t> fact_bits = as_global(pd.fact_bits);
         const int32_t n_words = (d.n_rows + 63) >> 6;
+        // a layout that fits beside the buffers is copied into LDS once, so
+        // no product reads global memory; otherwise the member's words are
+        // split among the waves for the AND stream
+        const LdsLayout L = lds_layout(d.n_rows, d.and_end, d.n_or, d.n_segs, pd.long_nnz);
+        const bool in_lds = team == 1 && L.end <= (int64_t)b.lds_layout_bytes;
+        if (!in_lds)
+            split_words(d, n_words, member, team, (lds_i32 *)s_split);
         for (int32_t i = threadIdx.x; i < n_words; i += blockDim.x) {
             const uint64_t f = fact_bits[i];
             buf0[i] = f;
             buf1[i] = f;
         }
         __syncthreads();
+        const StreamRange R =
+            in_lds ? StreamRange{0, 0, 0, 0}
+                   : stream_range<U>(d, __builtin_amdgcn_readfirstlane(s_split[threadIdx.x >> 6]),
+                                     __builtin_amdgcn_readfirstlane(s_split[(threadIdx.x >> 6) + 1]));
         lds_u64 *cur = buf0, *nxt = buf1;  // cur holds v_t, nxt holds v_{t-1}
         int32_t step = 1, slot = 1;        // slot = step mod 3
         uint32_t changed = 0;
         int32_t result;
         if (team == 1) {
-            // a layout that fits beside the buffers is copied into LDS once, so
-            // no product reads global memory
-            const LdsLayout L = lds_layout(d.n_rows, d.and_end, d.n_or, d.n_segs, pd.long_nnz);
             lds_u64 *fix;
-            if (L.end <= (int64_t)b.lds_layout_bytes) {
+            if (in_lds) {
                 const Prog<3> dl = copy_layout_to_lds(d, pd.long_nnz, L, (lds_u8 *)(buf1 + b.lds_words));
                 __syncthreads();
-                result = solve_alone<WPW, U, Prog<3>>(dl, cur, nxt, my_ball, s_new, (lds_u32 *)s_sb, &fix);
+                result = solve_alone<WPW, U, Prog<3>>(dl, cur, nxt, my_ball, s_new, R, &fix);
             } else {
-                result = solve_alone<WPW, U, GProg>(d, cur, nxt, my_ball, s_new, (lds_u32 *)s_sb, &fix);
+                result = solve_alone<WPW, U, GProg>(d, cur, nxt, my_ball, s_new, R, &fix);
             }
             cur = fix;
         } else {
@@ -727,15 +885,13 @@ __global__ __launch_bounds__(1024) void tp_batch_kernel(BatchParams b) {
                 // product t, after every member has read them for product t-2
                 if (member == 0 && threadIdx.x == 0)
                     __hip_atomic_store(&T[2 + nslot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (threadIdx.x == 0) s_sb[nslot] = 0;
                 {
                     g_u64 *Dn = xch + (int64_t)nslot * n_words;
                     for (int32_t i = s0 + (int32_t)threadIdx.x; i < s1; i += blockDim.x) Dn[i] = 0ull;
                 }
-                OrRows o;
-                or_rows_first(d, member, team, o);
-                uint32_t my_new = wg_block_rows<WPW, U>(d, cur, nxt, my_ball, member, team, (lds_u32 *)s_sb + slot);
-                my_new += wg_or_and_long_rows(d, cur, nxt, member, team, o);
+                uint32_t my_new = wg_stream_rows<WPW, U>(d, cur, nxt, my_ball, R, [&]() {
+                    return wg_or_and_long_rows(d, cur, nxt, member, team);
+                });
                 my_new = wave_sum(my_new);
                 if ((threadIdx.x & 63) == 0 && my_new)
                     __hip_atomic_fetch_add(&T[2 + slot], my_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -802,6 +958,7 @@ __global__ __launch_bounds__(kTinyBlock) void tp_tiny_kernel(ProgDesc pd, int32_
     GProg d;
     d.words = as_global(pd.words);
     d.and_len = as_global(pd.and_len);
+    d.lens4 = as_global(pd.lens4);
     d.col = as_global(pd.col);
     d.or_c0 = as_global(pd.or_c0);
     d.or_row = as_global(pd.or_row);
@@ -841,7 +998,7 @@ hipError_t launch_tiny(const ProgDesc &pd, int32_t lds_words, size_t lds_bytes, 
 
 // ------------------------------------------------------------------ launchers
 
-#define LP_BATCH_SHAPES(X) X(1, 8) X(2, 8) X(4, 4) X(1, 16) X(2, 16)
+#define LP_BATCH_SHAPES(X) X(4, 4) X(4, 8) X(4, 16) X(8, 8) X(8, 16)
 
 static const void *batch_fn(int wpw, int unroll) {
 #define LP_X(W, U) \

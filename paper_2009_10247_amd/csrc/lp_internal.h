@@ -23,6 +23,8 @@ constexpr int32_t kSegAnd = 4096;       // entries per AND segment
 constexpr int32_t kSegOrBits = 16384;   // bits per OR segment
 constexpr int32_t kColPad = 64 * 16;    // zero entries after col: chunk loads past the end stay in bounds
 constexpr int32_t kWordPad = 16;        // empty words after the last: super-block loads past the end stay in bounds
+constexpr int kBatchWpw = 8;            // default shape of the batch kernel: words per super-block
+constexpr int kBatchUnroll = 16;        // and chunks of 64 entries per round
 
 struct WordMeta {
     int32_t and_base;    // offset in col of the word's first AND entry

@@ -103,6 +103,7 @@ hipError_t persistent_occupancy(const StepShape &s, int *blocks_per_cu);
 struct ProgDesc {
     const WordMeta *words;
     const uint8_t *and_len;
+    const uint32_t *lens4;   // the AND lengths by lane, four words per dword (the step kernels' form)
     const int32_t *col;
     const int32_t *or_c0;
     const int32_t *or_row;

@@ -889,6 +889,7 @@ static ProgDesc prog_desc(const Matrix &m) {
     ProgDesc g{};
     g.words = dm.words;
     g.and_len = dm.and_len;
+    g.lens4 = dm.lens4;
     g.col = dm.col;
     g.or_c0 = dm.or_c0;
     g.or_row = dm.or_row;
@@ -934,7 +935,7 @@ static lp_status lds_loop_fixpoint(const Matrix &m, hipStream_t st, Scratch &S, 
     if (q.lds_layout_bytes > 0 && tiny_fits(m.n_rows, m.dev.n_or, m.dev.n_segs))
         LP_HIP(launch_tiny(q.one, q.lds_words, (size_t)(v_bytes + lay), st));  // rows kept in registers
     else
-        LP_HIP(launch_batch(2, 8, 1, 1024, (size_t)(v_bytes + q.lds_layout_bytes), q, st));
+        LP_HIP(launch_batch(kBatchWpw, kBatchUnroll, 1, 1024, (size_t)(v_bytes + q.lds_layout_bytes), q, st));
     int32_t prods = 0;
     if (host_bits) {
         // the product count and the model bits in one copy: [products, pad .. last word of bits]
@@ -2311,8 +2312,8 @@ static lp_status tune_impl(const Matrix &m, int32_t reps, lp_schedule *best, flo
 // single-program drivers when the results are read.
 
 struct BatchShape {
-    int wpw = 2;
-    int unroll = 8;
+    int wpw = kBatchWpw;
+    int unroll = kBatchUnroll;
     int block = 1024;  // the autotuner's usual winner (one workgroup of 16 waves per CU)
     int grid = 0;
     size_t lds_bytes = 0;
@@ -2408,7 +2409,7 @@ static BatchParams batch_params(const BatchPlan &b, const BatchShape &s) {
 // once, but no more than there are queue positions.
 static lp_status batch_fit_shape(const BatchPlan &b, BatchShape *s) {
     if (!batch_shape_supported(s->wpw, s->unroll) || (s->block != 256 && s->block != 512 && s->block != 1024)) {
-        set_error("unsupported batch shape (wpw/unroll 1/8, 2/8, 4/4, 1/16, 2/16; block 256, 512 or 1024)");
+        set_error("unsupported batch shape (wpw/unroll 4/4, 4/8, 4/16, 8/8, 8/16; block 256, 512 or 1024)");
         return LP_E_INVAL;
     }
     DevProps d;
@@ -2871,7 +2872,7 @@ static lp_status batch_tune(BatchPlan &b, int32_t reps, float *best_ms, hipStrea
         if (best_ms) *best_ms = 0.f;
         return batch_run(b, st);
     }
-    static const int shapes[][2] = {{1, 8}, {2, 8}, {4, 4}, {1, 16}, {2, 16}};
+    static const int shapes[][2] = {{4, 4}, {4, 8}, {4, 16}, {8, 8}, {8, 16}};
     static const int blocks[] = {256, 512, 1024};
     Events ev;
     if ((rc = ev.init())) return rc;

@@ -10,7 +10,7 @@ from paper_2009_10247_amd import gen, lp
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(1, 8), (2, 8), (4, 4), (1, 16), (2, 16)]
+SHAPES = [(4, 4), (4, 8), (4, 16), (8, 8), (8, 16)]
 
 
 def _want(progs):
@@ -175,7 +175,7 @@ def test_batch_unsupported_shape_rejected():
     p = gen.definite_uniform(1, 100, 200, 0.05, 3)
     with lp.Matrix(p) as m:
         with pytest.raises(lp.LPError) as e:
-            lp.least_model_batch([m], sched=lp.make_schedule(wpw=8, unroll=16))
+            lp.least_model_batch([m], sched=lp.make_schedule(wpw=2, unroll=8))
         assert e.value.code == lp.LP_E_INVAL
         with pytest.raises(lp.LPError) as e:
             lp.least_model_batch([m], sched=lp.make_schedule(block=128))
@@ -185,7 +185,7 @@ def test_batch_unsupported_shape_rejected():
 # ---------------------------------------------------------------- teams
 
 @pytest.mark.parametrize("team", [2, 3, 8])
-@pytest.mark.parametrize("wpw,unroll,block", [(2, 8, 1024), (1, 16, 256)])
+@pytest.mark.parametrize("wpw,unroll,block", [(4, 16, 1024), (4, 8, 256)])
 def test_batch_forced_teams(team, wpw, unroll, block):
     # every program solved by a team of `team` workgroups: members take every
     # team-th super-block, OR row and segment, and meet after each product

@@ -45,6 +45,17 @@ def _edge_programs():
     rules += [(int(h), [int(b)]) for h, b in zip(rng.integers(12_000, 18_000, 3000), rng.integers(0, 12_000, 3000))]
     rules += [(19_003, [19_001, 19_000])]
     out.append(gen.from_rules(n, rules))
+    # AND entries only past 5,000 fact rows (the waves' stretches of words
+    # split by work leave the leading words to few waves), rows of 200-255
+    # entries that span rounds and super-blocks, and a chain of 255-entry rows
+    # (254 facts and the previous link) whose links fire one product apart
+    rules = [(a, []) for a in range(5000)]
+    rules += [(5000 + i, [int(x) for x in rng.choice(5000, size=int(rng.integers(200, 256)), replace=False)])
+              for i in range(600)]
+    rules += [(5600 + i, [int(x) for x in rng.choice(5000, size=254, replace=False)] + [5599 + i])
+              for i in range(300)]
+    rules += [(5900, [int(x) for x in rng.choice(5000, size=255, replace=False)] + [5950])]  # 256 entries, never fires
+    out.append(gen.from_rules(6000, rules))
     return out
 
 

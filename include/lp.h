@@ -247,6 +247,11 @@ lp_status lp_least_model(const lp_matrix *m, uint8_t *model, int32_t *products,
  *            row a = atom a true in column j). Requires no pruning.
  * products:  nullable; number of theta(M_P M) evaluations until no column changed.
  * K = 0 gives exactly one model, the least model.
+ * Device memory: a matrix of at most 2^28 row-words (n_rows x
+ *   ceil(2^K/64), after pruning) keeps a solve plan after its first solve:
+ *   both interpretation matrices (at most 4 GiB), its row sets and a captured
+ *   graph, counted in lp_info's device bytes and released by lp_matrix_evict
+ *   or lp_free_matrix. Larger matrices allocate their buffers per solve.
  * Errors: LP_E_TOO_MANY_GUESSES (K > LP_MAX_NEG_ATOMS), LP_E_TRUNCATED (more
  *   than max_models models; every other output is still complete),
  *   LP_E_INVAL (interp requested with pruning), LP_E_NOMEM, LP_E_DEVICE.

@@ -9,12 +9,14 @@ copy of that many MiB follows (a known-size kernel that calibrates byte
 counters in a profile of the same run).
 
     python -m paper_2009_10247_amd.batch_solve [--reps 20] [--count 512] [--seed 0] [--shape 4,16,1024]
+        [--frontier]
 
 --shape wpw,unroll,block fixes the kernel shape instead of autotuning it (the
 queue order and teams are still laid out by the product counts of a first
 run, lp_batch_tune with reps 0), and --no-check skips the comparison with
 single-program solves, so that a profile holds batch launches of one shape
-only.
+only. --frontier times a frontier plan instead (the same programs solved by
+frontier levels, each program's transposed matrix read once per solve).
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-mb", type=int, default=0)
     ap.add_argument("--shape", default=None, help="wpw,unroll,block (no autotuning)")
     ap.add_argument("--no-check", action="store_true", help="skip the single-program solves (profiles)")
+    ap.add_argument("--frontier", action="store_true", help="a frontier plan instead of matrix products")
     args = ap.parse_args(argv)
     import torch
 
@@ -43,11 +46,15 @@ def main(argv=None) -> int:
     mats = [lp.Matrix(p, stream=st) for p in progs]
     try:
         sched = None
-        if args.shape:
+        if args.frontier:
+            sched = lp.make_schedule(driver=lp.LP_DRIVER_FRONTIER)
+        elif args.shape:
             sched = lp.lp_schedule()
             sched.wpw, sched.unroll, sched.block = (int(x) for x in args.shape.split(","))
         with lp.Batch(mats, sched=sched, stream=st) as plan:
-            if args.shape:
+            if args.frontier:
+                pass
+            elif args.shape:
                 plan.tune(reps=0, stream=st)  # order and teams by product counts, at the given shape
             elif not args.no_tune:
                 plan.tune(reps=3, stream=st)
@@ -73,9 +80,16 @@ def main(argv=None) -> int:
                       for m, pr in zip(mats, prods))
             print(json.dumps({"workload": f"{args.count} definite programs, atoms log-uniform 1e3-1e5, rules 2x "
                                           "atoms, bodies 1-6, 2% facts; one batch launch (graph replay)",
-                              "ms_per_batch": round(ms, 4), "entries_per_s": round(entries / (ms / 1e3), 1),
+                              "ms_per_batch": round(ms, 4),
+                              "entries_per_s": None if args.frontier else round(entries / (ms / 1e3), 1),
                               "products_total": int(sum(prods)), "nnz": info["nnz"],
-                              "csr_bytes_per_batch": int(csr), "csr_GB/s": round(csr / (ms / 1e3) / 1e9, 1),
+                              # (a frontier plan does not read the matrix once per product: no CSR rate for it)
+                              "csr_bytes_per_batch": int(csr),
+                              "csr_GB/s": None if args.frontier else round(csr / (ms / 1e3) / 1e9, 1),
+                              "plan": "frontier" if args.frontier else "matrix products",
+                              # the transposed matrices, which a frontier plan reads once per solve
+                              "transpose_bytes": int(sum(4 * (m.info["n_rows"] + 1) + 4 * m.info["nnz"]
+                                                         for m in mats)),
                               "shape": {k: info[k] for k in ("wpw", "unroll", "block", "grid", "lds_bytes")},
                               "teams": {k: info[k] for k in ("n_teams", "team_members", "team_fallbacks")}}),
                   flush=True)

@@ -96,6 +96,38 @@ def test_batch_shapes(wpw, unroll, block):
             m.close()
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_batch_random_plans(seed):
+    # random programs (skewed sizes, chains, facts-only and OR-heavy ones) under
+    # a random shape, block, grid and team setting; every model and product
+    # count against the oracle
+    rng = np.random.default_rng(100 + seed)
+    progs = gen.batch_programs(200 + seed, count=int(rng.integers(8, 40)), lo=20, hi=int(rng.integers(500, 30_000)))
+    L = int(rng.integers(2, 120))
+    progs.append(gen.from_rules(L, [(0, [])] + [(i, [i - 1]) for i in range(1, L)]))
+    n = int(rng.integers(200, 3000))
+    progs.append(gen.from_rules(n, [(a, []) for a in range(n // 2)] +
+                                [(int(h), [int(x)]) for h, x in zip(rng.integers(n // 2, n, 4 * n), rng.integers(0, n, 4 * n))]))
+    order = rng.permutation(len(progs))
+    progs = [progs[i] for i in order]
+    want = _want(progs)
+    wpw, unroll = SHAPES[int(rng.integers(len(SHAPES)))]
+    block = int(rng.choice([256, 512, 1024]))
+    team = int(rng.choice([0, 1, 2, 3]))
+    grid = int(rng.choice([0, 0, 7, 64]))
+    mats = [lp.Matrix(p) for p in progs]
+    try:
+        sched = lp.make_schedule(wpw=wpw, unroll=unroll, block=block, team=team, grid=grid)
+        with lp.Batch(mats, sched=sched) as b:
+            b.run()
+            _assert_equal(b.results(), want, (seed, wpw, unroll, block, team, grid))
+            b.run()
+            _assert_equal(b.results(), want, (seed, "replay"))
+    finally:
+        for m in mats:
+            m.close()
+
+
 @pytest.mark.parametrize("grid", [1, 3])
 def test_batch_few_workgroups_take_many_programs(grid):
     progs = gen.batch_programs(9, count=30, lo=20, hi=3000) + _edge_programs()

@@ -746,12 +746,13 @@ hipError_t launch_dirty_product(const DirtyParams &p, int max_grid, hipStream_t 
         hipLaunchKernelGGL(spmm_dirty_product_small_kernel, dim3(grid), dim3(kBlock), 0, st, p);
         return hipGetLastError();
     }
-    // chunks of 64 x 8 words where rows are that wide: a wave's rows in one
-    // bitmap word are evaluated one pair after another whatever the chunk, so
-    // wide chunks keep the most loads in flight
-    const int log2GC = std::min(3, p.log2W - 6);
+    // chunks of up to 64 x 4 words: more chunks per row put a changed row's
+    // words on more waves, which beat keeping more loads in flight per wave
+    // (8 words per lane and chunk: 0.272 / 0.296 / 0.681 ms per solve at 15 /
+    // 16 / 18 negated atoms on 10,000 atoms; 4: 0.233 / 0.273 / 0.681; 2 at
+    // 16: 0.298)
+    const int log2GC = std::min(2, p.log2W - 6);
     switch (log2GC) {
-        case 3: hipLaunchKernelGGL((spmm_dirty_product_kernel<8>), dim3(grid), dim3(kBlock), 0, st, p); break;
         case 2: hipLaunchKernelGGL((spmm_dirty_product_kernel<4>), dim3(grid), dim3(kBlock), 0, st, p); break;
         case 1: hipLaunchKernelGGL((spmm_dirty_product_kernel<2>), dim3(grid), dim3(kBlock), 0, st, p); break;
         default: hipLaunchKernelGGL((spmm_dirty_product_kernel<1>), dim3(grid), dim3(kBlock), 0, st, p); break;

@@ -443,6 +443,7 @@ __device__ __forceinline__ uint32_t wg_stream_rows(const GProg &d, const lds_u64
         __builtin_amdgcn_sched_barrier(0);
         // gathers in groups of at most 8 chunks (fewer registers held)
         constexpr int H = U > 8 ? 8 : U;
+        static_assert(U % H == 0, "a round's chunks must fill whole gather groups");
 #pragma unroll
         for (int h = 0; h < U; h += H) {
             uint32_t x[H];

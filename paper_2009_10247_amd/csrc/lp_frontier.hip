@@ -189,6 +189,7 @@ __global__ __launch_bounds__(kFrontierLoopBlock) void frontier_levels_kernel(Fro
 // level count is the product count of the full sweep. The last workgroup to
 // leave rewinds the queue, so graph replays need no memset.
 __global__ __launch_bounds__(kFBatchBlock) void frontier_batch_kernel(FBatchParams b) {
+    extern __shared__ __attribute__((aligned(16))) uint64_t s_fdyn[];
     constexpr int NW = kFBatchBlock / 64;
     __shared__ int32_t s_excl[NW][64];
     __shared__ int32_t s_start[NW][64];
@@ -212,8 +213,14 @@ __global__ __launch_bounds__(kFBatchBlock) void frontier_batch_kernel(FBatchPara
 #pragma unroll
             for (int i = 0; i < (int)(sizeof(FBatchProg) / 4); ++i) o[i] = s[i];
         }
-        for (int32_t i = threadIdx.x; i < P.n_rows; i += kFBatchBlock) P.cnt[i] = P.cnt0[i];
-        for (int32_t w = threadIdx.x; w < P.n_words; w += kFBatchBlock) P.v[w] = 0ull;
+        // a program of at most lds_rows rows keeps its counts and v in LDS (the
+        // pushes reach them through generic pointers, as atomics on LDS), and
+        // its v goes to memory once at the end
+        const bool in_lds = P.n_rows <= b.lds_rows;
+        uint64_t *v = in_lds ? (uint64_t *)s_fdyn : P.v;
+        int32_t *cnt = in_lds ? (int32_t *)(s_fdyn + ((b.lds_rows + 63) >> 6)) : P.cnt;
+        for (int32_t i = threadIdx.x; i < P.n_rows; i += kFBatchBlock) cnt[i] = P.cnt0[i];
+        for (int32_t w = threadIdx.x; w < P.n_words; w += kFBatchBlock) v[w] = 0ull;
         if (threadIdx.x == 0) {
             s_n[0] = (uint32_t)P.n_facts;
             s_n[1] = 0;
@@ -222,14 +229,14 @@ __global__ __launch_bounds__(kFBatchBlock) void frontier_batch_kernel(FBatchPara
         for (int32_t j = threadIdx.x; j < P.n_facts; j += kFBatchBlock) {
             const int32_t r = P.facts[j];
             q[0][j] = r;
-            atomicOr((unsigned long long *)&P.v[r >> 6], 1ull << (r & 63));
+            atomicOr((unsigned long long *)&v[r >> 6], 1ull << (r & 63));
         }
         __syncthreads();
         FrontierParams f{};
         f.occ_ptr = P.occ_ptr;
         f.occ = P.occ;
-        f.cnt = P.cnt;
-        f.v = P.v;
+        f.cnt = cnt;
+        f.v = v;
         int32_t t = 1;  // level t pushes F_{t-1} into F_t
         for (;; ++t) {
             const uint32_t n_in = s_n[(t - 1) & 3];
@@ -241,7 +248,9 @@ __global__ __launch_bounds__(kFBatchBlock) void frontier_batch_kernel(FBatchPara
             if (s_n[t & 3] == 0 || t > P.n_rows) break;
         }
         if (threadIdx.x == 0) *P.out_products = s_n[t & 3] == 0 ? t : -1;
-        __syncthreads();  // s_n, s_item and the queues are reused by the next program
+        if (in_lds)  // (after the last level's barrier: every push is done)
+            for (int32_t w = threadIdx.x; w < P.n_words; w += kFBatchBlock) P.v[w] = v[w];
+        __syncthreads();  // s_n, s_item, the queues and the LDS counts are reused by the next program
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -267,8 +276,15 @@ hipError_t launch_frontier_levels(const FrontierParams &f, const int32_t *facts,
 }
 
 hipError_t launch_frontier_batch(const FBatchParams &b, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(frontier_batch_kernel, dim3((unsigned)grid), dim3(kFBatchBlock), 0, st, b);
+    hipLaunchKernelGGL(frontier_batch_kernel, dim3((unsigned)grid), dim3(kFBatchBlock), fbatch_lds_bytes(b.lds_rows),
+                       st, b);
     return hipGetLastError();
+}
+
+void frontier_kernels_allow_lds(int max_dynamic_lds) {
+    (void)hipFuncSetAttribute((const void *)frontier_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              max_dynamic_lds);
+    (void)hipGetLastError();
 }
 
 }  // namespace lp

@@ -286,9 +286,15 @@ struct FBatchParams {
     int32_t *qbuf;            // two frontier buffers of qcap rows per workgroup
     int64_t qcap;
     int32_t n_items;
+    int32_t lds_rows;         // programs of at most this many rows keep counts and v in LDS (0: none)
 };
 constexpr int kFBatchBlock = 1024;
+// Dynamic LDS of the frontier batch kernel: v (8 bytes per 64 rows), then the counts.
+inline size_t fbatch_lds_bytes(int32_t lds_rows) {
+    return lds_rows > 0 ? 8 * (size_t)((lds_rows + 63) / 64) + 4 * (size_t)lds_rows : 0;
+}
 hipError_t launch_frontier_batch(const FBatchParams &b, int grid, hipStream_t st);
+void frontier_kernels_allow_lds(int max_dynamic_lds);
 
 hipError_t launch_init_m0(uint64_t *V, uint64_t *U, int64_t total, int32_t log2W, int32_t n_std,
                           const uint64_t *fact_bits, const int32_t *guess_pos, int32_t k_eff,

@@ -652,7 +652,10 @@ static lp_status dev_props(int dev, DevProps *out) {
         DevProps d;
         LP_HIP(hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         LP_HIP(hipDeviceGetAttribute(&d.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        if (d.max_lds > 4096) batch_kernels_allow_lds(d.max_lds - 4096);
+        if (d.max_lds > 4096) {
+            batch_kernels_allow_lds(d.max_lds - 4096);
+            frontier_kernels_allow_lds(d.max_lds - 4096);
+        }
         cache[dev] = d;
     }
     *out = cache[dev];
@@ -2337,6 +2340,9 @@ constexpr double kProductCost = 4500.0;
 // Polls after which a team barrier gives up (a few seconds: far beyond any
 // wait of members that run at once).
 constexpr uint32_t kTeamPolls = 1u << 22;
+// Dynamic LDS of the frontier batch kernel for the counts and v of programs
+// small enough to keep them there.
+constexpr size_t kFBatchLdsBytes = 128 << 10;
 
 struct BatchPlan {
     int device = -1;
@@ -2373,6 +2379,7 @@ struct BatchPlan {
     int32_t *d_cnt = nullptr;
     int32_t *d_fq = nullptr;
     int64_t fq_cap = 0;
+    int32_t f_lds_rows = 0;          // frontier plans: programs of at most this many rows keep counts and v in LDS
 };
 
 static void batch_release(BatchPlan &b) {
@@ -2560,6 +2567,15 @@ static lp_status frontier_batch_layout(BatchPlan &b, const lp_schedule *sched, h
     s.lds_bytes = 0;
     b.shape = s;
     b.fq_cap = max_rows;
+    // programs of up to f_lds_rows rows keep their counts and v in LDS: as many
+    // rows as kFBatchLdsBytes holds (beside the kernel's 8 KB of static LDS),
+    // but no more than the largest program needs
+    {
+        int32_t r = (int32_t)std::min<int64_t>(max_rows, (int64_t)kFBatchLdsBytes / 4);
+        const size_t cap = std::min<size_t>(kFBatchLdsBytes, (size_t)std::max(0, d.max_lds - 4096 - 8192));
+        while (r > 0 && fbatch_lds_bytes(r) > cap) r -= 64;
+        b.f_lds_rows = std::max(0, r);
+    }
     if ((rc = dev_alloc((void **)&b.d_out, (size_t)std::max<int64_t>(1, words) * 8, st)) ||
         (rc = dev_alloc((void **)&b.d_prod, sizeof(int32_t) * std::max(1, count), st)) ||
         (rc = dev_alloc((void **)&b.d_cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(1, cnts), st)) ||
@@ -2776,6 +2792,7 @@ static FBatchParams fbatch_params(const BatchPlan &b) {
     q.qbuf = b.d_fq;
     q.qcap = b.fq_cap;
     q.n_items = (int32_t)b.order.size();
+    q.lds_rows = b.f_lds_rows;
     return q;
 }
 
